@@ -1,0 +1,239 @@
+/*
+ * gpuqt.h -- C ABI of the MI355X (gfx950) Chebyshev / KPM linear-scaling Kubo
+ * transport library.
+ *
+ * Method: Fan, Vierimaa & Harju, "GPUQT: an efficient linear-scaling quantum
+ * transport code fully implemented on graphics processing units"
+ * (Comput. Phys. Commun.; arXiv:1705.01387).  hbar = 1 (Section 4.2.6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex numbers are interleaved {double re, double im} (the memory layout
+ *    of torch.complex128 / C99 double complex).  A "c128 pointer" below is a
+ *    `double*` to such pairs and must be 16-byte aligned.
+ *  - State vectors hold B columns in layout [n][B] (column index fastest):
+ *    element (i, b) is at c128 offset i*B + b.  B is 1, 2, 4, 8 or 16.
+ *  - Unless stated otherwise, vector, output and workspace pointers are DEVICE
+ *    pointers owned by the caller; the library never frees them.  Descriptor
+ *    arrays passed to gpuqt_build_h and the `dt` arrays of gpuqt_vac/gpuqt_msd
+ *    are HOST pointers, read during the call only.
+ *  - Compute calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*; NULL = the null stream).  All argument checks happen on the host
+ *    before anything is enqueued; a call that returns an error has enqueued
+ *    nothing.  Results are valid once the stream has reached the call.
+ *  - Compute calls never allocate device memory: scratch comes from the
+ *    caller's workspace, sized by gpuqt_workspace_size.  Two calls that run at
+ *    the same time on one handle need distinct workspaces.
+ *  - No entry point throws or aborts.  Each returns a gpuqt_status; on failure
+ *    gpuqt_last_error() gives a message (per thread).
+ */
+#ifndef GPUQT_H
+#define GPUQT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gpuqt_status;
+enum {
+  GPUQT_OK = 0,
+  GPUQT_ERR_ARG = 1,         /* null pointer, size out of range, misaligned or aliased buffer */
+  GPUQT_ERR_LAYOUT = 2,      /* neighbour index out of range, count > max_nn, bond between
+                                segments, non-Hermitian H, bond of exactly half the period */
+  GPUQT_ERR_SPECTRUM = 3,    /* DeltaE below the Gershgorin bound, or |E| >= DeltaE */
+  GPUQT_ERR_WORKSPACE = 4,   /* workspace smaller than gpuqt_workspace_size */
+  GPUQT_ERR_HIP = 5,         /* HIP runtime failure (no device, launch error, wrong device) */
+  GPUQT_ERR_NOMEM = 6,       /* device allocation failed (gpuqt_build_h only) */
+  GPUQT_ERR_UNSUPPORTED = 7  /* valid request this build does not handle (e.g. B = 3) */
+};
+
+typedef struct gpuqt_h_s *gpuqt_h;   /* opaque handle of a Hamiltonian on one device */
+
+/*
+ * Tight-binding model, as the paper's input files describe it (Section 4.2):
+ *   H = sum_mn H_mn |m><n| + sum_m U_m |m><m|,  X = diag(x),
+ *   V = i [H, X],  (V)_mn = i (x_n - x_m) H_mn.
+ * Several independent systems ("segments": disorder realisations of any
+ * sizes) may be stacked block-diagonally; each gets its own DeltaE, and every
+ * moment is then reported per segment.
+ */
+typedef struct {
+  int64_t n;                    /* number of orbitals (all segments), >= 1 */
+  int32_t max_nn;               /* neighbour slots per orbital (Section 4.2.1), >= 0 */
+  const int32_t *nn;            /* [n] neighbour count of each orbital, 0..max_nn */
+  const int32_t *nbr;           /* [n*max_nn] row-major: nbr[i*max_nn + s], s < nn[i], in [0, n) */
+  const double *hop;            /* NULL: every hopping is -1 (Section 4.2.2);
+                                   else [n*max_nn] real, or [2*n*max_nn] interleaved complex,
+                                   hop[i*max_nn + s] = H[i, nbr[i*max_nn + s]] */
+  int32_t hop_is_complex;       /* 0: real hoppings; 1: complex */
+  const int32_t *hop_class;     /* NULL or [n*max_nn]: class of each hopping, for gradients */
+  int32_t n_class;              /* number of hopping classes (>= 1) */
+  const double *onsite;         /* NULL: U = 0 (Section 4.2.3); else [n] */
+  const double *x;              /* [n] coordinate along the transport direction (Section 4.2.4) */
+  double length_x;              /* period along x (minimum-image differences); <= 0: open */
+  double volume;                /* system volume Omega (reported back; used by the caller) */
+  double energy_max;            /* DeltaE (Section 3.2); <= 0: 1.01 x Gershgorin bound */
+  int32_t n_segments;           /* 0 or 1: one system; > 1: block-diagonal segments */
+  const int64_t *seg_offsets;   /* [n_segments+1] first row of each segment, last = n */
+  const double *seg_energy_max; /* NULL or [n_segments]: per-segment DeltaE (<= 0: auto) */
+  const double *seg_length_x;   /* NULL or [n_segments]: per-segment period (else length_x) */
+  int32_t check_hermitian;      /* nonzero: require H_ji = conj(H_ij) (sums over duplicates) */
+  int32_t slice_height;         /* sliced-ELL slice height: 0 = default (64), else 32..1024, 2^k */
+} gpuqt_h_desc;
+
+/*
+ * Build the device layout of H (sliced ELL: neighbour indices, hoppings
+ * scaled by 1/DeltaE, position differences, on-site terms; Section 4.2).
+ * Validates the descriptor (GPUQT_ERR_LAYOUT / GPUQT_ERR_SPECTRUM before any
+ * device work), then allocates device memory on the current device and copies
+ * synchronously.  *out receives a handle owned by the caller (gpuqt_destroy_h).
+ * A DeltaE below the segment's Gershgorin bound max_i(|U_i| + sum_j |H_ij|) is
+ * rejected (GPUQT_ERR_SPECTRUM): the paper requires the spectrum of H/DeltaE
+ * to lie in [-1, 1] (Section 3.2, Section 4.2.7).
+ */
+gpuqt_status gpuqt_build_h(const gpuqt_h_desc *desc, void *stream, gpuqt_h *out);
+
+/* Free the handle and its device memory (NULL is ignored).  The caller must
+ * make sure no enqueued work still uses it. */
+void gpuqt_destroy_h(gpuqt_h h);
+
+typedef struct {
+  int64_t n;                 /* orbitals */
+  int32_t n_segments;
+  int32_t n_class;
+  int32_t hop_mode;          /* 0: uniform value per segment, 1: real, 2: complex */
+  int32_t slice_height;
+  int64_t n_slices;
+  int64_t entries;           /* stored ELL entries (with padding) */
+  int64_t nnz;               /* neighbour entries (without padding) */
+  int32_t max_width;         /* widest slice */
+  int32_t uniform_width;     /* width of every slice when equal and unpadded, else 0 */
+  int32_t grid_blocks;       /* workgroups per sparse-step launch */
+  int32_t reserved;
+  size_t device_bytes;       /* device memory held by the handle */
+} gpuqt_h_info_t;
+
+/* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
+ * gershgorin (may be NULL) the [n_segments] bounds. */
+gpuqt_status gpuqt_h_info(gpuqt_h h, gpuqt_h_info_t *info, double *energy_max, double *gershgorin);
+
+/* Operations, for gpuqt_workspace_size. */
+enum {
+  GPUQT_OP_MOMENTS = 0,
+  GPUQT_OP_EVOLVE = 1,
+  GPUQT_OP_EVOLVE_COMMUTATOR = 2,
+  GPUQT_OP_VAC = 3,
+  GPUQT_OP_MSD = 4,
+  GPUQT_OP_MOMENTS_BACKWARD = 5
+};
+
+/* Bytes of device workspace `op` needs for B columns, M moments and Np
+ * Chebyshev terms per time step.  Np = 0 reserves room for up to 8192 terms
+ * (enough for DeltaE*|dt| up to about 7000).  M is ignored by the EVOLVE
+ * operations, Np by MOMENTS and MOMENTS_BACKWARD. */
+gpuqt_status gpuqt_workspace_size(gpuqt_h h, int32_t op, int32_t B, int32_t M, int32_t Np,
+                                  size_t *bytes);
+
+/*
+ * Chebyshev moments (Section 3.3):  mu[s][b][k] = <phiL_b| T_k(H/DeltaE_s) |phiR_b>
+ * restricted to segment s, for k < M, by the recurrence of Section 3.2
+ * (T_0 = 1, T_1 = H~, T_k = 2 H~ T_{k-1} - T_{k-2}).
+ *   phiL, phiR : c128 [n][B] (may be the same pointer)
+ *   mu         : c128 [n_segments][B][M], device
+ * The reduction order is fixed, so repeated calls give bit-identical results.
+ */
+gpuqt_status gpuqt_moments(gpuqt_h h, int32_t B, const double *phiL, const double *phiR,
+                           int32_t M, double *mu, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Time evolution by the Chebyshev-Bessel series of Section 3.2:
+ *   psi_out = U(dt) psi_in,  U(dt) = exp(-i H dt) for dt > 0 and exp(+i H |dt|) for dt < 0,
+ *   U(+-dt) psi = sum_{m<Np} (2 - delta_m0) (-+i)^m J_m(DeltaE_s |dt|) T_m(H~) psi.
+ * When chi_out is not NULL, also the commutator series of Section 3.2 combined
+ * with the product rule:  chi_out = [X, U(dt)] psi_in + U(dt) chi_in
+ * (chi_in NULL means zero), using [X, T_m] = 2[X,H~]T_{m-1} + 2H~[X,T_{m-1}] - [X,T_{m-2}].
+ *   Np : terms; 0 = the smallest m > DeltaE|dt| with |J_m| < 1e-16 (max over segments)
+ *   psi_in, chi_in, psi_out, chi_out : c128 [n][B]; outputs must not overlap inputs.
+ */
+gpuqt_status gpuqt_evolve(gpuqt_h h, int32_t B, double dt, int32_t Np, const double *psi_in,
+                          double *psi_out, const double *chi_in, double *chi_out, void *ws,
+                          size_t ws_bytes, void *stream);
+
+enum { GPUQT_VELOCITY = 0, GPUQT_COMMUTATOR_XH = 1 };
+
+/*
+ * Velocity / commutator application (Section 4.2, velocity operator):
+ *   GPUQT_VELOCITY      : out = V psi,     (V psi)_i     = i sum_j (x_j - x_i) H_ij psi_j
+ *   GPUQT_COMMUTATOR_XH : out = [X,H] psi, ([X,H] psi)_i = -sum_j (x_j - x_i) H_ij psi_j
+ * (x_j - x_i by minimum image when the segment is periodic).  Unscaled H.
+ *   psi, out : c128 [n][B], must not overlap.
+ */
+gpuqt_status gpuqt_apply_commutator(gpuqt_h h, int32_t B, int32_t which, const double *psi,
+                                    double *out, void *stream);
+
+/*
+ * VAC moments (Section 3.3, C_n^VAC):  for k < n_t,
+ *   out[k][s][b][n] = Re <phi| U(t_k) V T_n(H~) U(t_k)^+ V |phi>,  t_k = dt[0] + ... + dt[k-1]
+ * (row 0 at t = 0), computed as Re <V psi_L| T_n |psi_R> with psi_L = U(-t_k) phi and
+ * psi_R = U(-t_k) V phi, advanced by U(-dt[k]) between rows.
+ *   phi : c128 [n][B];  dt : HOST [n_t];  out : double [n_t][n_segments][B][M], device
+ */
+gpuqt_status gpuqt_vac(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, const double *dt,
+                       int32_t M, int32_t Np, double *out, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
+ * MSD moments (Section 3.3, C_n^MSD):  for k < n_t,
+ *   out[k][s][b][n] = Re <chi_{k+1}| T_n(H~) |chi_{k+1}>,  chi_{k+1} = [X, U(t_{k+1})] phi,
+ *   t_{k+1} = dt[0] + ... + dt[k],
+ * with chi advanced by the product rule chi_{k+1} = [X, U(dt_k)] psi_k + U(dt_k) chi_k,
+ * psi_{k+1} = U(dt_k) psi_k, chi_0 = 0, psi_0 = phi.
+ *   phi : c128 [n][B];  dt : HOST [n_t];  out : double [n_t][n_segments][B][M], device
+ */
+gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, const double *dt,
+                       int32_t M, int32_t Np, double *out, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
+ * KPM reconstruction (Section 3.3, same prefactor for DOS, rho*C_vv, rho*DeltaX^2):
+ *   out[r][e] = 2 / (pi Omega DeltaE sqrt(1 - E~^2)) sum_{n<M} g_n (2 - delta_n0) T_n(E~) C[r][n],
+ *   E~ = energies[e] / DeltaE, g_n the Jackson damping (jackson != 0) or 1.
+ *   C : double [R][M], energies : double [n_E], out : double [R][n_E]; all device.
+ * The expansion only exists inside the scaled band: out is NaN where |E~| >= 1
+ * (the energies live on the device, so this is not checked on the host).
+ */
+gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double *C, int32_t n_E,
+                                   const double *energies, double energy_max, double volume,
+                                   int32_t jackson, double *out, void *stream);
+
+/* Host helpers (no device use). */
+
+/* Jackson damping g_n, n < M (Section 3.3):  g_n = (1 - n a) cos(pi n a) + a sin(pi n a) cot(pi a),
+ * a = 1/(M+1).  g: HOST [M]. */
+gpuqt_status gpuqt_jackson(int32_t M, double *g);
+
+/* Bessel functions of the first kind J_m(tau), m < Np, tau >= 0 (Miller's backward
+ * recurrence normalised by J_0 + 2 sum_k J_2k = 1).  J: HOST [Np]. */
+gpuqt_status gpuqt_bessel(double tau, int32_t Np, double *J);
+
+/* Number of Chebyshev terms for U(dt): the smallest m > tau with |J_m(tau)| < 1e-16,
+ * tau = DeltaE |dt| (Section 3.2: up to machine precision, proportional to dt).
+ * Returns -1 for tau < 0 or not finite. */
+int32_t gpuqt_auto_terms(double tau);
+
+/* Message of the last failure in this thread ("" if none). */
+const char *gpuqt_last_error(void);
+
+/* Measurement helper: copy `bytes` (multiple of 16) from src to dst on the
+ * device with the same 16-byte vector loads the sparse steps use; its
+ * duration gives the attainable HBM bandwidth.  src, dst: device, no overlap. */
+gpuqt_status gpuqt_copy_probe(const void *src, void *dst, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPUQT_H */

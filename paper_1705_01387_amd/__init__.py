@@ -1,1 +1,14 @@
-"""MI355X-native Chebyshev/KPM linear-scaling Kubo transport path (placeholder, binding follows)."""
+"""MI355X-native (gfx950) Chebyshev/KPM linear-scaling Kubo transport path.
+
+The compute lives in libgpuqt.so (HIP kernels behind a C ABI, include/gpuqt.h);
+this package binds its entry points under the same names (_binding) and holds
+the seeded input generators (inputs).
+"""
+from ._binding import (  # noqa: F401
+    GpuqtError, Hamiltonian, HInfo, LIB_PATH, lib,
+    OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD,
+    VELOCITY, COMMUTATOR_XH,
+    gpuqt_build_h, gpuqt_build_h_from_model, gpuqt_workspace_size, gpuqt_moments,
+    gpuqt_evolve, gpuqt_apply_commutator, gpuqt_vac, gpuqt_msd, gpuqt_kpm_reconstruct,
+    gpuqt_jackson, gpuqt_bessel, gpuqt_auto_terms, gpuqt_last_error, gpuqt_copy_probe,
+)

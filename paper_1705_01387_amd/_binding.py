@@ -1,0 +1,388 @@
+"""ctypes binding of libgpuqt.so: the C entry points under the same names.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Vectors are torch complex128 tensors on the GPU in layout [n][B];
+descriptor arrays are numpy arrays on the host.  The library is loaded from
+the package directory; if it has not been built the binding raises instead
+of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpuqt.so")
+
+GPUQT_OK = 0
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_LAYOUT", 3: "ERR_SPECTRUM", 4: "ERR_WORKSPACE",
+                5: "ERR_HIP", 6: "ERR_NOMEM", 7: "ERR_UNSUPPORTED"}
+OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD = range(6)
+VELOCITY, COMMUTATOR_XH = 0, 1
+
+
+class GpuqtError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("max_nn", ctypes.c_int32),
+        ("nn", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("hop", ctypes.c_void_p),
+        ("hop_is_complex", ctypes.c_int32), ("hop_class", ctypes.c_void_p),
+        ("n_class", ctypes.c_int32), ("onsite", ctypes.c_void_p), ("x", ctypes.c_void_p),
+        ("length_x", ctypes.c_double), ("volume", ctypes.c_double),
+        ("energy_max", ctypes.c_double), ("n_segments", ctypes.c_int32),
+        ("seg_offsets", ctypes.c_void_p), ("seg_energy_max", ctypes.c_void_p),
+        ("seg_length_x", ctypes.c_void_p), ("check_hermitian", ctypes.c_int32),
+        ("slice_height", ctypes.c_int32),
+    ]
+
+
+class HInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_segments", ctypes.c_int32), ("n_class", ctypes.c_int32),
+        ("hop_mode", ctypes.c_int32), ("slice_height", ctypes.c_int32),
+        ("n_slices", ctypes.c_int64), ("entries", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("max_width", ctypes.c_int32), ("uniform_width", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+_SIGS = {
+    "gpuqt_build_h": (ctypes.c_int32, [ctypes.POINTER(_Desc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "gpuqt_destroy_h": (None, [ctypes.c_void_p]),
+    "gpuqt_h_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(HInfo), ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_moments": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p]),
+    "gpuqt_evolve": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_apply_commutator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_vac": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_msd": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_kpm_reconstruct": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
+    "gpuqt_jackson": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p]),
+    "gpuqt_bessel": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]),
+    "gpuqt_auto_terms": (ctypes.c_int32, [ctypes.c_double]),
+    "gpuqt_last_error": (ctypes.c_char_p, []),
+    "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libgpuqt.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != GPUQT_OK:
+        raise GpuqtError(st, where, lib().gpuqt_last_error().decode())
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_vec(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _cols(t):
+    return 1 if t.dim() == 1 else int(t.shape[1])
+
+
+# --------------------------------------------------------------------------
+# host helpers
+# --------------------------------------------------------------------------
+
+def gpuqt_last_error() -> str:
+    return lib().gpuqt_last_error().decode()
+
+
+def gpuqt_jackson(M: int) -> np.ndarray:
+    g = np.zeros(max(M, 0))
+    _check(lib().gpuqt_jackson(M, _ptr(g) if M > 0 else None), "gpuqt_jackson")
+    return g
+
+
+def gpuqt_bessel(tau: float, Np: int) -> np.ndarray:
+    J = np.zeros(max(Np, 0))
+    _check(lib().gpuqt_bessel(float(tau), Np, _ptr(J) if Np > 0 else None), "gpuqt_bessel")
+    return J
+
+
+def gpuqt_auto_terms(tau: float) -> int:
+    return int(lib().gpuqt_auto_terms(float(tau)))
+
+
+# --------------------------------------------------------------------------
+# Hamiltonian handle
+# --------------------------------------------------------------------------
+
+class Hamiltonian:
+    """Owner of a gpuqt_h handle (device layout of H on the current device)."""
+
+    def __init__(self, handle: int, keep):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keep
+        info = HInfo()
+        _check(lib().gpuqt_h_info(self._h, ctypes.byref(info), None, None), "gpuqt_h_info")
+        dE = np.zeros(info.n_segments)
+        gb = np.zeros(info.n_segments)
+        _check(lib().gpuqt_h_info(self._h, ctypes.byref(info), _ptr(dE), _ptr(gb)), "gpuqt_h_info")
+        self.info = info
+        self.energy_max = dE
+        self.gershgorin = gb
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return int(self.info.n)
+
+    @property
+    def n_segments(self) -> int:
+        return int(self.info.n_segments)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().gpuqt_destroy_h(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1.0,
+                  energy_max=0.0, hop_class=None, n_class=1, seg_offsets=None,
+                  seg_energy_max=None, seg_length_x=None, check_hermitian=False,
+                  slice_height=0, stream=None) -> Hamiltonian:
+    """Build the device layout of H from a neighbour list (the paper's input files)."""
+    nn = np.ascontiguousarray(nn, dtype=np.int32)
+    n = nn.shape[0]
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32).reshape(n, -1)
+    max_nn = nbr.shape[1]
+    keep = [nn, nbr]
+    d = _Desc()
+    d.n = n
+    d.max_nn = max_nn
+    d.nn = _ptr(nn)
+    d.nbr = _ptr(nbr)
+    if hop is not None:
+        hop = np.asarray(hop)
+        if np.iscomplexobj(hop):
+            hop = np.ascontiguousarray(hop, dtype=np.complex128).reshape(n, max_nn)
+            d.hop_is_complex = 1
+        else:
+            hop = np.ascontiguousarray(hop, dtype=np.float64).reshape(n, max_nn)
+        keep.append(hop)
+        d.hop = _ptr(hop)
+    if hop_class is not None:
+        hop_class = np.ascontiguousarray(hop_class, dtype=np.int32).reshape(n, max_nn)
+        keep.append(hop_class)
+        d.hop_class = _ptr(hop_class)
+    d.n_class = int(n_class)
+    if onsite is not None:
+        onsite = np.ascontiguousarray(onsite, dtype=np.float64)
+        keep.append(onsite)
+        d.onsite = _ptr(onsite)
+    if x is None:
+        raise ValueError("positions x are required")
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    keep.append(x)
+    d.x = _ptr(x)
+    d.length_x = float(length_x)
+    d.volume = float(volume)
+    d.energy_max = float(energy_max)
+    if seg_offsets is not None:
+        so = np.ascontiguousarray(seg_offsets, dtype=np.int64)
+        keep.append(so)
+        d.n_segments = so.shape[0] - 1
+        d.seg_offsets = _ptr(so)
+    if seg_energy_max is not None:
+        se = np.ascontiguousarray(seg_energy_max, dtype=np.float64)
+        keep.append(se)
+        d.seg_energy_max = _ptr(se)
+    if seg_length_x is not None:
+        sl = np.ascontiguousarray(seg_length_x, dtype=np.float64)
+        keep.append(sl)
+        d.seg_length_x = _ptr(sl)
+    d.check_hermitian = 1 if check_hermitian else 0
+    d.slice_height = int(slice_height)
+    out = ctypes.c_void_p()
+    _check(lib().gpuqt_build_h(ctypes.byref(d), stream, ctypes.byref(out)), "gpuqt_build_h")
+    return Hamiltonian(out.value, None)
+
+
+def gpuqt_build_h_from_model(m, energy_max=0.0, **kw) -> Hamiltonian:
+    """gpuqt_build_h for an inputs.Model (neighbour list, hoppings, potentials, positions)."""
+    return gpuqt_build_h(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x, m.volume, energy_max,
+                         hop_class=m.hop_class if m.n_class > 1 else None, n_class=m.n_class, **kw)
+
+
+def gpuqt_workspace_size(H: Hamiltonian, op: int, B: int, M: int = 0, Np: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().gpuqt_workspace_size(H.handle, op, B, M, Np, ctypes.byref(out)), "gpuqt_workspace_size")
+    return int(out.value)
+
+
+def _workspace(H, op, B, M, Np, ws):
+    import torch
+    need = gpuqt_workspace_size(H, op, B, M, Np)
+    if ws is None:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device="cuda")
+    return ws, int(ws.numel() * ws.element_size())
+
+
+# --------------------------------------------------------------------------
+# compute entry points
+# --------------------------------------------------------------------------
+
+def gpuqt_moments(H: Hamiltonian, phiL, phiR, M: int, mu=None, ws=None, stream=None):
+    """mu[s, b, k] = <phiL_b|T_k(H/DeltaE_s)|phiR_b> (complex128 [n_seg, B, M] on the GPU)."""
+    import torch
+    _dev_vec(phiL, "phiL")
+    _dev_vec(phiR, "phiR")
+    B = _cols(phiR)
+    if mu is None:
+        mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=phiR.device)
+    ws, nb = _workspace(H, OP_MOMENTS, B, M, 0, ws)
+    _check(lib().gpuqt_moments(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(mu), _ptr(ws), nb,
+                               _stream(stream)), "gpuqt_moments")
+    return mu
+
+
+def gpuqt_evolve(H: Hamiltonian, psi, dt: float, Np: int = 0, psi_out=None, chi=None,
+                 chi_out=None, with_commutator=False, ws=None, stream=None):
+    """psi_out = U(dt) psi; with_commutator: also chi_out = [X,U(dt)] psi + U(dt) chi."""
+    import torch
+    _dev_vec(psi, "psi")
+    B = _cols(psi)
+    if psi_out is None:
+        psi_out = torch.empty_like(psi)
+    if with_commutator and chi_out is None:
+        chi_out = torch.empty_like(psi)
+    op = OP_EVOLVE_COMMUTATOR if chi_out is not None else OP_EVOLVE
+    if Np == 0:
+        Np_ws = max(gpuqt_auto_terms(e * abs(dt)) for e in H.energy_max)
+    else:
+        Np_ws = Np
+    ws, nb = _workspace(H, op, B, 0, Np_ws, ws)
+    _check(lib().gpuqt_evolve(H.handle, B, float(dt), Np, _ptr(psi), _ptr(psi_out), _ptr(chi),
+                              _ptr(chi_out), _ptr(ws), nb, _stream(stream)), "gpuqt_evolve")
+    return (psi_out, chi_out) if chi_out is not None else psi_out
+
+
+def gpuqt_apply_commutator(H: Hamiltonian, psi, which: int = VELOCITY, out=None, stream=None):
+    """out = V psi (which=VELOCITY) or [X,H] psi (which=COMMUTATOR_XH)."""
+    import torch
+    _dev_vec(psi, "psi")
+    if out is None:
+        out = torch.empty_like(psi)
+    _check(lib().gpuqt_apply_commutator(H.handle, _cols(psi), which, _ptr(psi), _ptr(out),
+                                        _stream(stream)), "gpuqt_apply_commutator")
+    return out
+
+
+def _series(fn, name, op, H, phi, dt, M, Np, out, ws, stream):
+    import torch
+    _dev_vec(phi, "phi")
+    B = _cols(phi)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    n_t = dt.shape[0]
+    if out is None:
+        out = torch.empty((n_t, H.n_segments, B, M), dtype=torch.float64, device=phi.device)
+    if Np == 0:
+        Np_ws = max([1] + [gpuqt_auto_terms(e * abs(t)) for e in H.energy_max for t in dt])
+    else:
+        Np_ws = Np
+    ws, nb = _workspace(H, op, B, M, Np_ws, ws)
+    _check(fn(H.handle, B, _ptr(phi), n_t, _ptr(dt), M, Np, _ptr(out), _ptr(ws), nb, _stream(stream)), name)
+    return out
+
+
+def gpuqt_vac(H: Hamiltonian, phi, dt: Sequence[float], M: int, Np: int = 0, out=None, ws=None,
+              stream=None):
+    """C^VAC rows [n_t, n_seg, B, M] (real, on the GPU); row k at t = dt[0] + ... + dt[k-1]."""
+    return _series(lib().gpuqt_vac, "gpuqt_vac", OP_VAC, H, phi, dt, M, Np, out, ws, stream)
+
+
+def gpuqt_msd(H: Hamiltonian, phi, dt: Sequence[float], M: int, Np: int = 0, out=None, ws=None,
+              stream=None):
+    """C^MSD rows [n_t, n_seg, B, M] (real, on the GPU); row k at t = dt[0] + ... + dt[k]."""
+    return _series(lib().gpuqt_msd, "gpuqt_msd", OP_MSD, H, phi, dt, M, Np, out, ws, stream)
+
+
+def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson=True,
+                          out=None, stream=None):
+    """KPM sum of the paper's Section 3.3 for moment rows C [R, M] (float64 on the GPU)."""
+    import torch
+    C = C.contiguous()
+    if C.dim() == 1:
+        C = C[None, :]
+    R, M = int(C.shape[0]), int(C.shape[1])
+    E = torch.as_tensor(np.asarray(energies, dtype=np.float64), device=C.device)
+    if out is None:
+        out = torch.empty((R, E.shape[0]), dtype=torch.float64, device=C.device)
+    _check(lib().gpuqt_kpm_reconstruct(R, M, _ptr(C), int(E.shape[0]), _ptr(E), float(energy_max),
+                                       float(volume), 1 if jackson else 0, _ptr(out), _stream(stream)),
+           "gpuqt_kpm_reconstruct")
+    return out
+
+
+def gpuqt_copy_probe(src, dst, stream=None):
+    nbytes = src.numel() * src.element_size()
+    _check(lib().gpuqt_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "gpuqt_copy_probe")
+    return dst

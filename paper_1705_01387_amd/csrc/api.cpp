@@ -1,0 +1,553 @@
+// C ABI of the transport library: handles, workspace layout, argument checks,
+// and the host-side sequencing of the Chebyshev recurrences (Sections 3.2-3.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "bessel.h"
+#include "internal.h"
+
+using namespace gpuqt;
+
+namespace {
+
+thread_local std::string g_err;
+
+gpuqt_status fail(gpuqt_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(GPUQT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kAutoNpCap = 8192;
+
+bool valid_B(int B) { return B == 1 || B == 2 || B == 4 || B == 8 || B == 16; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace layout: nv vectors [n][B] c128, then np rows of per-workgroup
+// partials [G][B] c128, then the Bessel table [n_seg][ldJ] double.
+struct WsLayout {
+  size_t vec_bytes = 0;
+  size_t off_part = 0;
+  size_t off_J = 0;
+  size_t total = 0;
+};
+
+WsLayout ws_layout(const Handle* h, int nv, int B, int64_t part_rows, int64_t ldJ) {
+  WsLayout L;
+  L.vec_bytes = round_up((size_t)h->n * (size_t)B * 16u, 256);
+  L.off_part = L.vec_bytes * (size_t)nv;
+  const size_t part = round_up((size_t)part_rows * (size_t)h->G * (size_t)B * 16u, 256);
+  L.off_J = L.off_part + part;
+  L.total = L.off_J + round_up((size_t)h->n_seg * (size_t)ldJ * 8u, 256);
+  return L;
+}
+
+int op_vectors(int op) {
+  switch (op) {
+    case GPUQT_OP_MOMENTS: return 2;
+    case GPUQT_OP_EVOLVE: return 2;
+    case GPUQT_OP_EVOLVE_COMMUTATOR: return 5;
+    case GPUQT_OP_VAC: return 7;
+    case GPUQT_OP_MSD: return 9;
+    case GPUQT_OP_MOMENTS_BACKWARD: return 6;
+    default: return -1;
+  }
+}
+
+gpuqt_status check_device(const Handle* h) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(GPUQT_ERR_HIP, "handle was built on device " + std::to_string(h->device) +
+                                   " but device " + std::to_string(dev) + " is current");
+  return GPUQT_OK;
+}
+
+gpuqt_status check_vec(const double* p, const char* name) {
+  if (!p) return fail(GPUQT_ERR_ARG, std::string(name) + " is NULL");
+  if (!aligned16(p)) return fail(GPUQT_ERR_ARG, std::string(name) + " is not 16-byte aligned");
+  return GPUQT_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  if (!a || !b) return false;
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+int auto_terms_host(double tau) {
+  if (!(tau >= 0) || !std::isfinite(tau)) return -1;
+  int m0 = (int)std::floor(tau) + 1;
+  int cap = m0 + 64 + (int)(16.0 * std::cbrt(tau + 1.0));
+  for (;;) {
+    std::vector<double> J(cap);
+    bessel_miller(tau, cap, J.data());
+    for (int m = m0; m < cap; ++m)
+      if (std::fabs(J[m]) < 1e-16) return m;
+    cap *= 2;
+    if (cap > (1 << 26)) return -1;
+  }
+}
+
+int terms_for(const Handle* h, double dt, int Np) {
+  if (Np > 0) return Np;
+  int best = 1;
+  for (double e : h->seg_dE) best = std::max(best, auto_terms_host(e * std::fabs(dt)));
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// sequencing helpers (enqueue only; arguments already checked)
+// ---------------------------------------------------------------------------
+
+// M moments into part rows 0..M-1 using buffers A, Bf.
+gpuqt_status run_moments(const Handle* h, int B, const double2* phiL, const double2* phiR, int M,
+                         double2* part, double2* A, double2* Bf, hipStream_t s) {
+  const DevMat D = h->view();
+  const int64_t row = (int64_t)h->G * B;
+  StepIO io{phiR, nullptr, A, 1};
+  HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, phiL, part + row, part, s));
+  const double2* prev = phiR;
+  double2* cur = A;
+  for (int k = 2; k < M; ++k) {
+    double2* out = (prev == phiR) ? Bf : const_cast<double2*>(prev);
+    StepIO st{cur, prev, out, 0};
+    HIP_TRY(launch_moment_step(D, h->hop_mode, B, st, phiL, part + row * k, nullptr, s));
+    prev = cur;
+    cur = out;
+  }
+  return GPUQT_OK;
+}
+
+double2 phase_pow(int m, double sgn) {
+  // (-i sgn)^m
+  switch (m & 3) {
+    case 0: return make_double2(1.0, 0.0);
+    case 1: return make_double2(0.0, -sgn);
+    case 2: return make_double2(-1.0, 0.0);
+    default: return make_double2(0.0, sgn);
+  }
+}
+
+// psi_out = U(dt) psi_in; when chi_out: chi_out = [X,U(dt)] psi_in + U(dt) chi_in.
+// Buffers: aA, aB always; bA, bB, zero when chi_out.  Jtab: [n_seg][Np].
+gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2* psi_in,
+                        double2* psi_out, const double2* chi_in, double2* chi_out, double2* aA,
+                        double2* aB, double2* bA, double2* bB, double2* zero, double* Jtab,
+                        hipStream_t s) {
+  const DevMat D = h->view();
+  const double sgn = dt >= 0 ? 1.0 : -1.0;
+  HIP_TRY(launch_bessel_table(h->d_seg_dE, h->n_seg, std::fabs(dt), Np, Np, Jtab, s));
+  const double2 ph0 = phase_pow(0, sgn);
+  if (!chi_out) {
+    if (Np == 1) {
+      HIP_TRY(launch_scale(D, B, psi_in, psi_out, Jtab, Np, s));
+      return GPUQT_OK;
+    }
+    StepIO io{psi_in, nullptr, aA, 1};
+    HIP_TRY(launch_evolve_term(D, h->hop_mode, B, io, psi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
+    const double2* prev = psi_in;
+    double2* cur = aA;
+    for (int m = 2; m < Np; ++m) {
+      double2* out = (prev == psi_in) ? aB : const_cast<double2*>(prev);
+      StepIO st{cur, prev, out, 0};
+      HIP_TRY(launch_evolve_term(D, h->hop_mode, B, st, psi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
+      prev = cur;
+      cur = out;
+    }
+    return GPUQT_OK;
+  }
+  const double2* b0 = chi_in;
+  if (!b0) {
+    HIP_TRY(launch_scale(D, B, nullptr, zero, Jtab, Np, s));  // zero fill
+    b0 = zero;
+  }
+  if (Np == 1) {
+    HIP_TRY(launch_scale(D, B, psi_in, psi_out, Jtab, Np, s));
+    HIP_TRY(launch_scale(D, B, b0, chi_out, Jtab, Np, s));
+    return GPUQT_OK;
+  }
+  ChainIO io{psi_in, nullptr, aA, b0, nullptr, bA, 1, 1};
+  HIP_TRY(launch_msd_term(D, h->hop_mode, B, io, psi_out, chi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
+  const double2 *pa = psi_in, *pb = b0;
+  double2 *ca = aA, *cb = bA;
+  for (int m = 2; m < Np; ++m) {
+    double2* oa = (pa == psi_in) ? aB : const_cast<double2*>(pa);
+    double2* ob = (pb == chi_in || pb == zero) ? bB : const_cast<double2*>(pb);
+    ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
+    HIP_TRY(launch_msd_term(D, h->hop_mode, B, st, psi_out, chi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
+    pa = ca;
+    pb = cb;
+    ca = oa;
+    cb = ob;
+  }
+  return GPUQT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gpuqt_last_error(void) { return g_err.c_str(); }
+
+gpuqt_status gpuqt_jackson(int32_t M, double* g) {
+  if (M < 0 || (M > 0 && !g)) return fail(GPUQT_ERR_ARG, "bad arguments to gpuqt_jackson");
+  const double a = 1.0 / (M + 1);
+  const double cot = std::cos(M_PI * a) / std::sin(M_PI * a);
+  for (int n = 0; n < M; ++n)
+    g[n] = (1.0 - n * a) * std::cos(M_PI * n * a) + a * std::sin(M_PI * n * a) * cot;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_bessel(double tau, int32_t Np, double* J) {
+  if (!(tau >= 0) || !std::isfinite(tau) || Np < 0 || (Np > 0 && !J))
+    return fail(GPUQT_ERR_ARG, "bad arguments to gpuqt_bessel");
+  bessel_miller(tau, Np, J);
+  return GPUQT_OK;
+}
+
+int32_t gpuqt_auto_terms(double tau) { return auto_terms_host(tau); }
+
+gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out) {
+  if (!out) return fail(GPUQT_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  HostLayout L;
+  std::string msg;
+  gpuqt_status st = build_host_layout(desc, &L, &msg);
+  if (st != GPUQT_OK) return fail(st, msg);
+  int dev = -1, ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) return fail(GPUQT_ERR_HIP, "no HIP device available");
+  HIP_TRY(hipGetDevice(&dev));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+
+  Handle* h = new Handle();
+  h->device = dev;
+  h->n = L.n;
+  h->n_seg = L.n_seg;
+  h->n_class = L.n_class;
+  h->hop_mode = L.hop_mode;
+  h->S = L.S;
+  h->S_log2 = L.S_log2;
+  h->n_slices = L.n_slices;
+  h->entries = (int64_t)L.col.size();
+  h->nnz = L.nnz;
+  h->max_width = L.max_width;
+  h->uniform_width = L.uniform_width;
+  h->seg_off = L.seg_off;
+  h->seg_dE = L.seg_dE;
+  h->seg_gersh = L.seg_gersh;
+  plan_blocks(L.seg_off, cus, &h->blk_row_host, &h->blk_seg_host);
+  h->G = (int32_t)h->blk_seg_host.size();
+  std::vector<int32_t> seg_blk0(h->n_seg + 1, 0);
+  {
+    int g = 0;
+    for (int sgi = 0; sgi < h->n_seg; ++sgi) {
+      seg_blk0[sgi] = g;
+      while (g < h->G && h->blk_seg_host[g] == sgi) ++g;
+    }
+    seg_blk0[h->n_seg] = h->G;
+  }
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool ok = true;
+  auto up = [&](void** dst, const void* src, size_t bytes) {
+    if (!ok || bytes == 0) return;
+    if (hipMalloc(dst, bytes) != hipSuccess) {
+      ok = false;
+      *dst = nullptr;
+      return;
+    }
+    h->device_bytes += bytes;
+    if (hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) ok = false;
+  };
+  up((void**)&h->d_slice_ptr, L.slice_ptr.data(), L.slice_ptr.size() * 8);
+  up((void**)&h->d_col, L.col.data(), L.col.size() * 4);
+  up((void**)&h->d_hop, L.hop.data(), L.hop.size() * 8);
+  up((void**)&h->d_dx, L.dx.data(), L.dx.size() * 8);
+  up((void**)&h->d_diag, L.diag.data(), L.diag.size() * 8);
+  up((void**)&h->d_cls, L.cls.data(), L.cls.size() * 4);
+  up((void**)&h->d_blk_row, h->blk_row_host.data(), h->blk_row_host.size() * 8);
+  up((void**)&h->d_blk_seg, h->blk_seg_host.data(), h->blk_seg_host.size() * 4);
+  up((void**)&h->d_seg_blk0, seg_blk0.data(), seg_blk0.size() * 4);
+  up((void**)&h->d_seg_dE, L.seg_dE.data(), L.seg_dE.size() * 8);
+  up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
+  if (ok && hipStreamSynchronize(s) != hipSuccess) ok = false;
+  if (!ok) {
+    gpuqt_destroy_h(reinterpret_cast<gpuqt_h>(h));
+    return fail(GPUQT_ERR_NOMEM, "device allocation or copy failed while building the layout");
+  }
+  *out = reinterpret_cast<gpuqt_h>(h);
+  return GPUQT_OK;
+}
+
+void gpuqt_destroy_h(gpuqt_h hh) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h) return;
+  void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
+                  h->d_blk_row, h->d_blk_seg, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, double* gershgorin) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h || !info) return fail(GPUQT_ERR_ARG, "NULL handle or info");
+  std::memset(info, 0, sizeof(*info));
+  info->n = h->n;
+  info->n_segments = h->n_seg;
+  info->n_class = h->n_class;
+  info->hop_mode = h->hop_mode;
+  info->slice_height = h->S;
+  info->n_slices = h->n_slices;
+  info->entries = h->entries;
+  info->nnz = h->nnz;
+  info->max_width = h->max_width;
+  info->uniform_width = h->uniform_width;
+  info->grid_blocks = h->G;
+  info->device_bytes = h->device_bytes;
+  for (int s = 0; s < h->n_seg; ++s) {
+    if (energy_max) energy_max[s] = h->seg_dE[s];
+    if (gershgorin) gershgorin[s] = h->seg_gersh[s];
+  }
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, int32_t Np,
+                                  size_t* bytes) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  const int nv = op_vectors(op);
+  if (nv < 0) return fail(GPUQT_ERR_ARG, "unknown op");
+  if (M < 0 || Np < 0) return fail(GPUQT_ERR_ARG, "M and Np must be >= 0");
+  const bool has_moments = op == GPUQT_OP_MOMENTS || op == GPUQT_OP_VAC || op == GPUQT_OP_MSD ||
+                           op == GPUQT_OP_MOMENTS_BACKWARD;
+  const bool has_J = op == GPUQT_OP_EVOLVE || op == GPUQT_OP_EVOLVE_COMMUTATOR ||
+                     op == GPUQT_OP_VAC || op == GPUQT_OP_MSD;
+  const int64_t rows = has_moments ? std::max(M, 2) : 0;
+  const int64_t ldJ = has_J ? (Np > 0 ? Np : kAutoNpCap) : 0;
+  *bytes = ws_layout(h, nv, B, rows, ldJ).total;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_moments(gpuqt_h hh, int32_t B, const double* phiL, const double* phiR, int32_t M,
+                           double* mu, void* ws, size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (M < 0) return fail(GPUQT_ERR_ARG, "M must be >= 0");
+  if (M == 0) return GPUQT_OK;
+  gpuqt_status st;
+  if ((st = check_vec(phiL, "phiL")) || (st = check_vec(phiR, "phiR")) || (st = check_vec(mu, "mu")))
+    return st;
+  const WsLayout W = ws_layout(h, 2, B, std::max(M, 2), 0);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double2* A = reinterpret_cast<double2*>(base);
+  double2* Bf = reinterpret_cast<double2*>(base + W.vec_bytes);
+  double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  if ((st = run_moments(h, B, reinterpret_cast<const double2*>(phiL),
+                        reinterpret_cast<const double2*>(phiR), M, part, A, Bf, s)))
+    return st;
+  HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0,
+                                reinterpret_cast<double2*>(mu), nullptr, s));
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_evolve(gpuqt_h hh, int32_t B, double dt, int32_t Np, const double* psi_in,
+                          double* psi_out, const double* chi_in, double* chi_out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (!std::isfinite(dt)) return fail(GPUQT_ERR_ARG, "dt is not finite");
+  if (Np < 0) return fail(GPUQT_ERR_ARG, "Np must be >= 0");
+  gpuqt_status st;
+  if ((st = check_vec(psi_in, "psi_in")) || (st = check_vec(psi_out, "psi_out"))) return st;
+  if (chi_in && !aligned16(chi_in)) return fail(GPUQT_ERR_ARG, "chi_in is not 16-byte aligned");
+  if (chi_out && !aligned16(chi_out)) return fail(GPUQT_ERR_ARG, "chi_out is not 16-byte aligned");
+  if (chi_in && !chi_out) return fail(GPUQT_ERR_ARG, "chi_in given without chi_out");
+  const size_t vb = (size_t)h->n * B * 16;
+  if (overlap(psi_out, psi_in, vb) || overlap(psi_out, chi_in, vb) || overlap(chi_out, psi_in, vb) ||
+      overlap(chi_out, chi_in, vb) || overlap(chi_out, psi_out, vb))
+    return fail(GPUQT_ERR_ARG, "outputs of gpuqt_evolve must not overlap its inputs or each other");
+  const int np = terms_for(h, dt, Np);
+  if (np < 1) return fail(GPUQT_ERR_ARG, "could not choose the number of terms");
+  const int op = chi_out ? GPUQT_OP_EVOLVE_COMMUTATOR : GPUQT_OP_EVOLVE;
+  const WsLayout W = ws_layout(h, op_vectors(op), B, 0, np);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  char* base = static_cast<char*>(ws);
+  auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
+  double* J = reinterpret_cast<double*>(base + W.off_J);
+  return run_evolve(h, B, dt, np, reinterpret_cast<const double2*>(psi_in),
+                    reinterpret_cast<double2*>(psi_out), reinterpret_cast<const double2*>(chi_in),
+                    reinterpret_cast<double2*>(chi_out), V(0), V(1), chi_out ? V(2) : nullptr,
+                    chi_out ? V(3) : nullptr, chi_out ? V(4) : nullptr, J,
+                    static_cast<hipStream_t>(stream));
+}
+
+gpuqt_status gpuqt_apply_commutator(gpuqt_h hh, int32_t B, int32_t which, const double* psi,
+                                    double* out, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (which != GPUQT_VELOCITY && which != GPUQT_COMMUTATOR_XH)
+    return fail(GPUQT_ERR_ARG, "which must be GPUQT_VELOCITY or GPUQT_COMMUTATOR_XH");
+  gpuqt_status st;
+  if ((st = check_vec(psi, "psi")) || (st = check_vec(out, "out"))) return st;
+  if (overlap(psi, out, (size_t)h->n * B * 16)) return fail(GPUQT_ERR_ARG, "psi and out overlap");
+  if ((st = check_device(h))) return st;
+  HIP_TRY(launch_commutator(h->view(), h->hop_mode, B, which, reinterpret_cast<const double2*>(psi),
+                            reinterpret_cast<double2*>(out), static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
+static gpuqt_status check_series(const Handle* h, int32_t B, const double* phi, int32_t n_t,
+                                 const double* dt, int32_t M, int32_t Np, const double* out) {
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (n_t < 0 || M < 0 || Np < 0) return fail(GPUQT_ERR_ARG, "n_t, M and Np must be >= 0");
+  if (n_t > 0 && !dt) return fail(GPUQT_ERR_ARG, "dt is NULL");
+  for (int k = 0; k < n_t; ++k)
+    if (!std::isfinite(dt[k])) return fail(GPUQT_ERR_ARG, "dt contains a non-finite value");
+  gpuqt_status st;
+  if ((st = check_vec(phi, "phi"))) return st;
+  if (!out) return fail(GPUQT_ERR_ARG, "out is NULL");
+  return GPUQT_OK;
+}
+
+static int max_terms(const Handle* h, int32_t n_t, const double* dt, int32_t Np) {
+  int best = 1;
+  for (int k = 0; k < n_t; ++k) best = std::max(best, terms_for(h, dt[k], Np));
+  return best;
+}
+
+gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
+                       int32_t M, int32_t Np, double* out, void* ws, size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, out);
+  if (st) return st;
+  if (n_t == 0 || M == 0) return GPUQT_OK;
+  const int np = max_terms(h, n_t - 1, dt, Np);
+  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_VAC), B, std::max(M, 2), np);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
+  double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  double* J = reinterpret_cast<double*>(base + W.off_J);
+  const DevMat D = h->view();
+  // psi_L = phi (input, read only), psi_R = V phi
+  const double2* psiL = reinterpret_cast<const double2*>(phi);
+  double2* Lbuf[2] = {V(0), V(1)};
+  double2* Rbuf[2] = {V(2), V(3)};
+  double2* phiL = V(4);
+  int ri = 0;
+  HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, Rbuf[0], s));
+  const double2* psiR = Rbuf[0];
+  const int64_t row = (int64_t)h->n_seg * B * M;
+  for (int k = 0; k < n_t; ++k) {
+    HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, phiL, s));
+    if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s))) return st;
+    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, nullptr, out + row * k, s));
+    if (k + 1 < n_t) {
+      const int np_k = terms_for(h, dt[k], Np);
+      double2* Ln = (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
+      if ((st = run_evolve(h, B, -dt[k], np_k, psiL, Ln, nullptr, nullptr, V(5), V(6), nullptr, nullptr,
+                           nullptr, J, s)))
+        return st;
+      double2* Rn = Rbuf[ri ^ 1];
+      if ((st = run_evolve(h, B, -dt[k], np_k, psiR, Rn, nullptr, nullptr, V(5), V(6), nullptr, nullptr,
+                           nullptr, J, s)))
+        return st;
+      psiL = Ln;
+      psiR = Rn;
+      ri ^= 1;
+    }
+  }
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
+                       int32_t M, int32_t Np, double* out, void* ws, size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, out);
+  if (st) return st;
+  if (n_t == 0 || M == 0) return GPUQT_OK;
+  const int np = max_terms(h, n_t, dt, Np);
+  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_MSD), B, std::max(M, 2), np);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
+  double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  double* J = reinterpret_cast<double*>(base + W.off_J);
+  double2* Pbuf[2] = {V(0), V(1)};
+  double2* Cbuf[2] = {V(2), V(3)};
+  const double2* psi = reinterpret_cast<const double2*>(phi);
+  const double2* chi = nullptr;
+  int pi = 0;
+  const int64_t row = (int64_t)h->n_seg * B * M;
+  for (int k = 0; k < n_t; ++k) {
+    const int np_k = terms_for(h, dt[k], Np);
+    double2* Pn = Pbuf[pi];
+    double2* Cn = Cbuf[pi];
+    if ((st = run_evolve(h, B, dt[k], np_k, psi, Pn, chi, Cn, V(4), V(5), V(6), V(7), V(8), J, s)))
+      return st;
+    if ((st = run_moments(h, B, Cn, Cn, M, part, V(4), V(5), s))) return st;
+    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, nullptr, out + row * k, s));
+    psi = Pn;
+    chi = Cn;
+    pi ^= 1;
+  }
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double* C, int32_t n_E,
+                                   const double* energies, double energy_max, double volume,
+                                   int32_t jackson, double* out, void* stream) {
+  if (R < 0 || M < 1 || n_E < 0 || n_E > 65536) return fail(GPUQT_ERR_ARG, "bad sizes");
+  if (!(energy_max > 0) || !(volume > 0)) return fail(GPUQT_ERR_ARG, "energy_max and volume must be > 0");
+  if (R == 0 || n_E == 0) return GPUQT_OK;
+  if (!C || !energies || !out) return fail(GPUQT_ERR_ARG, "NULL pointer");
+  const double pref = 2.0 / (M_PI * volume * energy_max);
+  HIP_TRY(launch_kpm(R, M, C, n_E, energies, 1.0 / energy_max, pref, jackson ? 1 : 0, out,
+                     static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_copy_probe(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || (bytes & 15) || !aligned16(src) || !aligned16(dst))
+    return fail(GPUQT_ERR_ARG, "copy probe needs 16-byte aligned buffers and a multiple of 16 bytes");
+  if (overlap(src, dst, bytes)) return fail(GPUQT_ERR_ARG, "copy probe buffers overlap");
+  HIP_TRY(launch_copy(static_cast<const double2*>(src), static_cast<double2*>(dst), bytes / 16,
+                      static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Internal declarations shared by the host API (api.cpp, layout.cpp) and the
+// HIP kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gpuqt.h"
+
+namespace gpuqt {
+
+enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2 };
+
+constexpr int kBlock = 256;         // threads per workgroup of every sparse kernel
+constexpr int kRowAlign = 256;      // block row ranges start at multiples of this
+constexpr int kMaxB = 16;           // widest vector block
+
+// Device view of a Hamiltonian in sliced ELL.  Rows are cut into slices of S
+// rows; slice s stores width_s entries per row, slot-major (entry j of row
+// s*S + r sits at slice_ptr[s] + j*S + r), so a wavefront reading one slot of
+// consecutive rows reads consecutive addresses.  Missing neighbours are
+// padding entries with col = -1.  Hoppings and on-site terms are stored
+// already divided by the segment's DeltaE (H~ = H / DeltaE, Section 3.2).
+struct DevMat {
+  const int64_t* slice_ptr;  // [n_slices + 1] first entry of each slice
+  const int32_t* col;        // [entries] neighbour index or -1
+  const double* hop;         // HOP_REAL: [entries]; HOP_COMPLEX: [2*entries] (re, im)
+  const double* dx;          // [entries] x_col - x_row (minimum image), 0 for padding
+  const double* diag;        // [n] U_i / DeltaE_seg
+  const int64_t* blk_row;    // [G + 1] row range of each logical workgroup
+  const int32_t* blk_seg;    // [G] segment of each logical workgroup
+  const double* seg_dE;      // [n_seg] DeltaE of each segment
+  const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
+  int64_t n;
+  int32_t S_log2;
+  int32_t G;
+  int32_t K;                 // entries per row when every slice has the same width, else 0
+};
+
+struct Handle {
+  int device = 0;
+  int64_t n = 0;
+  int32_t n_seg = 1;
+  int32_t n_class = 1;
+  int32_t hop_mode = HOP_REAL;
+  int32_t S = 64;
+  int32_t S_log2 = 6;
+  int64_t n_slices = 0;
+  int64_t entries = 0;
+  int64_t nnz = 0;
+  int32_t max_width = 0;
+  int32_t uniform_width = 0;
+  int32_t G = 0;
+  size_t device_bytes = 0;
+  std::vector<int64_t> seg_off;   // host copy [n_seg + 1]
+  std::vector<double> seg_dE;     // host copy
+  std::vector<double> seg_gersh;  // host copy
+  std::vector<int32_t> blk_seg_host;
+  std::vector<int64_t> blk_row_host;
+  // device allocations
+  int64_t* d_slice_ptr = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_hop = nullptr;
+  double* d_dx = nullptr;
+  double* d_diag = nullptr;
+  int32_t* d_cls = nullptr;
+  int64_t* d_blk_row = nullptr;
+  int32_t* d_blk_seg = nullptr;
+  int32_t* d_seg_blk0 = nullptr;   // [n_seg + 1] first logical workgroup of each segment
+  double* d_seg_dE = nullptr;
+  double* d_seg_hop = nullptr;
+
+  DevMat view() const {
+    DevMat m;
+    m.slice_ptr = d_slice_ptr;
+    m.col = d_col;
+    m.hop = d_hop;
+    m.dx = d_dx;
+    m.diag = d_diag;
+    m.blk_row = d_blk_row;
+    m.blk_seg = d_blk_seg;
+    m.seg_dE = d_seg_dE;
+    m.seg_hop = d_seg_hop;
+    m.n = n;
+    m.S_log2 = S_log2;
+    m.G = G;
+    m.K = uniform_width;
+    return m;
+  }
+};
+
+// Host-side layout produced by layout.cpp from a descriptor (pure C++).
+struct HostLayout {
+  int64_t n = 0;
+  int32_t n_seg = 1;
+  int32_t n_class = 1;
+  int32_t hop_mode = HOP_REAL;
+  int32_t S = 64;
+  int32_t S_log2 = 6;
+  int64_t n_slices = 0;
+  int32_t max_width = 0;
+  int32_t uniform_width = 0;
+  int64_t nnz = 0;
+  std::vector<int64_t> slice_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> hop;   // real or interleaved complex, or empty (uniform)
+  std::vector<double> dx;
+  std::vector<double> diag;
+  std::vector<int32_t> cls;  // class per entry, -1 for padding (empty if one class)
+  std::vector<int64_t> seg_off;
+  std::vector<double> seg_dE;
+  std::vector<double> seg_gersh;
+  std::vector<double> seg_hop;
+};
+
+// layout.cpp: validate the descriptor and build the sliced ELL on the host.
+// Returns GPUQT_OK or an error status with *msg set.
+gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string* msg);
+
+// Workgroup plan: G logical workgroups, each owning a contiguous row range
+// inside one segment.  G is a multiple of 8 when G >= 8 so that the physical
+// -> logical mapping can keep each XCD on a contiguous part of the rows.
+void plan_blocks(const std::vector<int64_t>& seg_off, int cus, std::vector<int64_t>* blk_row,
+                 std::vector<int32_t>* blk_seg);
+
+// ----------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
+// Vectors are double2 [n][B].
+// ----------------------------------------------------------------------------
+struct StepIO {
+  const double2* x;    // gathered input (v_{n-1})
+  const double2* w;    // v_{n-2} (unused when first)
+  double2* out;        // v_n
+  int first;           // 1: v_1 = H~ v_0 (no factor 2, no subtraction)
+};
+
+// One Chebyshev moment step: out = 2 H~ x - w (or H~ x), and per-workgroup
+// partial sums of <phiL|out> into part_n[lb*B + b] (and <phiL|x> into part_0
+// when first).
+hipError_t launch_moment_step(const DevMat& A, int hop_mode, int B, const StepIO& io,
+                              const double2* phiL, double2* part_n, double2* part_0,
+                              hipStream_t s);
+
+// One term of the evolution series: a_m as in a moment step, and
+// acc += c_m a_m with c_m = J[seg*ldJ + m] * phase (first: acc = c_0 a_0 + c_1 a_1).
+hipError_t launch_evolve_term(const DevMat& A, int hop_mode, int B, const StepIO& io,
+                              double2* acc, const double* Jtab, int ldJ, int m, double2 phase_m,
+                              double2 phase_0, hipStream_t s);
+
+// One term of the fused evolution + commutator series (a- and b-chains).
+struct ChainIO {
+  const double2* xa; const double2* wa; double2* oa;   // a-chain: T_m psi
+  const double2* xb; const double2* wb; double2* ob;   // b-chain: [X,T_m] psi + T_m chi
+  int first;
+  int has_b0;                                          // b_0 = chi_in is non-zero
+};
+hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io,
+                           double2* acc_a, double2* acc_b, const double* Jtab, int ldJ, int m,
+                           double2 phase_m, double2 phase_0, hipStream_t s);
+
+// out = V x (which = GPUQT_VELOCITY) or [X,H] x (GPUQT_COMMUTATOR_XH), unscaled H.
+hipError_t launch_commutator(const DevMat& A, int hop_mode, int B, int which, const double2* x,
+                             double2* out, hipStream_t s);
+
+// out = J_0 * in (Np = 1 evolution), per segment.
+hipError_t launch_scale(const DevMat& A, int B, const double2* in, double2* out,
+                        const double* Jtab, int ldJ, hipStream_t s);
+
+// Table J[s*ldJ + m] = (2 - delta_m0) J_m(DeltaE_s |dt|), m < Np, s < n_seg.
+hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, int Np, int ldJ,
+                               double* J, hipStream_t s);
+
+// Final deterministic reduction of per-workgroup partials:
+//   partials laid out [M][G][B]; result for (seg, b, k) = sum over the
+//   workgroups of seg in increasing order (tree inside one workgroup).
+//   mode 0: complex out[(seg*B + b)*M + k];
+//   mode 1: real part into out_real[(seg*B + b)*M + k].
+hipError_t launch_reduce_moments(const double2* part, int M, int G, int B, int n_seg,
+                                 const int32_t* seg_blk0_dev, double2* out, double* out_real,
+                                 hipStream_t s);
+
+// out[r][e] = pref_base / sqrt(1 - x^2) * sum_n g_n (2 - delta_n0) T_n(x) C[r][n],
+// x = E[e] * inv_dE (NaN where |x| >= 1).
+hipError_t launch_kpm(int R, int M, const double* C, int n_E, const double* E, double inv_dE,
+                      double pref_base, int jackson, double* out, hipStream_t s);
+
+hipError_t launch_copy(const double2* src, double2* dst, size_t n16, hipStream_t s);
+
+}  // namespace gpuqt

@@ -1,0 +1,560 @@
+// HIP kernels for gfx950 (CDNA4): the sparse Chebyshev steps of the
+// linear-scaling Kubo method and their helpers.
+//
+// Every sparse kernel streams the sliced-ELL Hamiltonian once per launch:
+// one row (or, for B > 1, one (row, column) pair per lane with the B lanes of
+// a row adjacent) per lane, slot-major entries so that a wavefront reading one
+// slot of 64 consecutive rows touches consecutive addresses, 16-byte loads of
+// complex128 vector elements, FP64 throughout (no MFMA: the step moves about
+// 20 bytes per flop pair, far below the matrix-core balance point).
+//
+// Launch geometry: G workgroups of 256 threads, each owning a contiguous row
+// range inside one segment (plan_blocks).  Workgroups are dispatched
+// round-robin over the 8 XCDs, so physical workgroup p is remapped to logical
+// workgroup (p % 8) * (G / 8) + p / 8: each XCD then walks one contiguous
+// eighth of the rows, and the neighbour gathers of nearby rows hit its own L2.
+//
+// Reductions (moments) are deterministic: wavefront butterfly, then a fixed
+// order over the four wavefronts, one partial per workgroup, and a final
+// fixed-shape reduction over workgroups.
+#include <hip/hip_runtime.h>
+
+#include "bessel.h"
+#include "internal.h"
+
+namespace gpuqt {
+
+namespace {
+
+__device__ __forceinline__ int logical_block(int G) {
+  const int p = blockIdx.x;
+  if ((G & 7) == 0) {
+    const int per = G >> 3;
+    return (p & 7) * per + (p >> 3);
+  }
+  return p;
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// a * b (complex)
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc += conj(a) * b
+__device__ __forceinline__ void cdot_acc(double& re, double& im, double2 a, double2 b) {
+  re = fma(a.x, b.x, fma(a.y, b.y, re));
+  im = fma(a.x, b.y, fma(-a.y, b.x, im));
+}
+
+// Products of one row with the gathered vector(s):
+//   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
+//   da = sum_j dx_rj H~_rj xa_j (DX; the diagonal has dx = 0).
+// K > 0: every slice has exactly K entries per row (fully unrolled; all
+// index loads issue before the gathers).  K == 0: runtime slice width.
+template <int B, int HOP, int K, bool TWO, bool DX, bool DIAG>
+__device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, double hu,
+                                          const double2* __restrict__ xa,
+                                          const double2* __restrict__ xb, double2& ha,
+                                          double2& hb, double2& da) {
+  const int S = 1 << A.S_log2;
+  const int64_t sl = r >> A.S_log2;
+  const int64_t p0 = A.slice_ptr[sl];
+  const int64_t e0 = p0 + (r & (S - 1));
+  ha = make_double2(0.0, 0.0);
+  hb = make_double2(0.0, 0.0);
+  da = make_double2(0.0, 0.0);
+  if (DIAG) {
+    const double d = A.diag[r];
+    ha = cscale(d, xa[r * B + b]);
+    if (TWO) hb = cscale(d, xb[r * B + b]);
+  }
+  auto body = [&](int32_t c, int64_t e) {
+    const bool ok = c >= 0;
+    const int64_t cc = ok ? (int64_t)c : r;
+    double hr, hi = 0.0;
+    if (HOP == HOP_UNIFORM) {
+      hr = ok ? hu : 0.0;
+    } else if (HOP == HOP_REAL) {
+      hr = A.hop[e];
+    } else {
+      const double2 h = reinterpret_cast<const double2*>(A.hop)[e];
+      hr = h.x;
+      hi = h.y;
+    }
+    const double2 v = xa[cc * B + b];
+    double2 hv;
+    if (HOP == HOP_COMPLEX) {
+      hv = cmul(make_double2(hr, hi), v);
+    } else {
+      hv = cscale(hr, v);
+    }
+    ha = cadd(ha, hv);
+    if (TWO) {
+      const double2 u = xb[cc * B + b];
+      if (HOP == HOP_COMPLEX) {
+        hb = cadd(hb, cmul(make_double2(hr, hi), u));
+      } else {
+        hb = cadd(hb, cscale(hr, u));
+      }
+    }
+    if (DX) {
+      const double dxv = A.dx[e];
+      da = make_double2(fma(dxv, hv.x, da.x), fma(dxv, hv.y, da.y));
+    }
+  };
+  if constexpr (K > 0) {
+    int32_t c[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) c[j] = A.col[e0 + (int64_t)j * S];
+#pragma unroll
+    for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
+  } else {
+    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    int j = 0;
+    for (; j + 4 <= w; j += 4) {
+      int32_t c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c[q] = A.col[e0 + (int64_t)(j + q) * S];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) body(c[q], e0 + (int64_t)(j + q) * S);
+    }
+    for (; j < w; ++j) body(A.col[e0 + (int64_t)j * S], e0 + (int64_t)j * S);
+  }
+}
+
+// Sum (re, im) over the lanes of the workgroup that share column b = tid % B,
+// in a fixed order, and store one partial per column.
+template <int B>
+__device__ __forceinline__ void block_reduce_store(double re, double im, double2* __restrict__ dst) {
+  __shared__ double sh[2][kBlock / 64][B];
+#pragma unroll
+  for (int off = 32; off >= B; off >>= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (lane < B) {
+    sh[0][wave][lane] = re;
+    sh[1][wave][lane] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x < B) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+      sr += sh[0][q][threadIdx.x];
+      si += sh[1][q][threadIdx.x];
+    }
+    dst[threadIdx.x] = make_double2(sr, si);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev moment step (Sections 3.2-3.3): v_n = 2 H~ v_{n-1} - v_{n-2}
+// (v_1 = H~ v_0) and the workgroup's part of <phiL|v_n> (and <phiL|v_0>).
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K>
+__global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
+                                                        const double2* __restrict__ phiL,
+                                                        double2* __restrict__ part_n,
+                                                        double2* __restrict__ part_0) {
+  const int lb = logical_block(A.G);
+  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[A.blk_seg[lb]] : 0.0;
+  const int b = threadIdx.x & (B - 1);
+  constexpr int RPI = kBlock / B;
+  const double2* __restrict__ x = io.x;
+  const double2* __restrict__ w = io.w;
+  double2* __restrict__ out = io.out;
+  double dr = 0.0, di = 0.0, zr = 0.0, zi = 0.0;
+  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
+    const int64_t idx = r * B + b;
+    double2 y;
+    if (io.first) {
+      y = ha;
+    } else {
+      const double2 wv = w[idx];
+      y = make_double2(fma(2.0, ha.x, -wv.x), fma(2.0, ha.y, -wv.y));
+    }
+    out[idx] = y;
+    const double2 p = phiL[idx];
+    cdot_acc(dr, di, p, y);
+    if (io.first) cdot_acc(zr, zi, p, x[idx]);
+  }
+  block_reduce_store<B>(dr, di, part_n + (int64_t)lb * B);
+  if (io.first) {
+    __syncthreads();
+    block_reduce_store<B>(zr, zi, part_0 + (int64_t)lb * B);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One term m of U(dt) psi = sum_m c_m T_m(H~) psi (Section 3.2):
+// a_m by the recurrence, acc += c_m a_m; c_m = J[seg][m] * phase_m with the
+// table holding (2 - delta_m0) J_m(DeltaE_seg |dt|).
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K>
+__global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
+                                                        const double* __restrict__ Jtab, int ldJ,
+                                                        int m, double2 ph_m, double2 ph_0) {
+  const int lb = logical_block(A.G);
+  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
+  const int seg = A.blk_seg[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
+  const double2 cm = cscale(Jtab[(int64_t)seg * ldJ + m], ph_m);
+  const double2 c0 = cscale(Jtab[(int64_t)seg * ldJ], ph_0);
+  const int b = threadIdx.x & (B - 1);
+  constexpr int RPI = kBlock / B;
+  const double2* __restrict__ x = io.x;
+  const double2* __restrict__ w = io.w;
+  double2* __restrict__ out = io.out;
+  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
+    const int64_t idx = r * B + b;
+    if (io.first) {
+      out[idx] = ha;
+      acc[idx] = cadd(cmul(c0, x[idx]), cmul(cm, ha));
+    } else {
+      const double2 wv = w[idx];
+      const double2 y = make_double2(fma(2.0, ha.x, -wv.x), fma(2.0, ha.y, -wv.y));
+      out[idx] = y;
+      acc[idx] = cadd(acc[idx], cmul(cm, y));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One term m of the fused evolution + commutator series (Section 3.2):
+//   a_m = T_m psi:                a_1 = H~ a_0,  a_m = 2 H~ a_{m-1} - a_{m-2}
+//   b_m = [X,T_m] psi + T_m chi:  b_0 = chi, b_1 = [X,H~] a_0 + H~ b_0,
+//                                 b_m = 2 [X,H~] a_{m-1} + 2 H~ b_{m-1} - b_{m-2}
+// (the sum of the paper's [X,T_m] recurrence and the T_m recurrence applied to
+// chi); acc_a += c_m a_m, acc_b += c_m b_m.  [X,H~]_rj = -dx_rj H~_rj.
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K>
+__global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
+                                                     double2* __restrict__ acc_b,
+                                                     const double* __restrict__ Jtab, int ldJ, int m,
+                                                     double2 ph_m, double2 ph_0) {
+  const int lb = logical_block(A.G);
+  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
+  const int seg = A.blk_seg[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
+  const double2 cm = cscale(Jtab[(int64_t)seg * ldJ + m], ph_m);
+  const double2 c0 = cscale(Jtab[(int64_t)seg * ldJ], ph_0);
+  const int b = threadIdx.x & (B - 1);
+  constexpr int RPI = kBlock / B;
+  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, true, true, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
+    const int64_t idx = r * B + b;
+    // [X,H~] a + H~ b
+    const double2 g = make_double2(hb.x - da.x, hb.y - da.y);
+    if (io.first) {
+      io.oa[idx] = ha;
+      io.ob[idx] = g;
+      acc_a[idx] = cadd(cmul(c0, io.xa[idx]), cmul(cm, ha));
+      acc_b[idx] = cadd(cmul(c0, io.xb[idx]), cmul(cm, g));
+    } else {
+      const double2 wa = io.wa[idx];
+      const double2 wb = io.wb[idx];
+      const double2 ya = make_double2(fma(2.0, ha.x, -wa.x), fma(2.0, ha.y, -wa.y));
+      const double2 yb = make_double2(fma(2.0, g.x, -wb.x), fma(2.0, g.y, -wb.y));
+      io.oa[idx] = ya;
+      io.ob[idx] = yb;
+      acc_a[idx] = cadd(acc_a[idx], cmul(cm, ya));
+      acc_b[idx] = cadd(acc_b[idx], cmul(cm, yb));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity V x (i sum dx H x) or [X,H] x (-sum dx H x), unscaled H
+// (Section 4.2).  Stored values are H~ = H / DeltaE_seg, so multiply back.
+// ---------------------------------------------------------------------------
+template <int B, int HOP>
+__global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
+                                                       double2* __restrict__ out) {
+  const int lb = logical_block(A.G);
+  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
+  const int seg = A.blk_seg[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
+  const double e = A.seg_dE[seg];
+  const int b = threadIdx.x & (B - 1);
+  constexpr int RPI = kBlock / B;
+  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, 0, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
+    const int64_t idx = r * B + b;
+    if (which == GPUQT_VELOCITY) {
+      out[idx] = make_double2(-e * da.y, e * da.x);   // i * e * da
+    } else {
+      out[idx] = make_double2(-e * da.x, -e * da.y);
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_scale(DevMat A, const double2* __restrict__ in,
+                                                  double2* __restrict__ out,
+                                                  const double* __restrict__ Jtab, int ldJ) {
+  const int lb = logical_block(A.G);
+  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
+  const double j0 = Jtab[(int64_t)A.blk_seg[lb] * ldJ];
+  const int b = threadIdx.x & (B - 1);
+  constexpr int RPI = kBlock / B;
+  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+    const int64_t idx = r * B + b;
+    out[idx] = in ? cscale(j0, in[idx]) : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void k_bessel_table(const double* __restrict__ seg_dE, int n_seg, double abs_dt, int Np,
+                               int ldJ, double* __restrict__ J) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_seg) return;
+  double* row = J + (int64_t)s * ldJ;
+  bessel_miller(seg_dE[s] * abs_dt, Np, row);
+  for (int m = 1; m < Np; ++m) row[m] *= 2.0;
+}
+
+// One wavefront per (moment k, segment*B + b): sum the segment's workgroup
+// partials in a fixed order.
+__global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part, int M, int G, int B,
+                                               const int32_t* __restrict__ seg_blk0,
+                                               double2* __restrict__ out, double* __restrict__ out_real) {
+  const int k = blockIdx.x;
+  const int sb = blockIdx.y;
+  const int seg = sb / B, b = sb - seg * B;
+  const int g0 = seg_blk0[seg], g1 = seg_blk0[seg + 1];
+  double re = 0.0, im = 0.0;
+  for (int g = g0 + (int)threadIdx.x; g < g1; g += 64) {
+    const double2 v = part[((int64_t)k * G + g) * B + b];
+    re += v.x;
+    im += v.y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+  }
+  if (threadIdx.x == 0) {
+    const int64_t o = (int64_t)sb * M + k;
+    if (out) out[o] = make_double2(re, im);
+    if (out_real) out_real[o] = re;
+  }
+}
+
+// KPM sum of Section 3.3 for one (row r, energy e) per thread.  T_n(E~) by the
+// Chebyshev recurrence, Jackson damping g_n computed in place.
+__global__ __launch_bounds__(256) void k_kpm(int R, int M, const double* __restrict__ C, int n_E,
+                                             const double* __restrict__ E, double inv_dE,
+                                             double pref_base, int jackson, double cot_pa,
+                                             double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= n_E || r >= R) return;
+  const double x = E[e] * inv_dE;
+  if (!(fabs(x) < 1.0)) {
+    out[(int64_t)r * n_E + e] = __builtin_nan("");
+    return;
+  }
+  const double a = 1.0 / (M + 1);
+  const double* c = C + (int64_t)r * M;
+  double t0 = 1.0, t1 = x, s = c[0];
+  for (int n = 1; n < M; ++n) {
+    double g = 1.0;
+    if (jackson) {
+      double sn, cs;
+      sincospi(n * a, &sn, &cs);
+      g = (1.0 - n * a) * cs + a * sn * cot_pa;
+    }
+    s += 2.0 * g * t1 * c[n];
+    const double t2 = 2.0 * x * t1 - t0;
+    t0 = t1;
+    t1 = t2;
+  }
+  out[(int64_t)r * n_E + e] = pref_base / sqrt(1.0 - x * x) * s;
+}
+
+__global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                              size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+
+#define GPUQT_DISPATCH_K(KFN, ...)                                        \
+  switch (K) {                                                            \
+    case 3: KFN<B, HOP, 3><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
+    case 4: KFN<B, HOP, 4><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
+    case 6: KFN<B, HOP, 6><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
+    case 8: KFN<B, HOP, 8><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
+    default: KFN<B, HOP, 0><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;  \
+  }
+
+namespace {
+
+int pick_k(const DevMat& A) {
+  switch (A.K) {
+    case 3: case 4: case 6: case 8: return A.K;
+    default: return 0;
+  }
+}
+
+template <int B, int HOP>
+void moment_step_bh(const DevMat& A, const StepIO& io, const double2* phiL, double2* pn, double2* p0,
+                    hipStream_t s) {
+  const dim3 grid(A.G);
+  const int K = pick_k(A);
+  GPUQT_DISPATCH_K(k_moment_step, A, io, phiL, pn, p0);
+}
+
+template <int B, int HOP>
+void evolve_term_bh(const DevMat& A, const StepIO& io, double2* acc, const double* J, int ldJ, int m,
+                    double2 pm, double2 p0, hipStream_t s) {
+  const dim3 grid(A.G);
+  const int K = pick_k(A);
+  GPUQT_DISPATCH_K(k_evolve_term, A, io, acc, J, ldJ, m, pm, p0);
+}
+
+template <int B, int HOP>
+void msd_term_bh(const DevMat& A, const ChainIO& io, double2* aa, double2* ab, const double* J, int ldJ,
+                 int m, double2 pm, double2 p0, hipStream_t s) {
+  const dim3 grid(A.G);
+  const int K = pick_k(A);
+  GPUQT_DISPATCH_K(k_msd_term, A, io, aa, ab, J, ldJ, m, pm, p0);
+}
+
+#define GPUQT_DISPATCH_BH(FN, ...)                                             \
+  do {                                                                         \
+    switch (B) {                                                               \
+      case 1: FN##_b<1>(hop_mode, __VA_ARGS__); break;                         \
+      case 2: FN##_b<2>(hop_mode, __VA_ARGS__); break;                         \
+      case 4: FN##_b<4>(hop_mode, __VA_ARGS__); break;                         \
+      case 8: FN##_b<8>(hop_mode, __VA_ARGS__); break;                         \
+      case 16: FN##_b<16>(hop_mode, __VA_ARGS__); break;                       \
+      default: return hipErrorInvalidValue;                                    \
+    }                                                                          \
+  } while (0)
+
+template <int B>
+void moment_step_b(int hop_mode, const DevMat& A, const StepIO& io, const double2* phiL, double2* pn,
+                   double2* p0, hipStream_t s) {
+  if (hop_mode == HOP_UNIFORM) moment_step_bh<B, HOP_UNIFORM>(A, io, phiL, pn, p0, s);
+  else if (hop_mode == HOP_REAL) moment_step_bh<B, HOP_REAL>(A, io, phiL, pn, p0, s);
+  else moment_step_bh<B, HOP_COMPLEX>(A, io, phiL, pn, p0, s);
+}
+
+template <int B>
+void evolve_term_b(int hop_mode, const DevMat& A, const StepIO& io, double2* acc, const double* J,
+                   int ldJ, int m, double2 pm, double2 p0, hipStream_t s) {
+  if (hop_mode == HOP_UNIFORM) evolve_term_bh<B, HOP_UNIFORM>(A, io, acc, J, ldJ, m, pm, p0, s);
+  else if (hop_mode == HOP_REAL) evolve_term_bh<B, HOP_REAL>(A, io, acc, J, ldJ, m, pm, p0, s);
+  else evolve_term_bh<B, HOP_COMPLEX>(A, io, acc, J, ldJ, m, pm, p0, s);
+}
+
+template <int B>
+void msd_term_b(int hop_mode, const DevMat& A, const ChainIO& io, double2* aa, double2* ab,
+                const double* J, int ldJ, int m, double2 pm, double2 p0, hipStream_t s) {
+  if (hop_mode == HOP_UNIFORM) msd_term_bh<B, HOP_UNIFORM>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
+  else if (hop_mode == HOP_REAL) msd_term_bh<B, HOP_REAL>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
+  else msd_term_bh<B, HOP_COMPLEX>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
+}
+
+template <int B>
+void commutator_b(int hop_mode, const DevMat& A, int which, const double2* x, double2* out,
+                  hipStream_t s) {
+  const dim3 grid(A.G);
+  if (hop_mode == HOP_UNIFORM) k_commutator<B, HOP_UNIFORM><<<grid, kBlock, 0, s>>>(A, which, x, out);
+  else if (hop_mode == HOP_REAL) k_commutator<B, HOP_REAL><<<grid, kBlock, 0, s>>>(A, which, x, out);
+  else k_commutator<B, HOP_COMPLEX><<<grid, kBlock, 0, s>>>(A, which, x, out);
+}
+
+template <int B>
+void scale_b(int hop_mode, const DevMat& A, const double2* in, double2* out, const double* J, int ldJ,
+             hipStream_t s) {
+  (void)hop_mode;
+  k_scale<B><<<dim3(A.G), kBlock, 0, s>>>(A, in, out, J, ldJ);
+}
+
+}  // namespace
+
+hipError_t launch_moment_step(const DevMat& A, int hop_mode, int B, const StepIO& io,
+                              const double2* phiL, double2* part_n, double2* part_0, hipStream_t s) {
+  GPUQT_DISPATCH_BH(moment_step, A, io, phiL, part_n, part_0, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_evolve_term(const DevMat& A, int hop_mode, int B, const StepIO& io, double2* acc,
+                              const double* Jtab, int ldJ, int m, double2 phase_m, double2 phase_0,
+                              hipStream_t s) {
+  GPUQT_DISPATCH_BH(evolve_term, A, io, acc, Jtab, ldJ, m, phase_m, phase_0, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
+                           double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
+                           double2 phase_0, hipStream_t s) {
+  GPUQT_DISPATCH_BH(msd_term, A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_commutator(const DevMat& A, int hop_mode, int B, int which, const double2* x,
+                             double2* out, hipStream_t s) {
+  GPUQT_DISPATCH_BH(commutator, A, which, x, out, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const DevMat& A, int B, const double2* in, double2* out, const double* Jtab,
+                        int ldJ, hipStream_t s) {
+  const int hop_mode = 0;
+  GPUQT_DISPATCH_BH(scale, A, in, out, Jtab, ldJ, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, int Np, int ldJ,
+                               double* J, hipStream_t s) {
+  const int threads = 64;
+  const int blocks = (n_seg + threads - 1) / threads;
+  k_bessel_table<<<blocks, threads, 0, s>>>(seg_dE, n_seg, abs_dt, Np, ldJ, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_moments(const double2* part, int M, int G, int B, int n_seg,
+                                 const int32_t* seg_blk0_dev, double2* out, double* out_real,
+                                 hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  k_reduce<<<dim3(M, n_seg * B), 64, 0, s>>>(part, M, G, B, seg_blk0_dev, out, out_real);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpm(int R, int M, const double* C, int n_E, const double* E, double inv_dE,
+                      double pref_base, int jackson, double* out, hipStream_t s) {
+  if (R <= 0 || n_E <= 0) return hipSuccess;
+  const double a = 1.0 / (M + 1);
+  const double cot_pa = cos(M_PI * a) / sin(M_PI * a);
+  k_kpm<<<dim3((n_E + 255) / 256, R), 256, 0, s>>>(R, M, C, n_E, E, inv_dE, pref_base, jackson, cot_pa,
+                                                   out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double2* src, double2* dst, size_t n16, hipStream_t s) {
+  if (n16 == 0) return hipSuccess;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 256 * 16) blocks = 256 * 16;
+  k_copy<<<dim3((unsigned)blocks), 256, 0, s>>>(src, dst, n16);
+  return hipGetLastError();
+}
+
+}  // namespace gpuqt

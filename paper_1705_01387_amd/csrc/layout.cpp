@@ -1,0 +1,358 @@
+// Host-side validation of a tight-binding descriptor and construction of the
+// sliced-ELL layout (pure C++, no device calls).
+//
+// The model is the one the paper's input files describe (Section 4.2):
+// neighbour list, hoppings (default -1), on-site potentials (default 0),
+// positions along the transport direction with the period used for bonds
+// across the boundary.  The spectrum of H / DeltaE must lie in [-1, 1]
+// (Section 3.2); DeltaE is checked against the Gershgorin bound
+// max_i (|U_i| + sum_j |H_ij|), which contains every eigenvalue.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "internal.h"
+
+namespace gpuqt {
+
+namespace {
+
+struct Bond {
+  int64_t i, j;
+  double re, im;
+};
+
+bool check_hermitian(const std::vector<Bond>& bonds, const std::vector<double>& diag_im,
+                     std::string* msg) {
+  // Sum duplicates, then require H_ji = conj(H_ij) for every stored pair.
+  std::vector<Bond> b = bonds;
+  std::sort(b.begin(), b.end(), [](const Bond& p, const Bond& q) {
+    return p.i != q.i ? p.i < q.i : p.j < q.j;
+  });
+  std::vector<Bond> u;
+  u.reserve(b.size());
+  double scale = 0.0;
+  for (const Bond& x : b) {
+    if (!u.empty() && u.back().i == x.i && u.back().j == x.j) {
+      u.back().re += x.re;
+      u.back().im += x.im;
+    } else {
+      u.push_back(x);
+    }
+  }
+  for (const Bond& x : u) scale = std::max(scale, std::hypot(x.re, x.im));
+  const double tol = 1e-12 * std::max(scale, 1e-300);
+  for (const Bond& x : u) {
+    if (x.i == x.j) {
+      if (std::fabs(x.im) > tol) {
+        *msg = "self-bond of orbital " + std::to_string(x.i) + " is not real";
+        return false;
+      }
+      continue;
+    }
+    auto it = std::lower_bound(u.begin(), u.end(), x, [](const Bond& p, const Bond& q) {
+      return p.i != q.j ? p.i < q.j : p.j < q.i;
+    });
+    double re = 0.0, im = 0.0;
+    if (it != u.end() && it->i == x.j && it->j == x.i) {
+      re = it->re;
+      im = it->im;
+    }
+    if (std::fabs(re - x.re) > tol || std::fabs(im + x.im) > tol) {
+      *msg = "H is not Hermitian: H[" + std::to_string(x.i) + "," + std::to_string(x.j) +
+             "] has no conjugate partner H[" + std::to_string(x.j) + "," +
+             std::to_string(x.i) + "]";
+      return false;
+    }
+  }
+  (void)diag_im;
+  return true;
+}
+
+}  // namespace
+
+gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string* msg) {
+  if (!d) {
+    *msg = "desc is NULL";
+    return GPUQT_ERR_ARG;
+  }
+  if (d->n < 1) {
+    *msg = "n must be >= 1";
+    return GPUQT_ERR_ARG;
+  }
+  if (d->n > (int64_t)INT32_MAX) {
+    *msg = "n must fit a 32-bit neighbour index";
+    return GPUQT_ERR_UNSUPPORTED;
+  }
+  if (d->max_nn < 0 || d->max_nn > 4096) {
+    *msg = "max_nn must be in [0, 4096]";
+    return GPUQT_ERR_ARG;
+  }
+  if (!d->nn || !d->x || (d->max_nn > 0 && !d->nbr)) {
+    *msg = "nn, x (and nbr when max_nn > 0) are required";
+    return GPUQT_ERR_ARG;
+  }
+  const int32_t n_class = d->n_class < 1 ? 1 : d->n_class;
+  if (d->hop_class && d->n_class < 1) {
+    *msg = "n_class must be >= 1 when hop_class is given";
+    return GPUQT_ERR_ARG;
+  }
+  int S = d->slice_height == 0 ? 64 : d->slice_height;
+  if (S < 32 || S > 1024 || (S & (S - 1))) {
+    *msg = "slice_height must be 0 or a power of two in [32, 1024]";
+    return GPUQT_ERR_ARG;
+  }
+  const int64_t n = d->n;
+  const int k = d->max_nn;
+
+  // segments
+  const int32_t n_seg = d->n_segments > 1 ? d->n_segments : 1;
+  std::vector<int64_t> seg_off(n_seg + 1);
+  if (n_seg > 1) {
+    if (!d->seg_offsets) {
+      *msg = "seg_offsets is required when n_segments > 1";
+      return GPUQT_ERR_ARG;
+    }
+    for (int s = 0; s <= n_seg; ++s) seg_off[s] = d->seg_offsets[s];
+    if (seg_off[0] != 0 || seg_off[n_seg] != n) {
+      *msg = "seg_offsets must start at 0 and end at n";
+      return GPUQT_ERR_ARG;
+    }
+    for (int s = 0; s < n_seg; ++s)
+      if (seg_off[s + 1] <= seg_off[s]) {
+        *msg = "seg_offsets must be strictly increasing";
+        return GPUQT_ERR_ARG;
+      }
+  } else {
+    seg_off[0] = 0;
+    seg_off[1] = n;
+  }
+
+  // neighbour list checks, position differences, Gershgorin per segment
+  std::vector<double> gersh(n_seg, 0.0);
+  std::vector<int32_t> seg_of_row(n);
+  for (int s = 0; s < n_seg; ++s)
+    for (int64_t i = seg_off[s]; i < seg_off[s + 1]; ++i) seg_of_row[i] = s;
+  const bool cplx = d->hop && d->hop_is_complex;
+  std::vector<double> rowsum(n, 0.0);
+  std::vector<Bond> bonds;
+  if (d->check_hermitian) bonds.reserve((size_t)n * (size_t)k);
+  bool any_imag = false;
+  int64_t nnz = 0;
+  int32_t max_deg = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = d->nn[i];
+    if (c < 0 || c > k) {
+      *msg = "neighbour count of orbital " + std::to_string(i) + " is " + std::to_string(c) +
+             ", outside [0, max_nn]";
+      return GPUQT_ERR_LAYOUT;
+    }
+    max_deg = std::max(max_deg, c);
+    nnz += c;
+    const int s = seg_of_row[i];
+    for (int j = 0; j < c; ++j) {
+      const int64_t e = i * k + j;
+      const int64_t col = d->nbr[e];
+      if (col < 0 || col >= n) {
+        *msg = "neighbour " + std::to_string(j) + " of orbital " + std::to_string(i) +
+               " is " + std::to_string(col) + ", outside [0, n)";
+        return GPUQT_ERR_LAYOUT;
+      }
+      if (col < seg_off[s] || col >= seg_off[s + 1]) {
+        *msg = "bond " + std::to_string(i) + "-" + std::to_string(col) + " joins two segments";
+        return GPUQT_ERR_LAYOUT;
+      }
+      double re = -1.0, im = 0.0;
+      if (d->hop) {
+        if (cplx) {
+          re = d->hop[2 * e];
+          im = d->hop[2 * e + 1];
+        } else {
+          re = d->hop[e];
+        }
+      }
+      if (!std::isfinite(re) || !std::isfinite(im)) {
+        *msg = "hopping " + std::to_string(j) + " of orbital " + std::to_string(i) +
+               " is not finite";
+        return GPUQT_ERR_ARG;
+      }
+      if (im != 0.0) any_imag = true;
+      if (d->hop_class) {
+        const int32_t cl = d->hop_class[e];
+        if (cl < 0 || cl >= n_class) {
+          *msg = "hop_class of bond " + std::to_string(i) + "-" + std::to_string(col) +
+                 " is outside [0, n_class)";
+          return GPUQT_ERR_ARG;
+        }
+      }
+      rowsum[i] += std::hypot(re, im);
+      if (d->check_hermitian) bonds.push_back({i, col, re, im});
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const double u = d->onsite ? d->onsite[i] : 0.0;
+    if (!std::isfinite(u) || !std::isfinite(d->x[i])) {
+      *msg = "on-site energy or position of orbital " + std::to_string(i) + " is not finite";
+      return GPUQT_ERR_ARG;
+    }
+    const int s = seg_of_row[i];
+    gersh[s] = std::max(gersh[s], std::fabs(u) + rowsum[i]);
+  }
+  if (d->check_hermitian && !check_hermitian(bonds, {}, msg)) return GPUQT_ERR_LAYOUT;
+  bonds.clear();
+  bonds.shrink_to_fit();
+
+  // DeltaE per segment
+  std::vector<double> dE(n_seg);
+  for (int s = 0; s < n_seg; ++s) {
+    double v = d->energy_max;
+    if (d->seg_energy_max && d->seg_energy_max[s] > 0) v = d->seg_energy_max[s];
+    if (!(v > 0)) v = gersh[s] > 0 ? 1.01 * gersh[s] : 1.0;
+    if (!std::isfinite(v)) {
+      *msg = "energy_max is not finite";
+      return GPUQT_ERR_ARG;
+    }
+    if (v < gersh[s] * (1.0 - 1e-12)) {
+      *msg = "energy_max " + std::to_string(v) + " of segment " + std::to_string(s) +
+             " is below the Gershgorin bound " + std::to_string(gersh[s]) +
+             ": the spectrum of H/DeltaE may leave [-1, 1]";
+      return GPUQT_ERR_SPECTRUM;
+    }
+    dE[s] = v;
+  }
+
+  // hopping storage mode: one value per segment when every hopping of the
+  // segment is the same real number (always so for the paper's default -1)
+  int mode = cplx && any_imag ? HOP_COMPLEX : HOP_REAL;
+  std::vector<double> seg_hop(n_seg, 0.0);
+  if (mode == HOP_REAL && n_class == 1) {
+    bool uniform = true;
+    std::vector<int> seen(n_seg, 0);
+    for (int64_t i = 0; i < n && uniform; ++i) {
+      const int s = seg_of_row[i];
+      for (int j = 0; j < d->nn[i]; ++j) {
+        const int64_t e = i * k + j;
+        const double h = d->hop ? (cplx ? d->hop[2 * e] : d->hop[e]) : -1.0;
+        if (!seen[s]) {
+          seen[s] = 1;
+          seg_hop[s] = h;
+        } else if (h != seg_hop[s]) {
+          uniform = false;
+          break;
+        }
+      }
+    }
+    if (uniform) mode = HOP_UNIFORM;
+  }
+  for (int s = 0; s < n_seg; ++s) seg_hop[s] /= dE[s];
+
+  // sliced ELL
+  int S_log2 = 0;
+  while ((1 << S_log2) < S) ++S_log2;
+  const int64_t n_slices = (n + S - 1) / S;
+  std::vector<int64_t> slice_ptr(n_slices + 1, 0);
+  int32_t max_w = 0;
+  for (int64_t s = 0; s < n_slices; ++s) {
+    int32_t w = 0;
+    const int64_t r1 = std::min<int64_t>(n, (s + 1) * S);
+    for (int64_t i = s * S; i < r1; ++i) w = std::max(w, d->nn[i]);
+    max_w = std::max(max_w, w);
+    slice_ptr[s + 1] = slice_ptr[s] + (int64_t)w * S;
+  }
+  bool unif_w = true;
+  for (int64_t i = 0; i < n; ++i)
+    if (d->nn[i] != max_deg) {
+      unif_w = false;
+      break;
+    }
+  const int64_t entries = slice_ptr[n_slices];
+  L->col.assign(entries, -1);
+  L->dx.assign(entries, 0.0);
+  if (mode == HOP_REAL) L->hop.assign(entries, 0.0);
+  if (mode == HOP_COMPLEX) L->hop.assign(2 * entries, 0.0);
+  if (d->hop_class && n_class > 1) L->cls.assign(entries, -1);
+  L->diag.assign(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int seg = seg_of_row[i];
+    const double Lx = d->seg_length_x ? d->seg_length_x[seg] : d->length_x;
+    const int64_t sl = i >> S_log2;
+    const int64_t base = slice_ptr[sl] + (i & (S - 1));
+    const double inv = 1.0 / dE[seg];
+    L->diag[i] = (d->onsite ? d->onsite[i] : 0.0) * inv;
+    for (int j = 0; j < d->nn[i]; ++j) {
+      const int64_t e = i * k + j;
+      const int64_t slot = base + (int64_t)j * S;
+      const int32_t col = d->nbr[e];
+      L->col[slot] = col;
+      double dxv = d->x[col] - d->x[i];
+      if (Lx > 0) {
+        const double img = dxv - Lx * std::round(dxv / Lx);
+        if (std::fabs(std::fabs(img) - 0.5 * Lx) <= 1e-9 * Lx) {
+          *msg = "bond " + std::to_string(i) + "-" + std::to_string(col) +
+                 " spans half the period: its direction across the boundary is ambiguous";
+          return GPUQT_ERR_LAYOUT;
+        }
+        dxv = img;
+      }
+      L->dx[slot] = dxv;
+      if (mode == HOP_REAL) L->hop[slot] = (d->hop ? (cplx ? d->hop[2 * e] : d->hop[e]) : -1.0) * inv;
+      if (mode == HOP_COMPLEX) {
+        L->hop[2 * slot] = d->hop[2 * e] * inv;
+        L->hop[2 * slot + 1] = d->hop[2 * e + 1] * inv;
+      }
+      if (!L->cls.empty()) L->cls[slot] = d->hop_class[e];
+    }
+  }
+
+  L->n = n;
+  L->n_seg = n_seg;
+  L->n_class = n_class;
+  L->hop_mode = mode;
+  L->S = S;
+  L->S_log2 = S_log2;
+  L->n_slices = n_slices;
+  L->max_width = max_w;
+  L->uniform_width = unif_w ? max_deg : 0;
+  L->nnz = nnz;
+  L->slice_ptr.swap(slice_ptr);
+  L->seg_off.swap(seg_off);
+  L->seg_dE.swap(dE);
+  L->seg_gersh.swap(gersh);
+  L->seg_hop.swap(seg_hop);
+  return GPUQT_OK;
+}
+
+void plan_blocks(const std::vector<int64_t>& seg_off, int cus, std::vector<int64_t>* blk_row,
+                 std::vector<int32_t>* blk_seg) {
+  const int n_seg = (int)seg_off.size() - 1;
+  const int64_t n = seg_off[n_seg];
+  // about eight resident 256-thread workgroups per compute unit, never more
+  // workgroups than 256-row chunks
+  const int64_t target = std::max<int64_t>(8, (int64_t)std::max(cus, 1) * 8);
+  blk_row->clear();
+  blk_seg->clear();
+  blk_row->push_back(0);
+  for (int s = 0; s < n_seg; ++s) {
+    const int64_t a = seg_off[s], b = seg_off[s + 1], ns = b - a;
+    int64_t gs = (int64_t)std::llround((double)target * (double)ns / (double)n);
+    gs = std::max<int64_t>(1, std::min<int64_t>(gs, (ns + kRowAlign - 1) / kRowAlign));
+    int64_t prev = a;
+    for (int64_t q = 1; q <= gs; ++q) {
+      int64_t r = (q == gs) ? b : a + (ns * q) / gs;
+      r = (r / 64) * 64;
+      r = std::min(b, std::max(prev, r));
+      if (q == gs) r = b;
+      blk_row->push_back(r);
+      blk_seg->push_back(s);
+      prev = r;
+    }
+  }
+  // pad with empty workgroups so that G is a multiple of 8 (XCD-aware order)
+  while (blk_seg->size() >= 8 && (blk_seg->size() & 7)) {
+    blk_row->push_back(n);
+    blk_seg->push_back(n_seg - 1);
+  }
+}
+
+}  // namespace gpuqt
