@@ -112,7 +112,7 @@ typedef struct {
   int32_t max_width;         /* widest slice */
   int32_t uniform_width;     /* width of every slice when equal and unpadded, else 0 */
   int32_t grid_blocks;       /* workgroups per sparse-step launch */
-  int32_t reserved;
+  int32_t kernel_variant;    /* 0: plain loads, 1: non-temporal streams (see gpuqt_autotune) */
   size_t device_bytes;       /* device memory held by the handle */
 } gpuqt_h_info_t;
 
@@ -196,6 +196,18 @@ gpuqt_status gpuqt_vac(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
 gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, const double *dt,
                        int32_t M, int32_t Np, double *out, void *ws, size_t ws_bytes,
                        void *stream);
+
+/*
+ * Choose the sparse-kernel variant for this handle by measurement: times 24
+ * Chebyshev moment steps (Section 3.2 recurrence on a scratch vector) with
+ * and without non-temporal loads of the once-read streams, keeps the faster
+ * variant for all later calls on the handle.  Synchronises the stream.
+ *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_VAC, B, 25, 1)
+ *   times_us : NULL or HOST [2], microseconds per step of variant 0 (plain) and 1 (NT).
+ * Not safe while other calls on the handle are in flight.
+ */
+gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
+                            double *times_us);
 
 /*
  * KPM reconstruction (Section 3.3, same prefactor for DOS, rho*C_vv, rho*DeltaX^2):

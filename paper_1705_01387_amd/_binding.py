@@ -50,7 +50,7 @@ class HInfo(ctypes.Structure):
         ("hop_mode", ctypes.c_int32), ("slice_height", ctypes.c_int32),
         ("n_slices", ctypes.c_int64), ("entries", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("max_width", ctypes.c_int32), ("uniform_width", ctypes.c_int32),
-        ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t),
     ]
 
@@ -85,6 +85,8 @@ _SIGS = {
     "gpuqt_bessel": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]),
     "gpuqt_auto_terms": (ctypes.c_int32, [ctypes.c_double]),
     "gpuqt_last_error": (ctypes.c_char_p, []),
+    "gpuqt_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
 
@@ -380,6 +382,17 @@ def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson
                                        float(volume), 1 if jackson else 0, _ptr(out), _stream(stream)),
            "gpuqt_kpm_reconstruct")
     return out
+
+
+def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
+    """Time the plain and non-temporal kernel variants, keep the faster; returns us/step of each."""
+    t = np.zeros(2)
+    ws, nb = _workspace(H, OP_VAC, B, 25, 1, ws)
+    _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
+    info = HInfo()
+    _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")
+    H.info = info
+    return t
 
 
 def gpuqt_copy_probe(src, dst, stream=None):

@@ -251,17 +251,9 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   h->seg_off = L.seg_off;
   h->seg_dE = L.seg_dE;
   h->seg_gersh = L.seg_gersh;
-  plan_blocks(L.seg_off, cus, &h->blk_row_host, &h->blk_seg_host);
-  h->G = (int32_t)h->blk_seg_host.size();
-  std::vector<int32_t> seg_blk0(h->n_seg + 1, 0);
-  {
-    int g = 0;
-    for (int sgi = 0; sgi < h->n_seg; ++sgi) {
-      seg_blk0[sgi] = g;
-      while (g < h->G && h->blk_seg_host[g] == sgi) ++g;
-    }
-    seg_blk0[h->n_seg] = h->G;
-  }
+  std::vector<int32_t> seg_blk0;
+  plan_blocks(L.seg_off, cus, 8, &h->plan_host, &seg_blk0);
+  h->G = (int32_t)h->plan_host.size();
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool ok = true;
@@ -281,8 +273,7 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_dx, L.dx.data(), L.dx.size() * 8);
   up((void**)&h->d_diag, L.diag.data(), L.diag.size() * 8);
   up((void**)&h->d_cls, L.cls.data(), L.cls.size() * 4);
-  up((void**)&h->d_blk_row, h->blk_row_host.data(), h->blk_row_host.size() * 8);
-  up((void**)&h->d_blk_seg, h->blk_seg_host.data(), h->blk_seg_host.size() * 4);
+  up((void**)&h->d_plan, h->plan_host.data(), h->plan_host.size() * sizeof(BlkPlan));
   up((void**)&h->d_seg_blk0, seg_blk0.data(), seg_blk0.size() * 4);
   up((void**)&h->d_seg_dE, L.seg_dE.data(), L.seg_dE.size() * 8);
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
@@ -299,7 +290,7 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
-                  h->d_blk_row, h->d_blk_seg, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop};
+                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -321,6 +312,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->uniform_width = h->uniform_width;
   info->grid_blocks = h->G;
   info->device_bytes = h->device_bytes;
+  info->kernel_variant = h->nt;
   for (int s = 0; s < h->n_seg; ++s) {
     if (energy_max) energy_max[s] = h->seg_dE[s];
     if (gershgorin) gershgorin[s] = h->seg_gersh[s];
@@ -525,6 +517,53 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
     chi = Cn;
     pi ^= 1;
   }
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, void* stream,
+                            double* times_us) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  constexpr int kSteps = 24;
+  const WsLayout W = ws_layout(h, 3, B, kSteps + 1, 0);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  gpuqt_status st;
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double2* phi = reinterpret_cast<double2*>(base);
+  double2* A = reinterpret_cast<double2*>(base + W.vec_bytes);
+  double2* Bf = reinterpret_cast<double2*>(base + 2 * W.vec_bytes);
+  double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  // a unit-modulus start vector, like the random-phase vectors of the method
+  HIP_TRY(launch_fill_phase(h->view(), B, phi, s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 0.0f;
+  int best_nt = h->nt;
+  for (int rep = 0; rep < 2; ++rep) {
+    for (int nt = 0; nt < 2; ++nt) {
+      h->nt = nt;
+      if ((st = run_moments(h, B, phi, phi, 4, part, A, Bf, s))) return st;   // warm
+      HIP_TRY(hipEventRecord(e0, s));
+      if ((st = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s))) return st;
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1 && times_us) times_us[nt] = 1e3 * ms / kSteps;
+      if (rep == 1 && (best == 0.0f || ms < best)) {
+        best = ms;
+        best_nt = nt;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->nt = best_nt;
   return GPUQT_OK;
 }
 

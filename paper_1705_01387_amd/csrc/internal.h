@@ -18,6 +18,14 @@ constexpr int kBlock = 256;         // threads per workgroup of every sparse ker
 constexpr int kRowAlign = 256;      // block row ranges start at multiples of this
 constexpr int kMaxB = 16;           // widest vector block
 
+// Row range of one logical workgroup: the workgroup is member j of a group of
+// g workgroups that share the contiguous rows [r0, r1) of segment seg; it
+// visits the tiles j, j + g, j + 2g, ... of that range.
+struct BlkPlan {
+  int64_t r0, r1;
+  int32_t j, g, seg, pad;
+};
+
 // Device view of a Hamiltonian in sliced ELL.  Rows are cut into slices of S
 // rows; slice s stores width_s entries per row, slot-major (entry j of row
 // s*S + r sits at slice_ptr[s] + j*S + r), so a wavefront reading one slot of
@@ -30,14 +38,14 @@ struct DevMat {
   const double* hop;         // HOP_REAL: [entries]; HOP_COMPLEX: [2*entries] (re, im)
   const double* dx;          // [entries] x_col - x_row (minimum image), 0 for padding
   const double* diag;        // [n] U_i / DeltaE_seg
-  const int64_t* blk_row;    // [G + 1] row range of each logical workgroup
-  const int32_t* blk_seg;    // [G] segment of each logical workgroup
+  const BlkPlan* plan;       // [G] row ranges of the logical workgroups
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   int64_t n;
   int32_t S_log2;
   int32_t G;
   int32_t K;                 // entries per row when every slice has the same width, else 0
+  int32_t nt;                // 1: non-temporal loads for the once-read streams (host dispatch)
 };
 
 struct Handle {
@@ -58,8 +66,8 @@ struct Handle {
   std::vector<int64_t> seg_off;   // host copy [n_seg + 1]
   std::vector<double> seg_dE;     // host copy
   std::vector<double> seg_gersh;  // host copy
-  std::vector<int32_t> blk_seg_host;
-  std::vector<int64_t> blk_row_host;
+  std::vector<BlkPlan> plan_host;
+  int32_t nt = 1;                 // kernel variant chosen by gpuqt_autotune (or the default)
   // device allocations
   int64_t* d_slice_ptr = nullptr;
   int32_t* d_col = nullptr;
@@ -67,8 +75,7 @@ struct Handle {
   double* d_dx = nullptr;
   double* d_diag = nullptr;
   int32_t* d_cls = nullptr;
-  int64_t* d_blk_row = nullptr;
-  int32_t* d_blk_seg = nullptr;
+  BlkPlan* d_plan = nullptr;
   int32_t* d_seg_blk0 = nullptr;   // [n_seg + 1] first logical workgroup of each segment
   double* d_seg_dE = nullptr;
   double* d_seg_hop = nullptr;
@@ -80,14 +87,14 @@ struct Handle {
     m.hop = d_hop;
     m.dx = d_dx;
     m.diag = d_diag;
-    m.blk_row = d_blk_row;
-    m.blk_seg = d_blk_seg;
+    m.plan = d_plan;
     m.seg_dE = d_seg_dE;
     m.seg_hop = d_seg_hop;
     m.n = n;
     m.S_log2 = S_log2;
     m.G = G;
     m.K = uniform_width;
+    m.nt = nt;
     return m;
   }
 };
@@ -120,11 +127,14 @@ struct HostLayout {
 // Returns GPUQT_OK or an error status with *msg set.
 gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string* msg);
 
-// Workgroup plan: G logical workgroups, each owning a contiguous row range
-// inside one segment.  G is a multiple of 8 when G >= 8 so that the physical
-// -> logical mapping can keep each XCD on a contiguous part of the rows.
-void plan_blocks(const std::vector<int64_t>& seg_off, int cus, std::vector<int64_t>* blk_row,
-                 std::vector<int32_t>* blk_seg);
+// Workgroup plan: about `per_cu` resident workgroups per compute unit, split
+// over the segments in proportion to their rows; G is a multiple of 8 when
+// G >= 8 (logical workgroup x*G/8 .. (x+1)*G/8-1 run on XCD x).  The logical
+// workgroups of one segment on one XCD form a group over a contiguous,
+// 64-row aligned part of the segment.  seg_blk0[s] is the first logical
+// workgroup of segment s (seg_blk0[n_seg] = G).
+void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
+                 std::vector<BlkPlan>* plan, std::vector<int32_t>* seg_blk0);
 
 // ----------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
@@ -169,7 +179,10 @@ hipError_t launch_commutator(const DevMat& A, int hop_mode, int B, int which, co
 hipError_t launch_scale(const DevMat& A, int B, const double2* in, double2* out,
                         const double* Jtab, int ldJ, hipStream_t s);
 
-// Table J[s*ldJ + m] = (2 - delta_m0) J_m(DeltaE_s |dt|), m < Np, s < n_seg.
+// out = a deterministic unit-modulus vector (timing input of gpuqt_autotune).
+hipError_t launch_fill_phase(const DevMat& A, int B, double2* out, hipStream_t s);
+
+// Table J[s*ldJ + m] =(2 - delta_m0) J_m(DeltaE_s |dt|), m < Np, s < n_seg.
 hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, int Np, int ldJ,
                                double* J, hipStream_t s);
 

@@ -2,22 +2,32 @@
 // linear-scaling Kubo method and their helpers.
 //
 // Every sparse kernel streams the sliced-ELL Hamiltonian once per launch:
-// one row (or, for B > 1, one (row, column) pair per lane with the B lanes of
-// a row adjacent) per lane, slot-major entries so that a wavefront reading one
-// slot of 64 consecutive rows touches consecutive addresses, 16-byte loads of
-// complex128 vector elements, FP64 throughout (no MFMA: the step moves about
-// 20 bytes per flop pair, far below the matrix-core balance point).
+// one row (for B > 1, one (row, column) pair per lane with the B lanes of a
+// row adjacent) per lane, slot-major entries so that a wavefront reading one
+// slot of consecutive rows touches consecutive addresses, 16-byte loads of
+// complex128 vector elements, FP64 throughout (no MFMA: a step moves about
+// 20 bytes per FP64 multiply-add pair, far below the matrix-core balance).
 //
-// Launch geometry: G workgroups of 256 threads, each owning a contiguous row
-// range inside one segment (plan_blocks).  Workgroups are dispatched
-// round-robin over the 8 XCDs, so physical workgroup p is remapped to logical
-// workgroup (p % 8) * (G / 8) + p / 8: each XCD then walks one contiguous
-// eighth of the rows, and the neighbour gathers of nearby rows hit its own L2.
+// Schedule: G workgroups of 256 threads.  The hardware hands workgroups to
+// the 8 XCDs round-robin, so physical workgroup p becomes logical workgroup
+// (p % 8) * (G / 8) + p / 8; the logical workgroups of one XCD that work on
+// one segment form a group owning a contiguous row range, and walk it in
+// tiles of 256/B rows with stride "group size".  All workgroups resident on
+// an XCD therefore sweep one compact window of rows together: a neighbour
+// gather (e.g. one lattice plane away) finds the line its neighbours fetched
+// moments ago in that XCD's L2 or in the last-level cache, instead of
+// re-reading it from HBM.
 //
-// Reductions (moments) are deterministic: wavefront butterfly, then a fixed
-// order over the four wavefronts, one partial per workgroup, and a final
-// fixed-shape reduction over workgroups.
+// NT variants mark the once-read streams (indices, hoppings, position
+// differences, on-site terms, v_{n-2}, phi_L) non-temporal so that they do
+// not push the gathered vector out of the caches.
+//
+// Moment reductions are deterministic: wavefront butterfly, then a fixed
+// order over the four wavefronts, one partial per workgroup and step, and a
+// fixed-shape final reduction over workgroups.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "bessel.h"
 #include "internal.h"
@@ -25,6 +35,30 @@
 namespace gpuqt {
 
 namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+template <bool NT>
+__device__ __forceinline__ double2 ld2(const double2* p) {
+  if constexpr (NT) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    return make_double2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
 
 __device__ __forceinline__ int logical_block(int G) {
   const int p = blockIdx.x;
@@ -41,6 +75,10 @@ __device__ __forceinline__ double2 cscale(double s, double2 a) { return make_dou
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
+// 2 a - w
+__device__ __forceinline__ double2 twice_minus(double2 a, double2 w) {
+  return make_double2(fma(2.0, a.x, -w.x), fma(2.0, a.y, -w.y));
+}
 // acc += conj(a) * b
 __device__ __forceinline__ void cdot_acc(double& re, double& im, double2 a, double2 b) {
   re = fma(a.x, b.x, fma(a.y, b.y, re));
@@ -50,9 +88,9 @@ __device__ __forceinline__ void cdot_acc(double& re, double& im, double2 a, doub
 // Products of one row with the gathered vector(s):
 //   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
 //   da = sum_j dx_rj H~_rj xa_j (DX; the diagonal has dx = 0).
-// K > 0: every slice has exactly K entries per row (fully unrolled; all
-// index loads issue before the gathers).  K == 0: runtime slice width.
-template <int B, int HOP, int K, bool TWO, bool DX, bool DIAG>
+// K > 0: every slice has exactly K entries per row (fully unrolled, all index
+// loads issued before the gathers).  K == 0: runtime slice width.
+template <int B, int HOP, int K, bool NT, bool TWO, bool DX, bool DIAG>
 __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, double hu,
                                           const double2* __restrict__ xa,
                                           const double2* __restrict__ xb, double2& ha,
@@ -65,7 +103,7 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
   hb = make_double2(0.0, 0.0);
   da = make_double2(0.0, 0.0);
   if (DIAG) {
-    const double d = A.diag[r];
+    const double d = ldg<NT>(A.diag + r);
     ha = cscale(d, xa[r * B + b]);
     if (TWO) hb = cscale(d, xb[r * B + b]);
   }
@@ -76,9 +114,9 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
     if (HOP == HOP_UNIFORM) {
       hr = ok ? hu : 0.0;
     } else if (HOP == HOP_REAL) {
-      hr = A.hop[e];
+      hr = ldg<NT>(A.hop + e);
     } else {
-      const double2 h = reinterpret_cast<const double2*>(A.hop)[e];
+      const double2 h = ld2<NT>(reinterpret_cast<const double2*>(A.hop) + e);
       hr = h.x;
       hi = h.y;
     }
@@ -99,14 +137,14 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
       }
     }
     if (DX) {
-      const double dxv = A.dx[e];
+      const double dxv = ldg<NT>(A.dx + e);
       da = make_double2(fma(dxv, hv.x, da.x), fma(dxv, hv.y, da.y));
     }
   };
   if constexpr (K > 0) {
     int32_t c[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) c[j] = A.col[e0 + (int64_t)j * S];
+    for (int j = 0; j < K; ++j) c[j] = ldg<NT>(A.col + e0 + (int64_t)j * S);
 #pragma unroll
     for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
   } else {
@@ -115,11 +153,24 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
     for (; j + 4 <= w; j += 4) {
       int32_t c[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) c[q] = A.col[e0 + (int64_t)(j + q) * S];
+      for (int q = 0; q < 4; ++q) c[q] = ldg<NT>(A.col + e0 + (int64_t)(j + q) * S);
 #pragma unroll
       for (int q = 0; q < 4; ++q) body(c[q], e0 + (int64_t)(j + q) * S);
     }
-    for (; j < w; ++j) body(A.col[e0 + (int64_t)j * S], e0 + (int64_t)j * S);
+    for (; j < w; ++j) body(ldg<NT>(A.col + e0 + (int64_t)j * S), e0 + (int64_t)j * S);
+  }
+}
+
+// Visit the rows of this workgroup: tiles of RPI = 256/B rows of the group's
+// range, starting at tile j, stride g tiles.  f(r) for each row r of the
+// thread (all threads of the workgroup iterate the same number of times).
+template <int B, typename F>
+__device__ __forceinline__ void for_rows(const BlkPlan& P, F&& f) {
+  constexpr int RPI = kBlock / B;
+  const int64_t step = (int64_t)P.g * RPI;
+  for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step) {
+    const int64_t r = base + threadIdx.x / B;
+    if (r < P.r1) f(r);
   }
 }
 
@@ -155,38 +206,32 @@ __device__ __forceinline__ void block_reduce_store(double re, double im, double2
 // Chebyshev moment step (Sections 3.2-3.3): v_n = 2 H~ v_{n-1} - v_{n-2}
 // (v_1 = H~ v_0) and the workgroup's part of <phiL|v_n> (and <phiL|v_0>).
 // ---------------------------------------------------------------------------
-template <int B, int HOP, int K>
+template <int B, int HOP, int K, bool NT>
 __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
                                                         const double2* __restrict__ phiL,
                                                         double2* __restrict__ part_n,
                                                         double2* __restrict__ part_0) {
   const int lb = logical_block(A.G);
-  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
-  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[A.blk_seg[lb]] : 0.0;
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
   const int b = threadIdx.x & (B - 1);
-  constexpr int RPI = kBlock / B;
   const double2* __restrict__ x = io.x;
   const double2* __restrict__ w = io.w;
   double2* __restrict__ out = io.out;
+  const bool first = io.first;
   double dr = 0.0, di = 0.0, zr = 0.0, zi = 0.0;
-  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+  for_rows<B>(P, [&](int64_t r) {
     double2 ha, hb, da;
-    row_apply<B, HOP, K, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
-    double2 y;
-    if (io.first) {
-      y = ha;
-    } else {
-      const double2 wv = w[idx];
-      y = make_double2(fma(2.0, ha.x, -wv.x), fma(2.0, ha.y, -wv.y));
-    }
+    const double2 y = first ? ha : twice_minus(ha, ld2<NT>(w + idx));
     out[idx] = y;
-    const double2 p = phiL[idx];
+    const double2 p = ld2<NT>(phiL + idx);
     cdot_acc(dr, di, p, y);
-    if (io.first) cdot_acc(zr, zi, p, x[idx]);
-  }
+    if (first) cdot_acc(zr, zi, p, x[idx]);
+  });
   block_reduce_store<B>(dr, di, part_n + (int64_t)lb * B);
-  if (io.first) {
+  if (first) {
     __syncthreads();
     block_reduce_store<B>(zr, zi, part_0 + (int64_t)lb * B);
   }
@@ -197,35 +242,32 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
 // a_m by the recurrence, acc += c_m a_m; c_m = J[seg][m] * phase_m with the
 // table holding (2 - delta_m0) J_m(DeltaE_seg |dt|).
 // ---------------------------------------------------------------------------
-template <int B, int HOP, int K>
+template <int B, int HOP, int K, bool NT>
 __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
                                                         const double* __restrict__ Jtab, int ldJ,
                                                         int m, double2 ph_m, double2 ph_0) {
-  const int lb = logical_block(A.G);
-  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
-  const int seg = A.blk_seg[lb];
-  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
-  const double2 cm = cscale(Jtab[(int64_t)seg * ldJ + m], ph_m);
-  const double2 c0 = cscale(Jtab[(int64_t)seg * ldJ], ph_0);
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double2 cm = cscale(Jtab[(int64_t)P.seg * ldJ + m], ph_m);
+  const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
   const int b = threadIdx.x & (B - 1);
-  constexpr int RPI = kBlock / B;
   const double2* __restrict__ x = io.x;
   const double2* __restrict__ w = io.w;
   double2* __restrict__ out = io.out;
-  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+  const bool first = io.first;
+  for_rows<B>(P, [&](int64_t r) {
     double2 ha, hb, da;
-    row_apply<B, HOP, K, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
-    if (io.first) {
+    if (first) {
       out[idx] = ha;
       acc[idx] = cadd(cmul(c0, x[idx]), cmul(cm, ha));
     } else {
-      const double2 wv = w[idx];
-      const double2 y = make_double2(fma(2.0, ha.x, -wv.x), fma(2.0, ha.y, -wv.y));
+      const double2 y = twice_minus(ha, ld2<NT>(w + idx));
       out[idx] = y;
-      acc[idx] = cadd(acc[idx], cmul(cm, y));
+      acc[idx] = cadd(ld2<NT>(acc + idx), cmul(cm, y));
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -236,41 +278,36 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
 // (the sum of the paper's [X,T_m] recurrence and the T_m recurrence applied to
 // chi); acc_a += c_m a_m, acc_b += c_m b_m.  [X,H~]_rj = -dx_rj H~_rj.
 // ---------------------------------------------------------------------------
-template <int B, int HOP, int K>
+template <int B, int HOP, int K, bool NT>
 __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
                                                      double2* __restrict__ acc_b,
                                                      const double* __restrict__ Jtab, int ldJ, int m,
                                                      double2 ph_m, double2 ph_0) {
-  const int lb = logical_block(A.G);
-  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
-  const int seg = A.blk_seg[lb];
-  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
-  const double2 cm = cscale(Jtab[(int64_t)seg * ldJ + m], ph_m);
-  const double2 c0 = cscale(Jtab[(int64_t)seg * ldJ], ph_0);
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double2 cm = cscale(Jtab[(int64_t)P.seg * ldJ + m], ph_m);
+  const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
   const int b = threadIdx.x & (B - 1);
-  constexpr int RPI = kBlock / B;
-  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+  const bool first = io.first;
+  for_rows<B>(P, [&](int64_t r) {
     double2 ha, hb, da;
-    row_apply<B, HOP, K, true, true, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
+    row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
-    // [X,H~] a + H~ b
-    const double2 g = make_double2(hb.x - da.x, hb.y - da.y);
-    if (io.first) {
+    const double2 g = make_double2(hb.x - da.x, hb.y - da.y);   // [X,H~] a + H~ b
+    if (first) {
       io.oa[idx] = ha;
       io.ob[idx] = g;
       acc_a[idx] = cadd(cmul(c0, io.xa[idx]), cmul(cm, ha));
       acc_b[idx] = cadd(cmul(c0, io.xb[idx]), cmul(cm, g));
     } else {
-      const double2 wa = io.wa[idx];
-      const double2 wb = io.wb[idx];
-      const double2 ya = make_double2(fma(2.0, ha.x, -wa.x), fma(2.0, ha.y, -wa.y));
-      const double2 yb = make_double2(fma(2.0, g.x, -wb.x), fma(2.0, g.y, -wb.y));
+      const double2 ya = twice_minus(ha, ld2<NT>(io.wa + idx));
+      const double2 yb = twice_minus(g, ld2<NT>(io.wb + idx));
       io.oa[idx] = ya;
       io.ob[idx] = yb;
-      acc_a[idx] = cadd(acc_a[idx], cmul(cm, ya));
-      acc_b[idx] = cadd(acc_b[idx], cmul(cm, yb));
+      acc_a[idx] = cadd(ld2<NT>(acc_a + idx), cmul(cm, ya));
+      acc_b[idx] = cadd(ld2<NT>(acc_b + idx), cmul(cm, yb));
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -280,38 +317,48 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
 template <int B, int HOP>
 __global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
                                                        double2* __restrict__ out) {
-  const int lb = logical_block(A.G);
-  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
-  const int seg = A.blk_seg[lb];
-  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[seg] : 0.0;
-  const double e = A.seg_dE[seg];
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double e = A.seg_dE[P.seg];
   const int b = threadIdx.x & (B - 1);
-  constexpr int RPI = kBlock / B;
-  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+  for_rows<B>(P, [&](int64_t r) {
     double2 ha, hb, da;
-    row_apply<B, HOP, 0, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
+    row_apply<B, HOP, 0, false, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
     if (which == GPUQT_VELOCITY) {
       out[idx] = make_double2(-e * da.y, e * da.x);   // i * e * da
     } else {
       out[idx] = make_double2(-e * da.x, -e * da.y);
     }
-  }
+  });
 }
 
+// out = J_0(seg) * in, or zero when in is NULL.
 template <int B>
 __global__ __launch_bounds__(kBlock) void k_scale(DevMat A, const double2* __restrict__ in,
                                                   double2* __restrict__ out,
                                                   const double* __restrict__ Jtab, int ldJ) {
-  const int lb = logical_block(A.G);
-  const int64_t r0 = A.blk_row[lb], r1 = A.blk_row[lb + 1];
-  const double j0 = Jtab[(int64_t)A.blk_seg[lb] * ldJ];
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double j0 = Jtab ? Jtab[(int64_t)P.seg * ldJ] : 0.0;
   const int b = threadIdx.x & (B - 1);
-  constexpr int RPI = kBlock / B;
-  for (int64_t r = r0 + threadIdx.x / B; r < r1; r += RPI) {
+  for_rows<B>(P, [&](int64_t r) {
     const int64_t idx = r * B + b;
     out[idx] = in ? cscale(j0, in[idx]) : make_double2(0.0, 0.0);
-  }
+  });
+}
+
+// out = exp(i theta) with theta = 2 pi frac(0.618... idx + 0.414... b): a
+// deterministic unit-modulus test vector (used only to time kernel variants).
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_fill_phase(DevMat A, double2* __restrict__ out) {
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const int b = threadIdx.x & (B - 1);
+  for_rows<B>(P, [&](int64_t r) {
+    const double t = (double)r * 0.6180339887498949 + (double)b * 0.4142135623730951;
+    double s, c;
+    sincospi(2.0 * (t - floor(t)), &s, &c);
+    out[r * B + b] = make_double2(c, s);
+  });
 }
 
 __global__ void k_bessel_table(const double* __restrict__ seg_dE, int n_seg, double abs_dt, int Np,
@@ -385,7 +432,56 @@ __global__ __launch_bounds__(256) void k_kpm(int R, int M, const double* __restr
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                               size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double2 a = ld2<true>(src + i);
+    const double2 b = ld2<true>(src + i + stride);
+    const double2 c = ld2<true>(src + i + 2 * stride);
+    const double2 d = ld2<true>(src + i + 3 * stride);
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// compile-time dispatch: B x hopping mode x non-temporal x row width
+// ---------------------------------------------------------------------------
+template <typename F>
+hipError_t dispatch_bh(int B, int hop_mode, F&& f) {
+  auto on_b = [&](auto Bc) {
+    if (hop_mode == HOP_UNIFORM) f(Bc, IC<HOP_UNIFORM>{});
+    else if (hop_mode == HOP_REAL) f(Bc, IC<HOP_REAL>{});
+    else f(Bc, IC<HOP_COMPLEX>{});
+  };
+  switch (B) {
+    case 1: on_b(IC<1>{}); break;
+    case 2: on_b(IC<2>{}); break;
+    case 4: on_b(IC<4>{}); break;
+    case 8: on_b(IC<8>{}); break;
+    case 16: on_b(IC<16>{}); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t dispatch_sparse(const DevMat& A, int hop_mode, int B, int nt, F&& f) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    auto on_k = [&](auto NTc) {
+      switch (A.K) {
+        case 3: f(Bc, Hc, IC<3>{}, NTc); break;
+        case 4: f(Bc, Hc, IC<4>{}, NTc); break;
+        case 6: f(Bc, Hc, IC<6>{}, NTc); break;
+        case 8: f(Bc, Hc, IC<8>{}, NTc); break;
+        default: f(Bc, Hc, IC<0>{}, NTc); break;
+      }
+    };
+    if (nt) on_k(std::true_type{});
+    else on_k(std::false_type{});
+  });
 }
 
 }  // namespace
@@ -394,133 +490,50 @@ __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, d
 // launchers
 // ----------------------------------------------------------------------------
 
-#define GPUQT_DISPATCH_K(KFN, ...)                                        \
-  switch (K) {                                                            \
-    case 3: KFN<B, HOP, 3><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
-    case 4: KFN<B, HOP, 4><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
-    case 6: KFN<B, HOP, 6><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
-    case 8: KFN<B, HOP, 8><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;   \
-    default: KFN<B, HOP, 0><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;  \
-  }
-
-namespace {
-
-int pick_k(const DevMat& A) {
-  switch (A.K) {
-    case 3: case 4: case 6: case 8: return A.K;
-    default: return 0;
-  }
-}
-
-template <int B, int HOP>
-void moment_step_bh(const DevMat& A, const StepIO& io, const double2* phiL, double2* pn, double2* p0,
-                    hipStream_t s) {
-  const dim3 grid(A.G);
-  const int K = pick_k(A);
-  GPUQT_DISPATCH_K(k_moment_step, A, io, phiL, pn, p0);
-}
-
-template <int B, int HOP>
-void evolve_term_bh(const DevMat& A, const StepIO& io, double2* acc, const double* J, int ldJ, int m,
-                    double2 pm, double2 p0, hipStream_t s) {
-  const dim3 grid(A.G);
-  const int K = pick_k(A);
-  GPUQT_DISPATCH_K(k_evolve_term, A, io, acc, J, ldJ, m, pm, p0);
-}
-
-template <int B, int HOP>
-void msd_term_bh(const DevMat& A, const ChainIO& io, double2* aa, double2* ab, const double* J, int ldJ,
-                 int m, double2 pm, double2 p0, hipStream_t s) {
-  const dim3 grid(A.G);
-  const int K = pick_k(A);
-  GPUQT_DISPATCH_K(k_msd_term, A, io, aa, ab, J, ldJ, m, pm, p0);
-}
-
-#define GPUQT_DISPATCH_BH(FN, ...)                                             \
-  do {                                                                         \
-    switch (B) {                                                               \
-      case 1: FN##_b<1>(hop_mode, __VA_ARGS__); break;                         \
-      case 2: FN##_b<2>(hop_mode, __VA_ARGS__); break;                         \
-      case 4: FN##_b<4>(hop_mode, __VA_ARGS__); break;                         \
-      case 8: FN##_b<8>(hop_mode, __VA_ARGS__); break;                         \
-      case 16: FN##_b<16>(hop_mode, __VA_ARGS__); break;                       \
-      default: return hipErrorInvalidValue;                                    \
-    }                                                                          \
-  } while (0)
-
-template <int B>
-void moment_step_b(int hop_mode, const DevMat& A, const StepIO& io, const double2* phiL, double2* pn,
-                   double2* p0, hipStream_t s) {
-  if (hop_mode == HOP_UNIFORM) moment_step_bh<B, HOP_UNIFORM>(A, io, phiL, pn, p0, s);
-  else if (hop_mode == HOP_REAL) moment_step_bh<B, HOP_REAL>(A, io, phiL, pn, p0, s);
-  else moment_step_bh<B, HOP_COMPLEX>(A, io, phiL, pn, p0, s);
-}
-
-template <int B>
-void evolve_term_b(int hop_mode, const DevMat& A, const StepIO& io, double2* acc, const double* J,
-                   int ldJ, int m, double2 pm, double2 p0, hipStream_t s) {
-  if (hop_mode == HOP_UNIFORM) evolve_term_bh<B, HOP_UNIFORM>(A, io, acc, J, ldJ, m, pm, p0, s);
-  else if (hop_mode == HOP_REAL) evolve_term_bh<B, HOP_REAL>(A, io, acc, J, ldJ, m, pm, p0, s);
-  else evolve_term_bh<B, HOP_COMPLEX>(A, io, acc, J, ldJ, m, pm, p0, s);
-}
-
-template <int B>
-void msd_term_b(int hop_mode, const DevMat& A, const ChainIO& io, double2* aa, double2* ab,
-                const double* J, int ldJ, int m, double2 pm, double2 p0, hipStream_t s) {
-  if (hop_mode == HOP_UNIFORM) msd_term_bh<B, HOP_UNIFORM>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
-  else if (hop_mode == HOP_REAL) msd_term_bh<B, HOP_REAL>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
-  else msd_term_bh<B, HOP_COMPLEX>(A, io, aa, ab, J, ldJ, m, pm, p0, s);
-}
-
-template <int B>
-void commutator_b(int hop_mode, const DevMat& A, int which, const double2* x, double2* out,
-                  hipStream_t s) {
-  const dim3 grid(A.G);
-  if (hop_mode == HOP_UNIFORM) k_commutator<B, HOP_UNIFORM><<<grid, kBlock, 0, s>>>(A, which, x, out);
-  else if (hop_mode == HOP_REAL) k_commutator<B, HOP_REAL><<<grid, kBlock, 0, s>>>(A, which, x, out);
-  else k_commutator<B, HOP_COMPLEX><<<grid, kBlock, 0, s>>>(A, which, x, out);
-}
-
-template <int B>
-void scale_b(int hop_mode, const DevMat& A, const double2* in, double2* out, const double* J, int ldJ,
-             hipStream_t s) {
-  (void)hop_mode;
-  k_scale<B><<<dim3(A.G), kBlock, 0, s>>>(A, in, out, J, ldJ);
-}
-
-}  // namespace
-
 hipError_t launch_moment_step(const DevMat& A, int hop_mode, int B, const StepIO& io,
                               const double2* phiL, double2* part_n, double2* part_0, hipStream_t s) {
-  GPUQT_DISPATCH_BH(moment_step, A, io, phiL, part_n, part_0, s);
-  return hipGetLastError();
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_moment_step<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
+        <<<dim3(A.G), kBlock, 0, s>>>(A, io, phiL, part_n, part_0);
+  });
 }
 
 hipError_t launch_evolve_term(const DevMat& A, int hop_mode, int B, const StepIO& io, double2* acc,
                               const double* Jtab, int ldJ, int m, double2 phase_m, double2 phase_0,
                               hipStream_t s) {
-  GPUQT_DISPATCH_BH(evolve_term, A, io, acc, Jtab, ldJ, m, phase_m, phase_0, s);
-  return hipGetLastError();
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_evolve_term<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
+        <<<dim3(A.G), kBlock, 0, s>>>(A, io, acc, Jtab, ldJ, m, phase_m, phase_0);
+  });
 }
 
 hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
                            double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
                            double2 phase_0, hipStream_t s) {
-  GPUQT_DISPATCH_BH(msd_term, A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, s);
-  return hipGetLastError();
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_msd_term<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
+        <<<dim3(A.G), kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0);
+  });
 }
 
 hipError_t launch_commutator(const DevMat& A, int hop_mode, int B, int which, const double2* x,
                              double2* out, hipStream_t s) {
-  GPUQT_DISPATCH_BH(commutator, A, which, x, out, s);
-  return hipGetLastError();
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    k_commutator<decltype(Bc)::value, decltype(Hc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, which, x, out);
+  });
 }
 
 hipError_t launch_scale(const DevMat& A, int B, const double2* in, double2* out, const double* Jtab,
                         int ldJ, hipStream_t s) {
-  const int hop_mode = 0;
-  GPUQT_DISPATCH_BH(scale, A, in, out, Jtab, ldJ, s);
-  return hipGetLastError();
+  return dispatch_bh(B, HOP_UNIFORM, [&](auto Bc, auto) {
+    k_scale<decltype(Bc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, in, out, Jtab, ldJ);
+  });
+}
+
+hipError_t launch_fill_phase(const DevMat& A, int B, double2* out, hipStream_t s) {
+  return dispatch_bh(B, HOP_UNIFORM, [&](auto Bc, auto) {
+    k_fill_phase<decltype(Bc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, out);
+  });
 }
 
 hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, int Np, int ldJ,

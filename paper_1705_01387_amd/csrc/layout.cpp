@@ -323,36 +323,59 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
   return GPUQT_OK;
 }
 
-void plan_blocks(const std::vector<int64_t>& seg_off, int cus, std::vector<int64_t>* blk_row,
-                 std::vector<int32_t>* blk_seg) {
+void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
+                 std::vector<BlkPlan>* plan, std::vector<int32_t>* seg_blk0) {
   const int n_seg = (int)seg_off.size() - 1;
   const int64_t n = seg_off[n_seg];
-  // about eight resident 256-thread workgroups per compute unit, never more
-  // workgroups than 256-row chunks
-  const int64_t target = std::max<int64_t>(8, (int64_t)std::max(cus, 1) * 8);
-  blk_row->clear();
-  blk_seg->clear();
-  blk_row->push_back(0);
+  const int64_t target = std::max<int64_t>(8, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
+  // workgroups per segment: proportional to rows, at least one, at most one
+  // per 64 rows
+  std::vector<int64_t> gs(n_seg);
+  int64_t G = 0;
   for (int s = 0; s < n_seg; ++s) {
+    const int64_t ns = seg_off[s + 1] - seg_off[s];
+    int64_t g = (int64_t)std::llround((double)target * (double)ns / (double)n);
+    gs[s] = std::max<int64_t>(1, std::min<int64_t>(g, (ns + 63) / 64));
+    G += gs[s];
+  }
+  int64_t padded = G >= 8 ? (G + 7) / 8 * 8 : G;
+  gs[n_seg - 1] += padded - G;   // spare workgroups join the last segment
+  G = padded;
+  const int64_t per_xcd = (G % 8 == 0) ? G / 8 : G;
+  plan->assign(G, BlkPlan{0, 0, 0, 1, 0, 0});
+  seg_blk0->assign(n_seg + 1, 0);
+  int64_t lb = 0;
+  for (int s = 0; s < n_seg; ++s) {
+    (*seg_blk0)[s] = (int32_t)lb;
     const int64_t a = seg_off[s], b = seg_off[s + 1], ns = b - a;
-    int64_t gs = (int64_t)std::llround((double)target * (double)ns / (double)n);
-    gs = std::max<int64_t>(1, std::min<int64_t>(gs, (ns + kRowAlign - 1) / kRowAlign));
-    int64_t prev = a;
-    for (int64_t q = 1; q <= gs; ++q) {
-      int64_t r = (q == gs) ? b : a + (ns * q) / gs;
-      r = (r / 64) * 64;
-      r = std::min(b, std::max(prev, r));
-      if (q == gs) r = b;
-      blk_row->push_back(r);
-      blk_seg->push_back(s);
+    // groups: runs of this segment's logical workgroups on one XCD
+    std::vector<std::pair<int64_t, int64_t>> groups;   // (first lb, size)
+    for (int64_t q = lb; q < lb + gs[s];) {
+      const int64_t x = q / per_xcd;
+      const int64_t end = std::min(lb + gs[s], (x + 1) * per_xcd);
+      groups.push_back({q, end - q});
+      q = end;
+    }
+    // rows of the segment in proportion to group sizes, 64-row aligned
+    int64_t done = 0, prev = a;
+    for (size_t k = 0; k < groups.size(); ++k) {
+      done += groups[k].second;
+      int64_t r = (k + 1 == groups.size()) ? b : a + (ns * done) / gs[s];
+      r = std::min(b, std::max(prev, (r / 64) * 64));
+      if (k + 1 == groups.size()) r = b;
+      for (int64_t q = 0; q < groups[k].second; ++q) {
+        BlkPlan& P = (*plan)[groups[k].first + q];
+        P.r0 = prev;
+        P.r1 = r;
+        P.j = (int32_t)q;
+        P.g = (int32_t)groups[k].second;
+        P.seg = s;
+      }
       prev = r;
     }
+    lb += gs[s];
   }
-  // pad with empty workgroups so that G is a multiple of 8 (XCD-aware order)
-  while (blk_seg->size() >= 8 && (blk_seg->size() & 7)) {
-    blk_row->push_back(n);
-    blk_seg->push_back(n_seg - 1);
-  }
+  (*seg_blk0)[n_seg] = (int32_t)G;
 }
 
 }  // namespace gpuqt
