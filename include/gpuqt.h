@@ -100,6 +100,20 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc *desc, void *stream, gpuqt_h *out)
  * make sure no enqueued work still uses it. */
 void gpuqt_destroy_h(gpuqt_h h);
 
+/*
+ * Replace model values in place (training loops, finite differences); DeltaE and the
+ * neighbour structure stay fixed.
+ *   onsite      : DEVICE double [n] or NULL: new on-site energies U_i (Section 4.2.3).
+ *   class_scale : HOST double [n_class] or NULL: every hopping of class c becomes
+ *                 class_scale[c] times the hopping given to gpuqt_build_h (at most 8 classes).
+ * Then recomputes the Gershgorin bound of every segment on the device and returns
+ * GPUQT_ERR_SPECTRUM if it exceeds the segment's DeltaE (the new values are kept; update
+ * again before computing).  Synchronises the stream; the first class update allocates a
+ * device copy of the build-time hoppings.  Not safe while other calls on the handle run.
+ */
+gpuqt_status gpuqt_update_h_values(gpuqt_h h, const double *onsite, const double *class_scale,
+                                   void *stream);
+
 typedef struct {
   int64_t n;                 /* orbitals */
   int32_t n_segments;
@@ -198,6 +212,54 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
                        void *stream);
 
 /*
+ * Gradient of a loss on the Chebyshev moments of gpuqt_moments (Section 3.3):
+ *   L = sum_{s,b,k} w[s][b][k] Re mu[s][b][k],  mu[s][b][k] = <phiL_b| T_k(H/DeltaE_s) |phiR_b>,
+ * with DeltaE held fixed, with respect to
+ *   - the on-site energies:   grad_onsite[i] += dL/dU_i,
+ *   - the hopping classes:    grad_class[c]  += dL/deps_c, where every hopping of class c
+ *                             is scaled as H_ij -> (1 + eps_c) H_ij (at eps = 0),
+ * and optionally lam0 = sum_k w_k T_k(H~) phiL (the adjoint of phiR).
+ * Method: the recurrence of Section 3.2 run forwards with checkpoints of
+ * (v_{js}, v_{js+1}) every s = ckpt_stride steps (0: ceil(sqrt(M))), then the
+ * adjoint recurrence lam_k = w_k phiL + 2 H~ lam_{k+1} - lam_{k+2} run backwards,
+ * recomputing each block of s forward vectors from its checkpoint;
+ * dL/dp = Re[ sum_{k>=2} 2 <lam_k| dH~/dp v_{k-1}> + <lam_1| dH~/dp v_0> ].
+ *   phiL, phiR : c128 [n][B];  w : double [n_segments][B][M];  grad_onsite : double [n];
+ *   grad_class : double [n_class] or NULL (at most 4 classes);  lam0 : c128 [n][B] or NULL.
+ *   All device.  Workspace: gpuqt_workspace_size(h, GPUQT_OP_MOMENTS_BACKWARD, B, M,
+ *   ckpt_stride) (its Np argument is the checkpoint stride).  Accumulation order is fixed:
+ *   repeated calls give bit-identical gradients.
+ */
+gpuqt_status gpuqt_moments_backward(gpuqt_h h, int32_t B, const double *phiL, const double *phiR,
+                                    int32_t M, const double *w, double *grad_onsite,
+                                    double *grad_class, double *lam0, int32_t ckpt_stride,
+                                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gradient of a loss on the VAC moments of gpuqt_vac (Section 3.3, C_n^VAC; Section 2.2):
+ *   L = sum_{k,s,b,n} w[k][s][b][n] out[k][s][b][n],  out as computed by gpuqt_vac,
+ * with DeltaE held fixed, with respect to the on-site energies (grad_onsite[i] += dL/dU_i)
+ * and the hopping classes (grad_class[c] += dL/deps_c, H_ij -> (1 + eps_c) H_ij; this also
+ * scales the velocity V = i[H, X] on those bonds).
+ * Method: the forward VAC series with every state psi_L(t_k), psi_R(t_k) kept, then the
+ * reverse over the rows: per row the adjoints of both moment arguments (reverse moment
+ * recurrence, as gpuqt_moments_backward, with checkpoints), back through phi_L = V psi_L
+ * (V is Hermitian), and back through each evolution U(-dt) = sum_m c_m T_m(H~) by the same
+ * reverse recurrence with sources conj(c_m) g, whose lam_0 is U(+dt) g.
+ *   phi : c128 [n][B];  dt : HOST [n_t];  w : double [n_t][n_segments][B][M];
+ *   grad_onsite : double [n];  grad_class : double [n_class] or NULL (at most 4 classes).
+ *   Workspace: gpuqt_vac_backward_workspace_size.
+ */
+gpuqt_status gpuqt_vac_backward(gpuqt_h h, int32_t B, const double *phi, int32_t n_t,
+                                const double *dt, int32_t M, int32_t Np, const double *w,
+                                double *grad_onsite, double *grad_class, void *ws, size_t ws_bytes,
+                                void *stream);
+
+/* Workspace bytes of gpuqt_vac_backward (dt: HOST [n_t], needed for the automatic Np). */
+gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t, const double *dt,
+                                               int32_t M, int32_t Np, size_t *bytes);
+
+/*
  * Choose the sparse-kernel variant for this handle by measurement: times 24
  * Chebyshev moment steps (Section 3.2 recurrence on a scratch vector) with
  * and without non-temporal loads of the once-read streams, keeps the faster
@@ -220,6 +282,14 @@ gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, voi
 gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double *C, int32_t n_E,
                                    const double *energies, double energy_max, double volume,
                                    int32_t jackson, double *out, void *stream);
+
+/* Transpose of gpuqt_kpm_reconstruct (for gradients of losses on the reconstructed
+ * functions): out[r][n] = sum_e g[r][e] * d out_kpm[r][e] / d C[r][n], energies with
+ * |E~| >= 1 contributing nothing.  g : double [R][n_E], energies : double [n_E],
+ * out : double [R][M]; all device. */
+gpuqt_status gpuqt_kpm_reconstruct_adjoint(int32_t R, int32_t M, const double *g, int32_t n_E,
+                                           const double *energies, double energy_max, double volume,
+                                           int32_t jackson, double *out, void *stream);
 
 /* Host helpers (no device use). */
 

@@ -20,14 +20,14 @@ Jacobi-Anger, Chebyshev-Gauss quadrature, ballistic identities, finite
 differences.
 """
 from .operators import operators, position_differences, gershgorin_bound
-from .kpm import (chebyshev_moments, jackson, kpm_reconstruct, chebyshev_T)
+from .kpm import (chebyshev_moments, chebyshev_series, jackson, kpm_reconstruct, chebyshev_T)
 from .transport import (evolution_coefficients, evolve, commutator_evolve,
                         dos_moments, vac_moments, msd_moments, auto_terms)
 from .adjoint import moments_gradient
 
 __all__ = [
     "operators", "position_differences", "gershgorin_bound",
-    "chebyshev_moments", "jackson", "kpm_reconstruct", "chebyshev_T",
+    "chebyshev_moments", "chebyshev_series", "jackson", "kpm_reconstruct", "chebyshev_T",
     "evolution_coefficients", "evolve", "commutator_evolve",
     "dos_moments", "vac_moments", "msd_moments", "auto_terms",
     "moments_gradient",

@@ -48,6 +48,21 @@ def chebyshev_moments(Ht, phiL, phiR, M):
     return mu
 
 
+def chebyshev_series(Ht, c, psi):
+    """sum_n c[n] T_n(Ht) psi for a coefficient list c (complex allowed), by the Section 3.2 recurrence."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    c = np.asarray(c)
+    out = c[0] * psi
+    if len(c) == 1:
+        return out
+    t_prev, t_cur = psi, Ht @ psi
+    out = out + c[1] * t_cur
+    for n in range(2, len(c)):
+        t_prev, t_cur = t_cur, 2.0 * (Ht @ t_cur) - t_prev
+        out = out + c[n] * t_cur
+    return out
+
+
 def jackson(M):
     """Jackson damping g_n = (1 - n a) cos(pi n a) + a sin(pi n a) cot(pi a), a = 1/(M+1) (Section 3.3)."""
     a = 1.0 / (M + 1)

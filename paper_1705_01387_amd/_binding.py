@@ -85,6 +85,24 @@ _SIGS = {
     "gpuqt_bessel": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]),
     "gpuqt_auto_terms": (ctypes.c_int32, [ctypes.c_double]),
     "gpuqt_last_error": (ctypes.c_char_p, []),
+    "gpuqt_moments_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                                ctypes.c_void_p]),
+    "gpuqt_vac_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]),
+    "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_kpm_reconstruct_adjoint": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                                       ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                                       ctypes.c_void_p]),
+    "gpuqt_update_h_values": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "gpuqt_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -382,6 +400,83 @@ def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson
                                        float(volume), 1 if jackson else 0, _ptr(out), _stream(stream)),
            "gpuqt_kpm_reconstruct")
     return out
+
+
+def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad_class=None,
+                           want_lam0=False, ckpt_stride=0, ws=None, stream=None):
+    """Accumulate dL/dU (grad_onsite, float64 [n]) and dL/deps_c (grad_class, float64 [n_class])
+    for L = sum w[s,b,k] Re mu[s,b,k]; returns (grad_onsite, grad_class, lam0 or None)."""
+    import torch
+    _dev_vec(phiL, "phiL")
+    _dev_vec(phiR, "phiR")
+    B = _cols(phiR)
+    w = w.contiguous()
+    M = int(w.shape[-1])
+    if grad_onsite is None:
+        grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phiR.device)
+    lam0 = torch.empty_like(phiR) if want_lam0 else None
+    ws, nb = _workspace(H, OP_MOMENTS_BACKWARD, B, M, ckpt_stride, ws)
+    _check(lib().gpuqt_moments_backward(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(w),
+                                        _ptr(grad_onsite), _ptr(grad_class), _ptr(lam0), ckpt_stride,
+                                        _ptr(ws), nb, _stream(stream)), "gpuqt_moments_backward")
+    return grad_onsite, grad_class, lam0
+
+
+def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0) -> int:
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    out = ctypes.c_size_t()
+    _check(lib().gpuqt_vac_backward_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np,
+                                                   ctypes.byref(out)), "gpuqt_vac_backward_workspace_size")
+    return int(out.value)
+
+
+def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=None, Np: int = 0,
+                       ws=None, stream=None):
+    """Accumulate dL/dU and dL/deps_c for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M])."""
+    import torch
+    _dev_vec(phi, "phi")
+    B = _cols(phi)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    w = w.contiguous()
+    M = int(w.shape[-1])
+    if grad_onsite is None:
+        grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
+    if ws is None:
+        ws = torch.empty(max(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np), 16), dtype=torch.uint8,
+                         device=phi.device)
+    nb = int(ws.numel() * ws.element_size())
+    _check(lib().gpuqt_vac_backward(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
+                                    _ptr(grad_onsite), _ptr(grad_class), _ptr(ws), nb, _stream(stream)),
+           "gpuqt_vac_backward")
+    return grad_onsite, grad_class
+
+
+def gpuqt_kpm_reconstruct_adjoint(g, energies, M: int, energy_max: float, volume: float,
+                                  jackson=True, out=None, stream=None):
+    """Transpose of gpuqt_kpm_reconstruct: g [R, n_E] (float64 on the GPU) -> [R, M]."""
+    import torch
+    g = g.contiguous()
+    if g.dim() == 1:
+        g = g[None, :]
+    R = int(g.shape[0])
+    E = torch.as_tensor(np.asarray(energies, dtype=np.float64), device=g.device)
+    if out is None:
+        out = torch.empty((R, M), dtype=torch.float64, device=g.device)
+    _check(lib().gpuqt_kpm_reconstruct_adjoint(R, M, _ptr(g), int(E.shape[0]), _ptr(E), float(energy_max),
+                                               float(volume), 1 if jackson else 0, _ptr(out),
+                                               _stream(stream)), "gpuqt_kpm_reconstruct_adjoint")
+    return out
+
+
+def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=None):
+    """New on-site energies (float64 CUDA tensor [n]) and/or hopping-class scales (host sequence)."""
+    cs = None if class_scale is None else np.ascontiguousarray(class_scale, dtype=np.float64)
+    if onsite is not None:
+        import torch
+        if onsite.dtype != torch.float64 or not onsite.is_cuda or not onsite.is_contiguous():
+            raise TypeError("onsite must be a contiguous float64 CUDA tensor")
+    _check(lib().gpuqt_update_h_values(H.handle, _ptr(onsite), _ptr(cs), _stream(stream)),
+           "gpuqt_update_h_values")
 
 
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):

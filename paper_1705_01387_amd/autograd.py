@@ -1,0 +1,80 @@
+"""torch.autograd Functions over the library's forward and adjoint entry points.
+
+Parameters are the on-site energies U (float64 CUDA tensor [n]) and the
+hopping-class scales s (float64 tensor [n_class]; every hopping of class c
+is s_c times the hopping given when the handle was built).  DeltaE stays fixed.
+Forward and backward both set the handle to the given parameter values
+(gpuqt_update_h_values) before running, so interleaved calls stay consistent.
+
+The library returns dL/deps_c for the relative change H -> (1 + eps_c) H on
+class c; at scale s_c this is s_c dL/ds_c, hence the division below.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _binding as Bd
+
+
+def _set(H, onsite, scales):
+    Bd.gpuqt_update_h_values(H, onsite.detach().contiguous(), scales.detach().cpu().numpy())
+
+
+class Moments(torch.autograd.Function):
+    """Re <phi|T_n(H~)|phi>, shape [n_seg, B, M]."""
+
+    @staticmethod
+    def forward(ctx, onsite, scales, H, phi, M):
+        _set(H, onsite, scales)
+        mu = Bd.gpuqt_moments(H, phi, phi, M)
+        ctx.H, ctx.M = H, M
+        ctx.save_for_backward(onsite, scales, phi)
+        return mu.real.contiguous()
+
+    @staticmethod
+    def backward(ctx, g):
+        onsite, scales, phi = ctx.saved_tensors
+        H = ctx.H
+        _set(H, onsite, scales)
+        gU = torch.zeros_like(onsite)
+        gC = torch.zeros(scales.shape[0], dtype=torch.float64, device=onsite.device)
+        Bd.gpuqt_moments_backward(H, phi, phi, g.contiguous(), gU, gC)
+        return gU, (gC.to(scales.device) / scales), None, None, None
+
+
+class VAC(torch.autograd.Function):
+    """C_n^VAC(t_k) rows, shape [n_t, n_seg, B, M]."""
+
+    @staticmethod
+    def forward(ctx, onsite, scales, H, phi, dt, M, Np):
+        _set(H, onsite, scales)
+        out = Bd.gpuqt_vac(H, phi, dt, M, Np)
+        ctx.H, ctx.dt, ctx.Np = H, np.asarray(dt, dtype=np.float64), Np
+        ctx.save_for_backward(onsite, scales, phi)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        onsite, scales, phi = ctx.saved_tensors
+        H = ctx.H
+        _set(H, onsite, scales)
+        gU = torch.zeros_like(onsite)
+        gC = torch.zeros(scales.shape[0], dtype=torch.float64, device=onsite.device)
+        Bd.gpuqt_vac_backward(H, phi, ctx.dt, g.contiguous(), gU, gC, Np=ctx.Np)
+        return gU, (gC.to(scales.device) / scales), None, None, None, None, None
+
+
+class KPM(torch.autograd.Function):
+    """Jackson-damped KPM sum of moment rows C [R, M] on an energy grid -> [R, n_E]."""
+
+    @staticmethod
+    def forward(ctx, C, energies, energy_max, volume):
+        ctx.args = (np.asarray(energies, dtype=np.float64), int(C.shape[-1]), float(energy_max),
+                    float(volume))
+        return Bd.gpuqt_kpm_reconstruct(C.detach().contiguous(), energies, energy_max, volume)
+
+    @staticmethod
+    def backward(ctx, g):
+        E, M, dE, vol = ctx.args
+        return Bd.gpuqt_kpm_reconstruct_adjoint(g.contiguous(), E, M, dE, vol), None, None, None

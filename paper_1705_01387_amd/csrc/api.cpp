@@ -109,6 +109,21 @@ int terms_for(const Handle* h, double dt, int Np) {
   return best;
 }
 
+int backward_stride(int M, int stride) {
+  if (stride >= 2) return stride;
+  int s = (int)std::ceil(std::sqrt((double)std::max(M, 1)));
+  return std::max(2, s);
+}
+
+// vectors of the backward workspace: 3 forward, 2 per checkpoint pair, s
+// recomputed, 3 adjoint
+int backward_vectors(int M, int s) {
+  const int K = M >= 2 ? (M - 1 + s - 1) / s : 0;
+  return 6 + 2 * K + s;
+}
+
+int class_stride(int n_class) { return n_class <= 1 ? 1 : (n_class <= 2 ? 2 : 4); }
+
 // ---------------------------------------------------------------------------
 // sequencing helpers (enqueue only; arguments already checked)
 // ---------------------------------------------------------------------------
@@ -197,6 +212,101 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
   return GPUQT_OK;
 }
 
+// Source of the adjoint recurrence: real loss weights w[seg][b][n] on Re mu_n,
+// or the complex coefficients c_n = J[seg][n] (-i sgn)^n of an evolution series
+// (the adjoint source is conj(c_n) phiL).
+struct BwdSource {
+  const double* wts = nullptr;
+  const double* Jtab = nullptr;
+  int ldJ = 0;
+  double sgn = 1.0;
+};
+
+// Reverse of the M-step recurrence started at phiR, with phiL the adjoint
+// source: when gU is set, parameter terms go to gU and (nc > 0) gcp, with the
+// forward vectors recomputed from checkpoints every s steps; lam0 (if set)
+// receives sum_n conj(c_n) T_n phiL (accumulated when acc0).  vec: at least
+// backward_vectors(M, s) workspace vectors.
+gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const double2* pR, int M,
+                          const BwdSource& src, double* gU, double* gcp, int nc, double2* lam0,
+                          bool acc0, int s, double2* const* vec, hipStream_t sm) {
+  const DevMat D = h->view();
+  const bool grad = gU != nullptr;
+  const int K = M >= 2 ? (M - 1 + s - 1) / s : 0;
+  double2* const* R = vec;
+  double2* const* Lm = vec + 3;
+  auto ck = [&](int k, int q) { return vec[6 + 2 * k + q]; };
+  auto sb = [&](int j) { return vec[6 + 2 * K + j]; };
+  auto make = [&](int n) {
+    AdjIO a;
+    a.x = (n + 1 <= M - 1) ? Lm[(n + 1) % 3] : nullptr;
+    a.w = (n + 2 <= M - 1) ? Lm[(n + 2) % 3] : nullptr;
+    a.out = Lm[n % 3];
+    a.phiL = pL;
+    a.wts = src.wts;
+    a.M = M;
+    a.n = n;
+    a.f_rec = 2.0;
+    a.v = nullptr;
+    a.f = n == 1 ? 1.0 : 2.0;
+    a.gU = gU;
+    a.gcp = gcp;
+    a.cls = h->d_cls;
+    a.Jtab = src.Jtab;
+    a.ldJ = src.ldJ;
+    a.accumulate = 0;
+    const double2 p = phase_pow(n, src.sgn);
+    a.src_phase = make_double2(p.x, -p.y);   // conj((-i sgn)^n)
+    return a;
+  };
+  if (grad) {
+    // forward: v_1 .. v_{M-2}, keeping v_{ks} and v_{ks+1} as checkpoints
+    const double2* prev2 = nullptr;
+    const double2* prev1 = pR;
+    for (int n = 1; n <= M - 2; ++n) {
+      double2* out = (n % s == 0 || n % s == 1) ? ck(n / s, n % s) : R[n % 3];
+      StepIO io{prev1, prev2, out, n == 1 ? 1 : 0};
+      HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+      prev2 = prev1;
+      prev1 = out;
+    }
+    auto slot = [&](int k, int j) -> const double2* {
+      if (j == 0) return k == 0 ? pR : ck(k, 0);
+      if (j == 1) return ck(k, 1);
+      return sb(j);
+    };
+    for (int k = K - 1; k >= 0; --k) {
+      const int lo = k * s + 1, hi = std::min((k + 1) * s, M - 1);
+      for (int j = 2; j <= hi - 1 - k * s; ++j) {   // recompute v_{ks+j}
+        StepIO io{slot(k, j - 1), slot(k, j - 2), sb(j), 0};
+        HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+      }
+      for (int n = hi; n >= lo; --n) {
+        AdjIO a = make(n);
+        a.v = slot(k, n - 1 - k * s);
+        HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, nc, a, sm));
+      }
+    }
+  } else {
+    for (int n = M - 1; n >= 1; --n) {
+      AdjIO a = make(n);
+      HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, 0, a, sm));
+    }
+  }
+  if (lam0) {   // lam_0 = conj(c_0) phiL + H~ lam_1 - lam_2 = sum_n conj(c_n) T_n(H~) phiL
+    AdjIO a = make(0);
+    a.x = M >= 2 ? Lm[1] : nullptr;
+    a.w = M >= 3 ? Lm[2] : nullptr;
+    a.out = lam0;
+    a.f_rec = 1.0;
+    a.gU = nullptr;
+    a.gcp = nullptr;
+    a.accumulate = acc0 ? 1 : 0;
+    HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, 0, a, sm));
+  }
+  return GPUQT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -277,6 +387,10 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_blk0, seg_blk0.data(), seg_blk0.size() * 4);
   up((void**)&h->d_seg_dE, L.seg_dE.data(), L.seg_dE.size() * 8);
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
+  std::vector<double> zeros_g(h->G, 0.0);
+  up((void**)&h->d_bound, zeros_g.data(), zeros_g.size() * 8);
+  h->seg_hop0 = L.seg_hop;
+  h->class_scale.assign(h->n_class, 1.0);
   if (ok && hipStreamSynchronize(s) != hipSuccess) ok = false;
   if (!ok) {
     gpuqt_destroy_h(reinterpret_cast<gpuqt_h>(h));
@@ -290,7 +404,7 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
-                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop};
+                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -320,6 +434,68 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   return GPUQT_OK;
 }
 
+gpuqt_status gpuqt_update_h_values(gpuqt_h hh, const double* onsite, const double* class_scale,
+                                   void* stream) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (onsite && (reinterpret_cast<uintptr_t>(onsite) & 7u))
+    return fail(GPUQT_ERR_ARG, "onsite is not 8-byte aligned");
+  if (class_scale) {
+    if (h->n_class > kMaxUpdateClasses)
+      return fail(GPUQT_ERR_UNSUPPORTED, "at most 8 hopping classes can be rescaled");
+    for (int c = 0; c < h->n_class; ++c)
+      if (!std::isfinite(class_scale[c])) return fail(GPUQT_ERR_ARG, "class_scale is not finite");
+  }
+  gpuqt_status st;
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevMat D = h->view();
+  if (onsite) HIP_TRY(launch_set_onsite(D, onsite, h->d_diag, s));
+  if (class_scale) {
+    if (h->hop_mode == HOP_UNIFORM) {
+      std::vector<double> v(h->n_seg);
+      for (int q = 0; q < h->n_seg; ++q) v[q] = h->seg_hop0[q] * class_scale[0];
+      HIP_TRY(hipMemcpyAsync(h->d_seg_hop, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } else {
+      const size_t hb = (size_t)h->entries * (h->hop_mode == HOP_COMPLEX ? 16 : 8);
+      if (!h->d_hop0) {   // first class update: keep the hoppings given at build time
+        if (hipMalloc((void**)&h->d_hop0, hb) != hipSuccess) {
+          h->d_hop0 = nullptr;
+          return fail(GPUQT_ERR_NOMEM, "could not allocate the copy of the build-time hoppings");
+        }
+        h->device_bytes += hb;
+        HIP_TRY(hipMemcpyAsync(h->d_hop0, h->d_hop, hb, hipMemcpyDeviceToDevice, s));
+      }
+      ClassScale sc{};
+      for (int c = 0; c < h->n_class; ++c) sc.s[c] = class_scale[c];
+      HIP_TRY(launch_scale_hops(h->entries, h->hop_mode == HOP_COMPLEX ? 1 : 0, h->d_hop0, h->d_hop,
+                                h->n_class > 1 ? h->d_cls : nullptr, sc, s));
+    }
+    for (int c = 0; c < h->n_class; ++c) h->class_scale[c] = class_scale[c];
+  }
+  // the spectrum of H / DeltaE must stay in [-1, 1]: recheck the Gershgorin bound
+  HIP_TRY(launch_row_bound(D, h->hop_mode, h->d_bound, s));
+  std::vector<double> bound(h->G);
+  HIP_TRY(hipMemcpyAsync(bound.data(), h->d_bound, bound.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int g = 0; g < h->G; ++g) {
+    const int q = h->plan_host[g].seg;
+    h->seg_gersh[q] = 0.0;
+  }
+  for (int g = 0; g < h->G; ++g) {
+    const int q = h->plan_host[g].seg;
+    h->seg_gersh[q] = std::max(h->seg_gersh[q], bound[g] * h->seg_dE[q]);
+  }
+  for (int q = 0; q < h->n_seg; ++q)
+    if (h->seg_gersh[q] > h->seg_dE[q] * (1.0 + 1e-12))
+      return fail(GPUQT_ERR_SPECTRUM, "after the update the Gershgorin bound " +
+                                          std::to_string(h->seg_gersh[q]) + " of segment " +
+                                          std::to_string(q) + " exceeds its DeltaE " +
+                                          std::to_string(h->seg_dE[q]));
+  return GPUQT_OK;
+}
+
 gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, int32_t Np,
                                   size_t* bytes) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
@@ -334,6 +510,11 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
                      op == GPUQT_OP_VAC || op == GPUQT_OP_MSD;
   const int64_t rows = has_moments ? std::max(M, 2) : 0;
   const int64_t ldJ = has_J ? (Np > 0 ? Np : kAutoNpCap) : 0;
+  if (op == GPUQT_OP_MOMENTS_BACKWARD) {
+    const int s = backward_stride(M, Np);
+    *bytes = ws_layout(h, backward_vectors(M, s), B, 2, 0).total;
+    return GPUQT_OK;
+  }
   *bytes = ws_layout(h, nv, B, rows, ldJ).total;
   return GPUQT_OK;
 }
@@ -520,6 +701,155 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   return GPUQT_OK;
 }
 
+gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, const double* phiR,
+                                    int32_t M, const double* w, double* grad_onsite,
+                                    double* grad_class, double* lam0, int32_t ckpt_stride,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (M < 0 || ckpt_stride < 0) return fail(GPUQT_ERR_ARG, "M and ckpt_stride must be >= 0");
+  if (M == 0) return GPUQT_OK;
+  gpuqt_status st;
+  if ((st = check_vec(phiL, "phiL")) || (st = check_vec(phiR, "phiR"))) return st;
+  if (!w) return fail(GPUQT_ERR_ARG, "w is NULL");
+  if (!grad_onsite && grad_class) return fail(GPUQT_ERR_ARG, "grad_class needs grad_onsite");
+  if (lam0 && !aligned16(lam0)) return fail(GPUQT_ERR_ARG, "lam0 is not 16-byte aligned");
+  if (grad_class && h->n_class > 4)
+    return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
+  const int s = backward_stride(M, ckpt_stride);
+  const WsLayout W = ws_layout(h, backward_vectors(M, s), B, 2, 0);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t sm = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  std::vector<double2*> vec(backward_vectors(M, s));
+  for (size_t i = 0; i < vec.size(); ++i) vec[i] = reinterpret_cast<double2*>(base + W.vec_bytes * i);
+  double* gcp = reinterpret_cast<double*>(base + W.off_part);
+  const int nc = grad_class ? class_stride(h->n_class) : 0;
+  if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
+  BwdSource src;
+  src.wts = w;
+  if ((st = run_backward(h, B, reinterpret_cast<const double2*>(phiL),
+                         reinterpret_cast<const double2*>(phiR), M, src, grad_onsite, gcp, nc,
+                         reinterpret_cast<double2*>(lam0), false, s, vec.data(), sm)))
+    return st;
+  if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
+  return GPUQT_OK;
+}
+
+// number of workspace vectors of gpuqt_vac_backward
+static int vac_backward_vectors(int n_t, int M, int Np) {
+  const int L = std::max(M, Np);
+  return 2 * n_t + 6 + backward_vectors(L, backward_stride(L, 0));
+}
+
+gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
+                                               int32_t M, int32_t Np, size_t* bytes) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (n_t < 0 || M < 0 || Np < 0 || (n_t > 0 && !dt)) return fail(GPUQT_ERR_ARG, "bad sizes");
+  const int np = max_terms(h, std::max(n_t - 1, 0), dt, Np);
+  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np), B, 2, np).total;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
+                                const double* dt, int32_t M, int32_t Np, const double* w,
+                                double* grad_onsite, double* grad_class, void* ws, size_t ws_bytes,
+                                void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, w);
+  if (st) return st;
+  if (!grad_onsite) return fail(GPUQT_ERR_ARG, "grad_onsite is NULL");
+  if (grad_class && h->n_class > 4)
+    return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
+  if (n_t == 0 || M == 0) return GPUQT_OK;
+  const int np = max_terms(h, n_t - 1, dt, Np);
+  const int L = std::max(M, np);
+  const int s = backward_stride(L, 0);
+  const int nv = vac_backward_vectors(n_t, M, np);
+  const WsLayout W = ws_layout(h, nv, B, 2, np);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t sm = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
+  double* gcp = reinterpret_cast<double*>(base + W.off_part);
+  double* J = reinterpret_cast<double*>(base + W.off_J);
+  const DevMat D = h->view();
+  const int nc = grad_class ? class_stride(h->n_class) : 0;
+  const double2* ph = reinterpret_cast<const double2*>(phi);
+  // states psi_L(k) (k >= 1) and psi_R(k), adjoints, scratch
+  auto psiL = [&](int k) -> const double2* { return k == 0 ? ph : V(k - 1); };
+  auto psiR = [&](int k) { return V(n_t - 1 + k); };
+  double2* gL[2] = {V(2 * n_t - 1), V(2 * n_t)};
+  double2* gR[2] = {V(2 * n_t + 1), V(2 * n_t + 2)};
+  double2* gphiL = V(2 * n_t + 3);
+  double2* phiL = V(2 * n_t + 4);
+  std::vector<double2*> pool(backward_vectors(L, s));
+  for (size_t i = 0; i < pool.size(); ++i) pool[i] = V(2 * n_t + 5 + (int)i);
+  double2* e0 = pool[0];   // evolution scratch during the forward pass
+  double2* e1 = pool[1];
+  if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
+  // forward: psi_R(0) = V phi; psi_{L,R}(k+1) = U(-dt_k) psi_{L,R}(k)
+  HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, psiR(0), sm));
+  for (int k = 0; k + 1 < n_t; ++k) {
+    const int npk = terms_for(h, dt[k], Np);
+    if ((st = run_evolve(h, B, -dt[k], npk, psiL(k), V(k), nullptr, nullptr, e0, e1, nullptr, nullptr,
+                         nullptr, J, sm)))
+      return st;
+    if ((st = run_evolve(h, B, -dt[k], npk, psiR(k), psiR(k + 1), nullptr, nullptr, e0, e1, nullptr,
+                         nullptr, nullptr, J, sm)))
+      return st;
+  }
+  // reverse over the rows
+  int cl = 0, cr = 0;
+  HIP_TRY(launch_scale(D, B, nullptr, gL[0], nullptr, 0, sm));
+  HIP_TRY(launch_scale(D, B, nullptr, gR[0], nullptr, 0, sm));
+  const int64_t row = (int64_t)h->n_seg * B * M;
+  for (int k = n_t - 1; k >= 0; --k) {
+    HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL(k), phiL, sm));
+    BwdSource src;
+    src.wts = w + row * k;
+    // moments of row k: parameter terms, and gR += sum_n w_n T_n phiL
+    if ((st = run_backward(h, B, phiL, psiR(k), M, src, grad_onsite, gcp, nc, gR[cr], true, s,
+                           pool.data(), sm)))
+      return st;
+    // gphiL = sum_n w_n T_n psi_R(k) (no parameter terms)
+    if ((st = run_backward(h, B, psiR(k), phiL, M, src, nullptr, nullptr, 0, gphiL, false, s,
+                           pool.data(), sm)))
+      return st;
+    // phiL = V psi_L: gL += V gphiL, class terms of V
+    HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY | kAccumulate, gphiL, gL[cl], sm));
+    if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gphiL, psiL(k), h->d_cls, gcp, sm));
+    if (k == 0) break;
+    // back through psi(k) = U(-dt) psi(k-1): parameter terms and g <- U(+dt) g
+    const double d = -dt[k - 1];
+    const int npk = terms_for(h, d, Np);
+    HIP_TRY(launch_bessel_table(h->d_seg_dE, h->n_seg, std::fabs(d), npk, npk, J, sm));
+    BwdSource ev;
+    ev.Jtab = J;
+    ev.ldJ = npk;
+    ev.sgn = d >= 0 ? 1.0 : -1.0;
+    if ((st = run_backward(h, B, gL[cl], psiL(k - 1), npk, ev, grad_onsite, gcp, nc, gL[cl ^ 1], false,
+                           s, pool.data(), sm)))
+      return st;
+    if ((st = run_backward(h, B, gR[cr], psiR(k - 1), npk, ev, grad_onsite, gcp, nc, gR[cr ^ 1], false,
+                           s, pool.data(), sm)))
+      return st;
+    cl ^= 1;
+    cr ^= 1;
+  }
+  // psi_R(0) = V phi: class terms of V
+  if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gR[cr], ph, h->d_cls, gcp, sm));
+  if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
+  return GPUQT_OK;
+}
+
 gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, void* stream,
                             double* times_us) {
   Handle* h = reinterpret_cast<Handle*>(hh);
@@ -577,6 +907,19 @@ gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double* C, int32_
   const double pref = 2.0 / (M_PI * volume * energy_max);
   HIP_TRY(launch_kpm(R, M, C, n_E, energies, 1.0 / energy_max, pref, jackson ? 1 : 0, out,
                      static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_kpm_reconstruct_adjoint(int32_t R, int32_t M, const double* g, int32_t n_E,
+                                           const double* energies, double energy_max, double volume,
+                                           int32_t jackson, double* out, void* stream) {
+  if (R < 0 || M < 1 || n_E < 0 || n_E > 65536) return fail(GPUQT_ERR_ARG, "bad sizes");
+  if (!(energy_max > 0) || !(volume > 0)) return fail(GPUQT_ERR_ARG, "energy_max and volume must be > 0");
+  if (R == 0) return GPUQT_OK;
+  if (!g || !energies || !out) return fail(GPUQT_ERR_ARG, "NULL pointer");
+  const double pref = 2.0 / (M_PI * volume * energy_max);
+  HIP_TRY(launch_kpm_adjoint(R, M, g, n_E, energies, 1.0 / energy_max, pref, jackson ? 1 : 0, out,
+                             static_cast<hipStream_t>(stream)));
   return GPUQT_OK;
 }
 

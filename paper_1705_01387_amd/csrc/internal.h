@@ -79,6 +79,12 @@ struct Handle {
   int32_t* d_seg_blk0 = nullptr;   // [n_seg + 1] first logical workgroup of each segment
   double* d_seg_dE = nullptr;
   double* d_seg_hop = nullptr;
+  // parameter updates: build-time hoppings (allocated on the first class update),
+  // current class scales, per-workgroup spectrum bounds
+  double* d_hop0 = nullptr;
+  double* d_bound = nullptr;
+  std::vector<double> seg_hop0;
+  std::vector<double> class_scale;
 
   DevMat view() const {
     DevMat m;
@@ -171,13 +177,58 @@ hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& 
                            double2* acc_a, double2* acc_b, const double* Jtab, int ldJ, int m,
                            double2 phase_m, double2 phase_0, hipStream_t s);
 
-// out = V x (which = GPUQT_VELOCITY) or [X,H] x (GPUQT_COMMUTATOR_XH), unscaled H.
+// out = V x (which = GPUQT_VELOCITY) or [X,H] x (GPUQT_COMMUTATOR_XH), unscaled H;
+// with kAccumulate or-ed into `which`, out += instead.
+constexpr int kAccumulate = 2;
 hipError_t launch_commutator(const DevMat& A, int hop_mode, int B, int which, const double2* x,
                              double2* out, hipStream_t s);
 
 // out = J_0 * in (Np = 1 evolution), per segment.
 hipError_t launch_scale(const DevMat& A, int B, const double2* in, double2* out,
                         const double* Jtab, int ldJ, hipStream_t s);
+
+// One reverse step of the moment recurrence (kernels_adjoint.hip):
+//   out = wts[seg][b][n] * phiL + f_rec * H~ x - w    (x, w may be NULL: zero)
+// and, when v (= v_{n-1}) is given, gU[r] += f sum_b Re(conj(out) v) / DeltaE and
+// gcp[lb][c] += f Re <out| H~_c v> over the workgroup's rows.
+struct AdjIO {
+  const double2* x;      // lam_{n+1}, gathered
+  const double2* w;      // lam_{n+2}
+  double2* out;          // lam_n
+  const double2* phiL;
+  const double* wts;     // [n_seg][B][M] loss weights on Re mu (NULL: zero)
+  int32_t M, n;
+  double f_rec;          // 2 for a reverse step, 1 for lam_0
+  const double2* v;      // v_{n-1} (NULL: no gradient terms)
+  double f;              // 2 for n >= 2, 1 for n = 1
+  double* gU;            // [n] accumulated
+  double* gcp;           // [G][nc] accumulated per workgroup
+  const int32_t* cls;    // [entries] class of each entry (nc > 1)
+  const double* Jtab;    // non-NULL: source coefficient J[seg*ldJ + n] * src_phase instead of wts
+  int32_t ldJ;
+  int32_t accumulate;    // 1: out += lam (instead of out = lam)
+  double2 src_phase;
+};
+// parameter updates (gpuqt_update_h_values)
+constexpr int kMaxUpdateClasses = 8;
+struct ClassScale {
+  double s[kMaxUpdateClasses];
+};
+hipError_t launch_set_onsite(const DevMat& A, const double* onsite, double* diag, hipStream_t s);
+hipError_t launch_scale_hops(int64_t entries, int cplx, const double* hop0, double* hop,
+                             const int32_t* cls, const ClassScale& sc, hipStream_t s);
+// bound[lb] = max over rows of |U~_r| + sum_j |H~_rj|
+hipError_t launch_row_bound(const DevMat& A, int hop_mode, double* bound, hipStream_t s);
+
+// gcp[lb][c] += Re sum_i conj(a_i) (V_c x)_i, V_c = i dx H_c (unscaled)
+hipError_t launch_velocity_class_grad(const DevMat& A, int hop_mode, int B, int nc, const double2* a,
+                                      const double2* x, const int32_t* cls, double* gcp, hipStream_t s);
+hipError_t launch_adjoint_step(const DevMat& A, int hop_mode, int B, int nc, const AdjIO& io,
+                               hipStream_t s);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// out[c] += sum_g gcp[g*nc + c] for c < n_out (fixed order)
+hipError_t launch_reduce_classes(const double* gcp, int G, int nc, int n_out, double* out,
+                                 hipStream_t s);
 
 // out = a deterministic unit-modulus vector (timing input of gpuqt_autotune).
 hipError_t launch_fill_phase(const DevMat& A, int B, double2* out, hipStream_t s);
@@ -199,6 +250,10 @@ hipError_t launch_reduce_moments(const double2* part, int M, int G, int B, int n
 // x = E[e] * inv_dE (NaN where |x| >= 1).
 hipError_t launch_kpm(int R, int M, const double* C, int n_E, const double* E, double inv_dE,
                       double pref_base, int jackson, double* out, hipStream_t s);
+
+// out[r][n] = sum_e g[r][e] d(KPM sum)[r][e] / dC[r][n]   (transpose of launch_kpm)
+hipError_t launch_kpm_adjoint(int R, int M, const double* g, int n_E, const double* E, double inv_dE,
+                              double pref_base, int jackson, double* out, hipStream_t s);
 
 hipError_t launch_copy(const double2* src, double2* dst, size_t n16, hipStream_t s);
 

@@ -32,175 +32,13 @@
 #include "bessel.h"
 #include "internal.h"
 
+#include "device_common.h"
+
 namespace gpuqt {
 
+using namespace dev;
+
 namespace {
-
-template <int V>
-using IC = std::integral_constant<int, V>;
-
-typedef double d2v __attribute__((ext_vector_type(2)));
-
-template <bool NT, typename T>
-__device__ __forceinline__ T ldg(const T* p) {
-  if constexpr (NT) {
-    return __builtin_nontemporal_load(p);
-  } else {
-    return *p;
-  }
-}
-
-template <bool NT>
-__device__ __forceinline__ double2 ld2(const double2* p) {
-  if constexpr (NT) {
-    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
-    return make_double2(v.x, v.y);
-  } else {
-    return *p;
-  }
-}
-
-__device__ __forceinline__ int logical_block(int G) {
-  const int p = blockIdx.x;
-  if ((G & 7) == 0) {
-    const int per = G >> 3;
-    return (p & 7) * per + (p >> 3);
-  }
-  return p;
-}
-
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
-// a * b (complex)
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
-}
-// 2 a - w
-__device__ __forceinline__ double2 twice_minus(double2 a, double2 w) {
-  return make_double2(fma(2.0, a.x, -w.x), fma(2.0, a.y, -w.y));
-}
-// acc += conj(a) * b
-__device__ __forceinline__ void cdot_acc(double& re, double& im, double2 a, double2 b) {
-  re = fma(a.x, b.x, fma(a.y, b.y, re));
-  im = fma(a.x, b.y, fma(-a.y, b.x, im));
-}
-
-// Products of one row with the gathered vector(s):
-//   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
-//   da = sum_j dx_rj H~_rj xa_j (DX; the diagonal has dx = 0).
-// K > 0: every slice has exactly K entries per row (fully unrolled, all index
-// loads issued before the gathers).  K == 0: runtime slice width.
-template <int B, int HOP, int K, bool NT, bool TWO, bool DX, bool DIAG>
-__device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, double hu,
-                                          const double2* __restrict__ xa,
-                                          const double2* __restrict__ xb, double2& ha,
-                                          double2& hb, double2& da) {
-  const int S = 1 << A.S_log2;
-  const int64_t sl = r >> A.S_log2;
-  const int64_t p0 = A.slice_ptr[sl];
-  const int64_t e0 = p0 + (r & (S - 1));
-  ha = make_double2(0.0, 0.0);
-  hb = make_double2(0.0, 0.0);
-  da = make_double2(0.0, 0.0);
-  if (DIAG) {
-    const double d = ldg<NT>(A.diag + r);
-    ha = cscale(d, xa[r * B + b]);
-    if (TWO) hb = cscale(d, xb[r * B + b]);
-  }
-  auto body = [&](int32_t c, int64_t e) {
-    const bool ok = c >= 0;
-    const int64_t cc = ok ? (int64_t)c : r;
-    double hr, hi = 0.0;
-    if (HOP == HOP_UNIFORM) {
-      hr = ok ? hu : 0.0;
-    } else if (HOP == HOP_REAL) {
-      hr = ldg<NT>(A.hop + e);
-    } else {
-      const double2 h = ld2<NT>(reinterpret_cast<const double2*>(A.hop) + e);
-      hr = h.x;
-      hi = h.y;
-    }
-    const double2 v = xa[cc * B + b];
-    double2 hv;
-    if (HOP == HOP_COMPLEX) {
-      hv = cmul(make_double2(hr, hi), v);
-    } else {
-      hv = cscale(hr, v);
-    }
-    ha = cadd(ha, hv);
-    if (TWO) {
-      const double2 u = xb[cc * B + b];
-      if (HOP == HOP_COMPLEX) {
-        hb = cadd(hb, cmul(make_double2(hr, hi), u));
-      } else {
-        hb = cadd(hb, cscale(hr, u));
-      }
-    }
-    if (DX) {
-      const double dxv = ldg<NT>(A.dx + e);
-      da = make_double2(fma(dxv, hv.x, da.x), fma(dxv, hv.y, da.y));
-    }
-  };
-  if constexpr (K > 0) {
-    int32_t c[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) c[j] = ldg<NT>(A.col + e0 + (int64_t)j * S);
-#pragma unroll
-    for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
-  } else {
-    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
-    int j = 0;
-    for (; j + 4 <= w; j += 4) {
-      int32_t c[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) c[q] = ldg<NT>(A.col + e0 + (int64_t)(j + q) * S);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) body(c[q], e0 + (int64_t)(j + q) * S);
-    }
-    for (; j < w; ++j) body(ldg<NT>(A.col + e0 + (int64_t)j * S), e0 + (int64_t)j * S);
-  }
-}
-
-// Visit the rows of this workgroup: tiles of RPI = 256/B rows of the group's
-// range, starting at tile j, stride g tiles.  f(r) for each row r of the
-// thread (all threads of the workgroup iterate the same number of times).
-template <int B, typename F>
-__device__ __forceinline__ void for_rows(const BlkPlan& P, F&& f) {
-  constexpr int RPI = kBlock / B;
-  const int64_t step = (int64_t)P.g * RPI;
-  for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step) {
-    const int64_t r = base + threadIdx.x / B;
-    if (r < P.r1) f(r);
-  }
-}
-
-// Sum (re, im) over the lanes of the workgroup that share column b = tid % B,
-// in a fixed order, and store one partial per column.
-template <int B>
-__device__ __forceinline__ void block_reduce_store(double re, double im, double2* __restrict__ dst) {
-  __shared__ double sh[2][kBlock / 64][B];
-#pragma unroll
-  for (int off = 32; off >= B; off >>= 1) {
-    re += __shfl_xor(re, off);
-    im += __shfl_xor(im, off);
-  }
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (lane < B) {
-    sh[0][wave][lane] = re;
-    sh[1][wave][lane] = im;
-  }
-  __syncthreads();
-  if (threadIdx.x < B) {
-    double sr = 0.0, si = 0.0;
-#pragma unroll
-    for (int q = 0; q < kBlock / 64; ++q) {
-      sr += sh[0][q][threadIdx.x];
-      si += sh[1][q][threadIdx.x];
-    }
-    dst[threadIdx.x] = make_double2(sr, si);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Chebyshev moment step (Sections 3.2-3.3): v_n = 2 H~ v_{n-1} - v_{n-2}
@@ -226,10 +64,13 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
     const int64_t idx = r * B + b;
     const double2 y = first ? ha : twice_minus(ha, ld2<NT>(w + idx));
     out[idx] = y;
-    const double2 p = ld2<NT>(phiL + idx);
-    cdot_acc(dr, di, p, y);
-    if (first) cdot_acc(zr, zi, p, x[idx]);
+    if (phiL) {   // plain recurrence step (no moment) when phiL is NULL
+      const double2 p = ld2<NT>(phiL + idx);
+      cdot_acc(dr, di, p, y);
+      if (first) cdot_acc(zr, zi, p, x[idx]);
+    }
   });
+  if (!phiL) return;
   block_reduce_store<B>(dr, di, part_n + (int64_t)lb * B);
   if (first) {
     __syncthreads();
@@ -325,11 +166,13 @@ __global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, cons
     double2 ha, hb, da;
     row_apply<B, HOP, 0, false, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
-    if (which == GPUQT_VELOCITY) {
-      out[idx] = make_double2(-e * da.y, e * da.x);   // i * e * da
+    double2 y;
+    if ((which & 1) == GPUQT_VELOCITY) {
+      y = make_double2(-e * da.y, e * da.x);   // i * e * da
     } else {
-      out[idx] = make_double2(-e * da.x, -e * da.y);
+      y = make_double2(-e * da.x, -e * da.y);
     }
+    out[idx] = (which & kAccumulate) ? cadd(out[idx], y) : y;
   });
 }
 
@@ -429,6 +272,31 @@ __global__ __launch_bounds__(256) void k_kpm(int R, int M, const double* __restr
   out[(int64_t)r * n_E + e] = pref_base / sqrt(1.0 - x * x) * s;
 }
 
+// Transpose of k_kpm: out[r][n] = sum_e g[r][e] pref(E_e) w_n T_n(E~_e), one (row r,
+// moment n) per thread; energies outside the band contribute nothing.
+__global__ __launch_bounds__(256) void k_kpm_adjoint(int R, int M, const double* __restrict__ g, int n_E,
+                                                     const double* __restrict__ E, double inv_dE,
+                                                     double pref_base, int jackson, double cot_pa,
+                                                     double* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= M || r >= R) return;
+  const double a = 1.0 / (M + 1);
+  double wn = n == 0 ? 1.0 : 2.0;
+  if (jackson && n > 0) {
+    double sn, cs;
+    sincospi(n * a, &sn, &cs);
+    wn *= (1.0 - n * a) * cs + a * sn * cot_pa;
+  }
+  double s = 0.0;
+  for (int e = 0; e < n_E; ++e) {
+    const double x = E[e] * inv_dE;
+    if (!(fabs(x) < 1.0)) continue;
+    s += g[(int64_t)r * n_E + e] * pref_base / sqrt(1.0 - x * x) * cos(n * acos(x));
+  }
+  out[(int64_t)r * M + n] = wn * s;
+}
+
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                               size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -446,45 +314,8 @@ __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, d
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
-// ---------------------------------------------------------------------------
-// compile-time dispatch: B x hopping mode x non-temporal x row width
-// ---------------------------------------------------------------------------
-template <typename F>
-hipError_t dispatch_bh(int B, int hop_mode, F&& f) {
-  auto on_b = [&](auto Bc) {
-    if (hop_mode == HOP_UNIFORM) f(Bc, IC<HOP_UNIFORM>{});
-    else if (hop_mode == HOP_REAL) f(Bc, IC<HOP_REAL>{});
-    else f(Bc, IC<HOP_COMPLEX>{});
-  };
-  switch (B) {
-    case 1: on_b(IC<1>{}); break;
-    case 2: on_b(IC<2>{}); break;
-    case 4: on_b(IC<4>{}); break;
-    case 8: on_b(IC<8>{}); break;
-    case 16: on_b(IC<16>{}); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename F>
-hipError_t dispatch_sparse(const DevMat& A, int hop_mode, int B, int nt, F&& f) {
-  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
-    auto on_k = [&](auto NTc) {
-      switch (A.K) {
-        case 3: f(Bc, Hc, IC<3>{}, NTc); break;
-        case 4: f(Bc, Hc, IC<4>{}, NTc); break;
-        case 6: f(Bc, Hc, IC<6>{}, NTc); break;
-        case 8: f(Bc, Hc, IC<8>{}, NTc); break;
-        default: f(Bc, Hc, IC<0>{}, NTc); break;
-      }
-    };
-    if (nt) on_k(std::true_type{});
-    else on_k(std::false_type{});
-  });
-}
-
 }  // namespace
+
 
 // ----------------------------------------------------------------------------
 // launchers
@@ -559,6 +390,16 @@ hipError_t launch_kpm(int R, int M, const double* C, int n_E, const double* E, d
   const double cot_pa = cos(M_PI * a) / sin(M_PI * a);
   k_kpm<<<dim3((n_E + 255) / 256, R), 256, 0, s>>>(R, M, C, n_E, E, inv_dE, pref_base, jackson, cot_pa,
                                                    out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpm_adjoint(int R, int M, const double* g, int n_E, const double* E, double inv_dE,
+                              double pref_base, int jackson, double* out, hipStream_t s) {
+  if (R <= 0 || M <= 0) return hipSuccess;
+  const double a = 1.0 / (M + 1);
+  const double cot_pa = cos(M_PI * a) / sin(M_PI * a);
+  k_kpm_adjoint<<<dim3((M + 255) / 256, R), 256, 0, s>>>(R, M, g, n_E, E, inv_dE, pref_base, jackson,
+                                                         cot_pa, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,327 @@
+// Reverse (adjoint) of the Chebyshev moment recurrence, for gradients of
+// losses built on the moments of Section 3.3 with respect to the on-site
+// energies and the hopping classes.
+//
+// Forward (Section 3.2): v_0 = phiR, v_1 = H~ v_0, v_n = 2 H~ v_{n-1} - v_{n-2},
+// mu_n = <phiL|v_n>.  For L = sum_n w_n Re mu_n the adjoint vectors obey
+//   lam_n = w_n phiL + 2 H~ lam_{n+1} - lam_{n+2},  lam_M = lam_{M+1} = 0,
+// a Clenshaw-type recurrence run backwards, and
+//   dL/dp = Re[ sum_{n>=2} 2 <lam_n| dH~/dp v_{n-1}> + <lam_1| dH~/dp v_0> ].
+// With dH~/dU_i = e_i e_i^T / DeltaE and dH~/deps_c = H~_c (the class-c
+// hoppings), one reverse step needs lam_{n+1} and v_{n-1} at the neighbours
+// of each row: the kernel gathers both with the same neighbour indices, so a
+// reverse step reads the matrix once.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace gpuqt {
+
+using namespace dev;
+
+namespace {
+
+template <int B, int HOP, int K, int NC>
+__global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double inv_dE = 1.0 / A.seg_dE[P.seg];
+  const int b = threadIdx.x & (B - 1);
+  // source coefficient of phiL: a real loss weight, or a complex series
+  // coefficient J[seg][n] * src_phase (already conjugated by the caller)
+  const double2 wn = io.Jtab ? cscale(io.Jtab[(int64_t)P.seg * io.ldJ + io.n], io.src_phase)
+                             : make_double2(io.wts ? io.wts[((int64_t)P.seg * B + b) * io.M + io.n] : 0.0,
+                                            0.0);
+  const double2* __restrict__ x = io.x;
+  const double2* __restrict__ v = io.v;
+  const int S = 1 << A.S_log2;
+  double gc[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int c = 0; c < (NC > 0 ? NC : 1); ++c) gc[c] = 0.0;
+  for_rows<B>(P, [&](int64_t r) {
+    const int64_t idx = r * B + b;
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = K > 0 ? K : (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    double2 h = make_double2(0.0, 0.0);
+    double2 hv[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int c = 0; c < (NC > 0 ? NC : 1); ++c) hv[c] = make_double2(0.0, 0.0);
+    if (x) h = cscale(A.diag[r], x[idx]);
+    for (int j = 0; j < w; ++j) {
+      const int64_t e = e0 + (int64_t)j * S;
+      const int32_t c = A.col[e];
+      const bool ok = c >= 0;
+      const int64_t cc = ok ? (int64_t)c : r;
+      double2 he;
+      if (HOP == HOP_UNIFORM) {
+        he = make_double2(ok ? hu : 0.0, 0.0);
+      } else if (HOP == HOP_REAL) {
+        he = make_double2(A.hop[e], 0.0);
+      } else {
+        he = reinterpret_cast<const double2*>(A.hop)[e];
+      }
+      if (x) {
+        const double2 xv = x[cc * B + b];
+        h = cadd(h, HOP == HOP_COMPLEX ? cmul(he, xv) : cscale(he.x, xv));
+      }
+      if (NC > 0 && v) {
+        const double2 vv = v[cc * B + b];
+        const double2 t = HOP == HOP_COMPLEX ? cmul(he, vv) : cscale(he.x, vv);
+        const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
+#pragma unroll
+        for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+          if (q == cls) hv[q] = cadd(hv[q], t);
+      }
+    }
+    double2 lam = cmul(wn, io.phiL[idx]);
+    lam = make_double2(fma(io.f_rec, h.x, lam.x), fma(io.f_rec, h.y, lam.y));
+    if (io.w) {
+      const double2 ww = io.w[idx];
+      lam = make_double2(lam.x - ww.x, lam.y - ww.y);
+    }
+    io.out[idx] = io.accumulate ? cadd(io.out[idx], lam) : lam;
+    if (v) {
+      const double2 vr = v[idx];
+      double gu = io.f * (lam.x * vr.x + lam.y * vr.y);     // f Re(conj(lam) v)
+#pragma unroll
+      for (int off = 1; off < B; off <<= 1) gu += __shfl_xor(gu, off);
+      if (b == 0) io.gU[r] += gu * inv_dE;
+#pragma unroll
+      for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+        if (NC > 0) gc[q] += io.f * (lam.x * hv[q].x + lam.y * hv[q].y);
+    }
+  });
+  if (NC == 0 || !v) return;
+  // class partials: workgroup sum in a fixed order, accumulated per workgroup
+  __shared__ double sh[kBlock / 64][NC > 0 ? NC : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < (NC > 0 ? NC : 1); ++q) {
+    double s = gc[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < (NC > 0 ? NC : 1)) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) s += sh[wv][threadIdx.x];
+    io.gcp[(int64_t)lb * NC + threadIdx.x] += s;
+  }
+}
+
+// gcp[lb][c] += Re sum_i conj(a_i) (V_c x)_i over the workgroup's rows, with
+// V_c = i dx H_c the velocity restricted to the class-c hoppings (unscaled:
+// the stored H~ is multiplied back by DeltaE).
+template <int B, int HOP, int NC>
+__global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const double2* __restrict__ a,
+                                                                const double2* __restrict__ x,
+                                                                const int32_t* __restrict__ cls,
+                                                                double* __restrict__ gcp) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double e = A.seg_dE[P.seg];
+  const int b = threadIdx.x & (B - 1);
+  const int S = 1 << A.S_log2;
+  double gc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) gc[q] = 0.0;
+  for_rows<B>(P, [&](int64_t r) {
+    const int64_t idx = r * B + b;
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    const double2 ar = a[idx];
+    for (int j = 0; j < w; ++j) {
+      const int64_t en = e0 + (int64_t)j * S;
+      const int32_t c = A.col[en];
+      if (c < 0) continue;
+      double2 he;
+      if (HOP == HOP_UNIFORM) he = make_double2(hu, 0.0);
+      else if (HOP == HOP_REAL) he = make_double2(A.hop[en], 0.0);
+      else he = reinterpret_cast<const double2*>(A.hop)[en];
+      const double2 t = cmul(he, x[(int64_t)c * B + b]);
+      const double s = e * A.dx[en];
+      const double2 vt = make_double2(-s * t.y, s * t.x);      // i e dx H~ x
+      const double contrib = ar.x * vt.x + ar.y * vt.y;        // Re conj(a) vt
+      const int q0 = (NC > 1) ? cls[en] : 0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q)
+        if (q == q0) gc[q] += contrib;
+    }
+  });
+  __shared__ double sh[kBlock / 64][NC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    double s = gc[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NC) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) s += sh[wv][threadIdx.x];
+    gcp[(int64_t)lb * NC + threadIdx.x] += s;
+  }
+}
+
+// diag[r] = onsite[r] / DeltaE_seg (new on-site energies)
+__global__ __launch_bounds__(kBlock) void k_set_onsite(DevMat A, const double* __restrict__ onsite,
+                                                       double* __restrict__ diag) {
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double inv = 1.0 / A.seg_dE[P.seg];
+  for_rows<1>(P, [&](int64_t r) { diag[r] = onsite[r] * inv; });
+}
+
+// hop[e] = hop0[e] * scale[class of e]  (real: one double per entry, complex: two)
+__global__ __launch_bounds__(256) void k_scale_hops(int64_t entries, int cplx, const double* __restrict__ hop0,
+                                                    double* __restrict__ hop, const int32_t* __restrict__ cls,
+                                                    ClassScale sc) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cls ? cls[e] : 0;
+    const double f = c >= 0 ? sc.s[c] : 0.0;
+    if (cplx) {
+      hop[2 * e] = hop0[2 * e] * f;
+      hop[2 * e + 1] = hop0[2 * e + 1] * f;
+    } else {
+      hop[e] = hop0[e] * f;
+    }
+  }
+}
+
+// bound[lb] = max over the workgroup's rows of |U~_r| + sum_j |H~_rj| (the
+// Gershgorin bound of H / DeltaE, which must stay <= 1)
+template <int HOP>
+__global__ __launch_bounds__(kBlock) void k_row_bound(DevMat A, double* __restrict__ bound) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? fabs(A.seg_hop[P.seg]) : 0.0;
+  const int S = 1 << A.S_log2;
+  double mx = 0.0;
+  for_rows<1>(P, [&](int64_t r) {
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    double s = fabs(A.diag[r]);
+    for (int j = 0; j < w; ++j) {
+      const int64_t e = e0 + (int64_t)j * S;
+      if (A.col[e] < 0) continue;
+      if (HOP == HOP_UNIFORM) s += hu;
+      else if (HOP == HOP_REAL) s += fabs(A.hop[e]);
+      else s += hypot(A.hop[2 * e], A.hop[2 * e + 1]);
+    }
+    mx = fmax(mx, s);
+  });
+  __shared__ double sh[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) m = fmax(m, sh[q]);
+    bound[lb] = m;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// grad_class[c] += sum over workgroups of gcp[g][c], in a fixed order.
+__global__ __launch_bounds__(64) void k_reduce_classes(const double* __restrict__ gcp, int G, int NC,
+                                                       double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < G; g += 64) s += gcp[(int64_t)g * NC + c];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (threadIdx.x == 0) out[c] += s;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(const DevMat& A, int hop_mode, int B, int nc, const AdjIO& io,
+                               hipStream_t s) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    constexpr int Bv = decltype(Bc)::value, Hv = decltype(Hc)::value;
+    auto go = [&](auto Kc) {
+      constexpr int Kv = decltype(Kc)::value;
+      switch (nc) {
+        case 0: k_adjoint_step<Bv, Hv, Kv, 0><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 1: k_adjoint_step<Bv, Hv, Kv, 1><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 2: k_adjoint_step<Bv, Hv, Kv, 2><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        default: k_adjoint_step<Bv, Hv, Kv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+      }
+    };
+    switch (A.K) {
+      case 3: go(IC<3>{}); break;
+      case 4: go(IC<4>{}); break;
+      case 6: go(IC<6>{}); break;
+      case 8: go(IC<8>{}); break;
+      default: go(IC<0>{}); break;
+    }
+  });
+}
+
+hipError_t launch_velocity_class_grad(const DevMat& A, int hop_mode, int B, int nc, const double2* a,
+                                      const double2* x, const int32_t* cls, double* gcp, hipStream_t s) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    constexpr int Bv = decltype(Bc)::value, Hv = decltype(Hc)::value;
+    switch (nc) {
+      case 1: k_velocity_class_grad<Bv, Hv, 1><<<dim3(A.G), kBlock, 0, s>>>(A, a, x, cls, gcp); break;
+      case 2: k_velocity_class_grad<Bv, Hv, 2><<<dim3(A.G), kBlock, 0, s>>>(A, a, x, cls, gcp); break;
+      default: k_velocity_class_grad<Bv, Hv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, a, x, cls, gcp); break;
+    }
+  });
+}
+
+hipError_t launch_set_onsite(const DevMat& A, const double* onsite, double* diag, hipStream_t s) {
+  k_set_onsite<<<dim3(A.G), kBlock, 0, s>>>(A, onsite, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_hops(int64_t entries, int cplx, const double* hop0, double* hop,
+                             const int32_t* cls, const ClassScale& sc, hipStream_t s) {
+  if (entries <= 0) return hipSuccess;
+  int64_t blocks = (entries + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_scale_hops<<<dim3((unsigned)blocks), 256, 0, s>>>(entries, cplx, hop0, hop, cls, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_bound(const DevMat& A, int hop_mode, double* bound, hipStream_t s) {
+  if (hop_mode == HOP_UNIFORM) k_row_bound<HOP_UNIFORM><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
+  else if (hop_mode == HOP_REAL) k_row_bound<HOP_REAL><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
+  else k_row_bound<HOP_COMPLEX><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_zero<<<dim3((unsigned)blocks), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_classes(const double* gcp, int G, int nc, int n_out, double* out, hipStream_t s) {
+  if (nc <= 0 || n_out <= 0) return hipSuccess;
+  k_reduce_classes<<<dim3(n_out), 64, 0, s>>>(gcp, G, nc, out);
+  return hipGetLastError();
+}
+
+}  // namespace gpuqt

@@ -1,0 +1,135 @@
+"""GPU parity of the moment gradients (reverse recurrence with checkpoints) against the
+oracle's reverse recurrence with every vector stored.  Bar: normwise 1e-10."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from oracle.adjoint import class_parts
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def err(got, ref):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1e-300))
+
+
+CASES = {
+    "square_nnn_2class": (lambda: I.square(21, 17, t1=-1.0, t2=-0.2, W=1.0, seed=41), 2),
+    "honeycomb_flux": (lambda: I.honeycomb(16, 12, flux=1.0 / 96.0, W=1.0, seed=42), 1),
+    "cubic_uniform": (lambda: I.cubic(9, W=2.0, seed=43), 1),
+    "square_open_padded": (lambda: I.square(19, 13, W=1.5, seed=44, periodic_x=False), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B,M,stride", [(1, 64, 0), (2, 97, 7), (1, 2, 0), (1, 3, 0)])
+def test_moments_backward(gpu, name, B, M, stride):
+    import torch
+    say(f"case: backward {name} B={B} M={M} stride={stride}")
+    mk, n_class = CASES[name]
+    m = mk()
+    H = P.gpuqt_build_h_from_model(m)
+    dE = float(H.energy_max[0])
+    Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    parts = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
+    phiL = I.random_phase(m.n, B, 45)
+    phiR = I.random_phase(m.n, B, 46)
+    w = np.random.default_rng(47).normal(size=(1, B, M))
+    gU = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    gC = torch.zeros(n_class, dtype=torch.float64, device="cuda")
+    gU, gC, lam0 = P.gpuqt_moments_backward(H, dev(phiL), dev(phiR), dev(w), gU, gC,
+                                            want_lam0=True, ckpt_stride=stride)
+    rU, rC = O.moments_gradient(Hs, phiL, phiR, dE, w[0].T, parts)
+    assert err(host(gU), rU) < TOL
+    assert err(host(gC), rC) < TOL
+    ref_l0 = np.stack([O.chebyshev_series(Hs / dE, w[0, b], phiL[:, b]) for b in range(B)], axis=1)
+    assert err(host(lam0), ref_l0) < TOL
+
+
+def test_backward_accumulates_and_is_deterministic(gpu):
+    import torch
+    say("case: backward accumulation / determinism")
+    m = I.square(30, 29, t1=-1.0, t2=-0.15, W=1.0, seed=48)
+    H = P.gpuqt_build_h_from_model(m)
+    phi = dev(I.random_phase(m.n, 1, 49))
+    w = dev(np.random.default_rng(50).normal(size=(1, 1, 80)))
+    a = P.gpuqt_moments_backward(H, phi, phi, w, grad_class=torch.zeros(2, dtype=torch.float64,
+                                                                        device="cuda"))
+    b = P.gpuqt_moments_backward(H, phi, phi, w, grad_class=torch.zeros(2, dtype=torch.float64,
+                                                                        device="cuda"))
+    assert np.array_equal(host(a[0]), host(b[0])) and np.array_equal(host(a[1]), host(b[1]))
+    g2 = a[0].clone()
+    P.gpuqt_moments_backward(H, phi, phi, w, grad_onsite=g2)
+    assert np.allclose(host(g2), 2 * host(a[0]), rtol=1e-14, atol=0)
+
+
+VAC_CASES = {
+    "square_nnn_2class": (lambda: I.square(11, 9, t1=-1.0, t2=-0.2, W=1.0, seed=55), 2),
+    "honeycomb_flux": (lambda: I.honeycomb(8, 6, flux=1.0 / 24.0, W=1.0, seed=56), 1),
+    "cubic_uniform": (lambda: I.cubic(6, W=2.0, seed=57), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(VAC_CASES))
+@pytest.mark.parametrize("B", [1, 2])
+def test_vac_backward(gpu, name, B):
+    import torch
+    from oracle.adjoint import vac_gradient, velocity_class_parts
+    say(f"case: VAC backward {name} B={B}")
+    mk, n_class = VAC_CASES[name]
+    m = mk()
+    H = P.gpuqt_build_h_from_model(m)
+    dE = float(H.energy_max[0])
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
+    phi = I.random_phase(m.n, B, 58)
+    dts = [0.3, 1.2, 0.0, 0.7]
+    M = 40
+    w = np.random.default_rng(59).normal(size=(len(dts), 1, B, M))
+    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w),
+                                  grad_class=torch.zeros(n_class, dtype=torch.float64, device="cuda"))
+    rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
+    assert err(host(gU), rU) < TOL
+    assert err(host(gC), rC) < TOL
+
+
+def test_backward_segments(gpu):
+    import torch
+    say("case: backward with segments")
+    mods = [I.square(12, 11, W=1.0, seed=51), I.square(17, 9, W=2.0, seed=52)]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=offs, seg_length_x=[mm.length_x for mm in mods])
+    phi = I.random_phase(cat.n, 1, 53)
+    M = 50
+    w = np.random.default_rng(54).normal(size=(2, 1, M))
+    gU, gC, _ = P.gpuqt_moments_backward(H, dev(phi), dev(phi), dev(w),
+                                         grad_class=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    gU = host(gU)
+    tot = 0.0
+    for s, mm in enumerate(mods):
+        Hs, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
+        dE = float(H.energy_max[s])
+        ph = phi[offs[s]:offs[s + 1]]
+        rU, rC = O.moments_gradient(Hs, ph, ph, dE, w[s].T, class_parts(mm.nn, mm.nbr, mm.hop, None, 1))
+        assert err(gU[offs[s]:offs[s + 1]], rU) < TOL
+        tot += rC[0]
+    assert abs(host(gC)[0] - tot) < TOL * abs(tot)

@@ -1,0 +1,106 @@
+"""HIP-graph capture of the compute entry points, and the batched form (uneven
+realisations x vector blocks in one launch) against the plain one-vector path."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def err(got, ref):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def test_graph_capture_replays_match_eager(gpu):
+    import torch
+    say("case: graph capture of moments + MSD + VAC")
+    m = I.square(40, 30, W=1.5, seed=61)
+    H = P.gpuqt_build_h_from_model(m)
+    phi = dev(I.random_phase(m.n, 2, 62))
+    M, dts = 300, [0.5, 1.0, 0.25]
+    ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MSD, 2, M, 64),
+                         P.gpuqt_workspace_size(H, P.OP_VAC, 2, M, 64)), dtype=torch.uint8, device="cuda")
+    mu_e = P.gpuqt_moments(H, phi, phi, M, ws=ws).clone()
+    msd_e = P.gpuqt_msd(H, phi, dts, M, Np=64, ws=ws).clone()
+    vac_e = P.gpuqt_vac(H, phi, dts, M, Np=64, ws=ws).clone()
+    mu_g = torch.empty_like(mu_e)
+    msd_g = torch.empty_like(msd_e)
+    vac_g = torch.empty_like(vac_e)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.gpuqt_moments(H, phi, phi, M, mu=mu_g, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.gpuqt_moments(H, phi, phi, M, mu=mu_g, ws=ws)
+        P.gpuqt_msd(H, phi, dts, M, Np=64, out=msd_g, ws=ws)
+        P.gpuqt_vac(H, phi, dts, M, Np=64, out=vac_g, ws=ws)
+    other = P.gpuqt_build_h_from_model(I.square(17, 13, W=3.0, seed=63))
+    ophi = dev(I.random_phase(other.n, 1, 64))
+    for rep in range(3):
+        mu_g.zero_()
+        msd_g.fill_(7.0)
+        vac_g.fill_(-1.0)
+        P.gpuqt_moments(other, ophi, ophi, 50)            # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(mu_g, mu_e), rep
+        assert torch.equal(msd_g, msd_e), rep
+        assert torch.equal(vac_g, vac_e), rep
+
+
+def test_batched_segments_B16_match_plain_vectors(gpu):
+    """Four uneven realisations x 16 vectors in one launch vs each (segment, vector) on its own."""
+    say("case: batched B=16 over 4 segments vs plain")
+    sides = [40, 53, 71, 97]
+    w = I.workload_batched(sides=sides, B=16, M=200)
+    mods = w["models"]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    Hb = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                         seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
+                         seg_length_x=[mm.length_x for mm in mods])
+    mu_b = host(P.gpuqt_moments(Hb, dev(w["phi"]), dev(w["phi"]), w["M"]))   # [seg, B, M]
+    for s, mm in enumerate(mods):
+        Hs = P.gpuqt_build_h_from_model(mm, energy_max=float(w["seg_energy_max"][s]))
+        for b in (0, 7, 15):
+            ph = np.ascontiguousarray(w["phi"][offs[s]:offs[s + 1], b:b + 1])
+            mu_1 = host(P.gpuqt_moments(Hs, dev(ph), dev(ph), w["M"]))[0, 0]
+            assert err(mu_b[s, b], mu_1) < 1e-12
+        Ho, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
+        ph = w["phi"][offs[s]:offs[s + 1]]
+        ref = O.chebyshev_moments(Ho / float(w["seg_energy_max"][s]), ph, ph, w["M"]).T
+        assert err(mu_b[s], ref) < TOL
+
+
+def test_autotune_keeps_results(gpu):
+    say("case: autotune variants give the same moments")
+    m = I.cubic(11, W=4.0, seed=65)
+    H = P.gpuqt_build_h_from_model(m)
+    phi = dev(I.random_phase(m.n, 4, 66))
+    t = P.gpuqt_autotune(H, 4)
+    assert np.all(np.isfinite(t)) and np.all(t > 0)
+    a = host(P.gpuqt_moments(H, phi, phi, 200))
+    Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    ref = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(phi), 200).T
+    assert err(a[0], ref) < TOL

@@ -1,0 +1,145 @@
+"""Differentiation: a loss on the KPM DOS and the VAC conductivity, differentiated through
+the library's adjoint kernels (torch.autograd), checked against the oracle's reverse
+recurrences and against central finite differences."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from oracle.adjoint import class_parts, velocity_class_parts
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def trapezoid_weights(dts):
+    """Trapezoid weights over rows at t_k = dt_0 + ... + dt_{k-1} (integral up to the last row)."""
+    n = len(dts)
+    w = np.zeros(n)
+    for k in range(n - 1):
+        w[k] += 0.5 * dts[k]
+        w[k + 1] += 0.5 * dts[k]
+    return w
+
+
+class Problem:
+    def __init__(self, L, M=512, n_E=1001, seed_shift=0):
+        import torch
+        w = I.workload_train(L)
+        self.m = w["model"]
+        self.dE = w["energy_max"]
+        self.M = M
+        self.E = np.linspace(-5.0, 5.0, n_E)
+        self.dts = list(w["dt"])
+        self.phi_np = w["phi"]
+        self.phi = torch.from_numpy(self.phi_np).cuda()
+        self.H = P.gpuqt_build_h_from_model(self.m, energy_max=self.dE)
+        self.vol = self.m.volume
+        self.U0 = torch.from_numpy(np.ascontiguousarray(self.m.onsite)).cuda()
+        self.s0 = torch.ones(2, dtype=torch.float64)
+        # target: DOS of a second realisation with the same hoppings
+        Ht = P.gpuqt_build_h_from_model(w["target_model"], energy_max=self.dE)
+        mu_t = P.gpuqt_moments(Ht, self.phi, self.phi, M).real
+        self.target = P.gpuqt_kpm_reconstruct(mu_t[0], self.E, self.dE, self.vol).detach()
+        self.tw = torch.from_numpy(trapezoid_weights(self.dts)).cuda()
+
+    def loss(self, U, s):
+        from paper_1705_01387_amd import autograd as A
+        mu = A.Moments.apply(U, s, self.H, self.phi, self.M)                   # [1, 1, M]
+        dos = A.KPM.apply(mu[0], self.E, self.dE, self.vol)                    # [1, n_E]
+        vac = A.VAC.apply(U, s, self.H, self.phi, self.dts, self.M, 0)         # [n_t, 1, 1, M]
+        rc = A.KPM.apply(vac[:, 0, 0, :], self.E, self.dE, self.vol)           # [n_t, n_E]
+        sigma = (self.tw[:, None] * rc).sum(0)                                 # running sigma / e^2
+        dEg = self.E[1] - self.E[0]
+        return ((dos - self.target) ** 2).sum() * dEg + sigma.mean()
+
+
+def test_training_gradient_matches_oracle_small(gpu):
+    import torch
+    say("case: training gradient vs oracle, square 20x20")
+    pb = Problem(20, M=96, n_E=201)
+    U = pb.U0.clone().requires_grad_(True)
+    s = pb.s0.clone().requires_grad_(True)
+    L = pb.loss(U, s)
+    L.backward()
+    gU = U.grad.cpu().numpy()
+    gs = s.grad.cpu().numpy()
+    # oracle: the same loss differentiated with the oracle's reverse recurrences
+    m = pb.m
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2)
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2, m.x, m.length_x)
+    dE, M, E = pb.dE, pb.M, pb.E
+    Et = E / dE
+    K = (O.chebyshev_T(np.arange(M), Et) * (O.jackson(M) * np.where(np.arange(M) == 0, 1, 2))[:, None]).T \
+        * (2 / (np.pi * pb.vol * dE * np.sqrt(1 - Et ** 2)))[:, None]                 # [n_E, M]
+    mu = O.dos_moments(Hs, pb.phi_np, dE, M)[:, 0].real
+    dos = K @ mu
+    tgt = pb.target.cpu().numpy()[0]
+    dEg = E[1] - E[0]
+    w_dos = K.T @ (2 * (dos - tgt) * dEg)
+    tw = trapezoid_weights(pb.dts)
+    w_vac = np.stack([tw[k] * (K.T @ (np.ones(len(E)) / len(E))) for k in range(len(pb.dts))])  # [n_t, M]
+    rU1, rC1 = O.moments_gradient(Hs, pb.phi_np, pb.phi_np, dE, w_dos, Hc)
+    from oracle.adjoint import vac_gradient
+    rU2, rC2 = vac_gradient(Hs, V, pb.phi_np, pb.dts, dE, M, w_vac[:, :, None], 0, Hc, Vc)
+    rU, rC = rU1 + rU2, rC1 + rC2
+    assert np.max(np.abs(gU - rU)) <= 1e-10 * np.max(np.abs(rU))
+    assert np.max(np.abs(gs - rC)) <= 1e-10 * np.max(np.abs(rC))        # scales are 1: d/ds = d/deps
+
+
+def test_training_gradient_finite_differences_full_size(gpu):
+    """Square 512x512 (262,144 orbitals), M = 512: the adjoint gradient against central finite
+    differences (h = 1e-6) on 30 seeded on-site energies and the two hopping scales."""
+    import torch
+    say("case: training gradient vs central FD, square 512x512")
+    pb = Problem(512)
+    U = pb.U0.clone().requires_grad_(True)
+    s = pb.s0.clone().requires_grad_(True)
+    L = pb.loss(U, s)
+    L.backward()
+    gU = U.grad.cpu().numpy()
+    gs = s.grad.cpu().numpy()
+    idx = np.random.default_rng(5004).choice(pb.m.n, 30, replace=False)
+    h = 1e-6
+    scale = max(np.max(np.abs(gU[idx])), np.max(np.abs(gs)))
+    with torch.no_grad():
+        for i in idx:
+            Up = pb.U0.clone()
+            Up[i] += h
+            Um = pb.U0.clone()
+            Um[i] -= h
+            fd = (pb.loss(Up, pb.s0).item() - pb.loss(Um, pb.s0).item()) / (2 * h)
+            assert abs(fd - gU[i]) <= 1e-6 * scale, (i, fd, gU[i])
+        for c in range(2):
+            sp_ = pb.s0.clone()
+            sp_[c] += h
+            sm_ = pb.s0.clone()
+            sm_[c] -= h
+            fd = (pb.loss(pb.U0, sp_).item() - pb.loss(pb.U0, sm_).item()) / (2 * h)
+            assert abs(fd - gs[c]) <= 1e-6 * scale, (c, fd, gs[c])
+
+
+def test_update_h_values_roundtrip_and_spectrum_guard(gpu):
+    import torch
+    say("case: update_h_values")
+    m = I.square(24, 20, t1=-1.0, t2=-0.1, onsite=np.random.default_rng(1).uniform(-1, 1, 480))
+    H = P.gpuqt_build_h_from_model(m, energy_max=6.0)
+    phi = torch.from_numpy(I.random_phase(m.n, 1, 2)).cuda()
+    a = P.gpuqt_moments(H, phi, phi, 64).cpu().numpy()
+    U2 = np.random.default_rng(3).uniform(-1, 1, m.n)
+    P.gpuqt_update_h_values(H, torch.from_numpy(U2).cuda(), [1.2, 0.5])
+    m2 = I.square(24, 20, t1=-1.2, t2=-0.05, onsite=U2)
+    H2 = P.gpuqt_build_h_from_model(m2, energy_max=6.0)
+    b = P.gpuqt_moments(H, phi, phi, 64).cpu().numpy()
+    c = P.gpuqt_moments(H2, phi, phi, 64).cpu().numpy()
+    assert np.max(np.abs(b - c)) <= 1e-12 * np.max(np.abs(c))
+    P.gpuqt_update_h_values(H, torch.from_numpy(np.ascontiguousarray(m.onsite)).cuda(), [1.0, 1.0])
+    assert np.max(np.abs(P.gpuqt_moments(H, phi, phi, 64).cpu().numpy() - a)) <= 1e-12 * np.max(np.abs(a))
+    with pytest.raises(P.GpuqtError) as e:
+        P.gpuqt_update_h_values(H, None, [1.5, 1.0])        # 4*1.5 + 4*0.1 + 1 > 6
+    assert e.value.status == 3

@@ -345,3 +345,45 @@ def test_gradient_finite_differences():
     for c in range(2):
         fd = (loss(H + h * parts[c]) - loss(H - h * parts[c])) / (2 * h)
         assert abs(fd - gC[c]) < 1e-6 * max(1.0, abs(gC[c]))
+
+
+def test_vac_gradient_finite_differences():
+    """Reverse of the VAC computation vs central differences (h = 1e-6): on-site energies and
+    both hopping classes, which move H and the velocity V = i dx H together."""
+    from oracle.adjoint import vac_gradient, velocity_class_parts
+    import scipy.sparse as sp
+    m = I.square(6, 5, t1=-1.0, t2=-0.2, W=1.0, seed=24)
+    H, V, XH = ops(m)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2)
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2, m.x, m.length_x)
+    dE = 6.0
+    phi = I.random_phase(m.n, 2, 25)
+    dts = [0.4, 0.9, 0.3]
+    M, Np = 24, 30
+    w = np.random.default_rng(26).normal(size=(len(dts), M, 2))
+
+    def loss(Hm, Vm):
+        return float(np.sum(w * O.vac_moments(Hm, Vm, phi, dts, dE, M, Np)))
+
+    gU, gC = vac_gradient(H, V, phi, dts, dE, M, w, Np, Hc, Vc)
+    h = 1e-6
+    scale = max(np.max(np.abs(gU)), np.max(np.abs(gC)))
+    for i in (0, 11, 29):
+        e = sp.csr_matrix(([1.0], ([i], [i])), shape=H.shape)
+        fd = (loss(H + h * e, V) - loss(H - h * e, V)) / (2 * h)
+        assert abs(fd - gU[i]) < 1e-6 * scale
+    for c in range(2):
+        fd = (loss(H + h * Hc[c], V + h * Vc[c]) - loss(H - h * Hc[c], V - h * Vc[c])) / (2 * h)
+        assert abs(fd - gC[c]) < 1e-6 * scale
+
+
+def test_chebyshev_series_matches_eigh():
+    """sum_n c_n T_n(H~) psi equals E diag(sum_n c_n T_n(lam/dE)) E^+ psi (exact diagonalisation)."""
+    m = I.honeycomb(3, 4, flux=1.0 / 12.0, W=1.0, seed=31)
+    H, _, _ = ops(m)
+    dE = 1.01 * O.gershgorin_bound(H)
+    lam, E = np.linalg.eigh(H.toarray())
+    c = np.random.default_rng(32).normal(size=40) + 1j * np.random.default_rng(33).normal(size=40)
+    psi = I.random_phase(m.n, 2, 34)
+    ref = E @ ((c @ T_closed(40, lam / dE))[:, None] * (E.conj().T @ psi))
+    assert rel(O.chebyshev_series(H / dE, c, psi), ref) < 1e-12
