@@ -72,6 +72,10 @@ def count_steps(M, dts, np_list, vac=True, msd=True):
     return total
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def copy_probe_gbs(P, torch, dev):
     nb = 1 << 30
     src = torch.zeros(nb // 16, dtype=torch.complex128, device=dev)
@@ -152,14 +156,17 @@ def transport_workload(args, name):
             P.gpuqt_vac(H, phi, dts, M, 0, out=vac, ws=ws)
         P.gpuqt_msd(H, phi, dts, M, 0, out=msd, ws=ws)
 
+    log("setup done (%d orbitals, B=%d)" % (m.n, B))
     for i in range(args.warmup):
         one_step(phis[i], False)
     torch.cuda.synchronize()
+    log("warmup done")
     t0 = time.perf_counter()
     for i in range(args.steps):
         one_step(phis[args.warmup + i], True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    log("timed steps done")
 
     steps_per = count_steps(M, dts, np_list, do_vac, True) * B
     launch_s = np.mean([a.elapsed_time(b) for a, b in ev]) / 1e3 / (M - 1)   # M-1 steps per DOS call
@@ -219,7 +226,8 @@ def batched_workload(args):
                         seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
                         seg_length_x=[mm.length_x for mm in mods])
     phi = torch.from_numpy(w["phi"]).to(dev)
-    ws = torch.empty(P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0),
+                         P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
     tune_us = P.gpuqt_autotune(H, B, ws=ws)
     mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=dev)
     for _ in range(args.warmup):
@@ -236,7 +244,8 @@ def batched_workload(args):
     H1 = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
                          seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
                          seg_length_x=[mm.length_x for mm in mods])
-    ws1 = torch.empty(P.gpuqt_workspace_size(H1, P.OP_MOMENTS, 1, M, 0), dtype=torch.uint8, device=dev)
+    ws1 = torch.empty(max(P.gpuqt_workspace_size(H1, P.OP_MOMENTS, 1, M, 0),
+                          P.gpuqt_workspace_size(H1, P.OP_AUTOTUNE, 1, 0, 0)), dtype=torch.uint8, device=dev)
     tune1 = P.gpuqt_autotune(H1, 1, ws=ws1)
     v1 = [phi[:, b].contiguous() for b in range(2)]
     P.gpuqt_moments(H1, v1[0], v1[0], M, ws=ws1)

@@ -141,7 +141,8 @@ enum {
   GPUQT_OP_EVOLVE_COMMUTATOR = 2,
   GPUQT_OP_VAC = 3,
   GPUQT_OP_MSD = 4,
-  GPUQT_OP_MOMENTS_BACKWARD = 5
+  GPUQT_OP_MOMENTS_BACKWARD = 5,
+  GPUQT_OP_AUTOTUNE = 6
 };
 
 /* Bytes of device workspace `op` needs for B columns, M moments and Np
@@ -264,7 +265,7 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
  * Chebyshev moment steps (Section 3.2 recurrence on a scratch vector) with
  * and without non-temporal loads of the once-read streams, keeps the faster
  * variant for all later calls on the handle.  Synchronises the stream.
- *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_VAC, B, 25, 1)
+ *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0)
  *   times_us : NULL or HOST [2], microseconds per step of variant 0 (plain) and 1 (NT).
  * Not safe while other calls on the handle are in flight.
  */

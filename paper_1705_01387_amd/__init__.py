@@ -6,7 +6,7 @@ the seeded input generators (inputs).
 """
 from ._binding import (  # noqa: F401
     GpuqtError, Hamiltonian, HInfo, LIB_PATH, lib,
-    OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD,
+    OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD, OP_AUTOTUNE,
     VELOCITY, COMMUTATOR_XH,
     gpuqt_build_h, gpuqt_build_h_from_model, gpuqt_workspace_size, gpuqt_moments,
     gpuqt_evolve, gpuqt_apply_commutator, gpuqt_vac, gpuqt_msd, gpuqt_kpm_reconstruct,

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgpuqt.so")
 GPUQT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_LAYOUT", 3: "ERR_SPECTRUM", 4: "ERR_WORKSPACE",
                 5: "ERR_HIP", 6: "ERR_NOMEM", 7: "ERR_UNSUPPORTED"}
-OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD = range(6)
+OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD, OP_AUTOTUNE = range(7)
 VELOCITY, COMMUTATOR_XH = 0, 1
 
 
@@ -482,7 +482,7 @@ def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
     """Time the plain and non-temporal kernel variants, keep the faster; returns us/step of each."""
     t = np.zeros(2)
-    ws, nb = _workspace(H, OP_VAC, B, 25, 1, ws)
+    ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
     info = HInfo()
     _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")

@@ -62,6 +62,7 @@ int op_vectors(int op) {
     case GPUQT_OP_VAC: return 7;
     case GPUQT_OP_MSD: return 9;
     case GPUQT_OP_MOMENTS_BACKWARD: return 6;
+    case GPUQT_OP_AUTOTUNE: return 3;
     default: return -1;
   }
 }
@@ -504,6 +505,10 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
   const int nv = op_vectors(op);
   if (nv < 0) return fail(GPUQT_ERR_ARG, "unknown op");
   if (M < 0 || Np < 0) return fail(GPUQT_ERR_ARG, "M and Np must be >= 0");
+  if (op == GPUQT_OP_AUTOTUNE) {
+    *bytes = ws_layout(h, 3, B, 25, 0).total;
+    return GPUQT_OK;
+  }
   const bool has_moments = op == GPUQT_OP_MOMENTS || op == GPUQT_OP_VAC || op == GPUQT_OP_MSD ||
                            op == GPUQT_OP_MOMENTS_BACKWARD;
   const bool has_J = op == GPUQT_OP_EVOLVE || op == GPUQT_OP_EVOLVE_COMMUTATOR ||
