@@ -189,6 +189,9 @@ def transport_workload(args, name):
     return out
 
 
+KERNEL_SOURCES = ("device_common.h", "internal.h", "kernels.hip")   # what the moment step is built from
+
+
 def measured_traffic(name, bytes_launch):
     """HBM bytes per moment-step launch from the committed counter summary, if it was taken
     on the kernel source that is built now (else None)."""
@@ -200,7 +203,7 @@ def measured_traffic(name, bytes_launch):
         rec = json.load(f)
     src = os.path.join(ROOT, "paper_1705_01387_amd", "csrc")
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(src)):
+    for fn in KERNEL_SOURCES:
         with open(os.path.join(src, fn), "rb") as g:
             h.update(g.read())
     e = rec.get(name)
