@@ -25,14 +25,19 @@ Other workloads (each prints its own line):
            the adjoint/forward time ratio.
 
 Every input is resident on the GPU before the timed region.  The value counts
-Chebyshev recurrence steps applied to one vector: a moment step, an evolution
-term and a velocity application count 1, a fused evolution + commutator term
-2 (two chains), a reverse (adjoint) step 1; a step on a block of B vectors
-counts B.
+Chebyshev recurrence steps on one vector as the plain recurrence of the method
+needs them for the same results: a set of M moments counts M - 1, an evolution
+term and a velocity application 1, a fused evolution + commutator term 2 (two
+chains), a reverse (adjoint) step 1; a step on a block of B vectors counts B.
+The library computes a moment set with the Chebyshev product identities in
+about half those launches; config.launched_steps_per_s gives the rate of the
+steps actually launched.
 
-Also reported: the roofline of the dominant kernel (the moment step) from HIP
-events around the DOS moment call of every timed step, and the CPU oracle
-timed on a bounded sample of the same recurrence.
+Also reported: per kernel family, launches, average launch time and the
+bandwidth its algorithmic bytes imply, from HIP events the library records on
+its own stream around every run of launches of that family in the timed
+region (gpuqt_set_timing); the roofline line is the family with the most
+time.  And the CPU oracle timed on a bounded sample of the same recurrence.
 """
 import argparse
 import json
@@ -48,27 +53,74 @@ METRIC = "Chebyshev H·psi steps/s, HBM GB/s %peak; batched & adjoint vs plain @
 HBM_PEAK_GBS = 8000.0
 
 
-def moment_step_bytes(info, B):
-    """Algorithmic HBM bytes of one moment-step launch (gathers counted once).
+# vector bytes per row and block column of one launch of each kernel family (16-byte complex
+# elements, each stream counted once): gathered inputs, v_{n-2} reads, outputs, dot partners
+# and series accumulators (read + write)
+FAMILY_VECTOR_BYTES = {
+    "moment": 64,        # x (gathered), v_{n-2}, v_n, phi_L
+    "moment_sym": 48,    # x (gathered, also the dot partner), v_{n-2}, v_n
+    "moment_pair": 96,   # two chains: 2 x (gathered), 2 v_{n-2}, 2 v_n
+    "evolve": 80,        # x, v_{n-2}, v_n, accumulator read + write
+    "msd": 160,          # two chains as moment_pair + two accumulators read + write
+}
+FAMILY_KERNEL = {"moment": "k_moment_step", "moment_sym": "k_moment_step_sym",
+                 "moment_pair": "k_moment_step_pair", "evolve": "k_evolve_term", "msd": "k_msd_term"}
 
-    Per row: neighbour indices 4 B/entry, hoppings 0 (one value per segment),
-    8 (real) or 16 (complex) B/entry, on-site term 8 B, and 4 vector streams of
-    16*B B (gathered v_{n-1}, v_{n-2}, phi_L, written v_n); per slice the 8-byte
-    slice offset.
+
+def family_bytes(info, B, family="moment"):
+    """Algorithmic HBM bytes of one launch of a sparse kernel family (gathers counted once).
+
+    Matrix part, per stored entry: neighbour index 4 B, hopping 0 (one value per segment),
+    8 (real) or 16 (complex) B, plus the position difference 8 B for the commutator
+    chain; per row the on-site term 8 B; per slice the 8-byte slice offset.  Vector part:
+    FAMILY_VECTOR_BYTES per row and block column.
     """
     hop_b = {0: 0, 1: 8, 2: 16}[int(info.hop_mode)]
     n = int(info.n)
-    return int(info.nnz) * (4 + hop_b) + n * 8 + n * 64 * B + int(info.n_slices) * 8
+    per_entry = 4 + hop_b + (8 if family == "msd" else 0)
+    return int(info.nnz) * per_entry + n * 8 + int(info.n_slices) * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 
-def count_steps(M, dts, np_list, vac=True, msd=True):
-    """Chebyshev H*psi steps of one vector's DOS (+ VAC) (+ MSD) calculation."""
+def moment_step_bytes(info, B):
+    """Algorithmic HBM bytes of one plain moment-step launch."""
+    return family_bytes(info, B, "moment")
+
+
+def kernel_table(info, B, fam, elapsed_s):
+    """Per family: launches, average launch time (event time of its runs / launches; the
+    runs are back-to-back launches, so this includes the small gaps between them),
+    algorithmic bytes per launch and the bandwidth they imply.  Returns (table, dominant
+    family = the one with the most time)."""
+    table = {}
+    for f, (ms, nl) in fam.items():
+        if nl <= 0:
+            continue
+        avg = ms / 1e3 / nl
+        b = family_bytes(info, B, f)
+        table[f] = {"kernel": FAMILY_KERNEL[f], "launches": nl, "total_ms": ms,
+                    "share_of_elapsed": ms / 1e3 / elapsed_s, "avg_us": avg * 1e6,
+                    "bytes_per_launch": b, "GBs": b / avg / 1e9}
+    dominant = max(table, key=lambda f: table[f]["total_ms"])
+    return table, dominant
+
+
+def count_steps(M, dts, np_list, vac=True, msd=True, applied=False):
+    """Chebyshev H*psi steps of one vector's DOS (+ VAC) (+ MSD) calculation.
+
+    applied=False: as the plain recurrence of the method counts them (a set of M moments
+    is M - 1 steps), the unit of the reported throughput.  applied=True: the steps the
+    library actually launches, where a Hermitian moment set takes max(1, M // 2) steps
+    and an off-diagonal one two chains of max(1, M // 2) steps (product identities).
+    """
     n_t = len(dts)
-    total = M - 1
+    K = max(1, M // 2)
+    mom_sym = K if applied else M - 1
+    mom_pair = 2 * K if applied else M - 1
+    total = mom_sym
     if vac:
-        total += 1 + n_t * (1 + (M - 1)) + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))
+        total += 1 + n_t * (1 + mom_pair) + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))
     if msd:
-        total += sum(2 * (np_list[k] - 1) for k in range(n_t)) + n_t * (M - 1)
+        total += sum(2 * (np_list[k] - 1) for k in range(n_t)) + n_t * mom_sym
     return total
 
 
@@ -141,48 +193,47 @@ def transport_workload(args, name):
     mu = torch.empty((1, B, M), dtype=torch.complex128, device=dev)
     vac = torch.empty((len(dts), 1, B, M), dtype=torch.float64, device=dev)
     msd = torch.empty_like(vac)
-    ev = []
 
-    def one_step(phi, record):
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
+    def one_step(phi):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
-        if record:
-            e1.record()
-            ev.append((e0, e1))
         if do_vac:
             P.gpuqt_vac(H, phi, dts, M, 0, out=vac, ws=ws)
         P.gpuqt_msd(H, phi, dts, M, 0, out=msd, ws=ws)
 
     log("setup done (%d orbitals, B=%d)" % (m.n, B))
     for i in range(args.warmup):
-        one_step(phis[i], False)
+        one_step(phis[i])
     torch.cuda.synchronize()
     log("warmup done")
+    P.gpuqt_set_timing(H, True)       # HIP events around each run of one kernel family
     t0 = time.perf_counter()
     for i in range(args.steps):
-        one_step(phis[args.warmup + i], True)
+        one_step(phis[args.warmup + i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    P.gpuqt_set_timing(H, False)
     log("timed steps done")
+    fam = P.gpuqt_timing(H)
 
     steps_per = count_steps(M, dts, np_list, do_vac, True) * B
-    launch_s = np.mean([a.elapsed_time(b) for a, b in ev]) / 1e3 / (M - 1)   # M-1 steps per DOS call
-    bytes_launch = moment_step_bytes(H.info, B)
-    achieved = bytes_launch / launch_s / 1e9
+    applied_per = count_steps(M, dts, np_list, do_vac, True, applied=True) * B
+    kernels, dominant = kernel_table(H.info, B, fam, elapsed)
+    d = kernels[dominant]
     out = dict(value=steps_per * args.steps / elapsed, ms_per_step=elapsed / args.steps * 1e3,
                config={"workload": desc + ", Np=auto (%d)" % np_list[0], "orbitals": int(m.n), "block": B,
                        "moments": M, "time_steps": len(dts), "cheb_steps_per_step": steps_per,
+                       "launched_steps_per_step": applied_per,
+                       "launched_steps_per_s": applied_per * args.steps / elapsed,
                        "steps_timed": args.steps},
-               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": measured_traffic(name, bytes_launch),
-                         "kernel": "k_moment_step (B=%d, hop mode %d, K=%d, variant %d)"
-                                   % (B, H.info.hop_mode, H.info.uniform_width, H.info.kernel_variant),
-                         "autotune_us_per_step": [float(t) for t in tune_us],
-                         "bytes_per_launch": bytes_launch, "avg_launch_us": launch_s * 1e6})
+               roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": d["GBs"] / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(name, dominant, d["bytes_per_launch"]),
+                         "kernel": "%s (B=%d, hop mode %d, K=%d, variant %d)"
+                                   % (FAMILY_KERNEL[dominant], B, H.info.hop_mode, H.info.uniform_width,
+                                      H.info.kernel_variant),
+                         "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+                         "autotune_us_per_step": [float(t) for t in tune_us]},
+               kernels=kernels)
     del ws
     out["roofline"]["copy_probe_GBs"] = copy_probe_gbs(P, torch, dev)
     out["cpu_baseline"] = None if args.no_cpu else cpu_oracle_sample(m, phis_np[0], dE, B, args.cpu_moments)
@@ -192,9 +243,9 @@ def transport_workload(args, name):
 KERNEL_SOURCES = ("device_common.h", "internal.h", "kernels.hip")   # what the moment step is built from
 
 
-def measured_traffic(name, bytes_launch):
-    """HBM bytes per moment-step launch from the committed counter summary, if it was taken
-    on the kernel source that is built now (else None)."""
+def measured_traffic(name, family, bytes_launch):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
+    was taken on that kernel family and on the kernel source that is built now (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -207,7 +258,7 @@ def measured_traffic(name, bytes_launch):
         with open(os.path.join(src, fn), "rb") as g:
             h.update(g.read())
     e = rec.get(name)
-    if not e or e.get("kernel_source_sha256") != h.hexdigest():
+    if not e or e.get("kernel_source_sha256") != h.hexdigest() or e.get("family") != family:
         return None
     return {"bytes": e["bytes_per_launch"], "ratio_to_algorithmic": e["bytes_per_launch"] / bytes_launch,
             "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"]}
@@ -236,13 +287,15 @@ def batched_workload(args):
     for _ in range(args.warmup):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
     torch.cuda.synchronize()
+    P.gpuqt_set_timing(H, True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    block_launch_s = elapsed / args.steps / (M - 1)
-    bytes_launch = moment_step_bytes(H.info, B)
+    P.gpuqt_set_timing(H, False)
+    kernels, dominant = kernel_table(H.info, B, P.gpuqt_timing(H), elapsed)
+    d = kernels[dominant]
     # the same moments one vector at a time (B = 1): two vectors, same M
     H1 = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
                          seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
@@ -259,18 +312,20 @@ def batched_workload(args):
     torch.cuda.synchronize()
     plain_vs = 2 * (M - 1) / (time.perf_counter() - t1)
     value = B * (M - 1) * args.steps / elapsed
-    achieved = bytes_launch / block_launch_s / 1e9
     return dict(value=value, ms_per_step=elapsed / args.steps * 1e3,
                 config={"workload": "8 square realisations 200^2..2000^2 (8,255,182 orbitals), W_r in [0.5,3], "
                                     "per-realisation DeltaE, block of 16 vectors, M=2000, one launch per step",
                         "orbitals": int(H.n), "block": B, "moments": M, "segments": H.n_segments,
                         "steps_timed": args.steps},
-                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                          "kernel": "k_moment_step (B=16, hop mode %d, K=%d, variant %d)"
-                                    % (H.info.hop_mode, H.info.uniform_width, H.info.kernel_variant),
-                          "bytes_per_launch": bytes_launch, "avg_launch_us": block_launch_s * 1e6,
+                roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": d["GBs"] / HBM_PEAK_GBS,
+                          "traffic": measured_traffic("batched", dominant, d["bytes_per_launch"]),
+                          "kernel": "%s (B=16, hop mode %d, K=%d, variant %d)"
+                                    % (FAMILY_KERNEL[dominant], H.info.hop_mode, H.info.uniform_width,
+                                       H.info.kernel_variant),
+                          "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
                           "autotune_us_per_step": [float(t) for t in tune_us]},
+                kernels=kernels,
                 batched_vs_plain={"plain_vector_steps_per_s": plain_vs, "batched_vector_steps_per_s": value,
                                   "speedup": value / plain_vs,
                                   "plain_autotune_us": [float(t) for t in tune1]},

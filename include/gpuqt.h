@@ -292,6 +292,27 @@ gpuqt_status gpuqt_kpm_reconstruct_adjoint(int32_t R, int32_t M, const double *g
                                            const double *energies, double energy_max, double volume,
                                            int32_t jackson, double *out, void *stream);
 
+/* Measurement: kernel families whose runs of launches gpuqt_timing reports. */
+enum {
+  GPUQT_K_MOMENT = 0,       /* plain moment step (recomputation, autotuning) */
+  GPUQT_K_MOMENT_SYM = 1,   /* moment step of a Hermitian set (phiL = phiR) */
+  GPUQT_K_MOMENT_PAIR = 2,  /* moment step with two chains (phiL != phiR) */
+  GPUQT_K_EVOLVE = 3,       /* evolution series term */
+  GPUQT_K_MSD = 4,          /* fused evolution + commutator series term */
+  GPUQT_K_COUNT = 5
+};
+
+/* enable != 0: every later compute call on the handle records a HIP event before and after
+ * each uninterrupted run of launches of one kernel family, on the call's stream (calls on a
+ * stream that is being captured into a graph record nothing).  The events are released by
+ * gpuqt_timing or gpuqt_destroy_h.  Not thread-safe: one host thread per handle. */
+gpuqt_status gpuqt_set_timing(gpuqt_h h, int32_t enable);
+
+/* Waits for the recorded events and returns, per family, the summed milliseconds of its
+ * runs (ms[GPUQT_K_COUNT], HOST) and the number of launches they held
+ * (launches[GPUQT_K_COUNT], HOST); then forgets the records. */
+gpuqt_status gpuqt_timing(gpuqt_h h, double *ms, int64_t *launches);
+
 /* Host helpers (no device use). */
 
 /* Jackson damping g_n, n < M (Section 3.3):  g_n = (1 - n a) cos(pi n a) + a sin(pi n a) cot(pi a),

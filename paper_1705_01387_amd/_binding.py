@@ -101,6 +101,8 @@ _SIGS = {
                                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                                        ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
                                                        ctypes.c_void_p]),
+    "gpuqt_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "gpuqt_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_update_h_values": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p]),
     "gpuqt_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
@@ -466,6 +468,21 @@ def gpuqt_kpm_reconstruct_adjoint(g, energies, M: int, energy_max: float, volume
                                                float(volume), 1 if jackson else 0, _ptr(out),
                                                _stream(stream)), "gpuqt_kpm_reconstruct_adjoint")
     return out
+
+
+K_FAMILIES = ("moment", "moment_sym", "moment_pair", "evolve", "msd")
+
+
+def gpuqt_set_timing(H: Hamiltonian, enable: bool = True):
+    _check(lib().gpuqt_set_timing(H.handle, 1 if enable else 0), "gpuqt_set_timing")
+
+
+def gpuqt_timing(H: Hamiltonian) -> dict:
+    """{family: (total ms, launches)} of the runs recorded since the last call."""
+    ms = np.zeros(len(K_FAMILIES))
+    n = np.zeros(len(K_FAMILIES), dtype=np.int64)
+    _check(lib().gpuqt_timing(H.handle, _ptr(ms), _ptr(n)), "gpuqt_timing")
+    return {f: (float(ms[i]), int(n[i])) for i, f in enumerate(K_FAMILIES)}
 
 
 def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=None):

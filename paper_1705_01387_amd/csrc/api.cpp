@@ -56,10 +56,10 @@ WsLayout ws_layout(const Handle* h, int nv, int B, int64_t part_rows, int64_t ld
 
 int op_vectors(int op) {
   switch (op) {
-    case GPUQT_OP_MOMENTS: return 2;
+    case GPUQT_OP_MOMENTS: return 4;
     case GPUQT_OP_EVOLVE: return 2;
     case GPUQT_OP_EVOLVE_COMMUTATOR: return 5;
-    case GPUQT_OP_VAC: return 7;
+    case GPUQT_OP_VAC: return 9;
     case GPUQT_OP_MSD: return 9;
     case GPUQT_OP_MOMENTS_BACKWARD: return 6;
     case GPUQT_OP_AUTOTUNE: return 3;
@@ -129,11 +129,85 @@ int class_stride(int n_class) { return n_class <= 1 ? 1 : (n_class <= 2 ? 2 : 4)
 // sequencing helpers (enqueue only; arguments already checked)
 // ---------------------------------------------------------------------------
 
-// M moments into part rows 0..M-1 using buffers A, Bf.
+// partial rows a moment call needs (the symmetric form writes up to row M)
+int moment_rows(int M) { return std::max(M + 1, 3); }
+
+// Opt-in timing: events around a run of `launches` launches of one family.
+struct TimeScope {
+  const Handle* h;
+  hipStream_t s;
+  Handle::TimingRec rec{};
+  bool on = false;
+  TimeScope(const Handle* hh, hipStream_t ss, int family, int64_t launches) : h(hh), s(ss) {
+    if (!h->timing || launches <= 0) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    rec.family = family;
+    rec.launches = launches;
+    if (hipEventCreate(&rec.a) != hipSuccess) return;
+    if (hipEventCreate(&rec.b) != hipSuccess) {
+      (void)hipEventDestroy(rec.a);
+      return;
+    }
+    on = hipEventRecord(rec.a, s) == hipSuccess;
+  }
+  ~TimeScope() {
+    if (!on) return;
+    if (hipEventRecord(rec.b, s) == hipSuccess) {
+      h->timing_recs.push_back(rec);
+    } else {
+      (void)hipEventDestroy(rec.a);
+      (void)hipEventDestroy(rec.b);
+    }
+  }
+};
+
+// M moments into part rows 0..M-1 using buffers A, Bf.  sym (phiL = phiR):
+// ceil((M-1)/2) steps of k_moment_step_sym leave raw dots that the reduction
+// in symmetric mode turns into the moments.
 gpuqt_status run_moments(const Handle* h, int B, const double2* phiL, const double2* phiR, int M,
-                         double2* part, double2* A, double2* Bf, hipStream_t s) {
+                         double2* part, double2* A, double2* Bf, hipStream_t s, bool sym = false,
+                         double2* A2 = nullptr, double2* B2 = nullptr) {
   const DevMat D = h->view();
   const int64_t row = (int64_t)h->G * B;
+  if (A2) {   // pair: chains phiL (A, Bf) and phiR (A2, B2), product identities
+    const int K = std::max(1, M / 2);
+    TimeScope ts(h, s, 2, K);
+    ChainIO io{phiL, nullptr, A, phiR, nullptr, A2, 1, 1};
+    HIP_TRY(launch_moment_step_pair(D, h->hop_mode, B, io, part, part + row, part + 2 * row, s));
+    const double2 *pa = phiL, *pb = phiR;
+    double2 *ca = A, *cb = A2;
+    for (int k = 2; k <= K; ++k) {
+      double2* oa = (pa == phiL) ? Bf : const_cast<double2*>(pa);
+      double2* ob = (pb == phiR) ? B2 : const_cast<double2*>(pb);
+      ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
+      HIP_TRY(launch_moment_step_pair(D, h->hop_mode, B, st, part + row * (2 * k - 1), nullptr,
+                                      part + row * (2 * k), s));
+      pa = ca;
+      pb = cb;
+      ca = oa;
+      cb = ob;
+    }
+    return GPUQT_OK;
+  }
+  if (sym) {
+    const int K = std::max(1, M / 2);   // ceil((M-1)/2), at least the first step
+    TimeScope ts(h, s, 1, K);
+    StepIO io{phiR, nullptr, A, 1};
+    HIP_TRY(launch_moment_step_sym(D, h->hop_mode, B, io, part, part + row, part + 2 * row, s));
+    const double2* prev = phiR;
+    double2* cur = A;
+    for (int k = 2; k <= K; ++k) {
+      double2* out = (prev == phiR) ? Bf : const_cast<double2*>(prev);
+      StepIO st{cur, prev, out, 0};
+      HIP_TRY(launch_moment_step_sym(D, h->hop_mode, B, st, part + row * (2 * k - 1), nullptr,
+                                     part + row * (2 * k), s));
+      prev = cur;
+      cur = out;
+    }
+    return GPUQT_OK;
+  }
+  TimeScope ts(h, s, 0, std::max(1, M - 1));
   StepIO io{phiR, nullptr, A, 1};
   HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, phiL, part + row, part, s));
   const double2* prev = phiR;
@@ -173,6 +247,7 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
       HIP_TRY(launch_scale(D, B, psi_in, psi_out, Jtab, Np, s));
       return GPUQT_OK;
     }
+    TimeScope ts(h, s, 3, Np - 1);
     StepIO io{psi_in, nullptr, aA, 1};
     HIP_TRY(launch_evolve_term(D, h->hop_mode, B, io, psi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
     const double2* prev = psi_in;
@@ -196,6 +271,7 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
     HIP_TRY(launch_scale(D, B, b0, chi_out, Jtab, Np, s));
     return GPUQT_OK;
   }
+  TimeScope ts(h, s, 4, Np - 1);
   ChainIO io{psi_in, nullptr, aA, b0, nullptr, bA, 1, 1};
   HIP_TRY(launch_msd_term(D, h->hop_mode, B, io, psi_out, chi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
   const double2 *pa = psi_in, *pb = b0;
@@ -408,6 +484,10 @@ void gpuqt_destroy_h(gpuqt_h hh) {
                   h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto& r : h->timing_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   delete h;
 }
 
@@ -513,7 +593,7 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
                            op == GPUQT_OP_MOMENTS_BACKWARD;
   const bool has_J = op == GPUQT_OP_EVOLVE || op == GPUQT_OP_EVOLVE_COMMUTATOR ||
                      op == GPUQT_OP_VAC || op == GPUQT_OP_MSD;
-  const int64_t rows = has_moments ? std::max(M, 2) : 0;
+  const int64_t rows = has_moments ? moment_rows(M) : 0;
   const int64_t ldJ = has_J ? (Np > 0 ? Np : kAutoNpCap) : 0;
   if (op == GPUQT_OP_MOMENTS_BACKWARD) {
     const int s = backward_stride(M, Np);
@@ -534,7 +614,7 @@ gpuqt_status gpuqt_moments(gpuqt_h hh, int32_t B, const double* phiL, const doub
   gpuqt_status st;
   if ((st = check_vec(phiL, "phiL")) || (st = check_vec(phiR, "phiR")) || (st = check_vec(mu, "mu")))
     return st;
-  const WsLayout W = ws_layout(h, 2, B, std::max(M, 2), 0);
+  const WsLayout W = ws_layout(h, 4, B, moment_rows(M), 0);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -543,10 +623,13 @@ gpuqt_status gpuqt_moments(gpuqt_h hh, int32_t B, const double* phiL, const doub
   double2* A = reinterpret_cast<double2*>(base);
   double2* Bf = reinterpret_cast<double2*>(base + W.vec_bytes);
   double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  const bool sym = phiL == phiR;   // Hermitian set: product identities, half the steps
   if ((st = run_moments(h, B, reinterpret_cast<const double2*>(phiL),
-                        reinterpret_cast<const double2*>(phiR), M, part, A, Bf, s)))
+                        reinterpret_cast<const double2*>(phiR), M, part, A, Bf, s, sym,
+                        sym ? nullptr : reinterpret_cast<double2*>(base + 2 * W.vec_bytes),
+                        sym ? nullptr : reinterpret_cast<double2*>(base + 3 * W.vec_bytes))))
     return st;
-  HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0,
+  HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1,   // raw dots, both forms
                                 reinterpret_cast<double2*>(mu), nullptr, s));
   return GPUQT_OK;
 }
@@ -628,7 +711,7 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   if (st) return st;
   if (n_t == 0 || M == 0) return GPUQT_OK;
   const int np = max_terms(h, n_t - 1, dt, Np);
-  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_VAC), B, std::max(M, 2), np);
+  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_VAC), B, moment_rows(M), np);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -649,8 +732,8 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   const int64_t row = (int64_t)h->n_seg * B * M;
   for (int k = 0; k < n_t; ++k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, phiL, s));
-    if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s))) return st;
-    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, nullptr, out + row * k, s));
+    if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s, false, V(7), V(8)))) return st;
+    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1, nullptr, out + row * k, s));
     if (k + 1 < n_t) {
       const int np_k = terms_for(h, dt[k], Np);
       double2* Ln = (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
@@ -676,7 +759,7 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   if (st) return st;
   if (n_t == 0 || M == 0) return GPUQT_OK;
   const int np = max_terms(h, n_t, dt, Np);
-  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_MSD), B, std::max(M, 2), np);
+  const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_MSD), B, moment_rows(M), np);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -697,8 +780,8 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
     double2* Cn = Cbuf[pi];
     if ((st = run_evolve(h, B, dt[k], np_k, psi, Pn, chi, Cn, V(4), V(5), V(6), V(7), V(8), J, s)))
       return st;
-    if ((st = run_moments(h, B, Cn, Cn, M, part, V(4), V(5), s))) return st;
-    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, nullptr, out + row * k, s));
+    if ((st = run_moments(h, B, Cn, Cn, M, part, V(4), V(5), s, true))) return st;
+    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1, nullptr, out + row * k, s));
     psi = Pn;
     chi = Cn;
     pi ^= 1;
@@ -913,6 +996,40 @@ gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double* C, int32_
   HIP_TRY(launch_kpm(R, M, C, n_E, energies, 1.0 / energy_max, pref, jackson ? 1 : 0, out,
                      static_cast<hipStream_t>(stream)));
   return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_set_timing(gpuqt_h hh, int32_t enable) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  h->timing = enable != 0;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_timing(gpuqt_h hh, double* ms, int64_t* launches) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h || !ms || !launches) return fail(GPUQT_ERR_ARG, "NULL argument");
+  for (int f = 0; f < GPUQT_K_COUNT; ++f) {
+    ms[f] = 0.0;
+    launches[f] = 0;
+  }
+  gpuqt_status st = GPUQT_OK;
+  for (auto& r : h->timing_recs) {
+    float t = 0.0f;
+    if (st == GPUQT_OK) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+      if (e != hipSuccess) {
+        st = fail(GPUQT_ERR_HIP, std::string("timing events: ") + hipGetErrorString(e));
+      } else {
+        ms[r.family] += t;
+        launches[r.family] += r.launches;
+      }
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  h->timing_recs.clear();
+  return st;
 }
 
 gpuqt_status gpuqt_kpm_reconstruct_adjoint(int32_t R, int32_t M, const double* g, int32_t n_E,

@@ -85,6 +85,14 @@ struct Handle {
   double* d_bound = nullptr;
   std::vector<double> seg_hop0;
   std::vector<double> class_scale;
+  // opt-in timing (gpuqt_set_timing): event pairs around runs of one kernel family
+  struct TimingRec {
+    int family;
+    hipEvent_t a, b;
+    int64_t launches;
+  };
+  bool timing = false;
+  mutable std::vector<TimingRec> timing_recs;
 
   DevMat view() const {
     DevMat m;
@@ -242,9 +250,25 @@ hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, i
 //   workgroups of seg in increasing order (tree inside one workgroup).
 //   mode 0: complex out[(seg*B + b)*M + k];
 //   mode 1: real part into out_real[(seg*B + b)*M + k].
+//   sym: the rows hold raw dots of launch_moment_step_sym; moment k >= 2 is
+//   2 row_k - moment_{k mod 2}.
 hipError_t launch_reduce_moments(const double2* part, int M, int G, int B, int n_seg,
-                                 const int32_t* seg_blk0_dev, double2* out, double* out_real,
+                                 const int32_t* seg_blk0_dev, int sym, double2* out, double* out_real,
                                  hipStream_t s);
+
+// Moment step of a Hermitian set (phiL = phiR = v_0) by the product identities
+// T_{2k} = 2 T_k^2 - T_0 and T_{2k-1} = 2 T_k T_{k-1} - T_1: writes the raw
+// per-workgroup dots <v_k|v_{k-1}> to part_a and <v_k|v_k> to part_c; the first
+// step writes <v_0|v_0> to part_a, <v_0|v_1> to part_b and <v_1|v_1> to part_c.
+hipError_t launch_moment_step_sym(const DevMat& A, int hop_mode, int B, const StepIO& io,
+                                  double2* part_a, double2* part_b, double2* part_c, hipStream_t s);
+
+// The same for <a|T_n|b>, a != b: chains a (xa, wa -> oa) and b (xb, wb -> ob)
+// advance together; raw dots <a_k|b_{k-1}> -> part_a, <a_k|b_k> -> part_c, and on
+// the first step <a|b> -> part_a, <a|b_1> -> part_b, <a_1|b_1> -> part_c.
+struct ChainIO;
+hipError_t launch_moment_step_pair(const DevMat& A, int hop_mode, int B, const ChainIO& io,
+                                   double2* part_a, double2* part_b, double2* part_c, hipStream_t s);
 
 // out[r][e] = pref_base / sqrt(1 - x^2) * sum_n g_n (2 - delta_n0) T_n(x) C[r][n],
 // x = E[e] * inv_dE (NaN where |x| >= 1).

@@ -79,6 +79,100 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
 }
 
 // ---------------------------------------------------------------------------
+// Moment step for a Hermitian moment set (phiL = phiR = v_0): the same
+// recurrence, but the moments come from the product identities
+//   T_{2k} = 2 T_k T_k - T_0,   T_{2k-1} = 2 T_k T_{k-1} - T_1,
+// so step k yields the raw dots <v_k|v_{k-1}> (row 2k-1) and <v_k|v_k>
+// (row 2k); the first step also <v_0|v_0> (row 0) and <v_0|v_1> (row 1).
+// k_reduce turns raw rows n >= 2 into 2 raw_n - mu_{n mod 2}.  Half the
+// steps of the plain recurrence, and no phi_L stream.
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K, bool NT>
+__global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
+                                                            double2* __restrict__ part_a,
+                                                            double2* __restrict__ part_b,
+                                                            double2* __restrict__ part_c) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const int b = threadIdx.x & (B - 1);
+  const double2* __restrict__ x = io.x;
+  const double2* __restrict__ w = io.w;
+  double2* __restrict__ out = io.out;
+  const bool first = io.first;
+  // first: a = <v0|v0>, b = <v0|v1>, c = <v1|v1>;  else: a = <vk|vk-1>, c = <vk|vk>
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
+  for_rows<B>(P, [&](int64_t r) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
+    const int64_t idx = r * B + b;
+    const double2 y = first ? ha : twice_minus(ha, ld2<NT>(w + idx));
+    out[idx] = y;
+    const double2 xr = x[idx];
+    if (first) {
+      cdot_acc(ar, ai, xr, xr);
+      cdot_acc(br, bi, xr, y);
+    } else {
+      cdot_acc(ar, ai, y, xr);
+    }
+    cdot_acc(cr, ci, y, y);
+  });
+  block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
+  __syncthreads();
+  block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
+  if (first) {
+    __syncthreads();
+    block_reduce_store<B>(br, bi, part_b + (int64_t)lb * B);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moment step for <a|T_n|b> with a != b: both chains a_k = T_k a, b_k = T_k b
+// advance in one launch (one matrix read, the two gathers share the indices)
+// and the identities give
+//   <a|T_{2k}|b> = 2 <a_k|b_k> - <a|b>,  <a|T_{2k-1}|b> = 2 <a_k|b_{k-1}> - <a|T_1 b>,
+// so step k yields <a_k|b_{k-1}> (row 2k-1) and <a_k|b_k> (row 2k); the first
+// step also <a|b> (row 0) and <a|b_1> (row 1).
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K, bool NT>
+__global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO io,
+                                                             double2* __restrict__ part_a,
+                                                             double2* __restrict__ part_b,
+                                                             double2* __restrict__ part_c) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const int b = threadIdx.x & (B - 1);
+  const bool first = io.first;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
+  for_rows<B>(P, [&](int64_t r) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
+    const int64_t idx = r * B + b;
+    const double2 ya = first ? ha : twice_minus(ha, ld2<NT>(io.wa + idx));
+    const double2 yb = first ? hb : twice_minus(hb, ld2<NT>(io.wb + idx));
+    io.oa[idx] = ya;
+    io.ob[idx] = yb;
+    const double2 xb = io.xb[idx];
+    if (first) {
+      const double2 xa = io.xa[idx];
+      cdot_acc(ar, ai, xa, xb);
+      cdot_acc(br, bi, xa, yb);
+    } else {
+      cdot_acc(ar, ai, ya, xb);
+    }
+    cdot_acc(cr, ci, ya, yb);
+  });
+  block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
+  __syncthreads();
+  block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
+  if (first) {
+    __syncthreads();
+    block_reduce_store<B>(br, bi, part_b + (int64_t)lb * B);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One term m of U(dt) psi = sum_m c_m T_m(H~) psi (Section 3.2):
 // a_m by the recurrence, acc += c_m a_m; c_m = J[seg][m] * phase_m with the
 // table holding (2 - delta_m0) J_m(DeltaE_seg |dt|).
@@ -213,15 +307,9 @@ __global__ void k_bessel_table(const double* __restrict__ seg_dE, int n_seg, dou
   for (int m = 1; m < Np; ++m) row[m] *= 2.0;
 }
 
-// One wavefront per (moment k, segment*B + b): sum the segment's workgroup
-// partials in a fixed order.
-__global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part, int M, int G, int B,
-                                               const int32_t* __restrict__ seg_blk0,
-                                               double2* __restrict__ out, double* __restrict__ out_real) {
-  const int k = blockIdx.x;
-  const int sb = blockIdx.y;
-  const int seg = sb / B, b = sb - seg * B;
-  const int g0 = seg_blk0[seg], g1 = seg_blk0[seg + 1];
+// Sum of one partial row over the segment's workgroups, fixed order.
+__device__ __forceinline__ double2 reduce_row(const double2* __restrict__ part, int k, int G, int B, int b,
+                                              int g0, int g1) {
   double re = 0.0, im = 0.0;
   for (int g = g0 + (int)threadIdx.x; g < g1; g += 64) {
     const double2 v = part[((int64_t)k * G + g) * B + b];
@@ -232,6 +320,26 @@ __global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part,
   for (int off = 32; off >= 1; off >>= 1) {
     re += __shfl_xor(re, off);
     im += __shfl_xor(im, off);
+  }
+  return make_double2(re, im);
+}
+
+// One wavefront per (moment k, segment*B + b): sum the segment's workgroup
+// partials in a fixed order.  sym: rows hold the raw dots of
+// k_moment_step_sym, and moment k >= 2 is 2 raw_k - mu_{k mod 2}.
+__global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part, int M, int G, int B,
+                                               const int32_t* __restrict__ seg_blk0, int sym,
+                                               double2* __restrict__ out, double* __restrict__ out_real) {
+  const int k = blockIdx.x;
+  const int sb = blockIdx.y;
+  const int seg = sb / B, b = sb - seg * B;
+  const int g0 = seg_blk0[seg], g1 = seg_blk0[seg + 1];
+  const double2 v = reduce_row(part, k, G, B, b, g0, g1);
+  double re = v.x, im = v.y;
+  if (sym && k >= 2) {
+    const double2 u = reduce_row(part, k & 1, G, B, b, g0, g1);
+    re = 2.0 * re - u.x;
+    im = 2.0 * im - u.y;
   }
   if (threadIdx.x == 0) {
     const int64_t o = (int64_t)sb * M + k;
@@ -376,11 +484,27 @@ hipError_t launch_bessel_table(const double* seg_dE, int n_seg, double abs_dt, i
 }
 
 hipError_t launch_reduce_moments(const double2* part, int M, int G, int B, int n_seg,
-                                 const int32_t* seg_blk0_dev, double2* out, double* out_real,
+                                 const int32_t* seg_blk0_dev, int sym, double2* out, double* out_real,
                                  hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  k_reduce<<<dim3(M, n_seg * B), 64, 0, s>>>(part, M, G, B, seg_blk0_dev, out, out_real);
+  k_reduce<<<dim3(M, n_seg * B), 64, 0, s>>>(part, M, G, B, seg_blk0_dev, sym, out, out_real);
   return hipGetLastError();
+}
+
+hipError_t launch_moment_step_pair(const DevMat& A, int hop_mode, int B, const ChainIO& io,
+                                   double2* part_a, double2* part_b, double2* part_c, hipStream_t s) {
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_moment_step_pair<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value,
+                       decltype(NTc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, io, part_a, part_b, part_c);
+  });
+}
+
+hipError_t launch_moment_step_sym(const DevMat& A, int hop_mode, int B, const StepIO& io,
+                                  double2* part_a, double2* part_b, double2* part_c, hipStream_t s) {
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_moment_step_sym<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value,
+                      decltype(NTc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, io, part_a, part_b, part_c);
+  });
 }
 
 hipError_t launch_kpm(int R, int M, const double* C, int n_E, const double* E, double inv_dE,

@@ -111,6 +111,27 @@ def test_moments_B16_and_small_M(torch_cuda):
         assert err(mu, O.chebyshev_moments(Hs / dE, phi[:, :4], phi[:, :4], M).T) < TOL
 
 
+@pytest.mark.parametrize("name", ["square61x53", "honeycomb30x20_flux", "cubic13", "diag777"])
+@pytest.mark.parametrize("B", [1, 4])
+def test_moments_sym_and_pair_forms(torch_cuda, name, B):
+    """phiL and phiR the same buffer: Hermitian (product identity) form; equal values in
+    two buffers: the two-chain form; both against the plain definition for odd and even M."""
+    say(f"case: moments sym/pair {name} B={B}")
+    m = MODELS[name]()
+    H = build(m)
+    Hs, _, _ = ops(m)
+    dE = float(H.energy_max[0])
+    phi = I.random_phase(m.n, B, 15)
+    same = dev(phi)
+    for M in (1, 2, 3, 4, 5, 6, 299, 300):
+        ref = O.chebyshev_moments(Hs / dE, phi, phi, M).T
+        sym = host(P.gpuqt_moments(H, same, same, M))[0]
+        pair = host(P.gpuqt_moments(H, dev(phi), dev(phi), M))[0]
+        assert err(sym, ref) < TOL, M
+        assert err(pair, ref) < TOL, M
+        assert np.max(np.abs(sym.imag)) <= TOL * np.max(np.abs(ref)), M
+
+
 def test_moments_bit_identical_reruns(torch_cuda):
     say("case: determinism")
     m = I.honeycomb(40, 30, flux=1.0 / 400.0, W=1.0, seed=9)
