@@ -1,0 +1,106 @@
+"""GPU parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+The oracle cannot run the full workloads (hours of CPU), so each test runs the
+GPU path on the full lattice with the benchmark's block width and kernel forms
+and compares a sample the oracle computes in seconds: the first moments of
+every realisation, a few block columns (columns are independent), one time
+row.  Bar as in the other parity tests: normwise relative error <= 1e-10.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def err(got, ref):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def test_full_size_honeycomb_bench_forms(gpu):
+    """Honeycomb 2,000,000 orbitals with Peierls phases, one vector: DOS moments through the
+    Hermitian form (the same buffer as phiL and phiR, as the benchmark calls it) and VAC rows
+    t = 0 and t = 15 fs through the two-chain form, M = 32, automatic term count."""
+    say("case: full-size honeycomb, DOS sym M=48 + VAC 2 rows M=32")
+    w = I.workload_honeycomb(n_vectors=1)
+    m, dE = w["model"], w["energy_max"]
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    P.gpuqt_autotune(H, 1)
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    phi = w["phis"][0]
+    d = dev(phi)
+    mu = host(P.gpuqt_moments(H, d, d, 48))[0, 0]
+    assert err(mu, O.dos_moments(Hs, phi, dE, 48)[:, 0]) < TOL
+    dts = [float(w["dt"][0])] * 2
+    vac = host(P.gpuqt_vac(H, d, dts, 32, 0))[:, 0, 0]
+    ref = O.vac_moments(Hs, V, phi, dts, dE, 32)[:, :, 0]
+    for k in range(2):
+        assert err(vac[k], ref[k]) < TOL, k
+
+
+def test_full_size_cubic_B4_sampled(gpu):
+    """Cubic 200^3 = 8,000,000 orbitals, W = 16, block of 4: DOS moments (Hermitian form) and
+    the MSD row at t = dt = 2 (fused evolution + commutator, automatic term count) on the whole
+    block; the oracle checks columns 0 and 3."""
+    say("case: full-size cubic 200^3 B=4, DOS M=24 + MSD 1 row M=16")
+    w = I.workload_cubic(L=200, W=16.0, B=4)
+    m, dE = w["model"], w["energy_max"]
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    P.gpuqt_autotune(H, 4)
+    assert H.info.hop_mode == 0 and H.info.uniform_width == 6
+    Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    phi = w["phi"]
+    d = dev(phi)
+    mu = host(P.gpuqt_moments(H, d, d, 24))[0]                # [B, M]
+    msd = host(P.gpuqt_msd(H, d, [2.0], 16, 0))[0, 0]           # [B, M]
+    del d
+    for b in (0, 3):
+        col = phi[:, b:b + 1]
+        assert err(mu[b], O.dos_moments(Hs, col, dE, 24)[:, 0]) < TOL, b
+        assert err(msd[b], O.msd_moments(Hs, XH, col, [2.0], dE, 16)[0, :, 0]) < TOL, b
+
+
+def test_full_size_batched_B16_sampled(gpu):
+    """Eight square realisations 200^2 .. 2000^2 (8,255,182 orbitals) with per-realisation
+    DeltaE, block of 16, one launch per step: the first 16 moments of every realisation for
+    columns 0 and 15."""
+    say("case: full-size batched 8 segments B=16, DOS M=16")
+    w = I.workload_batched(B=16, M=16)
+    mods = w["models"]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
+                        seg_length_x=[mm.length_x for mm in mods])
+    P.gpuqt_autotune(H, 16)
+    d = dev(w["phi"])
+    mu = host(P.gpuqt_moments(H, d, d, 16))                    # [seg, B, M]
+    del d
+    for s, mm in enumerate(mods):
+        Hs, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
+        for b in (0, 15):
+            col = w["phi"][offs[s]:offs[s + 1], b:b + 1]
+            ref = O.dos_moments(Hs, col, float(w["seg_energy_max"][s]), 16)[:, 0]
+            assert err(mu[s, b], ref) < TOL, (s, b)

@@ -74,11 +74,13 @@ def test_moments_square64_dos(torch_cuda):
     m = w["model"]
     H = build(m, w["energy_max"])
     phi = w["phi"]
-    mu = host(P.gpuqt_moments(H, dev(phi), dev(phi), w["M"]))[0, 0]
+    d = dev(phi)
     Hs, _, _ = ops(m)
     ref = O.dos_moments(Hs, phi, w["energy_max"], w["M"])[:, 0]
-    assert err(mu, ref) < TOL
-    assert abs(mu[0].real - m.n) < 1e-9 and abs(mu[0].imag) < 1e-9
+    for mu in (host(P.gpuqt_moments(H, d, d, w["M"]))[0, 0],              # Hermitian form
+               host(P.gpuqt_moments(H, dev(phi), dev(phi), w["M"]))[0, 0]):   # two chains
+        assert err(mu, ref) < TOL
+        assert abs(mu[0].real - m.n) < 1e-9 and abs(mu[0].imag) < 1e-9
 
 
 @pytest.mark.parametrize("name", list(MODELS))
