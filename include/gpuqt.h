@@ -82,6 +82,9 @@ typedef struct {
   const double *seg_length_x;   /* NULL or [n_segments]: per-segment period (else length_x) */
   int32_t check_hermitian;      /* nonzero: require H_ji = conj(H_ij) (sums over duplicates) */
   int32_t slice_height;         /* sliced-ELL slice height: 0 = default (64), else 32..1024, 2^k */
+  int32_t band_rows;            /* rows per band of the banded row order (see gpuqt_autotune):
+                                   0 = chosen per block width; else a multiple of 64, used for
+                                   every width and every segment whose row period exceeds it */
 } gpuqt_h_desc;
 
 /*
@@ -126,8 +129,11 @@ typedef struct {
   int32_t max_width;         /* widest slice */
   int32_t uniform_width;     /* width of every slice when equal and unpadded, else 0 */
   int32_t grid_blocks;       /* workgroups per sparse-step launch */
-  int32_t kernel_variant;    /* 0: plain loads, 1: non-temporal streams (see gpuqt_autotune) */
+  int32_t kernel_variant;    /* bit 0: non-temporal streams, bit 1: banded row order (see gpuqt_autotune) */
   size_t device_bytes;       /* device memory held by the handle */
+  int64_t row_period;        /* largest detected row period D over the segments (0: none) */
+  int32_t banded_mask;       /* bit log2(B) set: block width B has a banded row order */
+  int32_t reserved;
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -261,16 +267,27 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
                                                int32_t M, int32_t Np, size_t *bytes);
 
 /*
- * Choose the sparse-kernel variant for this handle by measurement: times 24
- * Chebyshev moment steps (Section 3.2 recurrence on a scratch vector) with
- * and without non-temporal loads of the once-read streams, keeps the faster
- * variant for all later calls on the handle.  Synchronises the stream.
+ * Choose the sparse-kernel variant for this handle by measurement: times 12
+ * Hermitian moment steps (Section 3.2 recurrence on a scratch vector) of each
+ * variant and keeps the fastest for all later calls on the handle.  Variant
+ * bit 0: non-temporal loads of the once-read streams; bit 1: the banded row
+ * order (built when a segment's row period D would make the window between
+ * the first and last use of a gathered element exceed about 2.5 MiB of
+ * streamed data at this B: workgroups then sweep bands of W rows of the
+ * period one period after another, so rows D apart are visited W rows apart).
+ * Synchronises the stream.
  *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0)
- *   times_us : NULL or HOST [2], microseconds per step of variant 0 (plain) and 1 (NT).
+ *   times_us : NULL or HOST [4], microseconds per step of variants 0..3 (0 for a banded
+ *              variant when this B has no banded order).
  * Not safe while other calls on the handle are in flight.
  */
 gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
                             double *times_us);
+
+/* Set the kernel variant (0..3, bits as in gpuqt_autotune) without measuring.  The banded
+ * bit only takes effect for block widths that have a banded order (gpuqt_h_info_t.banded_mask).
+ * GPUQT_ERR_ARG for a variant outside 0..3. */
+gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*
  * KPM reconstruction (Section 3.3, same prefactor for DOS, rho*C_vv, rho*DeltaX^2):
@@ -314,6 +331,18 @@ gpuqt_status gpuqt_set_timing(gpuqt_h h, int32_t enable);
 gpuqt_status gpuqt_timing(gpuqt_h h, double *ms, int64_t *launches);
 
 /* Host helpers (no device use). */
+
+/* The row schedule of the sparse kernels, as the library plans it for `cus` compute units
+ * and block width B (introspection; the kernels enumerate rows with the same host/device
+ * rule): segments seg_offsets (HOST [n_segments+1], from 0, ascending), row period per
+ * segment (HOST [n_segments] or NULL: plain order), band width band_rows (multiple of 64;
+ * segments whose period exceeds it take the banded order).  Writes for every row the
+ * logical workgroup that visits it (block_of_row, HOST int32 [n]) and the workgroup's
+ * iteration at that visit (iter_of_row, HOST int32 [n]); -1 for a row no workgroup visits.
+ * GPUQT_ERR_LAYOUT if some row would be visited twice. */
+gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t *seg_offsets, const int64_t *period,
+                                 int32_t band_rows, int32_t cus, int32_t B, int32_t *block_of_row,
+                                 int32_t *iter_of_row);
 
 /* Jackson damping g_n, n < M (Section 3.3):  g_n = (1 - n a) cos(pi n a) + a sin(pi n a) cot(pi a),
  * a = 1/(M+1).  g: HOST [M]. */

@@ -40,7 +40,7 @@ class _Desc(ctypes.Structure):
         ("energy_max", ctypes.c_double), ("n_segments", ctypes.c_int32),
         ("seg_offsets", ctypes.c_void_p), ("seg_energy_max", ctypes.c_void_p),
         ("seg_length_x", ctypes.c_void_p), ("check_hermitian", ctypes.c_int32),
-        ("slice_height", ctypes.c_int32),
+        ("slice_height", ctypes.c_int32), ("band_rows", ctypes.c_int32),
     ]
 
 
@@ -51,7 +51,8 @@ class HInfo(ctypes.Structure):
         ("n_slices", ctypes.c_int64), ("entries", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("max_width", ctypes.c_int32), ("uniform_width", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-        ("device_bytes", ctypes.c_size_t),
+        ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
+        ("banded_mask", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,9 @@ _SIGS = {
     "gpuqt_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_set_variant": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -230,7 +234,7 @@ class Hamiltonian:
 def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1.0,
                   energy_max=0.0, hop_class=None, n_class=1, seg_offsets=None,
                   seg_energy_max=None, seg_length_x=None, check_hermitian=False,
-                  slice_height=0, stream=None) -> Hamiltonian:
+                  slice_height=0, band_rows=0, stream=None) -> Hamiltonian:
     """Build the device layout of H from a neighbour list (the paper's input files)."""
     nn = np.ascontiguousarray(nn, dtype=np.int32)
     n = nn.shape[0]
@@ -283,6 +287,7 @@ def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1
         d.seg_length_x = _ptr(sl)
     d.check_hermitian = 1 if check_hermitian else 0
     d.slice_height = int(slice_height)
+    d.band_rows = int(band_rows)
     out = ctypes.c_void_p()
     _check(lib().gpuqt_build_h(ctypes.byref(d), stream, ctypes.byref(out)), "gpuqt_build_h")
     return Hamiltonian(out.value, None)
@@ -497,14 +502,35 @@ def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=
 
 
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
-    """Time the plain and non-temporal kernel variants, keep the faster; returns us/step of each."""
-    t = np.zeros(2)
+    """Time the kernel variants (plain / non-temporal loads, plain / banded row order), keep the
+    fastest; returns us per moment step of variants 0..3 (0 where a variant does not exist)."""
+    t = np.zeros(4)
     ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
     info = HInfo()
     _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")
     H.info = info
     return t
+
+
+def gpuqt_set_variant(H: Hamiltonian, variant: int):
+    """Pin the kernel variant (bit 0: non-temporal streams, bit 1: banded row order)."""
+    _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")
+    info = HInfo()
+    _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")
+    H.info = info
+
+
+def gpuqt_schedule_rows(seg_offsets, period=None, band_rows=0, cus=256, B=1):
+    """Host-only: (workgroup, iteration) visiting each row under the library's row schedule."""
+    off = np.ascontiguousarray(seg_offsets, dtype=np.int64)
+    per = None if period is None else np.ascontiguousarray(period, dtype=np.int64)
+    n = int(off[-1])
+    blk = np.empty(n, dtype=np.int32)
+    it = np.empty(n, dtype=np.int32)
+    _check(lib().gpuqt_schedule_rows(len(off) - 1, _ptr(off), _ptr(per), int(band_rows), int(cus), int(B),
+                                     _ptr(blk), _ptr(it)), "gpuqt_schedule_rows")
+    return blk, it
 
 
 def gpuqt_copy_probe(src, dst, stream=None):

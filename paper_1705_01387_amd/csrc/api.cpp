@@ -168,7 +168,7 @@ struct TimeScope {
 gpuqt_status run_moments(const Handle* h, int B, const double2* phiL, const double2* phiR, int M,
                          double2* part, double2* A, double2* Bf, hipStream_t s, bool sym = false,
                          double2* A2 = nullptr, double2* B2 = nullptr) {
-  const DevMat D = h->view();
+  const DevMat D = h->view(B);
   const int64_t row = (int64_t)h->G * B;
   if (A2) {   // pair: chains phiL (A, Bf) and phiR (A2, B2), product identities
     const int K = std::max(1, M / 2);
@@ -238,7 +238,7 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
                         double2* psi_out, const double2* chi_in, double2* chi_out, double2* aA,
                         double2* aB, double2* bA, double2* bB, double2* zero, double* Jtab,
                         hipStream_t s) {
-  const DevMat D = h->view();
+  const DevMat D = h->view(B);
   const double sgn = dt >= 0 ? 1.0 : -1.0;
   HIP_TRY(launch_bessel_table(h->d_seg_dE, h->n_seg, std::fabs(dt), Np, Np, Jtab, s));
   const double2 ph0 = phase_pow(0, sgn);
@@ -307,7 +307,7 @@ struct BwdSource {
 gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                           const BwdSource& src, double* gU, double* gcp, int nc, double2* lam0,
                           bool acc0, int s, double2* const* vec, hipStream_t sm) {
-  const DevMat D = h->view();
+  const DevMat D = h->view(B);
   const bool grad = gU != nullptr;
   const int K = M >= 2 ? (M - 1 + s - 1) / s : 0;
   double2* const* R = vec;
@@ -439,7 +439,7 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   h->seg_dE = L.seg_dE;
   h->seg_gersh = L.seg_gersh;
   std::vector<int32_t> seg_blk0;
-  plan_blocks(L.seg_off, cus, 8, &h->plan_host, &seg_blk0);
+  plan_blocks(L.seg_off, cus, kPerCU, &h->plan_host, &seg_blk0);
   h->G = (int32_t)h->plan_host.size();
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -466,6 +466,26 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
   std::vector<double> zeros_g(h->G, 0.0);
   up((void**)&h->d_bound, zeros_g.data(), zeros_g.size() * 8);
+  // banded unit orders, per block width: the row window between the first and
+  // last use of a gathered element is 2 D rows in the plain order and 2 W in
+  // the banded one; W keeps it (with everything else the step streams per
+  // row) within kBandBudget of an XCD's L2
+  h->seg_period.assign(L.n_seg, 0);
+  for (int sg = 0; sg < L.n_seg; ++sg) h->seg_period[sg] = row_period(L, sg);
+  const int64_t hop_b = L.hop_mode == HOP_COMPLEX ? 16 : L.hop_mode == HOP_REAL ? 8 : 0;
+  std::vector<std::vector<int32_t>> unit_lists(kNumB);
+  for (int lb = 0; lb < kNumB; ++lb) {
+    const int64_t B = int64_t(1) << lb;
+    const int64_t row_bytes = (4 + hop_b) * L.max_width + 8 + 48 * B;
+    const int64_t W = desc->band_rows > 0 ? desc->band_rows
+                                          : std::max<int64_t>(256, kBandBudget / (2 * row_bytes) / 64 * 64);
+    h->band_rows[lb] = (int32_t)W;
+    bool any = false;
+    for (int sg = 0; sg < L.n_seg; ++sg) any = any || h->seg_period[sg] > W;
+    if (!any) continue;
+    banded_units(L.seg_off, h->seg_period, W, &unit_lists[lb]);
+    up((void**)&h->d_units[lb], unit_lists[lb].data(), unit_lists[lb].size() * 4);
+  }
   h->seg_hop0 = L.seg_hop;
   h->class_scale.assign(h->n_class, 1.0);
   if (ok && hipStreamSynchronize(s) != hipSuccess) ok = false;
@@ -483,6 +503,8 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
                   h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound};
   for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int32_t* p : h->d_units)
     if (p) (void)hipFree(p);
   for (auto& r : h->timing_recs) {
     (void)hipEventDestroy(r.a);
@@ -507,7 +529,12 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->uniform_width = h->uniform_width;
   info->grid_blocks = h->G;
   info->device_bytes = h->device_bytes;
-  info->kernel_variant = h->nt;
+  info->kernel_variant = h->nt | (h->banded << 1);
+  info->row_period = 0;
+  for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
+  info->banded_mask = 0;
+  for (int b = 0; b < kNumB; ++b)
+    if (h->d_units[b]) info->banded_mask |= 1 << b;
   for (int s = 0; s < h->n_seg; ++s) {
     if (energy_max) energy_max[s] = h->seg_dE[s];
     if (gershgorin) gershgorin[s] = h->seg_gersh[s];
@@ -530,7 +557,7 @@ gpuqt_status gpuqt_update_h_values(gpuqt_h hh, const double* onsite, const doubl
   gpuqt_status st;
   if ((st = check_device(h))) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const DevMat D = h->view();
+  const DevMat D = h->view(1);
   if (onsite) HIP_TRY(launch_set_onsite(D, onsite, h->d_diag, s));
   if (class_scale) {
     if (h->hop_mode == HOP_UNIFORM) {
@@ -679,7 +706,7 @@ gpuqt_status gpuqt_apply_commutator(gpuqt_h hh, int32_t B, int32_t which, const 
   if ((st = check_vec(psi, "psi")) || (st = check_vec(out, "out"))) return st;
   if (overlap(psi, out, (size_t)h->n * B * 16)) return fail(GPUQT_ERR_ARG, "psi and out overlap");
   if ((st = check_device(h))) return st;
-  HIP_TRY(launch_commutator(h->view(), h->hop_mode, B, which, reinterpret_cast<const double2*>(psi),
+  HIP_TRY(launch_commutator(h->view(B), h->hop_mode, B, which, reinterpret_cast<const double2*>(psi),
                             reinterpret_cast<double2*>(out), static_cast<hipStream_t>(stream)));
   return GPUQT_OK;
 }
@@ -720,7 +747,7 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
   double2* part = reinterpret_cast<double2*>(base + W.off_part);
   double* J = reinterpret_cast<double*>(base + W.off_J);
-  const DevMat D = h->view();
+  const DevMat D = h->view(B);
   // psi_L = phi (input, read only), psi_R = V phi
   const double2* psiL = reinterpret_cast<const double2*>(phi);
   double2* Lbuf[2] = {V(0), V(1)};
@@ -868,7 +895,7 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   auto V = [&](int i) { return reinterpret_cast<double2*>(base + W.vec_bytes * i); };
   double* gcp = reinterpret_cast<double*>(base + W.off_part);
   double* J = reinterpret_cast<double*>(base + W.off_J);
-  const DevMat D = h->view();
+  const DevMat D = h->view(B);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   const double2* ph = reinterpret_cast<const double2*>(phi);
   // states psi_L(k) (k >= 1) and psi_R(k), adjoints, scratch
@@ -956,32 +983,91 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   double2* Bf = reinterpret_cast<double2*>(base + 2 * W.vec_bytes);
   double2* part = reinterpret_cast<double2*>(base + W.off_part);
   // a unit-modulus start vector, like the random-phase vectors of the method
-  HIP_TRY(launch_fill_phase(h->view(), B, phi, s));
+  HIP_TRY(launch_fill_phase(h->view(B), B, phi, s));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   float best = 0.0f;
-  int best_nt = h->nt;
+  int best_v = h->nt | (h->banded << 1);
+  const int n_var = h->d_units[Handle::log2B(B)] ? 4 : 2;
+  if (times_us)
+    for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
   for (int rep = 0; rep < 2; ++rep) {
-    for (int nt = 0; nt < 2; ++nt) {
-      h->nt = nt;
-      if ((st = run_moments(h, B, phi, phi, 4, part, A, Bf, s))) return st;   // warm
+    for (int v = 0; v < n_var; ++v) {
+      h->nt = v & 1;
+      h->banded = v >> 1;
+      // the Hermitian moment step, the one most calls run
+      if ((st = run_moments(h, B, phi, phi, 4, part, A, Bf, s, true))) return st;   // warm
       HIP_TRY(hipEventRecord(e0, s));
-      if ((st = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s))) return st;
+      if ((st = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true))) return st;
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.0f;
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (rep == 1 && times_us) times_us[nt] = 1e3 * ms / kSteps;
+      if (rep == 1 && times_us) times_us[v] = 1e3 * ms / (kSteps / 2);   // launches
       if (rep == 1 && (best == 0.0f || ms < best)) {
         best = ms;
-        best_nt = nt;
+        best_v = v;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  h->nt = best_nt;
+  h->nt = best_v & 1;
+  h->banded = best_v >> 1;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets, const int64_t* period,
+                                 int32_t band_rows, int32_t cus, int32_t B, int32_t* block_of_row,
+                                 int32_t* iter_of_row) {
+  if (n_segments < 1 || !seg_offsets || !block_of_row || !iter_of_row || cus < 1 || !valid_B(B))
+    return fail(GPUQT_ERR_ARG, "bad arguments to gpuqt_schedule_rows");
+  if (band_rows < 0 || band_rows % 64) return fail(GPUQT_ERR_ARG, "band_rows must be a multiple of 64");
+  std::vector<int64_t> off(seg_offsets, seg_offsets + n_segments + 1);
+  if (off[0] != 0) return fail(GPUQT_ERR_ARG, "seg_offsets[0] must be 0");
+  for (int s = 0; s < n_segments; ++s)
+    if (off[s + 1] <= off[s]) return fail(GPUQT_ERR_ARG, "segments must be non-empty and ascending");
+  const int64_t n = off[n_segments];
+  if (n > INT32_MAX) return fail(GPUQT_ERR_ARG, "too many rows");
+  std::vector<BlkPlan> plan;
+  std::vector<int32_t> blk0, units;
+  plan_blocks(off, cus, kPerCU, &plan, &blk0);
+  bool banded = false;
+  std::vector<int64_t> D(n_segments, 0);
+  for (int s = 0; s < n_segments && period; ++s) {
+    D[s] = period[s];
+    banded = banded || (band_rows > 0 && D[s] > band_rows);
+  }
+  if (banded) banded_units(off, D, band_rows, &units);
+  const int32_t* U = banded ? units.data() : nullptr;
+  for (int64_t r = 0; r < n; ++r) block_of_row[r] = iter_of_row[r] = -1;
+  const int RPI = kBlock / B;
+  for (size_t lb = 0; lb < plan.size(); ++lb) {
+    const BlkPlan& P = plan[lb];
+    const int64_t total = row_seq_len(P, U);
+    int32_t it = 0;
+    for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += (int64_t)P.g * RPI, ++it) {
+      for (int i = 0; i < RPI; ++i) {
+        const int64_t pos = pos0 + i;
+        if (pos >= total) break;
+        const int64_t r = row_at(P, U, pos);
+        if (r < 0) continue;
+        if (r >= n || block_of_row[r] != -1) return fail(GPUQT_ERR_LAYOUT, "schedule visits a row twice");
+        block_of_row[r] = (int32_t)lb;
+        iter_of_row[r] = it;
+      }
+    }
+  }
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
+  Handle* h = reinterpret_cast<Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (variant < 0 || variant > 3) return fail(GPUQT_ERR_ARG, "variant must be in 0..3");
+  h->nt = variant & 1;
+  h->banded = variant >> 1;
   return GPUQT_OK;
 }
 

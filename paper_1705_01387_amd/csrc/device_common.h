@@ -138,16 +138,29 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
   }
 }
 
-// Visit the rows of this workgroup: tiles of RPI = 256/B rows of the group's
-// range, starting at tile j, stride g tiles.  f(r) for each row r of the
-// thread (all threads of the workgroup iterate the same number of times).
+// Visit the rows of this workgroup in tiles of RPI = 256/B rows: tiles j,
+// j + g, j + 2g, ... of its group's row sequence (the contiguous range
+// [r0, r1), or the units u0 .. u0 + nu of the banded order when the view has
+// one).  f(r) for each row r of the thread; all threads of the workgroup
+// iterate the same number of times.
 template <int B, typename F>
-__device__ __forceinline__ void for_rows(const BlkPlan& P, F&& f) {
+__device__ __forceinline__ void for_rows(const DevMat& A, const BlkPlan& P, F&& f) {
   constexpr int RPI = kBlock / B;
   const int64_t step = (int64_t)P.g * RPI;
-  for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step) {
-    const int64_t r = base + threadIdx.x / B;
-    if (r < P.r1) f(r);
+  if (A.units == nullptr) {   // linear: the same rule as row_at, without the call
+    for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step) {
+      const int64_t r = base + threadIdx.x / B;
+      if (r < P.r1) f(r);
+    }
+    return;
+  }
+  const int64_t total = row_seq_len(P, A.units);
+  for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += step) {
+    const int64_t pos = pos0 + threadIdx.x / B;
+    if (pos < total) {
+      const int64_t r = row_at(P, A.units, pos);
+      if (r >= 0) f(r);
+    }
   }
 }
 

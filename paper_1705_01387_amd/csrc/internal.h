@@ -15,16 +15,50 @@ namespace gpuqt {
 enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2 };
 
 constexpr int kBlock = 256;         // threads per workgroup of every sparse kernel
+constexpr int kPerCU = 8;           // resident workgroups per compute unit the plan assumes
+// waves per SIMD that kPerCU workgroups of kBlock threads need (4 SIMDs per CU):
+// the sparse kernels are compiled for it (at most 64 VGPRs), so that the whole
+// grid is resident at once and no workgroup waits for another to finish
+constexpr int kWavesPerSimd = kPerCU * kBlock / 64 / 4;
 constexpr int kRowAlign = 256;      // block row ranges start at multiples of this
 constexpr int kMaxB = 16;           // widest vector block
 
-// Row range of one logical workgroup: the workgroup is member j of a group of
-// g workgroups that share the contiguous rows [r0, r1) of segment seg; it
-// visits the tiles j, j + g, j + 2g, ... of that range.
+// Rows of one logical workgroup.  The workgroup is member j of a group of g
+// workgroups of segment seg; it visits the tiles j, j + g, j + 2g, ... of
+// the group's row sequence, which is either
+//   linear: the contiguous rows [r0, r1), or
+//   banded: the 64-row units units[u0 .. u0 + nu) of a banded unit order
+//           (each unit is the part of one 64-row slice inside the segment,
+//           whose rows end at se).
 struct BlkPlan {
   int64_t r0, r1;
-  int32_t j, g, seg, pad;
+  int32_t j, g, seg, nu;
+  int64_t u0, se;
 };
+
+constexpr int kUnitLog2 = 6;        // rows per unit of a banded order: 64
+constexpr int kNumB = 5;            // block widths 1, 2, 4, 8, 16
+constexpr int64_t kBandBudget = int64_t(5) << 19;   // 2.5 MiB: bytes one row window may stream per XCD
+
+#if defined(__HIPCC__)
+#define GPUQT_PLAN_HD __host__ __device__
+#else
+#define GPUQT_PLAN_HD
+#endif
+
+// Row at position pos of a workgroup's row sequence, or -1 for an idle lane
+// (past the end of a clipped unit).  pos < row_seq_len(P, units).
+//   linear: r0 + pos;  banded: the pos % 64-th row of unit pos / 64.
+GPUQT_PLAN_HD inline int64_t row_seq_len(const BlkPlan& P, const int32_t* units) {
+  return units ? ((int64_t)P.nu << kUnitLog2) : (P.r1 - P.r0);
+}
+GPUQT_PLAN_HD inline int64_t row_at(const BlkPlan& P, const int32_t* units, int64_t pos) {
+  if (!units) return P.r0 + pos;
+  const int64_t a = units[P.u0 + (pos >> kUnitLog2)];
+  const int64_t r = a + (pos & ((int64_t(1) << kUnitLog2) - 1));
+  const int64_t end = ((a >> kUnitLog2) + 1) << kUnitLog2;
+  return (r < end && r < P.se) ? r : -1;
+}
 
 // Device view of a Hamiltonian in sliced ELL.  Rows are cut into slices of S
 // rows; slice s stores width_s entries per row, slot-major (entry j of row
@@ -39,6 +73,7 @@ struct DevMat {
   const double* dx;          // [entries] x_col - x_row (minimum image), 0 for padding
   const double* diag;        // [n] U_i / DeltaE_seg
   const BlkPlan* plan;       // [G] row ranges of the logical workgroups
+  const int32_t* units;      // banded unit order for this block width (first row of each unit), or NULL
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   int64_t n;
@@ -68,6 +103,12 @@ struct Handle {
   std::vector<double> seg_gersh;  // host copy
   std::vector<BlkPlan> plan_host;
   int32_t nt = 1;                 // kernel variant chosen by gpuqt_autotune (or the default)
+  int32_t banded = 0;             // 1: use the banded unit order where one exists
+  // banded orders per block width (index log2 B); NULL where the plain row order
+  // already keeps the neighbour window within the cache budget
+  int32_t* d_units[kNumB] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<int64_t> seg_period;   // detected row period D per segment (0: none)
+  int32_t band_rows[kNumB] = {0, 0, 0, 0, 0};
   // device allocations
   int64_t* d_slice_ptr = nullptr;
   int32_t* d_col = nullptr;
@@ -94,8 +135,11 @@ struct Handle {
   bool timing = false;
   mutable std::vector<TimingRec> timing_recs;
 
-  DevMat view() const {
+  static int log2B(int B) { return B <= 1 ? 0 : B == 2 ? 1 : B == 4 ? 2 : B == 8 ? 3 : 4; }
+
+  DevMat view(int B) const {
     DevMat m;
+    m.units = banded ? d_units[log2B(B)] : nullptr;
     m.slice_ptr = d_slice_ptr;
     m.col = d_col;
     m.hop = d_hop;
@@ -145,10 +189,28 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
 // over the segments in proportion to their rows; G is a multiple of 8 when
 // G >= 8 (logical workgroup x*G/8 .. (x+1)*G/8-1 run on XCD x).  The logical
 // workgroups of one segment on one XCD form a group over a contiguous,
-// 64-row aligned part of the segment.  seg_blk0[s] is the first logical
-// workgroup of segment s (seg_blk0[n_seg] = G).
+// 64-row aligned part of the segment, and over a contiguous part of the
+// segment's units in a banded order (the same count split for every order).
+// seg_blk0[s] is the first logical workgroup of segment s (seg_blk0[n_seg] = G).
 void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
                  std::vector<BlkPlan>* plan, std::vector<int32_t>* seg_blk0);
+
+// Units (64-row slices clipped to segments) of every segment, in segment order:
+// unit_first[s] is the index of segment s's first unit, starts[u] its first row.
+void segment_units(const std::vector<int64_t>& seg_off, std::vector<int64_t>* unit_first,
+                   std::vector<int32_t>* starts);
+
+// Row period D of a segment: the neighbour offset |c - r| that 90 % of rows
+// reach or exceed as their largest one (in a lattice numbered lexicographically,
+// the stride of its slowest index).  0 when the segment has no off-diagonal entries.
+int64_t row_period(const HostLayout& L, int s);
+
+// Banded order of the units of each segment for band width W rows: unit at
+// offset a from the segment start goes to (band (a mod D) / W, sweep a / D,
+// a mod D), so rows one period apart are visited W rows apart instead of D.
+// Segments with D = 0, or D <= W, keep the plain order.
+void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
+                  int64_t W, std::vector<int32_t>* out);
 
 // ----------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.

@@ -45,7 +45,7 @@ namespace {
 // (v_1 = H~ v_0) and the workgroup's part of <phiL|v_n> (and <phiL|v_0>).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step(DevMat A, StepIO io,
                                                         const double2* __restrict__ phiL,
                                                         double2* __restrict__ part_n,
                                                         double2* __restrict__ part_0) {
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
   double2* __restrict__ out = io.out;
   const bool first = io.first;
   double dr = 0.0, di = 0.0, zr = 0.0, zi = 0.0;
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
 // steps of the plain recurrence, and no phi_L stream.
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_sym(DevMat A, StepIO io,
                                                             double2* __restrict__ part_a,
                                                             double2* __restrict__ part_b,
                                                             double2* __restrict__ part_c) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
   const bool first = io.first;
   // first: a = <v0|v0>, b = <v0|v1>, c = <v1|v1>;  else: a = <vk|vk-1>, c = <vk|vk>
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
 // step also <a|b> (row 0) and <a|b_1> (row 1).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO io,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_pair(DevMat A, ChainIO io,
                                                              double2* __restrict__ part_a,
                                                              double2* __restrict__ part_b,
                                                              double2* __restrict__ part_c) {
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
   const int b = threadIdx.x & (B - 1);
   const bool first = io.first;
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
 // table holding (2 - delta_m0) J_m(DeltaE_seg |dt|).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
                                                         const double* __restrict__ Jtab, int ldJ,
                                                         int m, double2 ph_m, double2 ph_0) {
   const BlkPlan P = A.plan[logical_block(A.G)];
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
   const double2* __restrict__ w = io.w;
   double2* __restrict__ out = io.out;
   const bool first = io.first;
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
 // chi); acc_a += c_m a_m, acc_b += c_m b_m.  [X,H~]_rj = -dx_rj H~_rj.
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
                                                      double2* __restrict__ acc_b,
                                                      const double* __restrict__ Jtab, int ldJ, int m,
                                                      double2 ph_m, double2 ph_0) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
   const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
   const int b = threadIdx.x & (B - 1);
   const bool first = io.first;
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -250,13 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
 // (Section 4.2).  Stored values are H~ = H / DeltaE_seg, so multiply back.
 // ---------------------------------------------------------------------------
 template <int B, int HOP>
-__global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
                                                        double2* __restrict__ out) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
   const double e = A.seg_dE[P.seg];
   const int b = threadIdx.x & (B - 1);
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
     row_apply<B, HOP, 0, false, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
@@ -272,13 +272,13 @@ __global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, cons
 
 // out = J_0(seg) * in, or zero when in is NULL.
 template <int B>
-__global__ __launch_bounds__(kBlock) void k_scale(DevMat A, const double2* __restrict__ in,
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_scale(DevMat A, const double2* __restrict__ in,
                                                   double2* __restrict__ out,
                                                   const double* __restrict__ Jtab, int ldJ) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const double j0 = Jtab ? Jtab[(int64_t)P.seg * ldJ] : 0.0;
   const int b = threadIdx.x & (B - 1);
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     const int64_t idx = r * B + b;
     out[idx] = in ? cscale(j0, in[idx]) : make_double2(0.0, 0.0);
   });
@@ -287,10 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_scale(DevMat A, const double2* __res
 // out = exp(i theta) with theta = 2 pi frac(0.618... idx + 0.414... b): a
 // deterministic unit-modulus test vector (used only to time kernel variants).
 template <int B>
-__global__ __launch_bounds__(kBlock) void k_fill_phase(DevMat A, double2* __restrict__ out) {
+__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_fill_phase(DevMat A, double2* __restrict__ out) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const int b = threadIdx.x & (B - 1);
-  for_rows<B>(P, [&](int64_t r) {
+  for_rows<B>(A, P, [&](int64_t r) {
     const double t = (double)r * 0.6180339887498949 + (double)b * 0.4142135623730951;
     double s, c;
     sincospi(2.0 * (t - floor(t)), &s, &c);

@@ -103,6 +103,10 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
     *msg = "slice_height must be 0 or a power of two in [32, 1024]";
     return GPUQT_ERR_ARG;
   }
+  if (d->band_rows < 0 || d->band_rows % 64 != 0) {
+    *msg = "band_rows must be 0 or a positive multiple of 64";
+    return GPUQT_ERR_ARG;
+  }
   const int64_t n = d->n;
   const int k = d->max_nn;
 
@@ -323,11 +327,27 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
   return GPUQT_OK;
 }
 
+void segment_units(const std::vector<int64_t>& seg_off, std::vector<int64_t>* unit_first,
+                   std::vector<int32_t>* starts) {
+  const int n_seg = (int)seg_off.size() - 1;
+  unit_first->assign(n_seg + 1, 0);
+  starts->clear();
+  for (int s = 0; s < n_seg; ++s) {
+    (*unit_first)[s] = (int64_t)starts->size();
+    for (int64_t r = seg_off[s]; r < seg_off[s + 1]; r = ((r >> kUnitLog2) + 1) << kUnitLog2)
+      starts->push_back((int32_t)r);
+  }
+  (*unit_first)[n_seg] = (int64_t)starts->size();
+}
+
 void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
                  std::vector<BlkPlan>* plan, std::vector<int32_t>* seg_blk0) {
   const int n_seg = (int)seg_off.size() - 1;
   const int64_t n = seg_off[n_seg];
   const int64_t target = std::max<int64_t>(8, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
+  std::vector<int64_t> unit_first;
+  std::vector<int32_t> starts;
+  segment_units(seg_off, &unit_first, &starts);
   // workgroups per segment: proportional to rows, at least one, at most one
   // per 64 rows
   std::vector<int64_t> gs(n_seg);
@@ -342,12 +362,13 @@ void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
   gs[n_seg - 1] += padded - G;   // spare workgroups join the last segment
   G = padded;
   const int64_t per_xcd = (G % 8 == 0) ? G / 8 : G;
-  plan->assign(G, BlkPlan{0, 0, 0, 1, 0, 0});
+  plan->assign(G, BlkPlan{0, 0, 0, 1, 0, 0, 0, 0});
   seg_blk0->assign(n_seg + 1, 0);
   int64_t lb = 0;
   for (int s = 0; s < n_seg; ++s) {
     (*seg_blk0)[s] = (int32_t)lb;
     const int64_t a = seg_off[s], b = seg_off[s + 1], ns = b - a;
+    const int64_t U = unit_first[s + 1] - unit_first[s];
     // groups: runs of this segment's logical workgroups on one XCD
     std::vector<std::pair<int64_t, int64_t>> groups;   // (first lb, size)
     for (int64_t q = lb; q < lb + gs[s];) {
@@ -356,13 +377,15 @@ void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
       groups.push_back({q, end - q});
       q = end;
     }
-    // rows of the segment in proportion to group sizes, 64-row aligned
-    int64_t done = 0, prev = a;
+    // rows of the segment in proportion to group sizes, 64-row aligned; units
+    // of a banded order likewise by count
+    int64_t done = 0, prev = a, uprev = 0;
     for (size_t k = 0; k < groups.size(); ++k) {
       done += groups[k].second;
       int64_t r = (k + 1 == groups.size()) ? b : a + (ns * done) / gs[s];
       r = std::min(b, std::max(prev, (r / 64) * 64));
       if (k + 1 == groups.size()) r = b;
+      const int64_t u = (k + 1 == groups.size()) ? U : (U * done) / gs[s];
       for (int64_t q = 0; q < groups[k].second; ++q) {
         BlkPlan& P = (*plan)[groups[k].first + q];
         P.r0 = prev;
@@ -370,12 +393,60 @@ void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
         P.j = (int32_t)q;
         P.g = (int32_t)groups[k].second;
         P.seg = s;
+        P.u0 = unit_first[s] + uprev;
+        P.nu = (int32_t)(u - uprev);
+        P.se = b;
       }
       prev = r;
+      uprev = u;
     }
     lb += gs[s];
   }
   (*seg_blk0)[n_seg] = (int32_t)G;
+}
+
+int64_t row_period(const HostLayout& L, int s) {
+  const int64_t a = L.seg_off[s], b = L.seg_off[s + 1];
+  if (b <= a) return 0;
+  // rows sampled with a stride, enough for a stable 90th percentile
+  const int64_t stride = std::max<int64_t>(1, (b - a) / 65536);
+  std::vector<int64_t> far;
+  far.reserve((size_t)((b - a) / stride + 1));
+  for (int64_t r = a; r < b; r += stride) {
+    const int64_t sl = r >> L.S_log2;
+    const int64_t p0 = L.slice_ptr[sl];
+    const int64_t w = (L.slice_ptr[sl + 1] - p0) >> L.S_log2;
+    int64_t m = 0;
+    for (int64_t j = 0; j < w; ++j) {
+      const int32_t c = L.col[p0 + j * L.S + (r & (L.S - 1))];
+      if (c >= 0) m = std::max<int64_t>(m, c > r ? c - r : r - c);
+    }
+    far.push_back(m);
+  }
+  const size_t k = far.size() / 10;   // 10 % of rows reach less than D
+  std::nth_element(far.begin(), far.begin() + k, far.end());
+  return far[k];
+}
+
+void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
+                  int64_t W, std::vector<int32_t>* out) {
+  std::vector<int64_t> unit_first;
+  segment_units(seg_off, &unit_first, out);
+  const int n_seg = (int)seg_off.size() - 1;
+  for (int s = 0; s < n_seg; ++s) {
+    const int64_t D = period[s];
+    if (D <= W) continue;   // plain order: rows one period apart are already close
+    const int64_t a = seg_off[s];
+    auto first = out->begin() + unit_first[s], last = out->begin() + unit_first[s + 1];
+    std::stable_sort(first, last, [&](int32_t x, int32_t y) {
+      const int64_t ox = x - a, oy = y - a;
+      const int64_t bx = (ox % D) / W, by = (oy % D) / W;
+      if (bx != by) return bx < by;
+      const int64_t qx = ox / D, qy = oy / D;
+      if (qx != qy) return qx < qy;
+      return ox % D < oy % D;
+    });
+  }
 }
 
 }  // namespace gpuqt

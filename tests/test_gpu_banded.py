@@ -1,0 +1,149 @@
+"""GPU parity of the banded row order (kernel variants 2 and 3).
+
+Small lattices get a banded order by a small band width (band_rows); every entry point
+then runs with the variant pinned and is compared with the oracle, and the per-row
+results (evolution, commutator) with the plain order bit for bit (a row's result does
+not depend on when it is visited; moment sums may round differently)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def err(got, ref):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def cubic26(gpu):
+    m = I.cubic(26, W=4.0, seed=71)             # 17,576 rows, period 676 (not a multiple of 64)
+    H = P.gpuqt_build_h_from_model(m, band_rows=128)
+    Hs, V, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    return m, H, Hs, V, XH
+
+
+def test_banded_order_exists(cubic26):
+    m, H, *_ = cubic26
+    assert H.info.row_period == 676
+    assert H.info.banded_mask == 0b11111
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("B", [1, 4, 16])
+def test_banded_moments(cubic26, variant, B):
+    say(f"case: banded moments variant={variant} B={B}")
+    m, H, Hs, _, _ = cubic26
+    dE = float(H.energy_max[0])
+    P.gpuqt_set_variant(H, variant)
+    phi = I.random_phase(m.n, B, 72)
+    psi = I.random_phase(m.n, B, 73)
+    d = dev(phi)
+    for M in (2, 5, 120):
+        ref = O.chebyshev_moments(Hs / dE, phi, phi, M).T
+        assert err(host(P.gpuqt_moments(H, d, d, M))[0], ref) < TOL
+        ref2 = O.chebyshev_moments(Hs / dE, phi, psi, M).T
+        assert err(host(P.gpuqt_moments(H, d, dev(psi), M))[0], ref2) < TOL
+    P.gpuqt_set_variant(H, 0)
+
+
+@pytest.mark.parametrize("B", [1, 4])
+def test_banded_rowwise_results_bit_identical(cubic26, B):
+    say(f"case: banded evolve/commutator bit-identical B={B}")
+    m, H, Hs, _, XH = cubic26
+    dE = float(H.energy_max[0])
+    psi = dev(I.random_phase(m.n, B, 74))
+    outs = []
+    for v in (0, 2, 3):
+        P.gpuqt_set_variant(H, v)
+        a = host(P.gpuqt_evolve(H, psi, 1.3, 0))
+        b = host(P.gpuqt_apply_commutator(H, psi, P.VELOCITY))
+        c = host(P.gpuqt_evolve(H, psi, 0.7, 0, with_commutator=True)[1])
+        outs.append((a, b, c))
+    P.gpuqt_set_variant(H, 0)
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+    p = host(psi)
+    assert err(outs[1][0], O.evolve(Hs / dE, p, 1.3, dE)) < TOL
+    assert err(outs[1][2], O.commutator_evolve(Hs / dE, XH / dE, p, 0.7, dE)) < TOL
+
+
+def test_banded_vac_msd(cubic26):
+    say("case: banded VAC/MSD B=2")
+    m, H, Hs, V, XH = cubic26
+    dE = float(H.energy_max[0])
+    P.gpuqt_set_variant(H, 2)
+    phi = I.random_phase(m.n, 2, 75)
+    dts = [0.5, 1.5, 1.0]
+    v = host(P.gpuqt_vac(H, dev(phi), dts, 64))[:, 0]
+    s = host(P.gpuqt_msd(H, dev(phi), dts, 64))[:, 0]
+    P.gpuqt_set_variant(H, 0)
+    rv = O.vac_moments(Hs, V, phi, dts, dE, 64)
+    rs = O.msd_moments(Hs, XH, phi, dts, dE, 64)
+    for k in range(len(dts)):
+        assert err(v[k], rv[k].T) < TOL, k
+        assert err(s[k], rs[k].T) < TOL, k
+
+
+def test_banded_backward(cubic26):
+    say("case: banded moments backward B=1")
+    m, H, Hs, _, _ = cubic26
+    import torch
+    dE = float(H.energy_max[0])
+    P.gpuqt_set_variant(H, 3)
+    phi = I.random_phase(m.n, 1, 76)
+    M = 40
+    w = np.random.default_rng(77).normal(size=(1, 1, M))
+    gU = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    gC = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d = dev(phi)
+    P.gpuqt_moments_backward(H, d, d, dev(w), gU, gC)
+    P.gpuqt_set_variant(H, 0)
+    rU, _ = O.moments_gradient(Hs, phi, phi, dE, w[0].T)
+    assert err(host(gU), rU) < TOL
+
+
+def test_banded_segments_mixed(gpu):
+    """Segments with and without a banded order in one launch."""
+    say("case: banded segments mixed")
+    mods = [I.square(40, 37, W=1.0, seed=81), I.square(90, 80, W=2.0, seed=82),
+            I.square(30, 9, W=0.5, seed=83), I.square(130, 70, W=1.5, seed=84)]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=offs, seg_length_x=[mm.length_x for mm in mods], band_rows=64)
+    assert H.info.banded_mask == 0b11111
+    B = 4
+    phi = I.random_phase(int(offs[-1]), B, 85)
+    d = dev(phi)
+    for v in (2, 3):
+        P.gpuqt_set_variant(H, v)
+        mu = host(P.gpuqt_moments(H, d, d, 90))
+        for s, mm in enumerate(mods):
+            Hs, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
+            ph = phi[offs[s]:offs[s + 1]]
+            ref = O.chebyshev_moments(Hs / float(H.energy_max[s]), ph, ph, 90).T
+            assert err(mu[s], ref) < TOL, (v, s)

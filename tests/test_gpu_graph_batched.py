@@ -99,8 +99,13 @@ def test_autotune_keeps_results(gpu):
     H = P.gpuqt_build_h_from_model(m)
     phi = dev(I.random_phase(m.n, 4, 66))
     t = P.gpuqt_autotune(H, 4)
-    assert np.all(np.isfinite(t)) and np.all(t > 0)
+    assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:] == 0)   # no banded order
+    assert H.info.kernel_variant in (0, 1)
     a = host(P.gpuqt_moments(H, phi, phi, 200))
     Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     ref = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(phi), 200).T
     assert err(a[0], ref) < TOL
+    Hb = P.gpuqt_build_h_from_model(m, band_rows=64)                      # period 121 > 64
+    tb = P.gpuqt_autotune(Hb, 4)
+    assert np.all(np.isfinite(tb)) and np.all(tb > 0)
+    assert err(host(P.gpuqt_moments(Hb, phi, phi, 200))[0], ref) < TOL
