@@ -229,7 +229,8 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
  * Method: the recurrence of Section 3.2 run forwards with checkpoints of
  * (v_{js}, v_{js+1}) every s = ckpt_stride steps (0: ceil(sqrt(M))), then the
  * adjoint recurrence lam_k = w_k phiL + 2 H~ lam_{k+1} - lam_{k+2} run backwards,
- * recomputing each block of s forward vectors from its checkpoint;
+ * recomputing each block of s forward vectors from its checkpoint; ckpt_stride = 1
+ * keeps every forward vector instead (M - 1 vectors of workspace, no recomputation);
  * dL/dp = Re[ sum_{k>=2} 2 <lam_k| dH~/dp v_{k-1}> + <lam_1| dH~/dp v_0> ].
  *   phiL, phiR : c128 [n][B];  w : double [n_segments][B][M];  grad_onsite : double [n];
  *   grad_class : double [n_class] or NULL (at most 4 classes);  lam0 : c128 [n][B] or NULL.

@@ -409,16 +409,30 @@ def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson
     return out
 
 
+KEEP_ALL_FRACTION = 0.25   # keep every forward vector when that needs at most this share of free memory
+
+
 def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad_class=None,
-                           want_lam0=False, ckpt_stride=0, ws=None, stream=None):
+                           want_lam0=False, ckpt_stride=None, ws=None, stream=None):
     """Accumulate dL/dU (grad_onsite, float64 [n]) and dL/deps_c (grad_class, float64 [n_class])
-    for L = sum w[s,b,k] Re mu[s,b,k]; returns (grad_onsite, grad_class, lam0 or None)."""
+    for L = sum w[s,b,k] Re mu[s,b,k]; returns (grad_onsite, grad_class, lam0 or None).
+
+    ckpt_stride: 1 keeps every forward vector (no recomputation), >= 2 checkpoints every that
+    many steps, 0 every ceil(sqrt(M)); None (default) takes 1 when its workspace fits in
+    KEEP_ALL_FRACTION of the free device memory, else 0."""
     import torch
     _dev_vec(phiL, "phiL")
     _dev_vec(phiR, "phiR")
     B = _cols(phiR)
     w = w.contiguous()
     M = int(w.shape[-1])
+    if ckpt_stride is None:
+        if ws is not None:
+            ckpt_stride = 0
+        else:
+            need = gpuqt_workspace_size(H, OP_MOMENTS_BACKWARD, B, M, 1)
+            free, _ = torch.cuda.mem_get_info(phiR.device)
+            ckpt_stride = 1 if need <= KEEP_ALL_FRACTION * free else 0
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phiR.device)
     lam0 = torch.empty_like(phiR) if want_lam0 else None

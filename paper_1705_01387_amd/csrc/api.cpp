@@ -110,17 +110,22 @@ int terms_for(const Handle* h, double dt, int Np) {
   return best;
 }
 
+// checkpoint stride of the moments adjoint: 1 keeps every forward vector (no
+// recomputation), >= 2 as given, 0 chooses ceil(sqrt(M))
 int backward_stride(int M, int stride) {
-  if (stride >= 2) return stride;
+  if (stride >= 1) return stride;
   int s = (int)std::ceil(std::sqrt((double)std::max(M, 1)));
   return std::max(2, s);
 }
 
-// vectors of the backward workspace: 3 forward, 2 per checkpoint pair, s
-// recomputed, 3 adjoint
+// checkpoint pairs of the backward pass (none when every vector is kept)
+int backward_pairs(int M, int s) { return (M >= 2 && s >= 2) ? (M - 1 + s - 1) / s : 0; }
+
+// vectors of the backward workspace: 3 forward, 3 adjoint, 2 per checkpoint
+// pair and s recomputed (s >= 2), or the M - 2 kept vectors v_1 .. v_{M-2} (s = 1)
 int backward_vectors(int M, int s) {
-  const int K = M >= 2 ? (M - 1 + s - 1) / s : 0;
-  return 6 + 2 * K + s;
+  if (s == 1) return 6 + std::max(M - 1, 1);
+  return 6 + 2 * backward_pairs(M, s) + s;
 }
 
 int class_stride(int n_class) { return n_class <= 1 ? 1 : (n_class <= 2 ? 2 : 4); }
@@ -168,8 +173,9 @@ struct TimeScope {
 gpuqt_status run_moments(const Handle* h, int B, const double2* phiL, const double2* phiR, int M,
                          double2* part, double2* A, double2* Bf, hipStream_t s, bool sym = false,
                          double2* A2 = nullptr, double2* B2 = nullptr) {
-  const DevMat D = h->view(B);
-  const int64_t row = (int64_t)h->G * B;
+  const int fam = A2 ? FAM_PAIR : sym ? FAM_SYM : FAM_MOMENT;
+  const DevMat D = h->view(B, fam);
+  const int64_t row = (int64_t)D.G * B;   // partial rows: one per logical workgroup of this plan
   if (A2) {   // pair: chains phiL (A, Bf) and phiR (A2, B2), product identities
     const int K = std::max(1, M / 2);
     TimeScope ts(h, s, 2, K);
@@ -248,14 +254,15 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
       return GPUQT_OK;
     }
     TimeScope ts(h, s, 3, Np - 1);
+    const DevMat E = h->view(B, FAM_EVOLVE);
     StepIO io{psi_in, nullptr, aA, 1};
-    HIP_TRY(launch_evolve_term(D, h->hop_mode, B, io, psi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
+    HIP_TRY(launch_evolve_term(E, h->hop_mode, B, io, psi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
     const double2* prev = psi_in;
     double2* cur = aA;
     for (int m = 2; m < Np; ++m) {
       double2* out = (prev == psi_in) ? aB : const_cast<double2*>(prev);
       StepIO st{cur, prev, out, 0};
-      HIP_TRY(launch_evolve_term(D, h->hop_mode, B, st, psi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
+      HIP_TRY(launch_evolve_term(E, h->hop_mode, B, st, psi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
       prev = cur;
       cur = out;
     }
@@ -272,15 +279,16 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
     return GPUQT_OK;
   }
   TimeScope ts(h, s, 4, Np - 1);
+  const DevMat E = h->view(B, FAM_MSD);
   ChainIO io{psi_in, nullptr, aA, b0, nullptr, bA, 1, 1};
-  HIP_TRY(launch_msd_term(D, h->hop_mode, B, io, psi_out, chi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
+  HIP_TRY(launch_msd_term(E, h->hop_mode, B, io, psi_out, chi_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
   const double2 *pa = psi_in, *pb = b0;
   double2 *ca = aA, *cb = bA;
   for (int m = 2; m < Np; ++m) {
     double2* oa = (pa == psi_in) ? aB : const_cast<double2*>(pa);
     double2* ob = (pb == chi_in || pb == zero) ? bB : const_cast<double2*>(pb);
     ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
-    HIP_TRY(launch_msd_term(D, h->hop_mode, B, st, psi_out, chi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
+    HIP_TRY(launch_msd_term(E, h->hop_mode, B, st, psi_out, chi_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
     pa = ca;
     pb = cb;
     ca = oa;
@@ -307,9 +315,10 @@ struct BwdSource {
 gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                           const BwdSource& src, double* gU, double* gcp, int nc, double2* lam0,
                           bool acc0, int s, double2* const* vec, hipStream_t sm) {
-  const DevMat D = h->view(B);
+  const DevMat D = h->view(B);                  // adjoint steps: primary plan (class partials)
+  const DevMat F = h->view(B, FAM_MOMENT);      // forward recomputation: no partials
   const bool grad = gU != nullptr;
-  const int K = M >= 2 ? (M - 1 + s - 1) / s : 0;
+  const int K = backward_pairs(M, s);
   double2* const* R = vec;
   double2* const* Lm = vec + 3;
   auto ck = [&](int k, int q) { return vec[6 + 2 * k + q]; };
@@ -336,14 +345,29 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
     a.src_phase = make_double2(p.x, -p.y);   // conj((-i sgn)^n)
     return a;
   };
-  if (grad) {
+  if (grad && s == 1) {
+    // forward: v_1 .. v_{M-2}, every one kept (v_n in sb(n)); then the reverse
+    const double2* prev2 = nullptr;
+    const double2* prev1 = pR;
+    for (int n = 1; n <= M - 2; ++n) {
+      StepIO io{prev1, prev2, sb(n), n == 1 ? 1 : 0};
+      HIP_TRY(launch_moment_step(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+      prev2 = prev1;
+      prev1 = sb(n);
+    }
+    for (int n = M - 1; n >= 1; --n) {
+      AdjIO a = make(n);
+      a.v = n == 1 ? pR : sb(n - 1);
+      HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, nc, a, sm));
+    }
+  } else if (grad) {
     // forward: v_1 .. v_{M-2}, keeping v_{ks} and v_{ks+1} as checkpoints
     const double2* prev2 = nullptr;
     const double2* prev1 = pR;
     for (int n = 1; n <= M - 2; ++n) {
       double2* out = (n % s == 0 || n % s == 1) ? ck(n / s, n % s) : R[n % 3];
       StepIO io{prev1, prev2, out, n == 1 ? 1 : 0};
-      HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+      HIP_TRY(launch_moment_step(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
       prev2 = prev1;
       prev1 = out;
     }
@@ -356,7 +380,7 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
       const int lo = k * s + 1, hi = std::min((k + 1) * s, M - 1);
       for (int j = 2; j <= hi - 1 - k * s; ++j) {   // recompute v_{ks+j}
         StepIO io{slot(k, j - 1), slot(k, j - 2), sb(j), 0};
-        HIP_TRY(launch_moment_step(D, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+        HIP_TRY(launch_moment_step(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
       }
       for (int n = hi; n >= lo; --n) {
         AdjIO a = make(n);
@@ -464,6 +488,25 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_blk0, seg_blk0.data(), seg_blk0.size() * 4);
   up((void**)&h->d_seg_dE, L.seg_dE.data(), L.seg_dE.size() * 8);
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
+  // plans for fewer resident workgroups per CU, and each hot family's occupancy
+  h->d_plans[kPerCU - 1] = h->d_plan;
+  h->d_blk0s[kPerCU - 1] = h->d_seg_blk0;
+  h->Gs[kPerCU - 1] = h->G;
+  std::vector<std::vector<BlkPlan>> plans(kPerCU);   // alive until the stream is synchronised
+  std::vector<std::vector<int32_t>> blk0s(kPerCU);
+  for (int p = 1; p < kPerCU; ++p) {
+    plan_blocks(L.seg_off, cus, p, &plans[p - 1], &blk0s[p - 1]);
+    h->Gs[p - 1] = (int32_t)plans[p - 1].size();
+    up((void**)&h->d_plans[p - 1], plans[p - 1].data(), plans[p - 1].size() * sizeof(BlkPlan));
+    up((void**)&h->d_blk0s[p - 1], blk0s[p - 1].data(), blk0s[p - 1].size() * 4);
+  }
+  {
+    const DevMat D0 = h->view(1);
+    for (int f = 0; f < kFamilies; ++f)
+      for (int lb = 0; lb < kNumB; ++lb)
+        for (int v = 0; v < 2; ++v)
+          h->occ[f][lb][v] = (int8_t)std::min(kPerCU, kernel_occupancy(f, D0, h->hop_mode, 1 << lb, v));
+  }
   std::vector<double> zeros_g(h->G, 0.0);
   up((void**)&h->d_bound, zeros_g.data(), zeros_g.size() * 8);
   // banded unit orders, per block width: the row window between the first and
@@ -506,6 +549,10 @@ void gpuqt_destroy_h(gpuqt_h hh) {
     if (p) (void)hipFree(p);
   for (int32_t* p : h->d_units)
     if (p) (void)hipFree(p);
+  for (int p = 0; p + 1 < kPerCU; ++p) {   // the last entries alias d_plan / d_seg_blk0
+    if (h->d_plans[p]) (void)hipFree(h->d_plans[p]);
+    if (h->d_blk0s[p]) (void)hipFree(h->d_blk0s[p]);
+  }
   for (auto& r : h->timing_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -656,7 +703,8 @@ gpuqt_status gpuqt_moments(gpuqt_h hh, int32_t B, const double* phiL, const doub
                         sym ? nullptr : reinterpret_cast<double2*>(base + 2 * W.vec_bytes),
                         sym ? nullptr : reinterpret_cast<double2*>(base + 3 * W.vec_bytes))))
     return st;
-  HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1,   // raw dots, both forms
+  const int fam = sym ? FAM_SYM : FAM_PAIR;
+  HIP_TRY(launch_reduce_moments(part, M, h->G_of(B, fam), B, h->n_seg, h->blk0_of(B, fam), 1,   // raw dots
                                 reinterpret_cast<double2*>(mu), nullptr, s));
   return GPUQT_OK;
 }
@@ -760,7 +808,8 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   for (int k = 0; k < n_t; ++k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, phiL, s));
     if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s, false, V(7), V(8)))) return st;
-    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1, nullptr, out + row * k, s));
+    HIP_TRY(launch_reduce_moments(part, M, h->G_of(B, FAM_PAIR), B, h->n_seg, h->blk0_of(B, FAM_PAIR), 1,
+                                  nullptr, out + row * k, s));
     if (k + 1 < n_t) {
       const int np_k = terms_for(h, dt[k], Np);
       double2* Ln = (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
@@ -808,7 +857,8 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
     if ((st = run_evolve(h, B, dt[k], np_k, psi, Pn, chi, Cn, V(4), V(5), V(6), V(7), V(8), J, s)))
       return st;
     if ((st = run_moments(h, B, Cn, Cn, M, part, V(4), V(5), s, true))) return st;
-    HIP_TRY(launch_reduce_moments(part, M, h->G, B, h->n_seg, h->d_seg_blk0, 1, nullptr, out + row * k, s));
+    HIP_TRY(launch_reduce_moments(part, M, h->G_of(B, FAM_SYM), B, h->n_seg, h->blk0_of(B, FAM_SYM), 1,
+                                  nullptr, out + row * k, s));
     psi = Pn;
     chi = Cn;
     pi ^= 1;

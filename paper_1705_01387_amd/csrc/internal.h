@@ -15,11 +15,11 @@ namespace gpuqt {
 enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2 };
 
 constexpr int kBlock = 256;         // threads per workgroup of every sparse kernel
-constexpr int kPerCU = 8;           // resident workgroups per compute unit the plan assumes
-// waves per SIMD that kPerCU workgroups of kBlock threads need (4 SIMDs per CU):
-// the sparse kernels are compiled for it (at most 64 VGPRs), so that the whole
-// grid is resident at once and no workgroup waits for another to finish
-constexpr int kWavesPerSimd = kPerCU * kBlock / 64 / 4;
+constexpr int kPerCU = 8;           // resident workgroups per CU of the primary plan
+// Hot kernel families; each launches with the plan whose workgroup count its
+// compiled occupancy keeps resident all at once (a grid larger than what fits
+// would leave a tail of workgroups that start only when others finish).
+enum Family { FAM_MOMENT = 0, FAM_SYM = 1, FAM_PAIR = 2, FAM_EVOLVE = 3, FAM_MSD = 4, kFamilies = 5 };
 constexpr int kRowAlign = 256;      // block row ranges start at multiples of this
 constexpr int kMaxB = 16;           // widest vector block
 
@@ -103,6 +103,13 @@ struct Handle {
   std::vector<double> seg_gersh;  // host copy
   std::vector<BlkPlan> plan_host;
   int32_t nt = 1;                 // kernel variant chosen by gpuqt_autotune (or the default)
+  // plans for p = 1 .. kPerCU resident workgroups per CU (index p - 1; the last is
+  // the primary plan d_plan / d_seg_blk0 / G)
+  BlkPlan* d_plans[kPerCU] = {};
+  int32_t* d_blk0s[kPerCU] = {};
+  int32_t Gs[kPerCU] = {};
+  // resident workgroups per CU of each hot family [family][log2 B][nt] (0: unknown)
+  int8_t occ[kFamilies][kNumB][2] = {};
   int32_t banded = 0;             // 1: use the banded unit order where one exists
   // banded orders per block width (index log2 B); NULL where the plain row order
   // already keeps the neighbour window within the cache budget
@@ -136,6 +143,21 @@ struct Handle {
   mutable std::vector<TimingRec> timing_recs;
 
   static int log2B(int B) { return B <= 1 ? 0 : B == 2 ? 1 : B == 4 ? 2 : B == 8 ? 3 : 4; }
+
+  // plan of a hot family at block width B and the current load variant
+  int plan_index(int B, int family) const {
+    const int p = occ[family][log2B(B)][nt ? 1 : 0];
+    return (p < 1 || p > kPerCU) ? kPerCU - 1 : p - 1;
+  }
+  int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
+  const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
+  DevMat view(int B, int family) const {
+    DevMat m = view(B);
+    const int i = plan_index(B, family);
+    m.plan = d_plans[i];
+    m.G = Gs[i];
+    return m;
+  }
 
   DevMat view(int B) const {
     DevMat m;
@@ -211,6 +233,10 @@ int64_t row_period(const HostLayout& L, int s);
 // Segments with D = 0, or D <= W, keep the plain order.
 void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
                   int64_t W, std::vector<int32_t>* out);
+
+// Resident workgroups per CU of a hot family's kernel for this layout (hopping
+// mode, row width A.K), block width B and load variant nt (kernels.hip).
+int kernel_occupancy(int family, const DevMat& A, int hop_mode, int B, int nt);
 
 // ----------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.

@@ -45,7 +45,7 @@ namespace {
 // (v_1 = H~ v_0) and the workgroup's part of <phiL|v_n> (and <phiL|v_0>).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step(DevMat A, StepIO io,
+__global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
                                                         const double2* __restrict__ phiL,
                                                         double2* __restrict__ part_n,
                                                         double2* __restrict__ part_0) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step(DevMat A,
 // steps of the plain recurrence, and no phi_L stream.
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_sym(DevMat A, StepIO io,
+__global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
                                                             double2* __restrict__ part_a,
                                                             double2* __restrict__ part_b,
                                                             double2* __restrict__ part_c) {
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_sym(DevMa
 // step also <a|b> (row 0) and <a|b_1> (row 1).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_pair(DevMat A, ChainIO io,
+__global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO io,
                                                              double2* __restrict__ part_a,
                                                              double2* __restrict__ part_b,
                                                              double2* __restrict__ part_c) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_moment_step_pair(DevM
 // table holding (2 - delta_m0) J_m(DeltaE_seg |dt|).
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
+__global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, double2* __restrict__ acc,
                                                         const double* __restrict__ Jtab, int ldJ,
                                                         int m, double2 ph_m, double2 ph_0) {
   const BlkPlan P = A.plan[logical_block(A.G)];
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_evolve_term(DevMat A,
 // chi); acc_a += c_m a_m, acc_b += c_m b_m.  [X,H~]_rj = -dx_rj H~_rj.
 // ---------------------------------------------------------------------------
 template <int B, int HOP, int K, bool NT>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
+__global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
                                                      double2* __restrict__ acc_b,
                                                      const double* __restrict__ Jtab, int ldJ, int m,
                                                      double2 ph_m, double2 ph_0) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_msd_term(DevMat A, Ch
 // (Section 4.2).  Stored values are H~ = H / DeltaE_seg, so multiply back.
 // ---------------------------------------------------------------------------
 template <int B, int HOP>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, const double2* __restrict__ x,
                                                        double2* __restrict__ out) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_commutator(DevMat A, 
 
 // out = J_0(seg) * in, or zero when in is NULL.
 template <int B>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_scale(DevMat A, const double2* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_scale(DevMat A, const double2* __restrict__ in,
                                                   double2* __restrict__ out,
                                                   const double* __restrict__ Jtab, int ldJ) {
   const BlkPlan P = A.plan[logical_block(A.G)];
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_scale(DevMat A, const
 // out = exp(i theta) with theta = 2 pi frac(0.618... idx + 0.414... b): a
 // deterministic unit-modulus test vector (used only to time kernel variants).
 template <int B>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_fill_phase(DevMat A, double2* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_fill_phase(DevMat A, double2* __restrict__ out) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const int b = threadIdx.x & (B - 1);
   for_rows<B>(A, P, [&](int64_t r) {
@@ -428,6 +428,26 @@ __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, d
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
+
+int kernel_occupancy(int family, const DevMat& A, int hop_mode, int B, int nt) {
+  int nb = 0;
+  auto q = [&](auto fn) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess) nb = 0;
+  };
+  (void)dispatch_sparse(A, hop_mode, B, nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    constexpr int b = decltype(Bc)::value, hm = decltype(Hc)::value, k = decltype(Kc)::value;
+    constexpr bool n = decltype(NTc)::value;
+    switch (family) {
+      case FAM_MOMENT: q(k_moment_step<b, hm, k, n>); break;
+      case FAM_SYM: q(k_moment_step_sym<b, hm, k, n>); break;
+      case FAM_PAIR: q(k_moment_step_pair<b, hm, k, n>); break;
+      case FAM_EVOLVE: q(k_evolve_term<b, hm, k, n>); break;
+      default: q(k_msd_term<b, hm, k, n>); break;
+    }
+  });
+  (void)hipGetLastError();
+  return nb;
+}
 
 hipError_t launch_moment_step(const DevMat& A, int hop_mode, int B, const StepIO& io,
                               const double2* phiL, double2* part_n, double2* part_0, hipStream_t s) {

@@ -22,7 +22,7 @@ using namespace dev;
 namespace {
 
 template <int B, int HOP, int K, int NC>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_adjoint_step(DevMat A, AdjIO io) {
+__global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
   const int lb = logical_block(A.G);
   const BlkPlan P = A.plan[lb];
   const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_adjoint_step(DevMat A
 // V_c = i dx H_c the velocity restricted to the class-c hoppings (unscaled:
 // the stored H~ is multiplied back by DeltaE).
 template <int B, int HOP, int NC>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_velocity_class_grad(DevMat A, const double2* __restrict__ a,
+__global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const double2* __restrict__ a,
                                                                 const double2* __restrict__ x,
                                                                 const int32_t* __restrict__ cls,
                                                                 double* __restrict__ gcp) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_velocity_class_grad(D
 }
 
 // diag[r] = onsite[r] / DeltaE_seg (new on-site energies)
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_set_onsite(DevMat A, const double* __restrict__ onsite,
+__global__ __launch_bounds__(kBlock) void k_set_onsite(DevMat A, const double* __restrict__ onsite,
                                                        double* __restrict__ diag) {
   const BlkPlan P = A.plan[logical_block(A.G)];
   const double inv = 1.0 / A.seg_dE[P.seg];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_scale_hops(int64_t entries, int cplx, c
 // bound[lb] = max over the workgroup's rows of |U~_r| + sum_j |H~_rj| (the
 // Gershgorin bound of H / DeltaE, which must stay <= 1)
 template <int HOP>
-__global__ __launch_bounds__(kBlock, kWavesPerSimd) void k_row_bound(DevMat A, double* __restrict__ bound) {
+__global__ __launch_bounds__(kBlock) void k_row_bound(DevMat A, double* __restrict__ bound) {
   const int lb = logical_block(A.G);
   const BlkPlan P = A.plan[lb];
   const double hu = (HOP == HOP_UNIFORM) ? fabs(A.seg_hop[P.seg]) : 0.0;

@@ -38,7 +38,8 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("B,M,stride", [(1, 64, 0), (2, 97, 7), (1, 2, 0), (1, 3, 0)])
+@pytest.mark.parametrize("B,M,stride", [(1, 64, 0), (2, 97, 7), (1, 2, 0), (1, 3, 0),
+                                        (1, 64, 1), (2, 97, 1), (1, 2, 1), (1, 3, 1)])
 def test_moments_backward(gpu, name, B, M, stride):
     import torch
     say(f"case: backward {name} B={B} M={M} stride={stride}")
