@@ -316,6 +316,29 @@ def workload_cubic(L: int = 200, W: float = 16.0, B: int = 4) -> dict:
                 M=1000, dt=np.full(40, 2.0), Np=60, name=f"cubic{L}_W{int(W)}")
 
 
+def workload_paper_diffusive(L: int = 2000) -> dict:
+    """The paper's first example (Section 5.1): square L x L (2000 x 2000), periodic, t = -1,
+    Anderson W = 4 (seed 6001); one random-phase vector (seed 6002); DeltaE = 6.1, M = 1000
+    (default); VAC and MSD over 20 steps of 0.2; energies -6 .. 6 in steps of 0.02."""
+    m = square(L, L, W=4.0, seed=6001)
+    return dict(model=m, phi=random_phase(m.n, 1, 6002), energy_max=6.1, M=1000,
+                dt=np.full(20, 0.2), energies=np.linspace(-6.0, 6.0, 601), vac=True, msd=True,
+                name=f"paper_diffusive_square{L}")
+
+
+def workload_paper_localized(L: int = 4_000_000) -> dict:
+    """The paper's second example (Section 5.2): chain of 4,000,000 sites, periodic, t = -1,
+    Anderson W = 4 (seed 6101); two random-phase vectors (seeds 6102, 6103); DeltaE = 4.1,
+    M = 500; MSD only over 30 non-uniform steps 0.1 .. 1.0, 1 .. 10, 10 .. 100; energies
+    -4 .. 4 in steps of 0.02."""
+    m = chain(L, W=4.0, seed=6101)
+    dt = np.concatenate([np.arange(1, 11) * 0.1, np.arange(1, 11) * 1.0, np.arange(1, 11) * 10.0])
+    phi = np.concatenate([random_phase(m.n, 1, 6102 + r) for r in range(2)], axis=1)
+    return dict(model=m, phi=phi, energy_max=4.1, M=500, dt=dt,
+                energies=np.linspace(-4.0, 4.0, 401), vac=False, msd=True,
+                name=f"paper_localized_chain{L}")
+
+
 def workload_train(L: int = 512) -> dict:
     """Square L x L with trainable on-site energies (uniform in [-1,1]) and two
     hopping classes (t1 nearest, t2 next-nearest); DeltaE fixed at 6.0; M=512."""

@@ -387,3 +387,52 @@ def test_chebyshev_series_matches_eigh():
     psi = I.random_phase(m.n, 2, 34)
     ref = E @ ((c @ T_closed(40, lam / dE))[:, None] * (E.conj().T @ psi))
     assert rel(O.chebyshev_series(H / dE, c, psi), ref) < 1e-12
+
+
+def test_sigma_vac_trapezoid_exact_for_linear_rows_and_bounded_for_decay():
+    """Trapezoid rule: exact for rows linear in t; for exp(-t/tau) within its error bound
+    sum_k dt_k^3 / 12 max|f''|."""
+    dt = np.array([0.3, 0.1, 0.7, 0.0, 1.2, 0.4])
+    t = np.concatenate([[0.0], np.cumsum(dt)])[:len(dt)]          # VAC row times
+    a, b = np.array([0.5, -1.0, 2.0]), np.array([1.5, 0.25, -0.75])
+    rows = a[None, :] + b[None, :] * t[:, None]
+    assert rel(O.sigma_vac(rows, dt), a * t[:, None] + 0.5 * b * t[:, None] ** 2) < 1e-15
+    tau = 0.8
+    rows = np.exp(-t / tau)[:, None]
+    exact = (tau * (1.0 - np.exp(-t / tau)))[:, None]
+    bound = np.cumsum(np.concatenate([[0.0], dt[:-1] ** 3])) / 12.0 / tau ** 2
+    assert np.all(np.abs(O.sigma_vac(rows, dt) - exact)[:, 0] <= bound + 1e-15)
+
+
+def test_sigma_msd_exact_for_ballistic_rows():
+    """DeltaX^2 = c t^2 (ballistic): the chord slope over [t_k - dt, t_k] halved is c t_mid."""
+    dt = np.array([0.1, 0.5, 0.25, 2.0])
+    t = np.cumsum(dt)
+    c = np.array([1.0, 3.5])
+    s, t_mid = O.sigma_msd(c[None, :] * t[:, None] ** 2, dt)
+    assert rel(t_mid, t - dt / 2) < 1e-15
+    assert rel(s, c[None, :] * t_mid[:, None]) < 1e-14
+    s0, _ = O.sigma_msd(np.ones((2, 1)), np.array([1.0, 0.0]))
+    assert np.isnan(s0[1, 0])
+
+
+def test_sigma_vac_equals_sigma_msd_on_clean_chain():
+    """Both running conductivities of Section 2.2 agree (the paper's Fig. 1(d) statement);
+    on a clean chain they are rho v^2 t exactly, so sigma^MSD at the midpoints equals
+    sigma^VAC interpolated there."""
+    m = I.chain(40)
+    H, V, XH = ops(m)
+    dE = 2.1
+    phi = I.random_phase(m.n, 1, 33)
+    dts = [0.4, 0.4, 0.4, 0.4, 0.4]
+    E = np.linspace(-1.5, 1.5, 7)
+    Cv = O.vac_moments(H, V, phi, dts, dE, 64)[:, :, 0]
+    Cm = O.msd_moments(H, XH, phi, dts, dE, 64)[:, :, 0]
+    rv = O.kpm_reconstruct(Cv.T, E, dE, float(m.n)).T        # [N_t, n_E]
+    rm = O.kpm_reconstruct(Cm.T, E, dE, float(m.n)).T
+    sv = O.sigma_vac(rv, dts)                 # at 0, 0.4, ..., 1.6
+    sm, t_mid = O.sigma_msd(rm, dts)          # at 0.2, 0.6, ..., 1.8
+    tv = np.concatenate([[0.0], np.cumsum(dts)[:-1]])
+    slope = (sv[1] - sv[0]) / dts[0]
+    assert rel(sv, tv[:, None] * slope[None, :]) < 1e-11
+    assert rel(sm, t_mid[:, None] * slope[None, :]) < 1e-11
