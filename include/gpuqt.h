@@ -302,6 +302,19 @@ gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double *C, int32_
                                    const double *energies, double energy_max, double volume,
                                    int32_t jackson, double *out, void *stream);
 
+/* Running electrical conductivity (Section 2.2, e = 1) from KPM-reconstructed rows:
+ *   GPUQT_SIGMA_VAC: y[k][e] = rho C_vv(E_e, t_k) at the VAC row times t_k = sum_{j<k} dt_j;
+ *     sigma[k][e] = int_0^{t_k} rho C_vv dt by the trapezoid rule over the rows (sigma[0] = 0).
+ *   GPUQT_SIGMA_MSD: y[k][e] = rho DeltaX^2(E_e, t_{k+1}) at the MSD row times
+ *     t_{k+1} = sum_{j<=k} dt_j, with DeltaX^2 = 0 at t = 0; sigma[k][e] = (y_k - y_{k-1}) / (2 dt_k),
+ *     the slope of the straight line between consecutive rows halved, which belongs to the
+ *     midpoint t_{k+1} - dt_k / 2 (NaN where dt_k = 0).
+ *   dt : double [n_t], y and sigma : double [n_t][n_E]; all device; sigma must not overlap y.
+ */
+enum { GPUQT_SIGMA_VAC = 0, GPUQT_SIGMA_MSD = 1 };
+gpuqt_status gpuqt_running_conductivity(int32_t mode, int32_t n_t, const double *dt, int32_t n_E,
+                                        const double *y, double *sigma, void *stream);
+
 /* Transpose of gpuqt_kpm_reconstruct (for gradients of losses on the reconstructed
  * functions): out[r][n] = sum_e g[r][e] * d out_kpm[r][e] / d C[r][n], energies with
  * |E~| >= 1 contributing nothing.  g : double [R][n_E], energies : double [n_E],

@@ -110,6 +110,8 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gpuqt_set_variant": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "gpuqt_running_conductivity": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -406,6 +408,25 @@ def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson
     _check(lib().gpuqt_kpm_reconstruct(R, M, _ptr(C), int(E.shape[0]), _ptr(E), float(energy_max),
                                        float(volume), 1 if jackson else 0, _ptr(out), _stream(stream)),
            "gpuqt_kpm_reconstruct")
+    return out
+
+
+SIGMA_VAC, SIGMA_MSD = 0, 1
+
+
+def gpuqt_running_conductivity(mode: int, rows, dt, out=None, stream=None):
+    """Running conductivity over the time rows [N_t, n_E] (float64 on the GPU): SIGMA_VAC
+    integrates rho C_vv rows, SIGMA_MSD differentiates rho DeltaX^2 rows (Section 2.2)."""
+    import torch
+    rows = rows.contiguous()
+    n_t, n_E = int(rows.shape[0]), int(rows.shape[1])
+    d = torch.as_tensor(np.asarray(dt, dtype=np.float64), device=rows.device)
+    if d.shape[0] != n_t:
+        raise ValueError("dt must have one entry per row")
+    if out is None:
+        out = torch.empty_like(rows)
+    _check(lib().gpuqt_running_conductivity(int(mode), n_t, _ptr(d), n_E, _ptr(rows), _ptr(out),
+                                            _stream(stream)), "gpuqt_running_conductivity")
     return out
 
 

@@ -1134,6 +1134,17 @@ gpuqt_status gpuqt_kpm_reconstruct(int32_t R, int32_t M, const double* C, int32_
   return GPUQT_OK;
 }
 
+gpuqt_status gpuqt_running_conductivity(int32_t mode, int32_t n_t, const double* dt, int32_t n_E,
+                                        const double* y, double* sigma, void* stream) {
+  if (mode != GPUQT_SIGMA_VAC && mode != GPUQT_SIGMA_MSD) return fail(GPUQT_ERR_ARG, "unknown mode");
+  if (n_t < 0 || n_E < 0) return fail(GPUQT_ERR_ARG, "n_t and n_E must be >= 0");
+  if (n_t == 0 || n_E == 0) return GPUQT_OK;
+  if (!dt || !y || !sigma) return fail(GPUQT_ERR_ARG, "NULL pointer");
+  if (overlap(sigma, y, (size_t)n_t * n_E * 8)) return fail(GPUQT_ERR_ARG, "sigma must not overlap y");
+  HIP_TRY(launch_sigma(mode, n_t, dt, n_E, y, sigma, static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
 gpuqt_status gpuqt_set_timing(gpuqt_h hh, int32_t enable) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");

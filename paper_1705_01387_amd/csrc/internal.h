@@ -234,6 +234,10 @@ int64_t row_period(const HostLayout& L, int s);
 void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
                   int64_t W, std::vector<int32_t>* out);
 
+// Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
+hipError_t launch_sigma(int mode, int n_t, const double* dt, int n_E, const double* y, double* out,
+                        hipStream_t s);
+
 // Resident workgroups per CU of a hot family's kernel for this layout (hopping
 // mode, row width A.K), block width B and load variant nt (kernels.hip).
 int kernel_occupancy(int family, const DevMat& A, int hop_mode, int B, int nt);

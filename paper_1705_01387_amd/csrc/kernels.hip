@@ -348,6 +348,32 @@ __global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part,
   }
 }
 
+// Running conductivity (Section 2.2) over the time rows, one energy per thread:
+// mode 0 (VAC): trapezoid integral of rows at t_k = sum_{j<k} dt_j, sigma_0 = 0;
+// mode 1 (MSD): (y_k - y_{k-1}) / (2 dt_k), y_{-1} = 0 (NaN for dt_k = 0).
+__global__ __launch_bounds__(256) void k_sigma(int mode, int n_t, const double* __restrict__ dt, int n_E,
+                                               const double* __restrict__ y, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_E) return;
+  if (mode == 0) {
+    double acc = 0.0, prev = y[e];
+    out[e] = 0.0;
+    for (int k = 1; k < n_t; ++k) {
+      const double cur = y[(int64_t)k * n_E + e];
+      acc += 0.5 * dt[k - 1] * (prev + cur);
+      out[(int64_t)k * n_E + e] = acc;
+      prev = cur;
+    }
+  } else {
+    double prev = 0.0;
+    for (int k = 0; k < n_t; ++k) {
+      const double cur = y[(int64_t)k * n_E + e];
+      out[(int64_t)k * n_E + e] = dt[k] != 0.0 ? (cur - prev) / (2.0 * dt[k]) : __builtin_nan("");
+      prev = cur;
+    }
+  }
+}
+
 // KPM sum of Section 3.3 for one (row r, energy e) per thread.  T_n(E~) by the
 // Chebyshev recurrence, Jackson damping g_n computed in place.
 __global__ __launch_bounds__(256) void k_kpm(int R, int M, const double* __restrict__ C, int n_E,
@@ -544,6 +570,13 @@ hipError_t launch_kpm_adjoint(int R, int M, const double* g, int n_E, const doub
   const double cot_pa = cos(M_PI * a) / sin(M_PI * a);
   k_kpm_adjoint<<<dim3((M + 255) / 256, R), 256, 0, s>>>(R, M, g, n_E, E, inv_dE, pref_base, jackson,
                                                          cot_pa, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma(int mode, int n_t, const double* dt, int n_E, const double* y, double* out,
+                        hipStream_t s) {
+  if (n_t <= 0 || n_E <= 0) return hipSuccess;
+  k_sigma<<<dim3((n_E + 255) / 256), 256, 0, s>>>(mode, n_t, dt, n_E, y, out);
   return hipGetLastError();
 }
 

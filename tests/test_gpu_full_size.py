@@ -104,3 +104,27 @@ def test_full_size_batched_B16_sampled(gpu):
             col = w["phi"][offs[s]:offs[s + 1], b:b + 1]
             ref = O.dos_moments(Hs, col, float(w["seg_energy_max"][s]), 16)[:, 0]
             assert err(mu[s, b], ref) < TOL, (s, b)
+
+
+def test_full_size_paper_examples_sampled(gpu):
+    """The paper's examples at full size: 2000^2 square (DOS + the first two VAC rows) and the
+    4,000,000-site chain with its two vectors as one block (DOS + the first two MSD rows of
+    the non-uniform steps), M = 32, against the oracle."""
+    say("case: full-size paper examples, M=32")
+    for w, kind in ((I.workload_paper_diffusive(), "vac"), (I.workload_paper_localized(), "msd")):
+        m, dE = w["model"], w["energy_max"]
+        H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+        Hs, V, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+        phi = w["phi"]
+        d = dev(phi)
+        dts = list(w["dt"][:2])
+        mu = host(P.gpuqt_moments(H, d, d, 32))[0]                       # [B, M]
+        if kind == "vac":
+            got = host(P.gpuqt_vac(H, d, dts, 32))[:, 0]                  # [2, B, M]
+            ref = O.vac_moments(Hs, V, phi, dts, dE, 32)                  # [2, M, B]
+        else:
+            got = host(P.gpuqt_msd(H, d, dts, 32))[:, 0]
+            ref = O.msd_moments(Hs, XH, phi, dts, dE, 32)
+        assert err(mu, O.dos_moments(Hs, phi, dE, 32).T) < TOL
+        for k in range(2):
+            assert err(got[k], ref[k].T) < TOL, (w["name"], k)

@@ -332,3 +332,36 @@ def test_full_size_honeycomb_sampled(torch_cuda):
     ref = O.evolve(Hs / dE, phi, dt, dE, Np)
     assert err(out, ref) < TOL
     assert abs(np.sum(np.abs(out) ** 2) / m.n - 1) < 1e-12
+
+
+def test_running_conductivity(torch_cuda):
+    """sigma^VAC and sigma^MSD (Section 2.2) from the square64 workload's VAC and MSD rows,
+    reconstructed on the GPU, against the oracle's rows, reconstruction and post-processing;
+    plus random rows with a zero time step."""
+    say("case: running conductivity square64")
+    w = I.workload_square64()
+    m, dE, M = w["model"], w["energy_max"], 256
+    H = build(m, dE)
+    Hs, V, XH = ops(m)
+    E = np.linspace(-4.0, 4.0, 81)
+    dts = np.array([0.5, 1.0, 0.25, 2.0, 1.0])
+    d = dev(w["phi"])
+    vac = P.gpuqt_vac(H, d, dts, M)[:, 0, 0]                     # [N_t, M]
+    msd = P.gpuqt_msd(H, d, dts, M)[:, 0, 0]
+    rv = P.gpuqt_kpm_reconstruct(vac.contiguous(), E, dE, m.volume)
+    rm = P.gpuqt_kpm_reconstruct(msd.contiguous(), E, dE, m.volume)
+    sv = host(P.gpuqt_running_conductivity(P.SIGMA_VAC, rv, dts))
+    sm = host(P.gpuqt_running_conductivity(P.SIGMA_MSD, rm, dts))
+    ov = O.vac_moments(Hs, V, w["phi"], dts, dE, M)[:, :, 0]
+    om = O.msd_moments(Hs, XH, w["phi"], dts, dE, M)[:, :, 0]
+    ref_v = O.sigma_vac(O.kpm_reconstruct(ov.T, E, dE, m.volume).T, dts)
+    ref_m, _ = O.sigma_msd(O.kpm_reconstruct(om.T, E, dE, m.volume).T, dts)
+    assert err(sv, ref_v) < TOL
+    assert err(sm, ref_m) < TOL
+    rows = np.random.default_rng(34).normal(size=(4, 33))
+    dz = np.array([0.3, 0.0, 1.1, 0.7])
+    gv = host(P.gpuqt_running_conductivity(P.SIGMA_VAC, dev(rows), dz))
+    gm = host(P.gpuqt_running_conductivity(P.SIGMA_MSD, dev(rows), dz))
+    assert err(gv, O.sigma_vac(rows, dz)) < 1e-14
+    om2, _ = O.sigma_msd(rows, dz)
+    assert np.all(np.isnan(gm[1])) and err(np.delete(gm, 1, 0), np.delete(om2, 1, 0)) < 1e-14
