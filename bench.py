@@ -382,7 +382,8 @@ def train_workload(args):
     return dict(value=fwd_steps / (tf + tb), ms_per_step=(tf + tb) * 1e3,
                 config={"workload": "square 512^2 (262,144 orbitals), NN + NNN hopping classes, DeltaE=6, "
                                     "DOS M=512 + VAC 10 x dt=1; forward + adjoint (all on-site and class "
-                                    "gradients, sqrt(M) checkpoints)", "orbitals": int(m.n), "moments": M},
+                                    "gradients; every forward vector kept, moment sets reversed in "
+                                    "the two-chain form)", "orbitals": int(m.n), "moments": M},
                 adjoint_vs_forward={"forward_ms": tf * 1e3, "adjoint_ms": tb * 1e3, "ratio": tb / tf},
                 roofline=None, cpu_baseline=None)
 

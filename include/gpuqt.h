@@ -229,8 +229,12 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
  * Method: the recurrence of Section 3.2 run forwards with checkpoints of
  * (v_{js}, v_{js+1}) every s = ckpt_stride steps (0: ceil(sqrt(M))), then the
  * adjoint recurrence lam_k = w_k phiL + 2 H~ lam_{k+1} - lam_{k+2} run backwards,
- * recomputing each block of s forward vectors from its checkpoint; ckpt_stride = 1
- * keeps every forward vector instead (M - 1 vectors of workspace, no recomputation);
+ * recomputing each block of s forward vectors from its checkpoint.  ckpt_stride = 1
+ * keeps every forward vector instead and reverses the two-chain form of the moments
+ * (Section 3.3 moments by the product identities T_2k = 2 T_k T_k - T_0,
+ * T_2k-1 = 2 T_k T_k-1 - T_1): chains a_k = T_k phiL, b_k = T_k phiR over
+ * K = max(1, M/2) steps, both adjoint chains in one launch per step, about
+ * 2K vectors of workspace and no recomputation;
  * dL/dp = Re[ sum_{k>=2} 2 <lam_k| dH~/dp v_{k-1}> + <lam_1| dH~/dp v_0> ].
  *   phiL, phiR : c128 [n][B];  w : double [n_segments][B][M];  grad_onsite : double [n];
  *   grad_class : double [n_class] or NULL (at most 4 classes);  lam0 : c128 [n][B] or NULL.
@@ -250,22 +254,27 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h h, int32_t B, const double *phiL, co
  * and the hopping classes (grad_class[c] += dL/deps_c, H_ij -> (1 + eps_c) H_ij; this also
  * scales the velocity V = i[H, X] on those bonds).
  * Method: the forward VAC series with every state psi_L(t_k), psi_R(t_k) kept, then the
- * reverse over the rows: per row the adjoints of both moment arguments (reverse moment
- * recurrence, as gpuqt_moments_backward, with checkpoints), back through phi_L = V psi_L
- * (V is Hermitian), and back through each evolution U(-dt) = sum_m c_m T_m(H~) by the same
- * reverse recurrence with sources conj(c_m) g, whose lam_0 is U(+dt) g.
+ * reverse over the rows: per row the adjoints of both moment arguments (as
+ * gpuqt_moments_backward), back through phi_L = V psi_L (V is Hermitian), and back
+ * through each evolution U(-dt) = sum_m c_m T_m(H~) by the reverse recurrence with
+ * sources conj(c_m) g, whose lam_0 is U(+dt) g.
+ *   ckpt_stride 0: the moment and evolution reverses recompute forward vectors from
+ *   checkpoints every ceil(sqrt(L)) steps (L = max(M, Np)); 1: every forward vector is
+ *   kept and each row's moments are reversed in the two-chain form (one pass gives both
+ *   adjoints and the parameter terms); needs about L vectors more workspace.
  *   phi : c128 [n][B];  dt : HOST [n_t];  w : double [n_t][n_segments][B][M];
  *   grad_onsite : double [n];  grad_class : double [n_class] or NULL (at most 4 classes).
- *   Workspace: gpuqt_vac_backward_workspace_size.
+ *   Workspace: gpuqt_vac_backward_workspace_size with the same ckpt_stride.
  */
 gpuqt_status gpuqt_vac_backward(gpuqt_h h, int32_t B, const double *phi, int32_t n_t,
                                 const double *dt, int32_t M, int32_t Np, const double *w,
-                                double *grad_onsite, double *grad_class, void *ws, size_t ws_bytes,
-                                void *stream);
+                                double *grad_onsite, double *grad_class, int32_t ckpt_stride,
+                                void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes of gpuqt_vac_backward (dt: HOST [n_t], needed for the automatic Np). */
 gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t, const double *dt,
-                                               int32_t M, int32_t Np, size_t *bytes);
+                                               int32_t M, int32_t Np, int32_t ckpt_stride,
+                                               size_t *bytes);
 
 /*
  * Choose the sparse-kernel variant for this handle by measurement: times 12

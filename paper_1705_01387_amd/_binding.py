@@ -93,11 +93,11 @@ _SIGS = {
                                                 ctypes.c_void_p]),
     "gpuqt_vac_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
-                                            ctypes.c_void_p]),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p]),
     "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                                           ctypes.POINTER(ctypes.c_size_t)]),
+                                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_kpm_reconstruct_adjoint": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                                        ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
@@ -464,31 +464,44 @@ def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad
     return grad_onsite, grad_class, lam0
 
 
-def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0) -> int:
+def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0,
+                                      ckpt_stride: int = 0) -> int:
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     out = ctypes.c_size_t()
-    _check(lib().gpuqt_vac_backward_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np,
+    _check(lib().gpuqt_vac_backward_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np, int(ckpt_stride),
                                                    ctypes.byref(out)), "gpuqt_vac_backward_workspace_size")
     return int(out.value)
 
 
 def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=None, Np: int = 0,
-                       ws=None, stream=None):
-    """Accumulate dL/dU and dL/deps_c for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M])."""
+                       ckpt_stride=None, ws=None, stream=None):
+    """Accumulate dL/dU and dL/deps_c for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M]).
+
+    ckpt_stride: 1 keeps every forward vector (two-chain reverse of each row's moments), 0
+    recomputes from checkpoints; None (default) takes 1 when its workspace fits in
+    KEEP_ALL_FRACTION of the free device memory (or 0 when ws is given)."""
     import torch
     _dev_vec(phi, "phi")
     B = _cols(phi)
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     w = w.contiguous()
     M = int(w.shape[-1])
+    if ckpt_stride is None:
+        if ws is not None:
+            ckpt_stride = 0
+        else:
+            need = gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, 1)
+            free, _ = torch.cuda.mem_get_info(phi.device)
+            ckpt_stride = 1 if need <= KEEP_ALL_FRACTION * free else 0
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
     if ws is None:
-        ws = torch.empty(max(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np), 16), dtype=torch.uint8,
-                         device=phi.device)
+        ws = torch.empty(max(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride), 16),
+                         dtype=torch.uint8, device=phi.device)
     nb = int(ws.numel() * ws.element_size())
     _check(lib().gpuqt_vac_backward(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
-                                    _ptr(grad_onsite), _ptr(grad_class), _ptr(ws), nb, _stream(stream)),
+                                    _ptr(grad_onsite), _ptr(grad_class), int(ckpt_stride), _ptr(ws), nb,
+                                    _stream(stream)),
            "gpuqt_vac_backward")
     return grad_onsite, grad_class
 

@@ -121,12 +121,19 @@ int backward_stride(int M, int stride) {
 // checkpoint pairs of the backward pass (none when every vector is kept)
 int backward_pairs(int M, int s) { return (M >= 2 && s >= 2) ? (M - 1 + s - 1) / s : 0; }
 
+// steps of the two-chain (product identity) form of an M-moment set
+int pair_steps(int M) { return std::max(1, M / 2); }
+
 // vectors of the backward workspace: 3 forward, 3 adjoint, 2 per checkpoint
-// pair and s recomputed (s >= 2), or the M - 2 kept vectors v_1 .. v_{M-2} (s = 1)
+// pair and s recomputed (s >= 2); with every vector kept (s = 1) the two-chain
+// reverse: both chains' K forward vectors and 3 adjoint vectors per chain
 int backward_vectors(int M, int s) {
-  if (s == 1) return 6 + std::max(M - 1, 1);
+  if (s == 1) return 6 + 2 * pair_steps(M);
   return 6 + 2 * backward_pairs(M, s) + s;
 }
+
+// doubles per segment of the raw-dot weights of the two-chain reverse
+int64_t raw_weight_len(int B, int M) { return (int64_t)B * (2 * pair_steps(M) + 2); }
 
 int class_stride(int n_class) { return n_class <= 1 ? 1 : (n_class <= 2 ? 2 : 4); }
 
@@ -408,6 +415,64 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
   return GPUQT_OK;
 }
 
+
+// Reverse of the two-chain moment computation with every forward vector kept:
+// chains a_k = T_k pL and b_k = T_k pR over K = pair_steps(M) steps, loss
+// weights wts [seg][B][M] on Re mu_n turned into raw-dot weights om.  When gU
+// is set, parameter terms go to gU and (nc > 0) gcp.  abar_0 = sum_n w_n T_n pR
+// (the adjoint of pL) goes to outA and bbar_0 = sum_n w_n T_n pL (the adjoint of
+// pR) to outB when they are set, added to them when accA / accB.
+// vec: backward_vectors(M, 1) vectors; om: n_seg * raw_weight_len(B, M) doubles.
+gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const double2* pR, int M,
+                               const double* wts, double* gU, double* gcp, int nc, double2* outA,
+                               bool accA, double2* outB, bool accB, double2* const* vec, double* om,
+                               hipStream_t sm) {
+  const int K = pair_steps(M);
+  const int R = 2 * K + 2;
+  HIP_TRY(launch_raw_weights(wts, h->n_seg * B, M, R, om, sm));
+  auto fa = [&](int k) -> const double2* { return k == 0 ? pL : vec[k - 1]; };
+  auto fb = [&](int k) -> const double2* { return k == 0 ? pR : vec[K + k - 1]; };
+  {
+    TimeScope ts(h, sm, FAM_PAIR, K);
+    const DevMat F = h->view(B, FAM_PAIR);
+    for (int k = 1; k <= K; ++k) {
+      ChainIO io{fa(k - 1), k >= 2 ? fa(k - 2) : nullptr, vec[k - 1],
+                 fb(k - 1), k >= 2 ? fb(k - 2) : nullptr, vec[K + k - 1], k == 1 ? 1 : 0, 1};
+      HIP_TRY(launch_moment_step_pair(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+    }
+  }
+  double2* const* La = vec + 2 * K;       // rotating abar
+  double2* const* Lb = vec + 2 * K + 3;   // rotating bbar
+  const DevMat D = h->view(B);            // class partials over the primary plan
+  for (int k = K; k >= 0; --k) {
+    if (k == 0 && !outA && !outB) break;
+    AdjPairIO io{};
+    io.xa = k + 1 <= K ? La[(k + 1) % 3] : nullptr;
+    io.wa = k + 2 <= K ? La[(k + 2) % 3] : nullptr;
+    io.xb = k + 1 <= K ? Lb[(k + 1) % 3] : nullptr;
+    io.wb = k + 2 <= K ? Lb[(k + 2) % 3] : nullptr;
+    io.oa = (k == 0 && outA) ? outA : La[k % 3];
+    io.ob = (k == 0 && outB) ? outB : Lb[k % 3];
+    io.acc_a = (k == 0 && outA && accA) ? 1 : 0;
+    io.acc_b = (k == 0 && outB && accB) ? 1 : 0;
+    io.a_m1 = k >= 1 ? fa(k - 1) : nullptr;
+    io.a_k = fa(k);
+    io.a_p1 = k + 1 <= K ? fa(k + 1) : nullptr;
+    io.b_m1 = k >= 1 ? fb(k - 1) : nullptr;
+    io.b_k = fb(k);
+    io.om = om;
+    io.R = R;
+    io.k = k;
+    io.f_rec = k >= 1 ? 2.0 : 1.0;
+    io.f = k >= 2 ? 2.0 : 1.0;
+    io.gU = gU;
+    io.gcp = gcp;
+    io.cls = h->d_cls;
+    HIP_TRY(launch_adjoint_pair_step(D, h->hop_mode, B, gU ? nc : 0, io, sm));
+  }
+  return GPUQT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -671,7 +736,7 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
   const int64_t ldJ = has_J ? (Np > 0 ? Np : kAutoNpCap) : 0;
   if (op == GPUQT_OP_MOMENTS_BACKWARD) {
     const int s = backward_stride(M, Np);
-    *bytes = ws_layout(h, backward_vectors(M, s), B, 2, 0).total;
+    *bytes = ws_layout(h, backward_vectors(M, s), B, 2, s == 1 ? raw_weight_len(B, M) : 0).total;
     return GPUQT_OK;
   }
   *bytes = ws_layout(h, nv, B, rows, ldJ).total;
@@ -883,7 +948,7 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   const int s = backward_stride(M, ckpt_stride);
-  const WsLayout W = ws_layout(h, backward_vectors(M, s), B, 2, 0);
+  const WsLayout W = ws_layout(h, backward_vectors(M, s), B, 2, s == 1 ? raw_weight_len(B, M) : 0);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -894,49 +959,63 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   double* gcp = reinterpret_cast<double*>(base + W.off_part);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
-  BwdSource src;
-  src.wts = w;
-  if ((st = run_backward(h, B, reinterpret_cast<const double2*>(phiL),
-                         reinterpret_cast<const double2*>(phiR), M, src, grad_onsite, gcp, nc,
-                         reinterpret_cast<double2*>(lam0), false, s, vec.data(), sm)))
-    return st;
+  if (s == 1) {   // every forward vector kept: reverse of the two-chain form
+    if ((st = run_backward_pair(h, B, reinterpret_cast<const double2*>(phiL),
+                                reinterpret_cast<const double2*>(phiR), M, w, grad_onsite, gcp, nc,
+                                nullptr, false, reinterpret_cast<double2*>(lam0), false, vec.data(),
+                                reinterpret_cast<double*>(base + W.off_J), sm)))
+      return st;
+  } else {
+    BwdSource src;
+    src.wts = w;
+    if ((st = run_backward(h, B, reinterpret_cast<const double2*>(phiL),
+                           reinterpret_cast<const double2*>(phiR), M, src, grad_onsite, gcp, nc,
+                           reinterpret_cast<double2*>(lam0), false, s, vec.data(), sm)))
+      return st;
+  }
   if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
   return GPUQT_OK;
 }
 
-// number of workspace vectors of gpuqt_vac_backward
-static int vac_backward_vectors(int n_t, int M, int Np) {
+// number of workspace vectors of gpuqt_vac_backward (keep: every forward vector
+// kept, two-chain reverse of the rows; else checkpoints every ceil(sqrt(L)) steps)
+static int vac_backward_vectors(int n_t, int M, int Np, bool keep) {
   const int L = std::max(M, Np);
-  return 2 * n_t + 6 + backward_vectors(L, backward_stride(L, 0));
+  return 2 * n_t + 6 + backward_vectors(L, keep ? 1 : backward_stride(L, 0));
 }
 
 gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
-                                               int32_t M, int32_t Np, size_t* bytes) {
+                                               int32_t M, int32_t Np, int32_t ckpt_stride, size_t* bytes) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
   if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
   if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
   if (n_t < 0 || M < 0 || Np < 0 || (n_t > 0 && !dt)) return fail(GPUQT_ERR_ARG, "bad sizes");
+  if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
+  const bool keep = ckpt_stride == 1;
   const int np = max_terms(h, std::max(n_t - 1, 0), dt, Np);
-  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np), B, 2, np).total;
+  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np, keep), B, 2,
+                     np + (keep ? raw_weight_len(B, M) : 0)).total;
   return GPUQT_OK;
 }
 
 gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
                                 const double* dt, int32_t M, int32_t Np, const double* w,
-                                double* grad_onsite, double* grad_class, void* ws, size_t ws_bytes,
-                                void* stream) {
+                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, void* ws,
+                                size_t ws_bytes, void* stream) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, w);
   if (st) return st;
+  if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
+  const bool keep = ckpt_stride == 1;
   if (!grad_onsite) return fail(GPUQT_ERR_ARG, "grad_onsite is NULL");
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   if (n_t == 0 || M == 0) return GPUQT_OK;
   const int np = max_terms(h, n_t - 1, dt, Np);
   const int L = std::max(M, np);
-  const int s = backward_stride(L, 0);
-  const int nv = vac_backward_vectors(n_t, M, np);
-  const WsLayout W = ws_layout(h, nv, B, 2, np);
+  const int s = keep ? 1 : backward_stride(L, 0);
+  const int nv = vac_backward_vectors(n_t, M, np, keep);
+  const WsLayout W = ws_layout(h, nv, B, 2, np + (keep ? raw_weight_len(B, M) : 0));
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -978,16 +1057,24 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   const int64_t row = (int64_t)h->n_seg * B * M;
   for (int k = n_t - 1; k >= 0; --k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL(k), phiL, sm));
-    BwdSource src;
-    src.wts = w + row * k;
-    // moments of row k: parameter terms, and gR += sum_n w_n T_n phiL
-    if ((st = run_backward(h, B, phiL, psiR(k), M, src, grad_onsite, gcp, nc, gR[cr], true, s,
-                           pool.data(), sm)))
-      return st;
-    // gphiL = sum_n w_n T_n psi_R(k) (no parameter terms)
-    if ((st = run_backward(h, B, psiR(k), phiL, M, src, nullptr, nullptr, 0, gphiL, false, s,
-                           pool.data(), sm)))
-      return st;
+    if (keep) {
+      // moments of row k by the two-chain reverse: parameter terms,
+      // gphiL = sum_n w_n T_n psi_R(k) and gR += sum_n w_n T_n phiL in one pass
+      if ((st = run_backward_pair(h, B, phiL, psiR(k), M, w + row * k, grad_onsite, gcp, nc, gphiL, false,
+                                  gR[cr], true, pool.data(), J + (int64_t)h->n_seg * np, sm)))
+        return st;
+    } else {
+      BwdSource src;
+      src.wts = w + row * k;
+      // moments of row k: parameter terms, and gR += sum_n w_n T_n phiL
+      if ((st = run_backward(h, B, phiL, psiR(k), M, src, grad_onsite, gcp, nc, gR[cr], true, s,
+                             pool.data(), sm)))
+        return st;
+      // gphiL = sum_n w_n T_n psi_R(k) (no parameter terms)
+      if ((st = run_backward(h, B, psiR(k), phiL, M, src, nullptr, nullptr, 0, gphiL, false, s,
+                             pool.data(), sm)))
+        return st;
+    }
     // phiL = V psi_L: gL += V gphiL, class terms of V
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY | kAccumulate, gphiL, gL[cl], sm));
     if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gphiL, psiL(k), h->d_cls, gcp, sm));

@@ -309,6 +309,39 @@ struct AdjIO {
   int32_t accumulate;    // 1: out += lam (instead of out = lam)
   double2 src_phase;
 };
+// Reverse of the two-chain (product identity) moment computation: chains
+// a_k = T_k a_0, b_k = T_k b_0 and L = sum_n om_n Re r_n over the raw dots
+// r_2k = <a_k|b_k>, r_2k-1 = <a_k|b_k-1>, r_0 = <a_0|b_0>; one step k yields
+// abar_k = om_2k b_k + om_2k-1 b_k-1 + f_rec H~ abar_k+1 - abar_k+2 and
+// bbar_k = om_2k a_k + om_2k+1 a_k+1 + f_rec H~ bbar_k+1 - bbar_k+2.
+struct AdjPairIO {
+  const double2* xa;     // abar_{k+1}, gathered (NULL: zero)
+  const double2* wa;     // abar_{k+2} (NULL: zero)
+  double2* oa;           // abar_k
+  const double2* xb;
+  const double2* wb;
+  double2* ob;
+  const double2* a_m1;   // a_{k-1} (gradient terms; NULL for k = 0)
+  const double2* a_k;
+  const double2* a_p1;   // a_{k+1} (NULL: om_{2k+1} = 0)
+  const double2* b_m1;
+  const double2* b_k;
+  const double* om;      // [n_seg][B][R] raw-dot weights
+  int32_t R, k;
+  double f_rec;          // 2 for k >= 1, 1 for k = 0
+  double f;              // gradient factor: 2 for k >= 2, 1 for k = 1 (unused for k = 0)
+  double* gU;            // [n] accumulated (NULL: no parameter terms)
+  double* gcp;           // [G][nc] accumulated per workgroup
+  const int32_t* cls;
+  int32_t acc_a, acc_b;  // 1: oa += abar_k, ob += bbar_k
+};
+hipError_t launch_adjoint_pair_step(const DevMat& A, int hop_mode, int B, int nc, const AdjPairIO& io,
+                                    hipStream_t s);
+// om[s][b][r] for r < R from loss weights w[s][b][n], n < M (raw-dot weights of
+// the product identities: om_0 = w_0 - sum of even w_n (n >= 2), om_1 = w_1 -
+// sum of odd w_n (n >= 3), om_n = 2 w_n for 2 <= n < M, 0 beyond)
+hipError_t launch_raw_weights(const double* w, int rows, int M, int R, double* om, hipStream_t s);
+
 // parameter updates (gpuqt_update_h_values)
 constexpr int kMaxUpdateClasses = 8;
 struct ClassScale {

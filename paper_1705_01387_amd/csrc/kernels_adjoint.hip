@@ -114,6 +114,141 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
   }
 }
 
+// Reverse step of the two-chain form (both adjoint chains in one launch, the
+// matrix read once; abar_{k+1}, bbar_{k+1} and, for class gradients, a_{k-1},
+// b_{k-1} gathered with the same indices).  Parameter terms, as for the
+// single chain: dL/dp = Re sum_k f_k (<abar_k| dH~/dp a_{k-1}> + <bbar_k| dH~/dp b_{k-1}>).
+template <int B, int HOP, int K, int NC>
+__global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairIO io) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double inv_dE = 1.0 / A.seg_dE[P.seg];
+  const int b = threadIdx.x & (B - 1);
+  const double* om = io.om + ((int64_t)P.seg * B + b) * io.R;
+  const int k2 = 2 * io.k;
+  const double w0 = om[k2];
+  const double wm = io.k >= 1 ? om[k2 - 1] : 0.0;
+  const double wp = (io.a_p1 && k2 + 1 < io.R) ? om[k2 + 1] : 0.0;
+  const bool grad = io.gU != nullptr && io.k >= 1;
+  const int S = 1 << A.S_log2;
+  double gc[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int c = 0; c < (NC > 0 ? NC : 1); ++c) gc[c] = 0.0;
+  for_rows<B>(A, P, [&](int64_t r) {
+    const int64_t idx = r * B + b;
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = K > 0 ? K : (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    double2 ha = make_double2(0.0, 0.0), hb = make_double2(0.0, 0.0);
+    double2 hva[NC > 0 ? NC : 1], hvb[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int c = 0; c < (NC > 0 ? NC : 1); ++c) {
+      hva[c] = make_double2(0.0, 0.0);
+      hvb[c] = make_double2(0.0, 0.0);
+    }
+    if (io.xa) {
+      const double d = A.diag[r];
+      ha = cscale(d, io.xa[idx]);
+      hb = cscale(d, io.xb[idx]);
+    }
+    for (int j = 0; j < w; ++j) {
+      const int64_t e = e0 + (int64_t)j * S;
+      const int32_t c = A.col[e];
+      const bool ok = c >= 0;
+      const int64_t cc = ok ? (int64_t)c : r;
+      double2 he;
+      if (HOP == HOP_UNIFORM) {
+        he = make_double2(ok ? hu : 0.0, 0.0);
+      } else if (HOP == HOP_REAL) {
+        he = make_double2(A.hop[e], 0.0);
+      } else {
+        he = reinterpret_cast<const double2*>(A.hop)[e];
+      }
+      if (io.xa) {
+        const double2 xa = io.xa[cc * B + b], xb = io.xb[cc * B + b];
+        ha = cadd(ha, HOP == HOP_COMPLEX ? cmul(he, xa) : cscale(he.x, xa));
+        hb = cadd(hb, HOP == HOP_COMPLEX ? cmul(he, xb) : cscale(he.x, xb));
+      }
+      if (NC > 0 && grad) {
+        const double2 va = io.a_m1[cc * B + b], vb = io.b_m1[cc * B + b];
+        const double2 ta = HOP == HOP_COMPLEX ? cmul(he, va) : cscale(he.x, va);
+        const double2 tb = HOP == HOP_COMPLEX ? cmul(he, vb) : cscale(he.x, vb);
+        const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
+#pragma unroll
+        for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+          if (q == cls) {
+            hva[q] = cadd(hva[q], ta);
+            hvb[q] = cadd(hvb[q], tb);
+          }
+      }
+    }
+    // direct sensitivities of the raw dots
+    double2 ga = cscale(w0, io.b_k[idx]);
+    if (io.k >= 1) ga = cadd(ga, cscale(wm, io.b_m1[idx]));
+    double2 gb = cscale(w0, io.a_k[idx]);
+    if (io.a_p1) gb = cadd(gb, cscale(wp, io.a_p1[idx]));
+    double2 la = make_double2(fma(io.f_rec, ha.x, ga.x), fma(io.f_rec, ha.y, ga.y));
+    double2 lbv = make_double2(fma(io.f_rec, hb.x, gb.x), fma(io.f_rec, hb.y, gb.y));
+    if (io.wa) {
+      const double2 u = io.wa[idx], v = io.wb[idx];
+      la = make_double2(la.x - u.x, la.y - u.y);
+      lbv = make_double2(lbv.x - v.x, lbv.y - v.y);
+    }
+    io.oa[idx] = io.acc_a ? cadd(io.oa[idx], la) : la;
+    io.ob[idx] = io.acc_b ? cadd(io.ob[idx], lbv) : lbv;
+    if (grad) {
+      const double2 va = io.a_m1[idx], vb = io.b_m1[idx];
+      double gu = io.f * (la.x * va.x + la.y * va.y + lbv.x * vb.x + lbv.y * vb.y);
+#pragma unroll
+      for (int off = 1; off < B; off <<= 1) gu += __shfl_xor(gu, off);
+      if (b == 0) io.gU[r] += gu * inv_dE;
+#pragma unroll
+      for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+        if (NC > 0)
+          gc[q] += io.f * (la.x * hva[q].x + la.y * hva[q].y + lbv.x * hvb[q].x + lbv.y * hvb[q].y);
+    }
+  });
+  if (NC == 0 || !grad) return;
+  __shared__ double sh[kBlock / 64][NC > 0 ? NC : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < (NC > 0 ? NC : 1); ++q) {
+    double s = gc[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < (NC > 0 ? NC : 1)) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) s += sh[wv][threadIdx.x];
+    io.gcp[(int64_t)lb * NC + threadIdx.x] += s;
+  }
+}
+
+// Raw-dot weights of the product identities, one thread per (segment, column).
+__global__ void k_raw_weights(const double* __restrict__ w, int rows, int M, int R, double* __restrict__ om) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const double* wi = w + (int64_t)i * M;
+  double* oi = om + (int64_t)i * R;
+  double even = 0.0, odd = 0.0;
+  for (int n = 2; n < M; ++n) {
+    if (n & 1) odd += wi[n];
+    else even += wi[n];
+  }
+  for (int n = 0; n < R; ++n) {
+    double v = 0.0;
+    if (n == 0) v = (M > 0 ? wi[0] : 0.0) - even;
+    else if (n == 1) v = (M > 1 ? wi[1] : 0.0) - odd;
+    else if (n < M) v = 2.0 * wi[n];
+    oi[n] = v;
+  }
+}
+
 // gcp[lb][c] += Re sum_i conj(a_i) (V_c x)_i over the workgroup's rows, with
 // V_c = i dx H_c the velocity restricted to the class-c hoppings (unscaled:
 // the stored H~ is multiplied back by DeltaE).
@@ -275,6 +410,35 @@ hipError_t launch_adjoint_step(const DevMat& A, int hop_mode, int B, int nc, con
       default: go(IC<0>{}); break;
     }
   });
+}
+
+hipError_t launch_adjoint_pair_step(const DevMat& A, int hop_mode, int B, int nc, const AdjPairIO& io,
+                                    hipStream_t s) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    constexpr int Bv = decltype(Bc)::value, Hv = decltype(Hc)::value;
+    auto go = [&](auto Kc) {
+      constexpr int Kv = decltype(Kc)::value;
+      switch (nc) {
+        case 0: k_adjoint_pair_step<Bv, Hv, Kv, 0><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 1: k_adjoint_pair_step<Bv, Hv, Kv, 1><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 2: k_adjoint_pair_step<Bv, Hv, Kv, 2><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        default: k_adjoint_pair_step<Bv, Hv, Kv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+      }
+    };
+    switch (A.K) {
+      case 3: go(IC<3>{}); break;
+      case 4: go(IC<4>{}); break;
+      case 6: go(IC<6>{}); break;
+      case 8: go(IC<8>{}); break;
+      default: go(IC<0>{}); break;
+    }
+  });
+}
+
+hipError_t launch_raw_weights(const double* w, int rows, int M, int R, double* om, hipStream_t s) {
+  if (rows <= 0 || R <= 0) return hipSuccess;
+  k_raw_weights<<<dim3((rows + 63) / 64), 64, 0, s>>>(w, rows, M, R, om);
+  return hipGetLastError();
 }
 
 hipError_t launch_velocity_class_grad(const DevMat& A, int hop_mode, int B, int nc, const double2* a,

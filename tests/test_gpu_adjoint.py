@@ -77,7 +77,8 @@ def test_backward_accumulates_and_is_deterministic(gpu):
     assert np.array_equal(host(a[0]), host(b[0])) and np.array_equal(host(a[1]), host(b[1]))
     g2 = a[0].clone()
     P.gpuqt_moments_backward(H, phi, phi, w, grad_onsite=g2)
-    assert np.allclose(host(g2), 2 * host(a[0]), rtol=1e-14, atol=0)
+    # adding into a non-zero gradient rounds each step's term differently: normwise bar
+    assert err(host(g2), 2 * host(a[0])) < 1e-14
 
 
 VAC_CASES = {
@@ -89,10 +90,11 @@ VAC_CASES = {
 
 @pytest.mark.parametrize("name", list(VAC_CASES))
 @pytest.mark.parametrize("B", [1, 2])
-def test_vac_backward(gpu, name, B):
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_vac_backward(gpu, name, B, ckpt):
     import torch
     from oracle.adjoint import vac_gradient, velocity_class_parts
-    say(f"case: VAC backward {name} B={B}")
+    say(f"case: VAC backward {name} B={B} ckpt_stride={ckpt}")
     mk, n_class = VAC_CASES[name]
     m = mk()
     H = P.gpuqt_build_h_from_model(m)
@@ -104,7 +106,7 @@ def test_vac_backward(gpu, name, B):
     dts = [0.3, 1.2, 0.0, 0.7]
     M = 40
     w = np.random.default_rng(59).normal(size=(len(dts), 1, B, M))
-    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w),
+    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=ckpt,
                                   grad_class=torch.zeros(n_class, dtype=torch.float64, device="cuda"))
     rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
     assert err(host(gU), rU) < TOL
@@ -122,8 +124,11 @@ def test_backward_segments(gpu):
     phi = I.random_phase(cat.n, 1, 53)
     M = 50
     w = np.random.default_rng(54).normal(size=(2, 1, M))
-    gU, gC, _ = P.gpuqt_moments_backward(H, dev(phi), dev(phi), dev(w),
+    gU, gC, _ = P.gpuqt_moments_backward(H, dev(phi), dev(phi), dev(w), ckpt_stride=0,
                                          grad_class=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    gU1, gC1, _ = P.gpuqt_moments_backward(H, dev(phi), dev(phi), dev(w), ckpt_stride=1,
+                                           grad_class=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    assert err(host(gU1), host(gU)) < TOL and abs(host(gC1)[0] - host(gC)[0]) < TOL * abs(host(gC)[0])
     gU = host(gU)
     tot = 0.0
     for s, mm in enumerate(mods):
