@@ -355,6 +355,39 @@ gpuqt_status gpuqt_timing(gpuqt_h h, double *ms, int64_t *launches);
 
 /* Host helpers (no device use). */
 
+/*
+ * Input folder of the paper's program (Section 4.2), read on the host:
+ *   neighbour.in  "N max_nn", then per site "count j_1 j_2 ..." (required)
+ *   hopping.in    "real" or "complex", then per site the hoppings of its neighbours in
+ *                 neighbour.in order (complex: re im pairs); absent: every hopping is -1
+ *   potential.in  one on-site energy per site; absent: 0
+ *   position.in   "length_x volume", then one coordinate per site (required)
+ *   energy.in     count, then the energies (required)
+ *   time_step.in  count, then the time steps (required when VAC or MSD is asked for)
+ *   para.in       keywords calculate_vac, calculate_msd, number_of_random_vectors N_r,
+ *                 number_of_moments N_m, energy_max DeltaE; defaults N_r = 1,
+ *                 N_m = 1000, DeltaE = 10 (Section 4.2.7)
+ * gpuqt_model_load returns GPUQT_ERR_ARG for a missing required file and
+ * GPUQT_ERR_LAYOUT with file:line for malformed contents.  The model owns its arrays;
+ * gpuqt_model_desc fills a descriptor pointing into them (valid until gpuqt_model_free).
+ */
+typedef struct gpuqt_model_s *gpuqt_model;
+typedef struct {
+  int32_t n_random_vectors;
+  int32_t n_moments;
+  double energy_max;
+  int32_t calculate_vac;
+  int32_t calculate_msd;
+  int32_t n_energies;
+  int32_t n_time_steps;
+  const double *energies;    /* HOST [n_energies], owned by the model */
+  const double *time_steps;  /* HOST [n_time_steps] or NULL, owned by the model */
+} gpuqt_model_params_t;
+gpuqt_status gpuqt_model_load(const char *dir, gpuqt_model *out);
+gpuqt_status gpuqt_model_desc(gpuqt_model m, gpuqt_h_desc *d);
+gpuqt_status gpuqt_model_params(gpuqt_model m, gpuqt_model_params_t *p);
+void gpuqt_model_free(gpuqt_model m);
+
 /* The row schedule of the sparse kernels, as the library plans it for `cus` compute units
  * and block width B (introspection; the kernels enumerate rows with the same host/device
  * rule): segments seg_offsets (HOST [n_segments+1], from 0, ascending), row period per

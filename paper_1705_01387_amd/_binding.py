@@ -56,6 +56,14 @@ class HInfo(ctypes.Structure):
     ]
 
 
+class ModelParams(ctypes.Structure):
+    _fields_ = [
+        ("n_random_vectors", ctypes.c_int32), ("n_moments", ctypes.c_int32), ("energy_max", ctypes.c_double),
+        ("calculate_vac", ctypes.c_int32), ("calculate_msd", ctypes.c_int32), ("n_energies", ctypes.c_int32),
+        ("n_time_steps", ctypes.c_int32), ("energies", ctypes.c_void_p), ("time_steps", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 _SIGS = {
@@ -110,6 +118,10 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_copy_probe": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gpuqt_set_variant": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "gpuqt_model_load": (ctypes.c_int32, [ctypes.c_char_p, ctypes.c_void_p]),
+    "gpuqt_model_desc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_model_params": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_model_free": (None, [ctypes.c_void_p]),
     "gpuqt_running_conductivity": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
@@ -579,6 +591,49 @@ def gpuqt_schedule_rows(seg_offsets, period=None, band_rows=0, cus=256, B=1):
     _check(lib().gpuqt_schedule_rows(len(off) - 1, _ptr(off), _ptr(per), int(band_rows), int(cus), int(B),
                                      _ptr(blk), _ptr(it)), "gpuqt_schedule_rows")
     return blk, it
+
+
+class InputFolder:
+    """An input folder of the paper's program (Section 4.2), read by the library's reader:
+    the model arrays (nn, nbr, hop, onsite, x, length_x, volume) and the run parameters."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def gpuqt_model_load(path) -> InputFolder:
+    """Read neighbour.in, hopping.in, potential.in, position.in, energy.in, time_step.in and
+    para.in from a folder (host only); returns copies of the arrays."""
+    h = ctypes.c_void_p()
+    _check(lib().gpuqt_model_load(os.fsencode(str(path)), ctypes.byref(h)), "gpuqt_model_load")
+    try:
+        d = _Desc()
+        _check(lib().gpuqt_model_desc(h, ctypes.byref(d)), "gpuqt_model_desc")
+        p = ModelParams()
+        _check(lib().gpuqt_model_params(h, ctypes.byref(p)), "gpuqt_model_params")
+        n, k = int(d.n), int(d.max_nn)
+
+        def arr(ptr, count, ctype):
+            if not ptr or count == 0:
+                return None
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(count,)).copy()
+
+        hop = None
+        if d.hop:
+            raw = arr(d.hop, n * k * (2 if d.hop_is_complex else 1), ctypes.c_double)
+            hop = raw.view(np.complex128).reshape(n, k) if d.hop_is_complex else raw.reshape(n, k)
+        nbr = arr(d.nbr, n * k, ctypes.c_int32)
+        return InputFolder(
+            n=n, max_nn=k, nn=arr(d.nn, n, ctypes.c_int32),
+            nbr=nbr.reshape(n, k) if nbr is not None else np.zeros((n, 0), np.int32), hop=hop,
+            onsite=arr(d.onsite, n, ctypes.c_double), x=arr(d.x, n, ctypes.c_double),
+            length_x=float(d.length_x), volume=float(d.volume), energy_max=float(p.energy_max),
+            n_random_vectors=int(p.n_random_vectors), n_moments=int(p.n_moments),
+            calculate_vac=bool(p.calculate_vac), calculate_msd=bool(p.calculate_msd),
+            energies=arr(p.energies, p.n_energies, ctypes.c_double),
+            time_steps=arr(p.time_steps, p.n_time_steps, ctypes.c_double))
+    finally:
+        lib().gpuqt_model_free(h)
 
 
 def gpuqt_copy_probe(src, dst, stream=None):

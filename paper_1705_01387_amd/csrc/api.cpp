@@ -21,6 +21,12 @@ gpuqt_status fail(gpuqt_status st, const std::string& msg) {
   return st;
 }
 
+}  // namespace
+
+gpuqt_status gpuqt::set_error(gpuqt_status st, const std::string& msg) { return fail(st, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -422,11 +428,13 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
 // is set, parameter terms go to gU and (nc > 0) gcp.  abar_0 = sum_n w_n T_n pR
 // (the adjoint of pL) goes to outA and bbar_0 = sum_n w_n T_n pL (the adjoint of
 // pR) to outB when they are set, added to them when accA / accB.
-// vec: backward_vectors(M, 1) vectors; om: n_seg * raw_weight_len(B, M) doubles.
+// vec: backward_vectors(M, 1) vectors; om: n_seg * raw_weight_len(B, M) doubles;
+// scratch: 3 partial rows (G x B each) that the forward two-chain steps fill and
+// nobody reads.
 gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                                const double* wts, double* gU, double* gcp, int nc, double2* outA,
                                bool accA, double2* outB, bool accB, double2* const* vec, double* om,
-                               hipStream_t sm) {
+                               double2* scratch, hipStream_t sm) {
   const int K = pair_steps(M);
   const int R = 2 * K + 2;
   HIP_TRY(launch_raw_weights(wts, h->n_seg * B, M, R, om, sm));
@@ -435,10 +443,11 @@ gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const 
   {
     TimeScope ts(h, sm, FAM_PAIR, K);
     const DevMat F = h->view(B, FAM_PAIR);
+    const int64_t row = (int64_t)F.G * B;
     for (int k = 1; k <= K; ++k) {
       ChainIO io{fa(k - 1), k >= 2 ? fa(k - 2) : nullptr, vec[k - 1],
                  fb(k - 1), k >= 2 ? fb(k - 2) : nullptr, vec[K + k - 1], k == 1 ? 1 : 0, 1};
-      HIP_TRY(launch_moment_step_pair(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+      HIP_TRY(launch_moment_step_pair(F, h->hop_mode, B, io, scratch, scratch + row, scratch + 2 * row, sm));
     }
   }
   double2* const* La = vec + 2 * K;       // rotating abar
@@ -736,7 +745,7 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
   const int64_t ldJ = has_J ? (Np > 0 ? Np : kAutoNpCap) : 0;
   if (op == GPUQT_OP_MOMENTS_BACKWARD) {
     const int s = backward_stride(M, Np);
-    *bytes = ws_layout(h, backward_vectors(M, s), B, 2, s == 1 ? raw_weight_len(B, M) : 0).total;
+    *bytes = ws_layout(h, backward_vectors(M, s), B, s == 1 ? 5 : 2, s == 1 ? raw_weight_len(B, M) : 0).total;
     return GPUQT_OK;
   }
   *bytes = ws_layout(h, nv, B, rows, ldJ).total;
@@ -948,7 +957,7 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   const int s = backward_stride(M, ckpt_stride);
-  const WsLayout W = ws_layout(h, backward_vectors(M, s), B, 2, s == 1 ? raw_weight_len(B, M) : 0);
+  const WsLayout W = ws_layout(h, backward_vectors(M, s), B, s == 1 ? 5 : 2, s == 1 ? raw_weight_len(B, M) : 0);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -963,7 +972,8 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
     if ((st = run_backward_pair(h, B, reinterpret_cast<const double2*>(phiL),
                                 reinterpret_cast<const double2*>(phiR), M, w, grad_onsite, gcp, nc,
                                 nullptr, false, reinterpret_cast<double2*>(lam0), false, vec.data(),
-                                reinterpret_cast<double*>(base + W.off_J), sm)))
+                                reinterpret_cast<double*>(base + W.off_J),
+                                reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm)))
       return st;
   } else {
     BwdSource src;
@@ -993,7 +1003,7 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_
   if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
   const bool keep = ckpt_stride == 1;
   const int np = max_terms(h, std::max(n_t - 1, 0), dt, Np);
-  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np, keep), B, 2,
+  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np, keep), B, keep ? 5 : 2,
                      np + (keep ? raw_weight_len(B, M) : 0)).total;
   return GPUQT_OK;
 }
@@ -1015,7 +1025,7 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   const int L = std::max(M, np);
   const int s = keep ? 1 : backward_stride(L, 0);
   const int nv = vac_backward_vectors(n_t, M, np, keep);
-  const WsLayout W = ws_layout(h, nv, B, 2, np + (keep ? raw_weight_len(B, M) : 0));
+  const WsLayout W = ws_layout(h, nv, B, keep ? 5 : 2, np + (keep ? raw_weight_len(B, M) : 0));
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
   if ((st = check_device(h))) return st;
@@ -1061,7 +1071,8 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
       // moments of row k by the two-chain reverse: parameter terms,
       // gphiL = sum_n w_n T_n psi_R(k) and gR += sum_n w_n T_n phiL in one pass
       if ((st = run_backward_pair(h, B, phiL, psiR(k), M, w + row * k, grad_onsite, gcp, nc, gphiL, false,
-                                  gR[cr], true, pool.data(), J + (int64_t)h->n_seg * np, sm)))
+                                  gR[cr], true, pool.data(), J + (int64_t)h->n_seg * np,
+                                  reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm)))
         return st;
     } else {
       BwdSource src;

@@ -203,6 +203,9 @@ struct HostLayout {
   std::vector<double> seg_hop;
 };
 
+// Set the calling thread's gpuqt_last_error text and return st (api.cpp).
+gpuqt_status set_error(gpuqt_status st, const std::string& msg);
+
 // layout.cpp: validate the descriptor and build the sliced ELL on the host.
 // Returns GPUQT_OK or an error status with *msg set.
 gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string* msg);

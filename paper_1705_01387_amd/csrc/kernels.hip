@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
     const double2 yb = first ? hb : twice_minus(hb, ld2<NT>(io.wb + idx));
     io.oa[idx] = ya;
     io.ob[idx] = yb;
-    if (!part_a) return;   // both chains without the dots (adjoint's forward pass)
     const double2 xb = io.xb[idx];
     if (first) {
       const double2 xa = io.xa[idx];
@@ -164,7 +163,6 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
     }
     cdot_acc(cr, ci, ya, yb);
   });
-  if (!part_a) return;
   block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
   __syncthreads();
   block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);

@@ -28,9 +28,11 @@ def test_library_exports_every_declared_symbol():
     assert "gpuqt_moments" in syms and "gpuqt_msd" in syms and "gpuqt_build_h" in syms
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    # every declared symbol has a binding of the same name
+    # every declared symbol has a binding of the same name (handle lifetime and the model
+    # accessors are used inside Hamiltonian and gpuqt_model_load)
+    inside = ("gpuqt_destroy_h", "gpuqt_h_info", "gpuqt_model_desc", "gpuqt_model_params", "gpuqt_model_free")
     for s in syms:
-        assert hasattr(P, s) or s in ("gpuqt_destroy_h", "gpuqt_h_info"), s
+        assert hasattr(P, s) or s in inside, s
 
 
 def test_bessel_matches_high_precision():
@@ -107,7 +109,8 @@ def test_ctypes_mirrors_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gpuqt.h"', 'int main(void){']
-    for cname, mirror in (("gpuqt_h_desc", Bd._Desc), ("gpuqt_h_info_t", Bd.HInfo)):
+    for cname, mirror in (("gpuqt_h_desc", Bd._Desc), ("gpuqt_h_info_t", Bd.HInfo),
+                          ("gpuqt_model_params_t", Bd.ModelParams)):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in mirror._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -120,7 +123,8 @@ def test_ctypes_mirrors_match_the_header(tmp_path):
     for ln in subprocess.check_output([str(exe)], text=True).splitlines():
         cname, f, v = ln.split()
         got[(cname, f)] = int(v)
-    for cname, mirror in (("gpuqt_h_desc", Bd._Desc), ("gpuqt_h_info_t", Bd.HInfo)):
+    for cname, mirror in (("gpuqt_h_desc", Bd._Desc), ("gpuqt_h_info_t", Bd.HInfo),
+                          ("gpuqt_model_params_t", Bd.ModelParams)):
         assert got[(cname, "size")] == ctypes.sizeof(mirror)
         for f, _ in mirror._fields_:
             assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)
