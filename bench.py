@@ -66,9 +66,11 @@ FAMILY_VECTOR_BYTES = {
     "moment_pair": 96,   # two chains: 2 x (gathered), 2 v_{n-2}, 2 v_n
     "evolve": 80,        # x, v_{n-2}, v_n, accumulator read + write
     "msd": 160,          # two chains as moment_pair + two accumulators read + write
+    "evolve_pair": 160,  # two chains as moment_pair + two accumulators read + write
 }
 FAMILY_KERNEL = {"moment": "k_moment_step", "moment_sym": "k_moment_step_sym",
-                 "moment_pair": "k_moment_step_pair", "evolve": "k_evolve_term", "msd": "k_msd_term"}
+                 "moment_pair": "k_moment_step_pair", "evolve": "k_evolve_term", "msd": "k_msd_term",
+                 "evolve_pair": "k_evolve_pair_term"}
 
 
 def family_bytes(info, B, family="moment"):
@@ -149,7 +151,14 @@ def copy_probe_gbs(P, torch, dev):
 
 
 def cpu_oracle_sample(m, phi, dE, B, Mc, seconds=15.0):
-    """The oracle's DOS recurrence on the full lattice, sized to about `seconds` of CPU work."""
+    """The oracle's DOS recurrence on the full lattice, sized to about `seconds` of CPU work,
+    with every BLAS / OpenMP pool held to one thread (the figure is per host thread)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_oracle_sample(m, phi, dE, B, Mc, seconds)
+
+
+def _cpu_oracle_sample(m, phi, dE, B, Mc, seconds):
     import oracle as O
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     if Mc <= 0:

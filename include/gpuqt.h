@@ -339,7 +339,8 @@ enum {
   GPUQT_K_MOMENT_PAIR = 2,  /* moment step with two chains (phiL != phiR) */
   GPUQT_K_EVOLVE = 3,       /* evolution series term */
   GPUQT_K_MSD = 4,          /* fused evolution + commutator series term */
-  GPUQT_K_COUNT = 5
+  GPUQT_K_EVOLVE_PAIR = 5,  /* evolution series term on two vectors (the VAC states) */
+  GPUQT_K_COUNT = 6
 };
 
 /* enable != 0: every later compute call on the handle records a HIP event before and after

@@ -535,7 +535,7 @@ def gpuqt_kpm_reconstruct_adjoint(g, energies, M: int, energy_max: float, volume
     return out
 
 
-K_FAMILIES = ("moment", "moment_sym", "moment_pair", "evolve", "msd")
+K_FAMILIES = ("moment", "moment_sym", "moment_pair", "evolve", "msd", "evolve_pair")
 
 
 def gpuqt_set_timing(H: Hamiltonian, enable: bool = True):

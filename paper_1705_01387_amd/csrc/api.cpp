@@ -310,6 +310,39 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
   return GPUQT_OK;
 }
 
+// a_out = U(dt) a_in and b_out = U(dt) b_in with one matrix read per term
+// (scratch aA, aB, bA, bB; outputs must not alias the inputs).
+gpuqt_status run_evolve_pair(const Handle* h, int B, double dt, int Np, const double2* a_in, double2* a_out,
+                             const double2* b_in, double2* b_out, double2* aA, double2* aB, double2* bA,
+                             double2* bB, double* Jtab, hipStream_t s) {
+  const double sgn = dt >= 0 ? 1.0 : -1.0;
+  HIP_TRY(launch_bessel_table(h->d_seg_dE, h->n_seg, std::fabs(dt), Np, Np, Jtab, s));
+  if (Np == 1) {
+    const DevMat D = h->view(B);
+    HIP_TRY(launch_scale(D, B, a_in, a_out, Jtab, Np, s));
+    HIP_TRY(launch_scale(D, B, b_in, b_out, Jtab, Np, s));
+    return GPUQT_OK;
+  }
+  const double2 ph0 = phase_pow(0, sgn);
+  TimeScope ts(h, s, FAM_EVOLVE_PAIR, Np - 1);
+  const DevMat E = h->view(B, FAM_EVOLVE_PAIR);
+  ChainIO io{a_in, nullptr, aA, b_in, nullptr, bA, 1, 1};
+  HIP_TRY(launch_evolve_pair_term(E, h->hop_mode, B, io, a_out, b_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
+  const double2 *pa = a_in, *pb = b_in;
+  double2 *ca = aA, *cb = bA;
+  for (int m = 2; m < Np; ++m) {
+    double2* oa = (pa == a_in) ? aB : const_cast<double2*>(pa);
+    double2* ob = (pb == b_in) ? bB : const_cast<double2*>(pb);
+    ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
+    HIP_TRY(launch_evolve_pair_term(E, h->hop_mode, B, st, a_out, b_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
+    pa = ca;
+    pb = cb;
+    ca = oa;
+    cb = ob;
+  }
+  return GPUQT_OK;
+}
+
 // Source of the adjoint recurrence: real loss weights w[seg][b][n] on Re mu_n,
 // or the complex coefficients c_n = J[seg][n] (-i sgn)^n of an evolution series
 // (the adjoint source is conj(c_n) phiL).
@@ -887,12 +920,9 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
     if (k + 1 < n_t) {
       const int np_k = terms_for(h, dt[k], Np);
       double2* Ln = (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
-      if ((st = run_evolve(h, B, -dt[k], np_k, psiL, Ln, nullptr, nullptr, V(5), V(6), nullptr, nullptr,
-                           nullptr, J, s)))
-        return st;
       double2* Rn = Rbuf[ri ^ 1];
-      if ((st = run_evolve(h, B, -dt[k], np_k, psiR, Rn, nullptr, nullptr, V(5), V(6), nullptr, nullptr,
-                           nullptr, J, s)))
+      // both states advance with the same U(-dt): one two-chain series
+      if ((st = run_evolve_pair(h, B, -dt[k], np_k, psiL, Ln, psiR, Rn, V(5), V(6), V(7), V(8), J, s)))
         return st;
       psiL = Ln;
       psiR = Rn;
@@ -1053,11 +1083,8 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, psiR(0), sm));
   for (int k = 0; k + 1 < n_t; ++k) {
     const int npk = terms_for(h, dt[k], Np);
-    if ((st = run_evolve(h, B, -dt[k], npk, psiL(k), V(k), nullptr, nullptr, e0, e1, nullptr, nullptr,
-                         nullptr, J, sm)))
-      return st;
-    if ((st = run_evolve(h, B, -dt[k], npk, psiR(k), psiR(k + 1), nullptr, nullptr, e0, e1, nullptr,
-                         nullptr, nullptr, J, sm)))
+    if ((st = run_evolve_pair(h, B, -dt[k], npk, psiL(k), V(k), psiR(k), psiR(k + 1), e0, e1, pool[2],
+                              pool[3], J, sm)))
       return st;
   }
   // reverse over the rows

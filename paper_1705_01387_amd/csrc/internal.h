@@ -19,7 +19,9 @@ constexpr int kPerCU = 8;           // resident workgroups per CU of the primary
 // Hot kernel families; each launches with the plan whose workgroup count its
 // compiled occupancy keeps resident all at once (a grid larger than what fits
 // would leave a tail of workgroups that start only when others finish).
-enum Family { FAM_MOMENT = 0, FAM_SYM = 1, FAM_PAIR = 2, FAM_EVOLVE = 3, FAM_MSD = 4, kFamilies = 5 };
+enum Family {
+  FAM_MOMENT = 0, FAM_SYM = 1, FAM_PAIR = 2, FAM_EVOLVE = 3, FAM_MSD = 4, FAM_EVOLVE_PAIR = 5, kFamilies = 6
+};
 constexpr int kRowAlign = 256;      // block row ranges start at multiples of this
 constexpr int kMaxB = 16;           // widest vector block
 
@@ -279,6 +281,12 @@ struct ChainIO {
 hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io,
                            double2* acc_a, double2* acc_b, const double* Jtab, int ldJ, int m,
                            double2 phase_m, double2 phase_0, hipStream_t s);
+
+// One term of U(dt) on two vectors (chains a and b of io, has_b0 unused):
+// acc_a += c_m a_m, acc_b += c_m b_m.
+hipError_t launch_evolve_pair_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
+                                   double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
+                                   double2 phase_0, hipStream_t s);
 
 // out = V x (which = GPUQT_VELOCITY) or [X,H] x (GPUQT_COMMUTATOR_XH), unscaled H;
 // with kAccumulate or-ed into `which`, out += instead.

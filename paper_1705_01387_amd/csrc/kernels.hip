@@ -206,6 +206,43 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
 }
 
 // ---------------------------------------------------------------------------
+// One term m of U(dt) applied to two vectors at once (both VAC states advance
+// with the same U(-dt), Section 3.3): chains a_m = T_m psi_a, b_m = T_m psi_b
+// share the matrix read and the gather indices; acc_a += c_m a_m,
+// acc_b += c_m b_m.
+// ---------------------------------------------------------------------------
+template <int B, int HOP, int K, bool NT>
+__global__ __launch_bounds__(kBlock) void k_evolve_pair_term(DevMat A, ChainIO io, double2* __restrict__ acc_a,
+                                                             double2* __restrict__ acc_b,
+                                                             const double* __restrict__ Jtab, int ldJ, int m,
+                                                             double2 ph_m, double2 ph_0) {
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double2 cm = cscale(Jtab[(int64_t)P.seg * ldJ + m], ph_m);
+  const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
+  const int b = threadIdx.x & (B - 1);
+  const bool first = io.first;
+  for_rows<B>(A, P, [&](int64_t r) {
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
+    const int64_t idx = r * B + b;
+    if (first) {
+      io.oa[idx] = ha;
+      io.ob[idx] = hb;
+      acc_a[idx] = cadd(cmul(c0, io.xa[idx]), cmul(cm, ha));
+      acc_b[idx] = cadd(cmul(c0, io.xb[idx]), cmul(cm, hb));
+    } else {
+      const double2 ya = twice_minus(ha, ld2<NT>(io.wa + idx));
+      const double2 yb = twice_minus(hb, ld2<NT>(io.wb + idx));
+      io.oa[idx] = ya;
+      io.ob[idx] = yb;
+      acc_a[idx] = cadd(ld2<NT>(acc_a + idx), cmul(cm, ya));
+      acc_b[idx] = cadd(ld2<NT>(acc_b + idx), cmul(cm, yb));
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
 // One term m of the fused evolution + commutator series (Section 3.2):
 //   a_m = T_m psi:                a_1 = H~ a_0,  a_m = 2 H~ a_{m-1} - a_{m-2}
 //   b_m = [X,T_m] psi + T_m chi:  b_0 = chi, b_1 = [X,H~] a_0 + H~ b_0,
@@ -468,6 +505,7 @@ int kernel_occupancy(int family, const DevMat& A, int hop_mode, int B, int nt) {
       case FAM_SYM: q(k_moment_step_sym<b, hm, k, n>); break;
       case FAM_PAIR: q(k_moment_step_pair<b, hm, k, n>); break;
       case FAM_EVOLVE: q(k_evolve_term<b, hm, k, n>); break;
+      case FAM_EVOLVE_PAIR: q(k_evolve_pair_term<b, hm, k, n>); break;
       default: q(k_msd_term<b, hm, k, n>); break;
     }
   });
@@ -497,6 +535,15 @@ hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& 
                            double2 phase_0, hipStream_t s) {
   return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
     k_msd_term<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
+        <<<dim3(A.G), kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0);
+  });
+}
+
+hipError_t launch_evolve_pair_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
+                                   double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
+                                   double2 phase_0, hipStream_t s) {
+  return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
+    k_evolve_pair_term<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
         <<<dim3(A.G), kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0);
   });
 }
