@@ -85,6 +85,11 @@ typedef struct {
   int32_t band_rows;            /* rows per band of the banded row order (see gpuqt_autotune):
                                    0 = chosen per block width; else a multiple of 64, used for
                                    every width and every segment whose row period exceeds it */
+  int32_t no_dictionary;        /* nonzero: keep one hopping per entry.  Otherwise, with one
+                                   hopping class, when the (hopping, position difference) pairs
+                                   take at most 65,535 distinct values (a uniform field, a few
+                                   bond types) each entry stores a 16-bit index into a table of
+                                   them (hop_mode 3 in gpuqt_h_info_t) */
 } gpuqt_h_desc;
 
 /*
@@ -121,7 +126,7 @@ typedef struct {
   int64_t n;                 /* orbitals */
   int32_t n_segments;
   int32_t n_class;
-  int32_t hop_mode;          /* 0: uniform value per segment, 1: real, 2: complex */
+  int32_t hop_mode;          /* 0: one value per segment, 1: real, 2: complex per entry, 3: table */          /* 0: uniform value per segment, 1: real, 2: complex */
   int32_t slice_height;
   int64_t n_slices;
   int64_t entries;           /* stored ELL entries (with padding) */

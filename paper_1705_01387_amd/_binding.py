@@ -40,7 +40,7 @@ class _Desc(ctypes.Structure):
         ("energy_max", ctypes.c_double), ("n_segments", ctypes.c_int32),
         ("seg_offsets", ctypes.c_void_p), ("seg_energy_max", ctypes.c_void_p),
         ("seg_length_x", ctypes.c_void_p), ("check_hermitian", ctypes.c_int32),
-        ("slice_height", ctypes.c_int32), ("band_rows", ctypes.c_int32),
+        ("slice_height", ctypes.c_int32), ("band_rows", ctypes.c_int32), ("no_dictionary", ctypes.c_int32),
     ]
 
 
@@ -248,7 +248,7 @@ class Hamiltonian:
 def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1.0,
                   energy_max=0.0, hop_class=None, n_class=1, seg_offsets=None,
                   seg_energy_max=None, seg_length_x=None, check_hermitian=False,
-                  slice_height=0, band_rows=0, stream=None) -> Hamiltonian:
+                  slice_height=0, band_rows=0, no_dictionary=False, stream=None) -> Hamiltonian:
     """Build the device layout of H from a neighbour list (the paper's input files)."""
     nn = np.ascontiguousarray(nn, dtype=np.int32)
     n = nn.shape[0]
@@ -302,6 +302,7 @@ def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1
     d.check_hermitian = 1 if check_hermitian else 0
     d.slice_height = int(slice_height)
     d.band_rows = int(band_rows)
+    d.no_dictionary = 1 if no_dictionary else 0
     out = ctypes.c_void_p()
     _check(lib().gpuqt_build_h(ctypes.byref(d), stream, ctypes.byref(out)), "gpuqt_build_h")
     return Hamiltonian(out.value, None)

@@ -589,6 +589,10 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_col, L.col.data(), L.col.size() * 4);
   up((void**)&h->d_hop, L.hop.data(), L.hop.size() * 8);
   up((void**)&h->d_dx, L.dx.data(), L.dx.size() * 8);
+  up((void**)&h->d_hidx, L.hidx.data(), L.hidx.size() * 2);
+  up((void**)&h->d_htab, L.htab.data(), L.htab.size() * 8);
+  up((void**)&h->d_dxtab, L.dxtab.data(), L.dxtab.size() * 8);
+  h->dict_size = (int32_t)L.dxtab.size();
   up((void**)&h->d_diag, L.diag.data(), L.diag.size() * 8);
   up((void**)&h->d_cls, L.cls.data(), L.cls.size() * 4);
   up((void**)&h->d_plan, h->plan_host.data(), h->plan_host.size() * sizeof(BlkPlan));
@@ -622,7 +626,7 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   // row) within kBandBudget of an XCD's L2
   h->seg_period.assign(L.n_seg, 0);
   for (int sg = 0; sg < L.n_seg; ++sg) h->seg_period[sg] = row_period(L, sg);
-  const int64_t hop_b = L.hop_mode == HOP_COMPLEX ? 16 : L.hop_mode == HOP_REAL ? 8 : 0;
+  const int64_t hop_b = L.hop_mode == HOP_COMPLEX ? 16 : L.hop_mode == HOP_REAL ? 8 : L.hop_mode == HOP_DICT ? 2 : 0;
   std::vector<std::vector<int32_t>> unit_lists(kNumB);
   for (int lb = 0; lb < kNumB; ++lb) {
     const int64_t B = int64_t(1) << lb;
@@ -651,7 +655,8 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
-                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound};
+                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound,
+                  h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int32_t* p : h->d_units)
@@ -720,19 +725,25 @@ gpuqt_status gpuqt_update_h_values(gpuqt_h hh, const double* onsite, const doubl
       HIP_TRY(hipMemcpyAsync(h->d_seg_hop, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
       HIP_TRY(hipStreamSynchronize(s));
     } else {
-      const size_t hb = (size_t)h->entries * (h->hop_mode == HOP_COMPLEX ? 16 : 8);
-      if (!h->d_hop0) {   // first class update: keep the hoppings given at build time
-        if (hipMalloc((void**)&h->d_hop0, hb) != hipSuccess) {
-          h->d_hop0 = nullptr;
+      // per-entry hoppings, or (HOP_DICT, one class) the table of distinct values
+      const bool dict = h->hop_mode == HOP_DICT;
+      const int64_t count = dict ? h->dict_size : h->entries;
+      const bool cplx = dict || h->hop_mode == HOP_COMPLEX;
+      double*& cur = dict ? h->d_htab : h->d_hop;
+      double*& orig = dict ? h->d_htab0 : h->d_hop0;
+      const size_t hb = (size_t)count * (cplx ? 16 : 8);
+      if (!orig) {   // first class update: keep the hoppings given at build time
+        if (hipMalloc((void**)&orig, hb) != hipSuccess) {
+          orig = nullptr;
           return fail(GPUQT_ERR_NOMEM, "could not allocate the copy of the build-time hoppings");
         }
         h->device_bytes += hb;
-        HIP_TRY(hipMemcpyAsync(h->d_hop0, h->d_hop, hb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(orig, cur, hb, hipMemcpyDeviceToDevice, s));
       }
       ClassScale sc{};
       for (int c = 0; c < h->n_class; ++c) sc.s[c] = class_scale[c];
-      HIP_TRY(launch_scale_hops(h->entries, h->hop_mode == HOP_COMPLEX ? 1 : 0, h->d_hop0, h->d_hop,
-                                h->n_class > 1 ? h->d_cls : nullptr, sc, s));
+      HIP_TRY(launch_scale_hops(count, cplx ? 1 : 0, orig, cur, (!dict && h->n_class > 1) ? h->d_cls : nullptr,
+                                sc, s));
     }
     for (int c = 0; c < h->n_class; ++c) h->class_scale[c] = class_scale[c];
   }

@@ -62,6 +62,29 @@ __device__ __forceinline__ void cdot_acc(double& re, double& im, double2 a, doub
   im = fma(a.x, b.y, fma(-a.y, b.x, im));
 }
 
+// Hopping H~ of entry e (ok: not padding) and its position difference, for
+// every storage mode.
+template <int HOP, bool NT = false>
+__device__ __forceinline__ double2 hop_entry(const DevMat& A, int64_t e, bool ok, double hu) {
+  if constexpr (HOP == HOP_UNIFORM) {
+    return make_double2(ok ? hu : 0.0, 0.0);
+  } else if constexpr (HOP == HOP_REAL) {
+    return make_double2(ldg<NT>(A.hop + e), 0.0);
+  } else if constexpr (HOP == HOP_COMPLEX) {
+    return ld2<NT>(reinterpret_cast<const double2*>(A.hop) + e);
+  } else {
+    return A.htab[ldg<NT>(A.hidx + e)];
+  }
+}
+template <int HOP, bool NT = false>
+__device__ __forceinline__ double dx_entry(const DevMat& A, int64_t e) {
+  if constexpr (HOP == HOP_DICT) {
+    return A.dxtab[ldg<NT>(A.hidx + e)];
+  } else {
+    return ldg<NT>(A.dx + e);
+  }
+}
+
 // Products of one row with the gathered vector(s):
 //   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
 //   da = sum_j dx_rj H~_rj xa_j (DX; the diagonal has dx = 0).
@@ -87,36 +110,25 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
   auto body = [&](int32_t c, int64_t e) {
     const bool ok = c >= 0;
     const int64_t cc = ok ? (int64_t)c : r;
-    double hr, hi = 0.0;
-    if (HOP == HOP_UNIFORM) {
-      hr = ok ? hu : 0.0;
-    } else if (HOP == HOP_REAL) {
-      hr = ldg<NT>(A.hop + e);
+    constexpr bool CPLX = HOP == HOP_COMPLEX || HOP == HOP_DICT;
+    double2 h;
+    double dxv = 0.0;
+    if constexpr (HOP == HOP_DICT) {   // one index load serves the hopping and dx
+      const uint32_t id = ldg<NT>(A.hidx + e);
+      h = A.htab[id];
+      if (DX) dxv = A.dxtab[id];
     } else {
-      const double2 h = ld2<NT>(reinterpret_cast<const double2*>(A.hop) + e);
-      hr = h.x;
-      hi = h.y;
+      h = hop_entry<HOP, NT>(A, e, ok, hu);
+      if (DX) dxv = ldg<NT>(A.dx + e);
     }
     const double2 v = xa[cc * B + b];
-    double2 hv;
-    if (HOP == HOP_COMPLEX) {
-      hv = cmul(make_double2(hr, hi), v);
-    } else {
-      hv = cscale(hr, v);
-    }
+    const double2 hv = CPLX ? cmul(h, v) : cscale(h.x, v);
     ha = cadd(ha, hv);
     if (TWO) {
       const double2 u = xb[cc * B + b];
-      if (HOP == HOP_COMPLEX) {
-        hb = cadd(hb, cmul(make_double2(hr, hi), u));
-      } else {
-        hb = cadd(hb, cscale(hr, u));
-      }
+      hb = cadd(hb, CPLX ? cmul(h, u) : cscale(h.x, u));
     }
-    if (DX) {
-      const double dxv = ldg<NT>(A.dx + e);
-      da = make_double2(fma(dxv, hv.x, da.x), fma(dxv, hv.y, da.y));
-    }
+    if (DX) da = make_double2(fma(dxv, hv.x, da.x), fma(dxv, hv.y, da.y));
   };
   if constexpr (K > 0) {
     int32_t c[K];
@@ -200,7 +212,8 @@ inline hipError_t dispatch_bh(int B, int hop_mode, F&& f) {
   auto on_b = [&](auto Bc) {
     if (hop_mode == HOP_UNIFORM) f(Bc, IC<HOP_UNIFORM>{});
     else if (hop_mode == HOP_REAL) f(Bc, IC<HOP_REAL>{});
-    else f(Bc, IC<HOP_COMPLEX>{});
+    else if (hop_mode == HOP_COMPLEX) f(Bc, IC<HOP_COMPLEX>{});
+    else f(Bc, IC<HOP_DICT>{});
   };
   switch (B) {
     case 1: on_b(IC<1>{}); break;

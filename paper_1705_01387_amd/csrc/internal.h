@@ -12,7 +12,11 @@
 
 namespace gpuqt {
 
-enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2 };
+// Hopping storage: one value per segment, a double or a complex double per
+// entry, or (HOP_DICT) a 16-bit index per entry into a table of the distinct
+// (hopping, position difference) pairs.
+enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2, HOP_DICT = 3 };
+constexpr int kDictMax = 65535;     // table entries of HOP_DICT (index 0: padding, value 0)
 
 constexpr int kBlock = 256;         // threads per workgroup of every sparse kernel
 constexpr int kPerCU = 8;           // resident workgroups per CU of the primary plan
@@ -72,7 +76,10 @@ struct DevMat {
   const int64_t* slice_ptr;  // [n_slices + 1] first entry of each slice
   const int32_t* col;        // [entries] neighbour index or -1
   const double* hop;         // HOP_REAL: [entries]; HOP_COMPLEX: [2*entries] (re, im)
-  const double* dx;          // [entries] x_col - x_row (minimum image), 0 for padding
+  const double* dx;          // [entries] x_col - x_row (minimum image), 0 for padding (not HOP_DICT)
+  const uint16_t* hidx;      // HOP_DICT: [entries] table index of each entry
+  const double2* htab;       // HOP_DICT: [T] hopping of each table entry (re, im)
+  const double* dxtab;       // HOP_DICT: [T] position difference of each table entry
   const double* diag;        // [n] U_i / DeltaE_seg
   const BlkPlan* plan;       // [G] row ranges of the logical workgroups
   const int32_t* units;      // banded unit order for this block width (first row of each unit), or NULL
@@ -123,6 +130,11 @@ struct Handle {
   int32_t* d_col = nullptr;
   double* d_hop = nullptr;
   double* d_dx = nullptr;
+  uint16_t* d_hidx = nullptr;      // HOP_DICT
+  double* d_htab = nullptr;        // HOP_DICT [2T]
+  double* d_htab0 = nullptr;       // HOP_DICT: build-time table (allocated on the first class update)
+  double* d_dxtab = nullptr;       // HOP_DICT [T]
+  int32_t dict_size = 0;
   double* d_diag = nullptr;
   int32_t* d_cls = nullptr;
   BlkPlan* d_plan = nullptr;
@@ -168,6 +180,9 @@ struct Handle {
     m.col = d_col;
     m.hop = d_hop;
     m.dx = d_dx;
+    m.hidx = d_hidx;
+    m.htab = reinterpret_cast<const double2*>(d_htab);
+    m.dxtab = d_dxtab;
     m.diag = d_diag;
     m.plan = d_plan;
     m.seg_dE = d_seg_dE;
@@ -197,6 +212,9 @@ struct HostLayout {
   std::vector<int32_t> col;
   std::vector<double> hop;   // real or interleaved complex, or empty (uniform)
   std::vector<double> dx;
+  std::vector<uint16_t> hidx;  // HOP_DICT
+  std::vector<double> htab;    // HOP_DICT, interleaved (re, im)
+  std::vector<double> dxtab;   // HOP_DICT
   std::vector<double> diag;
   std::vector<int32_t> cls;  // class per entry, -1 for padding (empty if one class)
   std::vector<int64_t> seg_off;

@@ -55,21 +55,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
       const int32_t c = A.col[e];
       const bool ok = c >= 0;
       const int64_t cc = ok ? (int64_t)c : r;
-      double2 he;
-      if (HOP == HOP_UNIFORM) {
-        he = make_double2(ok ? hu : 0.0, 0.0);
-      } else if (HOP == HOP_REAL) {
-        he = make_double2(A.hop[e], 0.0);
-      } else {
-        he = reinterpret_cast<const double2*>(A.hop)[e];
-      }
+      const double2 he = hop_entry<HOP>(A, e, ok, hu);
       if (x) {
         const double2 xv = x[cc * B + b];
-        h = cadd(h, HOP == HOP_COMPLEX ? cmul(he, xv) : cscale(he.x, xv));
+        h = cadd(h, (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, xv) : cscale(he.x, xv));
       }
       if (NC > 0 && v) {
         const double2 vv = v[cc * B + b];
-        const double2 t = HOP == HOP_COMPLEX ? cmul(he, vv) : cscale(he.x, vv);
+        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vv) : cscale(he.x, vv);
         const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
@@ -158,23 +151,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
       const int32_t c = A.col[e];
       const bool ok = c >= 0;
       const int64_t cc = ok ? (int64_t)c : r;
-      double2 he;
-      if (HOP == HOP_UNIFORM) {
-        he = make_double2(ok ? hu : 0.0, 0.0);
-      } else if (HOP == HOP_REAL) {
-        he = make_double2(A.hop[e], 0.0);
-      } else {
-        he = reinterpret_cast<const double2*>(A.hop)[e];
-      }
+      const double2 he = hop_entry<HOP>(A, e, ok, hu);
       if (io.xa) {
         const double2 xa = io.xa[cc * B + b], xb = io.xb[cc * B + b];
-        ha = cadd(ha, HOP == HOP_COMPLEX ? cmul(he, xa) : cscale(he.x, xa));
-        hb = cadd(hb, HOP == HOP_COMPLEX ? cmul(he, xb) : cscale(he.x, xb));
+        ha = cadd(ha, (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, xa) : cscale(he.x, xa));
+        hb = cadd(hb, (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, xb) : cscale(he.x, xb));
       }
       if (NC > 0 && grad) {
         const double2 va = io.a_m1[cc * B + b], vb = io.b_m1[cc * B + b];
-        const double2 ta = HOP == HOP_COMPLEX ? cmul(he, va) : cscale(he.x, va);
-        const double2 tb = HOP == HOP_COMPLEX ? cmul(he, vb) : cscale(he.x, vb);
+        const double2 ta = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, va) : cscale(he.x, va);
+        const double2 tb = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vb) : cscale(he.x, vb);
         const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
@@ -277,12 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
       const int64_t en = e0 + (int64_t)j * S;
       const int32_t c = A.col[en];
       if (c < 0) continue;
-      double2 he;
-      if (HOP == HOP_UNIFORM) he = make_double2(hu, 0.0);
-      else if (HOP == HOP_REAL) he = make_double2(A.hop[en], 0.0);
-      else he = reinterpret_cast<const double2*>(A.hop)[en];
+      const double2 he = hop_entry<HOP>(A, en, true, hu);
       const double2 t = cmul(he, x[(int64_t)c * B + b]);
-      const double s = e * A.dx[en];
+      const double s = e * dx_entry<HOP>(A, en);
       const double2 vt = make_double2(-s * t.y, s * t.x);      // i e dx H~ x
       const double contrib = ar.x * vt.x + ar.y * vt.y;        // Re conj(a) vt
       const int q0 = (NC > 1) ? cls[en] : 0;
@@ -352,9 +335,8 @@ __global__ __launch_bounds__(kBlock) void k_row_bound(DevMat A, double* __restri
     for (int j = 0; j < w; ++j) {
       const int64_t e = e0 + (int64_t)j * S;
       if (A.col[e] < 0) continue;
-      if (HOP == HOP_UNIFORM) s += hu;
-      else if (HOP == HOP_REAL) s += fabs(A.hop[e]);
-      else s += hypot(A.hop[2 * e], A.hop[2 * e + 1]);
+      const double2 he = hop_entry<HOP>(A, e, true, hu);
+      s += HOP == HOP_UNIFORM ? hu : (HOP == HOP_REAL ? fabs(he.x) : hypot(he.x, he.y));
     }
     mx = fmax(mx, s);
   });
@@ -470,7 +452,8 @@ hipError_t launch_scale_hops(int64_t entries, int cplx, const double* hop0, doub
 hipError_t launch_row_bound(const DevMat& A, int hop_mode, double* bound, hipStream_t s) {
   if (hop_mode == HOP_UNIFORM) k_row_bound<HOP_UNIFORM><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
   else if (hop_mode == HOP_REAL) k_row_bound<HOP_REAL><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
-  else k_row_bound<HOP_COMPLEX><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
+  else if (hop_mode == HOP_COMPLEX) k_row_bound<HOP_COMPLEX><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
+  else k_row_bound<HOP_DICT><<<dim3(A.G), kBlock, 0, s>>>(A, bound);
   return hipGetLastError();
 }
 

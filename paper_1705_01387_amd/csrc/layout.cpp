@@ -11,6 +11,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <functional>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -306,6 +308,55 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
         L->hop[2 * slot + 1] = d->hop[2 * e + 1] * inv;
       }
       if (!L->cls.empty()) L->cls[slot] = d->hop_class[e];
+    }
+  }
+
+  // value dictionary (one hopping class, few distinct (hopping, dx) pairs)
+  if ((mode == HOP_REAL || mode == HOP_COMPLEX) && n_class == 1 && !d->no_dictionary) {
+    struct Key {
+      uint64_t a, b, c;
+      bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c; }
+    };
+    struct KeyHash {
+      size_t operator()(const Key& k) const {
+        return std::hash<uint64_t>()(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x632BE59BD9B4E019ull) ^ (k.c << 1));
+      }
+    };
+    auto bits = [](double v) {
+      uint64_t u;
+      std::memcpy(&u, &v, 8);
+      return u;
+    };
+    std::unordered_map<Key, uint16_t, KeyHash> ids;
+    std::vector<double> tab = {0.0, 0.0}, dtab = {0.0};
+    ids[Key{bits(0.0), bits(0.0), bits(0.0)}] = 0;
+    std::vector<uint16_t> hidx(entries, 0);
+    bool fits = true;
+    for (int64_t e = 0; e < entries && fits; ++e) {
+      if (L->col[e] < 0) continue;
+      const double re = mode == HOP_COMPLEX ? L->hop[2 * e] : L->hop[e];
+      const double im = mode == HOP_COMPLEX ? L->hop[2 * e + 1] : 0.0;
+      const Key key{bits(re), bits(im), bits(L->dx[e])};
+      auto it = ids.find(key);
+      if (it == ids.end()) {
+        if ((int64_t)dtab.size() >= kDictMax) {
+          fits = false;
+          break;
+        }
+        it = ids.emplace(key, (uint16_t)dtab.size()).first;
+        tab.push_back(re);
+        tab.push_back(im);
+        dtab.push_back(L->dx[e]);
+      }
+      hidx[e] = it->second;
+    }
+    if (fits) {
+      mode = HOP_DICT;
+      L->hidx.swap(hidx);
+      L->htab.swap(tab);
+      L->dxtab.swap(dtab);
+      std::vector<double>().swap(L->hop);
+      std::vector<double>().swap(L->dx);
     }
   }
 

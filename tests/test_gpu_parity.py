@@ -319,7 +319,7 @@ def test_full_size_honeycomb_sampled(torch_cuda):
     w = I.workload_honeycomb(n_vectors=1)
     m = w["model"]
     H = build(m, w["energy_max"])
-    assert H.info.hop_mode == 2 and H.info.uniform_width == 3
+    assert H.info.hop_mode == 3 and H.info.uniform_width == 3     # table of distinct hoppings
     Hs, V, XH = ops(m)
     dE = w["energy_max"]
     phi = w["phis"][0]
@@ -365,3 +365,68 @@ def test_running_conductivity(torch_cuda):
     assert err(gv, O.sigma_vac(rows, dz)) < 1e-14
     om2, _ = O.sigma_msd(rows, dz)
     assert np.all(np.isnan(gm[1])) and err(np.delete(gm, 1, 0), np.delete(om2, 1, 0)) < 1e-14
+
+
+def _random_real_hops(m, seed, values):
+    """A copy of m whose bonds carry hoppings drawn from `values` (Hermitian: each bond's two
+    entries get the same value)."""
+    rng = np.random.default_rng(seed)
+    hop = np.zeros(m.nbr.shape)
+    for i in range(m.n):
+        for s_ in range(m.nn[i]):
+            j = m.nbr[i, s_]
+            a, b = min(i, j), max(i, j)
+            hop[i, s_] = values[(a * 7919 + b * 104729 + seed) % len(values)]
+    return I.Model(m.nn, m.nbr, hop, m.onsite, m.x, m.length_x, m.volume, name=m.name + "_hops")
+
+
+@pytest.mark.parametrize("name", ["honeycomb30x20_flux", "square_few_hops", "cubic_few_hops"])
+def test_value_table_matches_per_entry_storage(torch_cuda, name):
+    """The table layout (16-bit index per entry) against per-entry hoppings: row-wise results
+    bit for bit (complex) or to rounding (real), moments and the MSD series against the oracle."""
+    say(f"case: value table {name}")
+    if name == "square_few_hops":
+        m = _random_real_hops(I.square(41, 37, W=1.0, seed=95), 1, [-1.0, -0.8, -1.25, -0.5])
+    elif name == "cubic_few_hops":
+        m = _random_real_hops(I.cubic(12, W=2.0, seed=96), 2, [-1.0, -0.9])
+    else:
+        m = MODELS[name]()
+    Ht = build(m)
+    Hp = build(m, no_dictionary=True)
+    assert Ht.info.hop_mode == 3 and Hp.info.hop_mode in (1, 2)
+    Hs, V, XH = ops(m)
+    dE = float(Ht.energy_max[0])
+    assert dE == float(Hp.energy_max[0])
+    psi = dev(I.random_phase(m.n, 2, 97))
+    for H in (Ht, Hp):
+        P.gpuqt_autotune(H, 2)
+    a = [host(P.gpuqt_evolve(H, psi, 0.9, 0, with_commutator=True)[1]) for H in (Ht, Hp)]
+    v = [host(P.gpuqt_apply_commutator(H, psi, P.VELOCITY)) for H in (Ht, Hp)]
+    if Hp.info.hop_mode == 2:   # both complex products: the same operations
+        assert np.array_equal(a[0], a[1]) and np.array_equal(v[0], v[1])
+    else:                       # real products fuse differently from complex ones: rounding only
+        assert err(a[0], a[1]) < 1e-14 and err(v[0], v[1]) < 1e-14
+    p = host(psi)
+    mu = host(P.gpuqt_moments(Ht, psi, psi, 150))[0]
+    assert err(mu, O.chebyshev_moments(Hs / dE, p, p, 150).T) < TOL
+    ms = host(P.gpuqt_msd(Ht, psi, [0.4, 1.1], 64))[:, 0]
+    ref = O.msd_moments(Hs, XH, p, [0.4, 1.1], dE, 64)
+    for k in range(2):
+        assert err(ms[k], ref[k].T) < TOL
+
+
+def test_value_table_class_update(torch_cuda):
+    """Rescaling the one hopping class rescales the table: moments of H(eps) against the
+    oracle's, and back."""
+    say("case: value table class update")
+    m = I.honeycomb(20, 14, flux=1.0 / 140.0, W=0.5, seed=98)
+    H = build(m, 10.0)
+    assert H.info.hop_mode == 3
+    phi = dev(I.random_phase(m.n, 1, 99))
+    a = host(P.gpuqt_moments(H, phi, phi, 80))
+    P.gpuqt_update_h_values(H, class_scale=[1.1])
+    Hs, _, _ = ops(I.Model(m.nn, m.nbr, m.hop * 1.1, m.onsite, m.x, m.length_x, m.volume))
+    p = host(phi)
+    assert err(host(P.gpuqt_moments(H, phi, phi, 80))[0], O.chebyshev_moments(Hs / 10.0, p, p, 80).T) < TOL
+    P.gpuqt_update_h_values(H, class_scale=[1.0])
+    assert err(host(P.gpuqt_moments(H, phi, phi, 80)), a) < 1e-14
