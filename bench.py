@@ -76,16 +76,19 @@ FAMILY_KERNEL = {"moment": "k_moment_step", "moment_sym": "k_moment_step_sym",
 def family_bytes(info, B, family="moment"):
     """Algorithmic HBM bytes of one launch of a sparse kernel family (gathers counted once).
 
-    Matrix part, per stored entry: neighbour index 4 B, hopping 0 (one value per segment),
-    8 (real), 16 (complex) or 2 B (index into the table of distinct values, which stays in
-    cache), plus the position difference 8 B for the commutator chain (in the table in
-    mode 3); per row the on-site term 8 B; per slice the 8-byte slice offset.  Vector part:
-    FAMILY_VECTOR_BYTES per row and block column.
+    Matrix part, per stored entry: neighbour index 4 B and hopping 0 (one value per
+    segment), 8 (real) or 16 (complex) B, plus the position difference 8 B for the
+    commutator chain; in table mode (3) one 2-byte index into the table of distinct
+    (column offset, hopping, dx) triples, which stays in cache.  Per row the on-site term
+    8 B; per slice the 8-byte slice offset.  Vector part: FAMILY_VECTOR_BYTES per row and
+    block column.
     """
     mode = int(info.hop_mode)
-    hop_b = {0: 0, 1: 8, 2: 16, 3: 2}[mode]          # 3: 16-bit index into the value table
     n = int(info.n)
-    per_entry = 4 + hop_b + (8 if family == "msd" and mode != 3 else 0)   # the table also holds dx
+    if mode == 3:        # one 16-bit index into the table of (column offset, hopping, dx)
+        per_entry = 2
+    else:
+        per_entry = 4 + {0: 0, 1: 8, 2: 16}[mode] + (8 if family == "msd" else 0)
     return int(info.nnz) * per_entry + n * 8 + int(info.n_slices) * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 

@@ -586,12 +586,14 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
     if (hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) ok = false;
   };
   up((void**)&h->d_slice_ptr, L.slice_ptr.data(), L.slice_ptr.size() * 8);
-  up((void**)&h->d_col, L.col.data(), L.col.size() * 4);
+  if (L.hop_mode != HOP_DICT)   // the value table holds the column offsets
+    up((void**)&h->d_col, L.col.data(), L.col.size() * 4);
   up((void**)&h->d_hop, L.hop.data(), L.hop.size() * 8);
   up((void**)&h->d_dx, L.dx.data(), L.dx.size() * 8);
   up((void**)&h->d_hidx, L.hidx.data(), L.hidx.size() * 2);
   up((void**)&h->d_htab, L.htab.data(), L.htab.size() * 8);
   up((void**)&h->d_dxtab, L.dxtab.data(), L.dxtab.size() * 8);
+  up((void**)&h->d_offtab, L.offtab.data(), L.offtab.size() * 4);
   h->dict_size = (int32_t)L.dxtab.size();
   up((void**)&h->d_diag, L.diag.data(), L.diag.size() * 8);
   up((void**)&h->d_cls, L.cls.data(), L.cls.size() * 4);
@@ -626,11 +628,12 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   // row) within kBandBudget of an XCD's L2
   h->seg_period.assign(L.n_seg, 0);
   for (int sg = 0; sg < L.n_seg; ++sg) h->seg_period[sg] = row_period(L, sg);
-  const int64_t hop_b = L.hop_mode == HOP_COMPLEX ? 16 : L.hop_mode == HOP_REAL ? 8 : L.hop_mode == HOP_DICT ? 2 : 0;
+  // bytes streamed per stored entry: column index + hopping, or one 16-bit table index
+  const int64_t entry_b = L.hop_mode == HOP_DICT ? 2 : 4 + (L.hop_mode == HOP_COMPLEX ? 16 : L.hop_mode == HOP_REAL ? 8 : 0);
   std::vector<std::vector<int32_t>> unit_lists(kNumB);
   for (int lb = 0; lb < kNumB; ++lb) {
     const int64_t B = int64_t(1) << lb;
-    const int64_t row_bytes = (4 + hop_b) * L.max_width + 8 + 48 * B;
+    const int64_t row_bytes = entry_b * L.max_width + 8 + 48 * B;
     const int64_t W = desc->band_rows > 0 ? desc->band_rows
                                           : std::max<int64_t>(256, kBandBudget / (2 * row_bytes) / 64 * 64);
     h->band_rows[lb] = (int32_t)W;
@@ -656,7 +659,7 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
                   h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound,
-                  h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab};
+                  h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab, h->d_offtab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int32_t* p : h->d_units)

@@ -84,6 +84,19 @@ __device__ __forceinline__ double dx_entry(const DevMat& A, int64_t e) {
     return ldg<NT>(A.dx + e);
   }
 }
+// Column of entry e of row r: false for padding (then *cc = r, the hopping is 0).
+template <int HOP>
+__device__ __forceinline__ bool col_entry(const DevMat& A, int64_t r, int64_t e, int64_t* cc) {
+  if constexpr (HOP == HOP_DICT) {
+    const uint32_t id = A.hidx[e];
+    *cc = r + A.offtab[id];
+    return id != 0;
+  } else {
+    const int32_t c = A.col[e];
+    *cc = c >= 0 ? (int64_t)c : r;
+    return c >= 0;
+  }
+}
 
 // Products of one row with the gathered vector(s):
 //   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
@@ -107,17 +120,27 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
     ha = cscale(d, xa[r * B + b]);
     if (TWO) hb = cscale(d, xb[r * B + b]);
   }
-  auto body = [&](int32_t c, int64_t e) {
-    const bool ok = c >= 0;
-    const int64_t cc = ok ? (int64_t)c : r;
+  // key of an entry: its column (-1: padding), or (HOP_DICT) its table index,
+  // whose entry holds the column offset, the hopping and dx (index 0: padding)
+  auto key_at = [&](int64_t e) -> int32_t {
+    if constexpr (HOP == HOP_DICT) {
+      return (int32_t)ldg<NT>(A.hidx + e);
+    } else {
+      return ldg<NT>(A.col + e);
+    }
+  };
+  auto body = [&](int32_t key, int64_t e) {
     constexpr bool CPLX = HOP == HOP_COMPLEX || HOP == HOP_DICT;
     double2 h;
     double dxv = 0.0;
-    if constexpr (HOP == HOP_DICT) {   // one index load serves the hopping and dx
-      const uint32_t id = ldg<NT>(A.hidx + e);
-      h = A.htab[id];
-      if (DX) dxv = A.dxtab[id];
+    int64_t cc;
+    if constexpr (HOP == HOP_DICT) {
+      cc = r + A.offtab[key];
+      h = A.htab[key];
+      if (DX) dxv = A.dxtab[key];
     } else {
+      const bool ok = key >= 0;
+      cc = ok ? (int64_t)key : r;
       h = hop_entry<HOP, NT>(A, e, ok, hu);
       if (DX) dxv = ldg<NT>(A.dx + e);
     }
@@ -133,7 +156,7 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
   if constexpr (K > 0) {
     int32_t c[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) c[j] = ldg<NT>(A.col + e0 + (int64_t)j * S);
+    for (int j = 0; j < K; ++j) c[j] = key_at(e0 + (int64_t)j * S);
 #pragma unroll
     for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
   } else {
@@ -142,11 +165,11 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
     for (; j + 4 <= w; j += 4) {
       int32_t c[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) c[q] = ldg<NT>(A.col + e0 + (int64_t)(j + q) * S);
+      for (int q = 0; q < 4; ++q) c[q] = key_at(e0 + (int64_t)(j + q) * S);
 #pragma unroll
       for (int q = 0; q < 4; ++q) body(c[q], e0 + (int64_t)(j + q) * S);
     }
-    for (; j < w; ++j) body(ldg<NT>(A.col + e0 + (int64_t)j * S), e0 + (int64_t)j * S);
+    for (; j < w; ++j) body(key_at(e0 + (int64_t)j * S), e0 + (int64_t)j * S);
   }
 }
 

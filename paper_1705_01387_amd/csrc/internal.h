@@ -14,7 +14,8 @@ namespace gpuqt {
 
 // Hopping storage: one value per segment, a double or a complex double per
 // entry, or (HOP_DICT) a 16-bit index per entry into a table of the distinct
-// (hopping, position difference) pairs.
+// (column offset, hopping, position difference) triples, which then replaces
+// the column indices too.
 enum HopMode { HOP_UNIFORM = 0, HOP_REAL = 1, HOP_COMPLEX = 2, HOP_DICT = 3 };
 constexpr int kDictMax = 65535;     // table entries of HOP_DICT (index 0: padding, value 0)
 
@@ -80,6 +81,7 @@ struct DevMat {
   const uint16_t* hidx;      // HOP_DICT: [entries] table index of each entry
   const double2* htab;       // HOP_DICT: [T] hopping of each table entry (re, im)
   const double* dxtab;       // HOP_DICT: [T] position difference of each table entry
+  const int32_t* offtab;     // HOP_DICT: [T] column offset (column - row) of each table entry
   const double* diag;        // [n] U_i / DeltaE_seg
   const BlkPlan* plan;       // [G] row ranges of the logical workgroups
   const int32_t* units;      // banded unit order for this block width (first row of each unit), or NULL
@@ -134,6 +136,7 @@ struct Handle {
   double* d_htab = nullptr;        // HOP_DICT [2T]
   double* d_htab0 = nullptr;       // HOP_DICT: build-time table (allocated on the first class update)
   double* d_dxtab = nullptr;       // HOP_DICT [T]
+  int32_t* d_offtab = nullptr;     // HOP_DICT [T]
   int32_t dict_size = 0;
   double* d_diag = nullptr;
   int32_t* d_cls = nullptr;
@@ -183,6 +186,7 @@ struct Handle {
     m.hidx = d_hidx;
     m.htab = reinterpret_cast<const double2*>(d_htab);
     m.dxtab = d_dxtab;
+    m.offtab = d_offtab;
     m.diag = d_diag;
     m.plan = d_plan;
     m.seg_dE = d_seg_dE;
@@ -215,6 +219,7 @@ struct HostLayout {
   std::vector<uint16_t> hidx;  // HOP_DICT
   std::vector<double> htab;    // HOP_DICT, interleaved (re, im)
   std::vector<double> dxtab;   // HOP_DICT
+  std::vector<int32_t> offtab; // HOP_DICT
   std::vector<double> diag;
   std::vector<int32_t> cls;  // class per entry, -1 for padding (empty if one class)
   std::vector<int64_t> seg_off;

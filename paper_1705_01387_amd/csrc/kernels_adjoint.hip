@@ -52,9 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
     if (x) h = cscale(A.diag[r], x[idx]);
     for (int j = 0; j < w; ++j) {
       const int64_t e = e0 + (int64_t)j * S;
-      const int32_t c = A.col[e];
-      const bool ok = c >= 0;
-      const int64_t cc = ok ? (int64_t)c : r;
+      int64_t cc;
+      const bool ok = col_entry<HOP>(A, r, e, &cc);
       const double2 he = hop_entry<HOP>(A, e, ok, hu);
       if (x) {
         const double2 xv = x[cc * B + b];
@@ -148,9 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
     }
     for (int j = 0; j < w; ++j) {
       const int64_t e = e0 + (int64_t)j * S;
-      const int32_t c = A.col[e];
-      const bool ok = c >= 0;
-      const int64_t cc = ok ? (int64_t)c : r;
+      int64_t cc;
+      const bool ok = col_entry<HOP>(A, r, e, &cc);
       const double2 he = hop_entry<HOP>(A, e, ok, hu);
       if (io.xa) {
         const double2 xa = io.xa[cc * B + b], xb = io.xb[cc * B + b];
@@ -261,10 +259,10 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
     const double2 ar = a[idx];
     for (int j = 0; j < w; ++j) {
       const int64_t en = e0 + (int64_t)j * S;
-      const int32_t c = A.col[en];
-      if (c < 0) continue;
+      int64_t c;
+      if (!col_entry<HOP>(A, r, en, &c)) continue;
       const double2 he = hop_entry<HOP>(A, en, true, hu);
-      const double2 t = cmul(he, x[(int64_t)c * B + b]);
+      const double2 t = cmul(he, x[c * B + b]);
       const double s = e * dx_entry<HOP>(A, en);
       const double2 vt = make_double2(-s * t.y, s * t.x);      // i e dx H~ x
       const double contrib = ar.x * vt.x + ar.y * vt.y;        // Re conj(a) vt
@@ -334,7 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_row_bound(DevMat A, double* __restri
     double s = fabs(A.diag[r]);
     for (int j = 0; j < w; ++j) {
       const int64_t e = e0 + (int64_t)j * S;
-      if (A.col[e] < 0) continue;
+      int64_t c;
+      if (!col_entry<HOP>(A, r, e, &c)) continue;
       const double2 he = hop_entry<HOP>(A, e, true, hu);
       s += HOP == HOP_UNIFORM ? hu : (HOP == HOP_REAL ? fabs(he.x) : hypot(he.x, he.y));
     }

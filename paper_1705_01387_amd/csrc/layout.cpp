@@ -311,15 +311,17 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
     }
   }
 
-  // value dictionary (one hopping class, few distinct (hopping, dx) pairs)
+  // value table (one hopping class, few distinct (column offset, hopping, dx) triples)
   if ((mode == HOP_REAL || mode == HOP_COMPLEX) && n_class == 1 && !d->no_dictionary) {
     struct Key {
       uint64_t a, b, c;
-      bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c; }
+      int64_t off;
+      bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c && off == o.off; }
     };
     struct KeyHash {
       size_t operator()(const Key& k) const {
-        return std::hash<uint64_t>()(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x632BE59BD9B4E019ull) ^ (k.c << 1));
+        return std::hash<uint64_t>()(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x632BE59BD9B4E019ull) ^ (k.c << 1) ^
+                                     ((uint64_t)k.off * 0xC2B2AE3D27D4EB4Full));
       }
     };
     auto bits = [](double v) {
@@ -329,32 +331,42 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
     };
     std::unordered_map<Key, uint16_t, KeyHash> ids;
     std::vector<double> tab = {0.0, 0.0}, dtab = {0.0};
-    ids[Key{bits(0.0), bits(0.0), bits(0.0)}] = 0;
+    std::vector<int32_t> otab = {0};
+    ids[Key{bits(0.0), bits(0.0), bits(0.0), 0}] = 0;   // padding: offset 0, hopping 0
     std::vector<uint16_t> hidx(entries, 0);
     bool fits = true;
-    for (int64_t e = 0; e < entries && fits; ++e) {
-      if (L->col[e] < 0) continue;
-      const double re = mode == HOP_COMPLEX ? L->hop[2 * e] : L->hop[e];
-      const double im = mode == HOP_COMPLEX ? L->hop[2 * e + 1] : 0.0;
-      const Key key{bits(re), bits(im), bits(L->dx[e])};
-      auto it = ids.find(key);
-      if (it == ids.end()) {
-        if ((int64_t)dtab.size() >= kDictMax) {
-          fits = false;
-          break;
+    for (int64_t sl = 0; sl < n_slices && fits; ++sl) {
+      const int64_t w = (slice_ptr[sl + 1] - slice_ptr[sl]) >> S_log2;
+      for (int64_t j = 0; j < w && fits; ++j) {
+        for (int64_t q = 0; q < S; ++q) {
+          const int64_t e = slice_ptr[sl] + j * S + q;
+          const int64_t row = sl * S + q;
+          if (L->col[e] < 0) continue;
+          const double re = mode == HOP_COMPLEX ? L->hop[2 * e] : L->hop[e];
+          const double im = mode == HOP_COMPLEX ? L->hop[2 * e + 1] : 0.0;
+          const Key key{bits(re), bits(im), bits(L->dx[e]), (int64_t)L->col[e] - row};
+          auto it = ids.find(key);
+          if (it == ids.end()) {
+            if ((int64_t)dtab.size() >= kDictMax) {
+              fits = false;
+              break;
+            }
+            it = ids.emplace(key, (uint16_t)dtab.size()).first;
+            tab.push_back(re);
+            tab.push_back(im);
+            dtab.push_back(L->dx[e]);
+            otab.push_back((int32_t)key.off);
+          }
+          hidx[e] = it->second;
         }
-        it = ids.emplace(key, (uint16_t)dtab.size()).first;
-        tab.push_back(re);
-        tab.push_back(im);
-        dtab.push_back(L->dx[e]);
       }
-      hidx[e] = it->second;
     }
     if (fits) {
       mode = HOP_DICT;
       L->hidx.swap(hidx);
       L->htab.swap(tab);
       L->dxtab.swap(dtab);
+      L->offtab.swap(otab);
       std::vector<double>().swap(L->hop);
       std::vector<double>().swap(L->dx);
     }
