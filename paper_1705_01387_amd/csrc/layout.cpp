@@ -312,6 +312,8 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
   }
 
   // value table (one hopping class, few distinct (column offset, hopping, dx) triples)
+  // (not for one uniform hopping per segment: there the column array plus the
+  // per-segment value streams faster than the table's dependent index loads)
   if ((mode == HOP_REAL || mode == HOP_COMPLEX) && n_class == 1 && !d->no_dictionary) {
     struct Key {
       uint64_t a, b, c;

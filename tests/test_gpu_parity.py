@@ -430,3 +430,22 @@ def test_value_table_class_update(torch_cuda):
     assert err(host(P.gpuqt_moments(H, phi, phi, 80))[0], O.chebyshev_moments(Hs / 10.0, p, p, 80).T) < TOL
     P.gpuqt_update_h_values(H, class_scale=[1.0])
     assert err(host(P.gpuqt_moments(H, phi, phi, 80)), a) < 1e-14
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_per_entry_storage_modes(torch_cuda, name):
+    """Layouts without the value table (one hopping per segment, real or complex per entry):
+    moments and the evolution + commutator series against the oracle."""
+    say(f"case: per-entry storage {name}")
+    m = MODELS[name]()
+    H = build(m, no_dictionary=True)
+    assert H.info.hop_mode in (0, 1, 2)
+    Hs, _, XH = ops(m)
+    dE = float(H.energy_max[0])
+    phi = I.random_phase(m.n, 2, 101)
+    d = dev(phi)
+    assert err(host(P.gpuqt_moments(H, d, d, 120))[0], O.chebyshev_moments(Hs / dE, phi, phi, 120).T) < TOL
+    po, co = P.gpuqt_evolve(H, d, 1.1, 0, with_commutator=True)
+    assert err(host(po), O.evolve(Hs / dE, phi, 1.1, dE)) < TOL
+    if np.max(np.abs(XH @ phi)) > 0:
+        assert err(host(co), O.commutator_evolve(Hs / dE, XH / dE, phi, 1.1, dE)) < TOL
