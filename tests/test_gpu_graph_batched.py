@@ -28,11 +28,20 @@ def err(got, ref):
     return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1e-300))
 
 
-def test_graph_capture_replays_match_eager(gpu):
+@pytest.mark.parametrize("lattice", ["square", "honeycomb_table"])
+def test_graph_capture_replays_match_eager(gpu, lattice):
+    """Capture moments + MSD + VAC; the honeycomb case (value-table layout, two-chain
+    evolution) is captured with kernel timing switched on, which records nothing while
+    capturing."""
     import torch
-    say("case: graph capture of moments + MSD + VAC")
-    m = I.square(40, 30, W=1.5, seed=61)
+    say(f"case: graph capture of moments + MSD + VAC, {lattice}")
+    if lattice == "square":
+        m = I.square(40, 30, W=1.5, seed=61)
+    else:
+        m = I.honeycomb(24, 18, flux=1.0 / 216.0, W=1.0, seed=61)
     H = P.gpuqt_build_h_from_model(m)
+    if lattice != "square":
+        assert H.info.hop_mode == 3
     phi = dev(I.random_phase(m.n, 2, 62))
     M, dts = 300, [0.5, 1.0, 0.25]
     ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MSD, 2, M, 64),
@@ -50,10 +59,13 @@ def test_graph_capture_replays_match_eager(gpu):
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
+    P.gpuqt_set_timing(H, lattice != "square")
     with torch.cuda.graph(g):
         P.gpuqt_moments(H, phi, phi, M, mu=mu_g, ws=ws)
         P.gpuqt_msd(H, phi, dts, M, Np=64, out=msd_g, ws=ws)
         P.gpuqt_vac(H, phi, dts, M, Np=64, out=vac_g, ws=ws)
+    P.gpuqt_set_timing(H, False)
+    assert all(n == 0 for _, n in P.gpuqt_timing(H).values())
     other = P.gpuqt_build_h_from_model(I.square(17, 13, W=3.0, seed=63))
     ophi = dev(I.random_phase(other.n, 1, 64))
     for rep in range(3):
