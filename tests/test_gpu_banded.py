@@ -147,3 +147,32 @@ def test_banded_segments_mixed(gpu):
             ph = phi[offs[s]:offs[s + 1]]
             ref = O.chebyshev_moments(Hs / float(H.energy_max[s]), ph, ph, 90).T
             assert err(mu[s], ref) < TOL, (v, s)
+
+
+def test_banded_with_value_table(gpu):
+    """A 3D lattice with complex y-bond phases (value-table layout) in the banded order:
+    moments of both forms and an MSD row against the oracle."""
+    say("case: banded + value table, cubic 26 with phases")
+    L = 26
+    m = I.cubic(L, W=2.0, seed=102)
+    ix = (np.arange(m.n) % L).astype(float)
+    theta = 2 * np.pi * 3 / L
+    hop = np.full(m.nbr.shape, -1.0 + 0j)
+    hop[:, 2] = -np.exp(1j * theta * ix)       # +y bond of site i
+    hop[:, 3] = -np.exp(-1j * theta * ix)      # -y bond (same x): the conjugate
+    m = I.Model(m.nn, m.nbr, hop, m.onsite, m.x, m.length_x, m.volume, name="cubic26_phases")
+    H = P.gpuqt_build_h_from_model(m, band_rows=128, check_hermitian=True)
+    assert H.info.hop_mode == 3 and H.info.banded_mask == 0b11111
+    Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = float(H.energy_max[0])
+    phi = I.random_phase(m.n, 2, 103)
+    psi = I.random_phase(m.n, 2, 104)
+    d = dev(phi)
+    for v in (2, 3):
+        P.gpuqt_set_variant(H, v)
+        assert err(host(P.gpuqt_moments(H, d, d, 90))[0], O.chebyshev_moments(Hs / dE, phi, phi, 90).T) < TOL
+        assert err(host(P.gpuqt_moments(H, d, dev(psi), 90))[0],
+                   O.chebyshev_moments(Hs / dE, phi, psi, 90).T) < TOL
+        ms = host(P.gpuqt_msd(H, d, [0.7], 48))[0, 0]
+        assert err(ms, O.msd_moments(Hs, XH, phi, [0.7], dE, 48)[0].T) < TOL
+    P.gpuqt_set_variant(H, 0)
