@@ -92,6 +92,13 @@ def family_bytes(info, B, family="moment"):
     return int(info.nnz) * per_entry + n * 8 + int(info.n_slices) * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 
+def variant_text(v):
+    """The autotuned kernel variant: load variant (bit 0 non-temporal, bit 1 banded order)
+    and the cap on resident workgroups per CU (bits 2-5, 0 = none)."""
+    cap = v >> 2
+    return "variant %d, %s" % (v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
+
+
 def moment_step_bytes(info, B):
     """Algorithmic HBM bytes of one plain moment-step launch."""
     return family_bytes(info, B, "moment")
@@ -246,9 +253,9 @@ def transport_workload(args, name):
                roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": d["GBs"] / HBM_PEAK_GBS,
                          "traffic": measured_traffic(name, dominant, d["bytes_per_launch"]),
-                         "kernel": "%s (B=%d, hop mode %d, K=%d, variant %d)"
+                         "kernel": "%s (B=%d, hop mode %d, K=%d, %s)"
                                    % (FAMILY_KERNEL[dominant], B, H.info.hop_mode, H.info.uniform_width,
-                                      H.info.kernel_variant),
+                                      variant_text(H.info.kernel_variant)),
                          "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
                          "autotune_us_per_step": [float(t) for t in tune_us]},
                kernels=kernels)
@@ -338,9 +345,9 @@ def batched_workload(args):
                 roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": d["GBs"] / HBM_PEAK_GBS,
                           "traffic": measured_traffic("batched", dominant, d["bytes_per_launch"]),
-                          "kernel": "%s (B=16, hop mode %d, K=%d, variant %d)"
+                          "kernel": "%s (B=16, hop mode %d, K=%d, %s)"
                                     % (FAMILY_KERNEL[dominant], H.info.hop_mode, H.info.uniform_width,
-                                       H.info.kernel_variant),
+                                       variant_text(H.info.kernel_variant)),
                           "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
                           "autotune_us_per_step": [float(t) for t in tune_us]},
                 kernels=kernels,

@@ -134,7 +134,8 @@ typedef struct {
   int32_t max_width;         /* widest slice */
   int32_t uniform_width;     /* width of every slice when equal and unpadded, else 0 */
   int32_t grid_blocks;       /* workgroups per sparse-step launch */
-  int32_t kernel_variant;    /* bit 0: non-temporal streams, bit 1: banded row order (see gpuqt_autotune) */
+  int32_t kernel_variant;    /* bit 0: non-temporal streams, bit 1: banded row order, bits 2-5:
+                                per-CU workgroup cap (see gpuqt_autotune) */
   size_t device_bytes;       /* device memory held by the handle */
   int64_t row_period;        /* largest detected row period D over the segments (0: none) */
   int32_t banded_mask;       /* bit log2(B) set: block width B has a banded row order */
@@ -289,19 +290,25 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
  * order (built when a segment's row period D would make the window between
  * the first and last use of a gathered element exceed about 2.5 MiB of
  * streamed data at this B: workgroups then sweep bands of W rows of the
- * period one period after another, so rows D apart are visited W rows apart).
- * Synchronises the stream.
+ * period one period after another, so rows D apart are visited W rows apart);
+ * bits 2-5: a cap on resident workgroups per compute unit (0: as many as the
+ * kernel's registers allow).  Each of the four load/order variants is timed
+ * uncapped and at every cap of 2..6 below its occupancy limit: fewer waves in
+ * flight shrink the window of rows whose gathered elements must stay cached,
+ * which can outweigh the lost latency hiding.  The cap applies to every
+ * kernel family on the handle.  Synchronises the stream.
  *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0)
- *   times_us : NULL or HOST [4], microseconds per step of variants 0..3 (0 for a banded
- *              variant when this B has no banded order).
+ *   times_us : NULL or HOST [4], microseconds per step of load/order variants 0..3, each at
+ *              its best cap (0 for a banded variant when this B has no banded order).
  * Not safe while other calls on the handle are in flight.
  */
 gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
                             double *times_us);
 
-/* Set the kernel variant (0..3, bits as in gpuqt_autotune) without measuring.  The banded
- * bit only takes effect for block widths that have a banded order (gpuqt_h_info_t.banded_mask).
- * GPUQT_ERR_ARG for a variant outside 0..3. */
+/* Set the kernel variant (bits as in gpuqt_autotune: load variant in bits 0-1, per-CU cap
+ * 0..8 in bits 2-5) without measuring.  The banded bit only takes effect for block widths
+ * that have a banded order (gpuqt_h_info_t.banded_mask).  GPUQT_ERR_ARG for a negative
+ * variant or a cap above 8. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*

@@ -563,8 +563,10 @@ def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=
 
 
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
-    """Time the kernel variants (plain / non-temporal loads, plain / banded row order), keep the
-    fastest; returns us per moment step of variants 0..3 (0 where a variant does not exist)."""
+    """Time the kernel variants (plain / non-temporal loads, plain / banded row order, each
+    uncapped and at per-CU workgroup caps below its occupancy limit), keep the fastest; returns
+    us per moment step of load variants 0..3 at their best cap (0 where a variant does not
+    exist).  H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none)."""
     t = np.zeros(4)
     ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
@@ -575,7 +577,8 @@ def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
 
 
 def gpuqt_set_variant(H: Hamiltonian, variant: int):
-    """Pin the kernel variant (bit 0: non-temporal streams, bit 1: banded row order)."""
+    """Pin the kernel variant (bit 0: non-temporal streams, bit 1: banded row order,
+    bits 2-5: resident workgroups per CU at most, 0 = no cap)."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")
     info = HInfo()
     _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")

@@ -691,7 +691,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->uniform_width = h->uniform_width;
   info->grid_blocks = h->G;
   info->device_bytes = h->device_bytes;
-  info->kernel_variant = h->nt | (h->banded << 1);
+  info->kernel_variant = h->variant_code();
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -1177,34 +1177,49 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   float best = 0.0f;
-  int best_v = h->nt | (h->banded << 1);
-  const int n_var = h->d_units[Handle::log2B(B)] ? 4 : 2;
+  int best_v = h->variant_code();
+  const int lb = Handle::log2B(B);
+  const int n_var = h->d_units[lb] ? 4 : 2;
   if (times_us)
     for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
-  for (int rep = 0; rep < 2; ++rep) {
-    for (int v = 0; v < n_var; ++v) {
-      h->nt = v & 1;
-      h->banded = v >> 1;
-      // the Hermitian moment step, the one most calls run
-      if ((st = run_moments(h, B, phi, phi, 4, part, A, Bf, s, true))) return st;   // warm
-      HIP_TRY(hipEventRecord(e0, s));
-      if ((st = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true))) return st;
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (rep == 1 && times_us) times_us[v] = 1e3 * ms / (kSteps / 2);   // launches
-      if (rep == 1 && (best == 0.0f || ms < best)) {
+  // the Hermitian moment step (the one most calls run) of one variant and cap;
+  // returns milliseconds for kSteps / 2 launches
+  auto time_one = [&](int v, int cap, float* ms) -> gpuqt_status {
+    h->nt = v & 1;
+    h->banded = v >> 1;
+    h->per_cu_cap = cap;
+    gpuqt_status q;
+    if ((q = run_moments(h, B, phi, phi, 4, part, A, Bf, s, true))) return q;   // warm
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(GPUQT_ERR_HIP, "hipEventRecord failed");
+    if ((q = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true))) return q;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(GPUQT_ERR_HIP, "event timing failed");
+    return GPUQT_OK;
+  };
+  float ms = 0.0f;
+  st = time_one(0, 0, &ms);   // settle clocks and caches before the sweep
+  for (int v = 0; v < n_var && !st; ++v) {
+    // caps below the occupancy limit of this variant's Hermitian step, then none
+    const int occ = std::max<int>(1, h->occ[FAM_SYM][lb][v & 1]);
+    const int caps[] = {2, 3, 4, 5, 6, 0};
+    for (int cap : caps) {
+      if (cap != 0 && cap >= occ) continue;
+      if ((st = time_one(v, cap, &ms))) break;
+      const double us = 1e3 * ms / (kSteps / 2);   // per launch
+      if (times_us && (times_us[v] == 0.0 || us < times_us[v])) times_us[v] = us;
+      if (best == 0.0f || ms < best) {
         best = ms;
-        best_v = v;
+        best_v = v | (cap << 2);
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->nt = best_v & 1;
-  h->banded = best_v >> 1;
-  return GPUQT_OK;
+  h->banded = (best_v >> 1) & 1;
+  h->per_cu_cap = best_v >> 2;
+  return st;
 }
 
 gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets, const int64_t* period,
@@ -1254,9 +1269,11 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
 gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
-  if (variant < 0 || variant > 3) return fail(GPUQT_ERR_ARG, "variant must be in 0..3");
+  if (variant < 0 || (variant >> 2) > kPerCU)
+    return fail(GPUQT_ERR_ARG, "variant must be bits 0-1 plus a per-CU cap of 0..8 in bits 2-5");
   h->nt = variant & 1;
-  h->banded = variant >> 1;
+  h->banded = (variant >> 1) & 1;
+  h->per_cu_cap = variant >> 2;
   return GPUQT_OK;
 }
 

@@ -101,24 +101,27 @@ __device__ __forceinline__ bool col_entry(const DevMat& A, int64_t r, int64_t e,
 // Products of one row with the gathered vector(s):
 //   ha = sum_j H~_rj xa_j (+ H~_rr xa_r),  hb likewise for xb (TWO),
 //   da = sum_j dx_rj H~_rj xa_j (DX; the diagonal has dx = 0).
-// K > 0: every slice has exactly K entries per row (fully unrolled, all index
-// loads issued before the gathers).  K == 0: runtime slice width.
+// xra / xrb are the row's own elements xa_r / xb_r, loaded by the caller
+// together with its other per-row operands, so that every load that does not
+// depend on a column index is in flight before the index loads return.
+// K > 0: every slice has exactly K entries per row, so the row's first entry
+// follows from r alone (no slice-offset load) and the loop is fully unrolled
+// with all index loads issued before the gathers.  K == 0: runtime slice width.
 template <int B, int HOP, int K, bool NT, bool TWO, bool DX, bool DIAG>
 __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, double hu,
                                           const double2* __restrict__ xa,
-                                          const double2* __restrict__ xb, double2& ha,
-                                          double2& hb, double2& da) {
+                                          const double2* __restrict__ xb, double2 xra, double2 xrb,
+                                          double2& ha, double2& hb, double2& da) {
   const int S = 1 << A.S_log2;
   const int64_t sl = r >> A.S_log2;
-  const int64_t p0 = A.slice_ptr[sl];
-  const int64_t e0 = p0 + (r & (S - 1));
+  const int64_t e0 = (K > 0 ? sl * ((int64_t)K << A.S_log2) : A.slice_ptr[sl]) + (r & (S - 1));
   ha = make_double2(0.0, 0.0);
   hb = make_double2(0.0, 0.0);
   da = make_double2(0.0, 0.0);
   if (DIAG) {
     const double d = ldg<NT>(A.diag + r);
-    ha = cscale(d, xa[r * B + b]);
-    if (TWO) hb = cscale(d, xb[r * B + b]);
+    ha = cscale(d, xra);
+    if (TWO) hb = cscale(d, xrb);
   }
   // key of an entry: its column (-1: padding), or (HOP_DICT) its table index,
   // whose entry holds the column offset, the hopping and dx (index 0: padding)
@@ -160,7 +163,7 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
 #pragma unroll
     for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
   } else {
-    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    const int w = (int)((A.slice_ptr[sl + 1] - A.slice_ptr[sl]) >> A.S_log2);
     int j = 0;
     for (; j + 4 <= w; j += 4) {
       int32_t c[4];

@@ -122,6 +122,10 @@ struct Handle {
   // resident workgroups per CU of each hot family [family][log2 B][nt] (0: unknown)
   int8_t occ[kFamilies][kNumB][2] = {};
   int32_t banded = 0;             // 1: use the banded unit order where one exists
+  // at most this many resident workgroups per CU (0: as many as fit).  Fewer
+  // waves in flight can beat full occupancy when the gathers reuse cached
+  // lines: the window of rows in flight, and so the cache footprint, shrinks.
+  int32_t per_cu_cap = 0;
   // banded orders per block width (index log2 B); NULL where the plain row order
   // already keeps the neighbour window within the cache budget
   int32_t* d_units[kNumB] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -163,9 +167,12 @@ struct Handle {
 
   // plan of a hot family at block width B and the current load variant
   int plan_index(int B, int family) const {
-    const int p = occ[family][log2B(B)][nt ? 1 : 0];
-    return (p < 1 || p > kPerCU) ? kPerCU - 1 : p - 1;
+    int p = occ[family][log2B(B)][nt ? 1 : 0];
+    if (p < 1 || p > kPerCU) p = kPerCU;
+    if (per_cu_cap > 0 && per_cu_cap < p) p = per_cu_cap;
+    return p - 1;
   }
+  int32_t variant_code() const { return nt | (banded << 1) | (per_cu_cap << 2); }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
   DevMat view(int B, int family) const {

@@ -57,17 +57,23 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
   const double2* __restrict__ w = io.w;
   double2* __restrict__ out = io.out;
   const bool first = io.first;
+  // per-row operands that need no column index are loaded first (w is read
+  // from x on the first step, where it is unused, to keep the load unconditional)
+  const double2* __restrict__ wsrc = first ? x : w;
   double dr = 0.0, di = 0.0, zr = 0.0, zi = 0.0;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
-    const double2 y = first ? ha : twice_minus(ha, ld2<NT>(w + idx));
+    const double2 xr = x[idx];
+    const double2 wv = ld2<NT>(wsrc + idx);
+    double2 p = make_double2(0.0, 0.0);
+    if (phiL) p = ld2<NT>(phiL + idx);   // plain recurrence step (no moment) when phiL is NULL
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
+    const double2 y = first ? ha : twice_minus(ha, wv);
     out[idx] = y;
-    if (phiL) {   // plain recurrence step (no moment) when phiL is NULL
-      const double2 p = ld2<NT>(phiL + idx);
+    if (phiL) {
       cdot_acc(dr, di, p, y);
-      if (first) cdot_acc(zr, zi, p, x[idx]);
+      if (first) cdot_acc(zr, zi, p, xr);
     }
   });
   if (!phiL) return;
@@ -101,14 +107,16 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
   double2* __restrict__ out = io.out;
   const bool first = io.first;
   // first: a = <v0|v0>, b = <v0|v1>, c = <v1|v1>;  else: a = <vk|vk-1>, c = <vk|vk>
+  const double2* __restrict__ wsrc = first ? x : w;   // w unused on the first step
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
-    const double2 y = first ? ha : twice_minus(ha, ld2<NT>(w + idx));
-    out[idx] = y;
     const double2 xr = x[idx];
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
+    const double2 wv = ld2<NT>(wsrc + idx);
+    const double2 y = first ? ha : twice_minus(ha, wv);
+    out[idx] = y;
     if (first) {
       cdot_acc(ar, ai, xr, xr);
       cdot_acc(br, bi, xr, y);
@@ -144,18 +152,22 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
   const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
   const int b = threadIdx.x & (B - 1);
   const bool first = io.first;
+  const double2* __restrict__ wa = first ? io.xa : io.wa;   // unused on the first step
+  const double2* __restrict__ wb = first ? io.xb : io.wb;
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
-    const double2 ya = first ? ha : twice_minus(ha, ld2<NT>(io.wa + idx));
-    const double2 yb = first ? hb : twice_minus(hb, ld2<NT>(io.wb + idx));
+    const double2 xa = io.xa[idx];
+    const double2 xb = io.xb[idx];
+    const double2 wav = ld2<NT>(wa + idx);
+    const double2 wbv = ld2<NT>(wb + idx);
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
+    const double2 ya = first ? ha : twice_minus(ha, wav);
+    const double2 yb = first ? hb : twice_minus(hb, wbv);
     io.oa[idx] = ya;
     io.ob[idx] = yb;
-    const double2 xb = io.xb[idx];
     if (first) {
-      const double2 xa = io.xa[idx];
       cdot_acc(ar, ai, xa, xb);
       cdot_acc(br, bi, xa, yb);
     } else {
@@ -190,17 +202,24 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
   const double2* __restrict__ w = io.w;
   double2* __restrict__ out = io.out;
   const bool first = io.first;
+  // w and acc are unused on the first step: read x there instead, so that the
+  // loads stay unconditional and ahead of the gathers
+  const double2* __restrict__ wsrc = first ? x : w;
+  const double2* __restrict__ asrc = first ? x : acc;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, ha, hb, da);
     const int64_t idx = r * B + b;
+    const double2 xr = x[idx];
+    const double2 wv = ld2<NT>(wsrc + idx);
+    const double2 av = ld2<NT>(asrc + idx);
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
     if (first) {
       out[idx] = ha;
-      acc[idx] = cadd(cmul(c0, x[idx]), cmul(cm, ha));
+      acc[idx] = cadd(cmul(c0, xr), cmul(cm, ha));
     } else {
-      const double2 y = twice_minus(ha, ld2<NT>(w + idx));
+      const double2 y = twice_minus(ha, wv);
       out[idx] = y;
-      acc[idx] = cadd(ld2<NT>(acc + idx), cmul(cm, y));
+      acc[idx] = cadd(av, cmul(cm, y));
     }
   });
 }
@@ -222,22 +241,33 @@ __global__ __launch_bounds__(kBlock) void k_evolve_pair_term(DevMat A, ChainIO i
   const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
   const int b = threadIdx.x & (B - 1);
   const bool first = io.first;
+  // the w and acc operands are unused on the first step (read x there instead)
+  const double2* __restrict__ wa = first ? io.xa : io.wa;
+  const double2* __restrict__ wb = first ? io.xb : io.wb;
+  const double2* __restrict__ sa = first ? io.xa : acc_a;
+  const double2* __restrict__ sb = first ? io.xb : acc_b;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
+    const double2 xa = io.xa[idx];
+    const double2 xb = io.xb[idx];
+    const double2 wav = ld2<NT>(wa + idx);
+    const double2 wbv = ld2<NT>(wb + idx);
+    const double2 aav = ld2<NT>(sa + idx);
+    const double2 abv = ld2<NT>(sb + idx);
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
     if (first) {
       io.oa[idx] = ha;
       io.ob[idx] = hb;
-      acc_a[idx] = cadd(cmul(c0, io.xa[idx]), cmul(cm, ha));
-      acc_b[idx] = cadd(cmul(c0, io.xb[idx]), cmul(cm, hb));
+      acc_a[idx] = cadd(cmul(c0, xa), cmul(cm, ha));
+      acc_b[idx] = cadd(cmul(c0, xb), cmul(cm, hb));
     } else {
-      const double2 ya = twice_minus(ha, ld2<NT>(io.wa + idx));
-      const double2 yb = twice_minus(hb, ld2<NT>(io.wb + idx));
+      const double2 ya = twice_minus(ha, wav);
+      const double2 yb = twice_minus(hb, wbv);
       io.oa[idx] = ya;
       io.ob[idx] = yb;
-      acc_a[idx] = cadd(ld2<NT>(acc_a + idx), cmul(cm, ya));
-      acc_b[idx] = cadd(ld2<NT>(acc_b + idx), cmul(cm, yb));
+      acc_a[idx] = cadd(aav, cmul(cm, ya));
+      acc_b[idx] = cadd(abv, cmul(cm, yb));
     }
   });
 }
@@ -261,23 +291,34 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
   const double2 c0 = cscale(Jtab[(int64_t)P.seg * ldJ], ph_0);
   const int b = threadIdx.x & (B - 1);
   const bool first = io.first;
+  // the w and acc operands are unused on the first step (read x there instead)
+  const double2* __restrict__ wa = first ? io.xa : io.wa;
+  const double2* __restrict__ wb = first ? io.xb : io.wb;
+  const double2* __restrict__ sa = first ? io.xa : acc_a;
+  const double2* __restrict__ sb = first ? io.xb : acc_b;
   for_rows<B>(A, P, [&](int64_t r) {
-    double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, ha, hb, da);
     const int64_t idx = r * B + b;
+    const double2 xa = io.xa[idx];
+    const double2 xb = io.xb[idx];
+    const double2 wav = ld2<NT>(wa + idx);
+    const double2 wbv = ld2<NT>(wb + idx);
+    const double2 aav = ld2<NT>(sa + idx);
+    const double2 abv = ld2<NT>(sb + idx);
+    double2 ha, hb, da;
+    row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
     const double2 g = make_double2(hb.x - da.x, hb.y - da.y);   // [X,H~] a + H~ b
     if (first) {
       io.oa[idx] = ha;
       io.ob[idx] = g;
-      acc_a[idx] = cadd(cmul(c0, io.xa[idx]), cmul(cm, ha));
-      acc_b[idx] = cadd(cmul(c0, io.xb[idx]), cmul(cm, g));
+      acc_a[idx] = cadd(cmul(c0, xa), cmul(cm, ha));
+      acc_b[idx] = cadd(cmul(c0, xb), cmul(cm, g));
     } else {
-      const double2 ya = twice_minus(ha, ld2<NT>(io.wa + idx));
-      const double2 yb = twice_minus(g, ld2<NT>(io.wb + idx));
+      const double2 ya = twice_minus(ha, wav);
+      const double2 yb = twice_minus(g, wbv);
       io.oa[idx] = ya;
       io.ob[idx] = yb;
-      acc_a[idx] = cadd(ld2<NT>(acc_a + idx), cmul(cm, ya));
-      acc_b[idx] = cadd(ld2<NT>(acc_b + idx), cmul(cm, yb));
+      acc_a[idx] = cadd(aav, cmul(cm, ya));
+      acc_b[idx] = cadd(abv, cmul(cm, yb));
     }
   });
 }
@@ -295,7 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_commutator(DevMat A, int which, cons
   const int b = threadIdx.x & (B - 1);
   for_rows<B>(A, P, [&](int64_t r) {
     double2 ha, hb, da;
-    row_apply<B, HOP, 0, false, false, true, false>(A, r, b, hu, x, nullptr, ha, hb, da);
+    const double2 z = make_double2(0.0, 0.0);   // no diagonal term: own element unused
+    row_apply<B, HOP, 0, false, false, true, false>(A, r, b, hu, x, nullptr, z, z, ha, hb, da);
     const int64_t idx = r * B + b;
     double2 y;
     if ((which & 1) == GPUQT_VELOCITY) {

@@ -51,7 +51,8 @@ def test_banded_order_exists(cubic26):
     assert H.info.banded_mask == 0b11111
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+# variant bits: 0 non-temporal loads, 1 banded order, 2-5 resident workgroups per CU at most
+@pytest.mark.parametrize("variant", [2, 3, 3 | (2 << 2)])
 @pytest.mark.parametrize("B", [1, 4, 16])
 def test_banded_moments(cubic26, variant, B):
     say(f"case: banded moments variant={variant} B={B}")
@@ -76,7 +77,7 @@ def test_banded_rowwise_results_bit_identical(cubic26, B):
     dE = float(H.energy_max[0])
     psi = dev(I.random_phase(m.n, B, 74))
     outs = []
-    for v in (0, 2, 3):
+    for v in (0, 2, 3, 2 | (3 << 2), 1 << 2):   # row-wise results do not depend on the schedule
         P.gpuqt_set_variant(H, v)
         a = host(P.gpuqt_evolve(H, psi, 1.3, 0))
         b = host(P.gpuqt_apply_commutator(H, psi, P.VELOCITY))
@@ -176,3 +177,21 @@ def test_banded_with_value_table(gpu):
         ms = host(P.gpuqt_msd(H, d, [0.7], 48))[0, 0]
         assert err(ms, O.msd_moments(Hs, XH, phi, [0.7], dE, 48)[0].T) < TOL
     P.gpuqt_set_variant(H, 0)
+
+
+def test_variant_codes(cubic26):
+    say("case: variant codes with a per-CU cap")
+    m, H, Hs, _, _ = cubic26
+    dE = float(H.energy_max[0])
+    phi = I.random_phase(m.n, 4, 75)
+    ref = O.chebyshev_moments(Hs / dE, phi, phi, 64).T
+    G = H.info.grid_blocks
+    for cap in range(0, 9):
+        P.gpuqt_set_variant(H, 1 | (cap << 2))
+        assert H.info.kernel_variant == 1 | (cap << 2)
+        assert err(host(P.gpuqt_moments(H, dev(phi), dev(phi), 64))[0], ref) < TOL, cap
+    for bad in (-1, 9 << 2, 1 << 6):
+        with pytest.raises(P.GpuqtError):
+            P.gpuqt_set_variant(H, bad)
+    P.gpuqt_set_variant(H, 0)
+    assert H.info.kernel_variant == 0 and H.info.grid_blocks == G
