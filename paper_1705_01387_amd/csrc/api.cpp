@@ -637,10 +637,20 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
     const int64_t W = desc->band_rows > 0 ? desc->band_rows
                                           : std::max<int64_t>(256, kBandBudget / (2 * row_bytes) / 64 * 64);
     h->band_rows[lb] = (int32_t)W;
+    // per segment: W where the period exceeds it; by default also two bands per
+    // period where the period is long (>= 1024 rows) but within W, since the
+    // plain order's 2 D window can still outgrow what stays cached while the
+    // whole chip's rows are in flight (the autotuner keeps whichever is faster)
+    std::vector<int64_t> width(L.n_seg, 0);
     bool any = false;
-    for (int sg = 0; sg < L.n_seg; ++sg) any = any || h->seg_period[sg] > W;
+    for (int sg = 0; sg < L.n_seg; ++sg) {
+      const int64_t D = h->seg_period[sg];
+      if (D > W) width[sg] = W;
+      else if (desc->band_rows == 0 && D >= 1024) width[sg] = D / 2 / 64 * 64;
+      any = any || width[sg] > 0;
+    }
     if (!any) continue;
-    banded_units(L.seg_off, h->seg_period, W, &unit_lists[lb]);
+    banded_units(L.seg_off, h->seg_period, width, &unit_lists[lb]);
     up((void**)&h->d_units[lb], unit_lists[lb].data(), unit_lists[lb].size() * 4);
   }
   h->seg_hop0 = L.seg_hop;
@@ -1243,7 +1253,7 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
     D[s] = period[s];
     banded = banded || (band_rows > 0 && D[s] > band_rows);
   }
-  if (banded) banded_units(off, D, band_rows, &units);
+  if (banded) banded_units(off, D, std::vector<int64_t>(n_segments, band_rows), &units);
   const int32_t* U = banded ? units.data() : nullptr;
   for (int64_t r = 0; r < n; ++r) block_of_row[r] = iter_of_row[r] = -1;
   const int RPI = kBlock / B;

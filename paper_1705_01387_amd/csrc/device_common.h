@@ -192,12 +192,18 @@ __device__ __forceinline__ void for_rows(const DevMat& A, const BlkPlan& P, F&& 
     }
     return;
   }
+  // banded: the same rule as row_at, with the unit start of the next tile
+  // loaded one iteration ahead so that the lookup is off the row's load chain
   const int64_t total = row_seq_len(P, A.units);
-  for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += step) {
-    const int64_t pos = pos0 + threadIdx.x / B;
+  const int32_t* __restrict__ units = A.units + P.u0;
+  int64_t pos = (int64_t)P.j * RPI + threadIdx.x / B;
+  int32_t a_next = pos < total ? units[pos >> kUnitLog2] : 0;
+  for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += step, pos += step) {
+    const int64_t a = a_next;
+    if (pos + step < total) a_next = units[(pos + step) >> kUnitLog2];
     if (pos < total) {
-      const int64_t r = row_at(P, A.units, pos);
-      if (r >= 0) f(r);
+      const int64_t r = a + (pos & ((int64_t(1) << kUnitLog2) - 1));
+      if (r < (((a >> kUnitLog2) + 1) << kUnitLog2) && r < P.se) f(r);
     }
   }
 }

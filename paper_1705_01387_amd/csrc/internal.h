@@ -265,9 +265,10 @@ int64_t row_period(const HostLayout& L, int s);
 // Banded order of the units of each segment for band width W rows: unit at
 // offset a from the segment start goes to (band (a mod D) / W, sweep a / D,
 // a mod D), so rows one period apart are visited W rows apart instead of D.
-// Segments with D = 0, or D <= W, keep the plain order.
+// W is given per segment (width[s]); segments with W = 0, D = 0 or D <= W keep
+// the plain order.
 void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
-                  int64_t W, std::vector<int32_t>* out);
+                  const std::vector<int64_t>& width, std::vector<int32_t>* out);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
 hipError_t launch_sigma(int mode, int n_t, const double* dt, int n_E, const double* y, double* out,

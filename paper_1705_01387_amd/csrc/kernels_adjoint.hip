@@ -213,18 +213,22 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
   }
 }
 
-// Raw-dot weights of the product identities, one thread per (segment, column).
-__global__ void k_raw_weights(const double* __restrict__ w, int rows, int M, int R, double* __restrict__ om) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows) return;
-  const double* wi = w + (int64_t)i * M;
-  double* oi = om + (int64_t)i * R;
-  double even = 0.0, odd = 0.0;
-  for (int n = 2; n < M; ++n) {
-    if (n & 1) odd += wi[n];
-    else even += wi[n];
-  }
-  for (int n = 0; n < R; ++n) {
+// Raw-dot weights of the product identities, one wavefront per (segment,
+// column) row: lane l sums w_n for n = 2 + l + 64 j (all of one parity, the
+// parity of l), a butterfly over lanes of equal parity gives the even and odd
+// tails in a fixed order, and the lanes write om[n] for n = l, l + 64, ...
+__global__ __launch_bounds__(64) void k_raw_weights(const double* __restrict__ w, int M, int R,
+                                                    double* __restrict__ om) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* wi = w + i * M;
+  double* oi = om + i * R;
+  double t = 0.0;
+  for (int n = 2 + lane; n < M; n += 64) t += wi[n];
+#pragma unroll
+  for (int off = 2; off < 64; off <<= 1) t += __shfl_xor(t, off);
+  const double even = __shfl(t, 0), odd = __shfl(t, 1);
+  for (int n = lane; n < R; n += 64) {
     double v = 0.0;
     if (n == 0) v = (M > 0 ? wi[0] : 0.0) - even;
     else if (n == 1) v = (M > 1 ? wi[1] : 0.0) - odd;
@@ -418,7 +422,7 @@ hipError_t launch_adjoint_pair_step(const DevMat& A, int hop_mode, int B, int nc
 
 hipError_t launch_raw_weights(const double* w, int rows, int M, int R, double* om, hipStream_t s) {
   if (rows <= 0 || R <= 0) return hipSuccess;
-  k_raw_weights<<<dim3((rows + 63) / 64), 64, 0, s>>>(w, rows, M, R, om);
+  k_raw_weights<<<dim3(rows), 64, 0, s>>>(w, M, R, om);
   return hipGetLastError();
 }
 

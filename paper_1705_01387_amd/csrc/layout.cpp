@@ -494,13 +494,13 @@ int64_t row_period(const HostLayout& L, int s) {
 }
 
 void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
-                  int64_t W, std::vector<int32_t>* out) {
+                  const std::vector<int64_t>& width, std::vector<int32_t>* out) {
   std::vector<int64_t> unit_first;
   segment_units(seg_off, &unit_first, out);
   const int n_seg = (int)seg_off.size() - 1;
   for (int s = 0; s < n_seg; ++s) {
-    const int64_t D = period[s];
-    if (D <= W) continue;   // plain order: rows one period apart are already close
+    const int64_t D = period[s], W = width[s];
+    if (W <= 0 || D <= W) continue;   // plain order for this segment
     const int64_t a = seg_off[s];
     auto first = out->begin() + unit_first[s], last = out->begin() + unit_first[s + 1];
     std::stable_sort(first, last, [&](int32_t x, int32_t y) {
