@@ -92,6 +92,16 @@ def family_bytes(info, B, family="moment"):
     return int(info.nnz) * per_entry + n * 8 + int(info.n_slices) * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 
+def pick_variant(P, H, B, ws, args):
+    """Autotune the kernel variant of H at block width B, or pin the one given by --variant
+    (for profiling runs whose counters must all come from one configuration).  Returns the
+    autotune times per load variant (zeros when pinned)."""
+    if args.variant >= 0:
+        P.gpuqt_set_variant(H, args.variant)
+        return [0.0] * 4
+    return P.gpuqt_autotune(H, B, ws=ws)
+
+
 def variant_text(v):
     """The autotuned kernel variant: load variant (bit 0 non-temporal, bit 1 banded order)
     and the cap on resident workgroups per CU (bits 2-5, 0 = none)."""
@@ -214,7 +224,7 @@ def transport_workload(args, name):
                          P.gpuqt_workspace_size(H, P.OP_MSD, B, M, max(np_list)),
                          P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0)),
                      dtype=torch.uint8, device=dev)
-    tune_us = P.gpuqt_autotune(H, B, ws=ws)           # untimed: pick the kernel variant
+    tune_us = pick_variant(P, H, B, ws, args)          # untimed: pick the kernel variant
     mu = torch.empty((1, B, M), dtype=torch.complex128, device=dev)
     vac = torch.empty((len(dts), 1, B, M), dtype=torch.float64, device=dev)
     msd = torch.empty_like(vac)
@@ -252,7 +262,8 @@ def transport_workload(args, name):
                        "steps_timed": args.steps},
                roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": d["GBs"] / HBM_PEAK_GBS,
-                         "traffic": measured_traffic(name, dominant, d["bytes_per_launch"]),
+                         "traffic": measured_traffic(name, dominant, d["bytes_per_launch"],
+                                                     H.info.kernel_variant),
                          "kernel": "%s (B=%d, hop mode %d, K=%d, %s)"
                                    % (FAMILY_KERNEL[dominant], B, H.info.hop_mode, H.info.uniform_width,
                                       variant_text(H.info.kernel_variant)),
@@ -268,9 +279,11 @@ def transport_workload(args, name):
 KERNEL_SOURCES = ("device_common.h", "internal.h", "kernels.hip")   # what the moment step is built from
 
 
-def measured_traffic(name, family, bytes_launch):
+def measured_traffic(name, family, bytes_launch, variant):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
-    was taken on that kernel family and on the kernel source that is built now (else None)."""
+    was taken on that kernel family and on the kernel source that is built now (else None).
+    The record names the kernel variant it was taken with (pinned by --variant); the
+    autotuner of this run may have chosen another one (variant_matches)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -286,7 +299,8 @@ def measured_traffic(name, family, bytes_launch):
     if not e or e.get("kernel_source_sha256") != h.hexdigest() or e.get("family") != family:
         return None
     return {"bytes": e["bytes_per_launch"], "ratio_to_algorithmic": e["bytes_per_launch"] / bytes_launch,
-            "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"]}
+            "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"],
+            "variant": e.get("variant"), "variant_matches": e.get("variant") == int(variant)}
 
 
 def batched_workload(args):
@@ -307,7 +321,7 @@ def batched_workload(args):
     phi = torch.from_numpy(w["phi"]).to(dev)
     ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0),
                          P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
-    tune_us = P.gpuqt_autotune(H, B, ws=ws)
+    tune_us = pick_variant(P, H, B, ws, args)
     mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=dev)
     for _ in range(args.warmup):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
@@ -344,7 +358,8 @@ def batched_workload(args):
                         "steps_timed": args.steps},
                 roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": d["GBs"] / HBM_PEAK_GBS,
-                          "traffic": measured_traffic("batched", dominant, d["bytes_per_launch"]),
+                          "traffic": measured_traffic("batched", dominant, d["bytes_per_launch"],
+                                                      H.info.kernel_variant),
                           "kernel": "%s (B=16, hop mode %d, K=%d, %s)"
                                     % (FAMILY_KERNEL[dominant], H.info.hop_mode, H.info.uniform_width,
                                        variant_text(H.info.kernel_variant)),
@@ -487,6 +502,9 @@ def main():
     ap.add_argument("--workload", default="honeycomb",
                     choices=["honeycomb", "cubic", "batched", "train", "paper"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="pin the kernel variant code of the timed handle instead of autotuning "
+                         "(bits 0-1 load variant, 2-5 per-CU cap; honeycomb, cubic, batched)")
     ap.add_argument("--cpu-moments", type=int, default=0,
                     help="moments in the CPU oracle sample (0: sized to about 15 s)")
     args = ap.parse_args()
