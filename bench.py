@@ -102,11 +102,17 @@ def pick_variant(P, H, B, ws, args):
     return P.gpuqt_autotune(H, B, ws=ws)
 
 
-def variant_text(v):
-    """The autotuned kernel variant: load variant (bit 0 non-temporal, bit 1 banded order)
-    and the cap on resident workgroups per CU (bits 2-5, 0 = none)."""
-    cap = v >> 2
-    return "variant %d, %s" % (v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
+def variant_text(v, family=None):
+    """The autotuned kernel variant code v: load variant (bit 0 non-temporal, bit 1 banded
+    order), the cap on resident workgroups per CU (bits 2-5, 0 = none), or the family's own
+    cap (3 bits per family from bit 8: 0 = the per-CU cap, 1 + c = cap c) when it has one."""
+    from paper_1705_01387_amd._binding import K_FAMILIES
+    cap = (v >> 2) & 15
+    if family is not None:
+        c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
+        if c:
+            cap = c - 1
+    return "code %d: variant %d, %s" % (v, v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
 
 
 def moment_step_bytes(info, B):
@@ -266,7 +272,7 @@ def transport_workload(args, name):
                                                      H.info.kernel_variant),
                          "kernel": "%s (B=%d, hop mode %d, K=%d, %s)"
                                    % (FAMILY_KERNEL[dominant], B, H.info.hop_mode, H.info.uniform_width,
-                                      variant_text(H.info.kernel_variant)),
+                                      variant_text(H.info.kernel_variant, dominant)),
                          "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
                          "autotune_us_per_step": [float(t) for t in tune_us]},
                kernels=kernels)
@@ -362,7 +368,7 @@ def batched_workload(args):
                                                       H.info.kernel_variant),
                           "kernel": "%s (B=16, hop mode %d, K=%d, %s)"
                                     % (FAMILY_KERNEL[dominant], H.info.hop_mode, H.info.uniform_width,
-                                       variant_text(H.info.kernel_variant)),
+                                       variant_text(H.info.kernel_variant, dominant)),
                           "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
                           "autotune_us_per_step": [float(t) for t in tune_us]},
                 kernels=kernels,
@@ -504,7 +510,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--variant", type=int, default=-1,
                     help="pin the kernel variant code of the timed handle instead of autotuning "
-                         "(bits 0-1 load variant, 2-5 per-CU cap; honeycomb, cubic, batched)")
+                         "(as gpuqt_h_info reports it: bits 0-1 load variant, 2-5 per-CU cap, 3 bits "
+                         "per kernel family from bit 8; honeycomb, cubic, batched)")
     ap.add_argument("--cpu-moments", type=int, default=0,
                     help="moments in the CPU oracle sample (0: sized to about 15 s)")
     args = ap.parse_args()

@@ -141,7 +141,8 @@ typedef struct {
   size_t device_bytes;       /* device memory held by the handle */
   int64_t row_period;        /* largest detected row period D over the segments (0: none) */
   int32_t banded_mask;       /* bit log2(B) set: block width B has a banded row order */
-  int32_t reserved;
+  int32_t family_caps;       /* per kernel family f (GPUQT_K_*), bits 4f..4f+3: 0 = the per-CU
+                                cap of kernel_variant, else 1 + that family's own cap (1: none) */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -299,8 +300,13 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
  * uncapped and at every cap of 2..6 below its occupancy limit: fewer waves in
  * flight shrink the window of rows whose gathered elements must stay cached,
  * which can outweigh the lost latency hiding.  The cap applies to every
- * kernel family on the handle.  Synchronises the stream.
- *   ws : device workspace of at least gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0)
+ * kernel family on the handle; then, at the chosen load variant, the
+ * two-chain moment step, the two-vector evolution term and the MSD term are
+ * each timed at the same caps and get their own (kernel_variant bits 8-25).
+ * Synchronises the stream.
+ *   ws : device workspace of gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0) bytes
+ *        (eight vectors); one of three vectors plus the partial sums tunes the
+ *        Hermitian step only.
  *   times_us : NULL or HOST [4], microseconds per step of load/order variants 0..3, each at
  *              its best cap (0 for a banded variant when this B has no banded order).
  * Not safe while other calls on the handle are in flight.
@@ -308,10 +314,12 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
 gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
                             double *times_us);
 
-/* Set the kernel variant (bits as in gpuqt_autotune: load variant in bits 0-1, per-CU cap
- * 0..8 in bits 2-5) without measuring.  The banded bit only takes effect for block widths
- * that have a banded order (gpuqt_h_info_t.banded_mask).  GPUQT_ERR_ARG for a negative
- * variant or a cap above 8. */
+/* Set the kernel variant without measuring, with the bits of gpuqt_h_info_t.kernel_variant:
+ * load variant in bits 0-1, per-CU cap 0..8 in bits 2-5, bits 6-7 zero, and from bit 8 three
+ * bits per kernel family (0: the per-CU cap, 1 + c: cap c of 0..6), so a code read from
+ * gpuqt_h_info after gpuqt_autotune reproduces the tuned configuration.  The banded bit only
+ * takes effect for block widths that have a banded order (gpuqt_h_info_t.banded_mask).
+ * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8 or bits set above the families. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*

@@ -52,7 +52,7 @@ class HInfo(ctypes.Structure):
         ("max_width", ctypes.c_int32), ("uniform_width", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
-        ("banded_mask", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32),
     ]
 
 
@@ -566,7 +566,8 @@ def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
     """Time the kernel variants (plain / non-temporal loads, plain / banded row order, each
     uncapped and at per-CU workgroup caps below its occupancy limit), keep the fastest; returns
     us per moment step of load variants 0..3 at their best cap (0 where a variant does not
-    exist).  H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none)."""
+    exist).  H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none),
+    from bit 8 the two-chain moment, MSD and two-vector evolution families' own caps."""
     t = np.zeros(4)
     ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
@@ -577,8 +578,10 @@ def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
 
 
 def gpuqt_set_variant(H: Hamiltonian, variant: int):
-    """Pin the kernel variant (bit 0: non-temporal streams, bit 1: banded row order,
-    bits 2-5: resident workgroups per CU at most, 0 = no cap)."""
+    """Pin the kernel variant code (bit 0: non-temporal streams, bit 1: banded row order,
+    bits 2-5: resident workgroups per CU at most, 0 = no cap; from bit 8, 3 bits per kernel
+    family: 0 = that cap, 1 + c = the family's own cap c).  H.info.kernel_variant after
+    gpuqt_autotune is such a code."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")
     info = HInfo()
     _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")

@@ -34,6 +34,11 @@ namespace {
   } while (0)
 
 constexpr int kAutoNpCap = 8192;
+// autotuner: Chebyshev steps per timing, and the workspace that also lets it
+// time the two-chain moment, two-vector evolution and MSD families
+constexpr int kTuneSteps = 24;
+constexpr int kTuneNp = 13;
+constexpr int kTuneVectors = 8;
 
 bool valid_B(int B) { return B == 1 || B == 2 || B == 4 || B == 8 || B == 16; }
 
@@ -68,7 +73,7 @@ int op_vectors(int op) {
     case GPUQT_OP_VAC: return 9;
     case GPUQT_OP_MSD: return 9;
     case GPUQT_OP_MOMENTS_BACKWARD: return 6;
-    case GPUQT_OP_AUTOTUNE: return 3;
+    case GPUQT_OP_AUTOTUNE: return kTuneVectors;
     default: return -1;
   }
 }
@@ -702,6 +707,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->grid_blocks = h->G;
   info->device_bytes = h->device_bytes;
   info->kernel_variant = h->variant_code();
+  info->family_caps = h->family_caps_code();
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -791,7 +797,7 @@ gpuqt_status gpuqt_workspace_size(gpuqt_h hh, int32_t op, int32_t B, int32_t M, 
   if (nv < 0) return fail(GPUQT_ERR_ARG, "unknown op");
   if (M < 0 || Np < 0) return fail(GPUQT_ERR_ARG, "M and Np must be >= 0");
   if (op == GPUQT_OP_AUTOTUNE) {
-    *bytes = ws_layout(h, 3, B, 25, 0).total;
+    *bytes = ws_layout(h, kTuneVectors, B, kTuneSteps + 1, kTuneNp).total;
     return GPUQT_OK;
   }
   const bool has_moments = op == GPUQT_OP_MOMENTS || op == GPUQT_OP_VAC || op == GPUQT_OP_MSD ||
@@ -1169,7 +1175,7 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
   if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
-  constexpr int kSteps = 24;
+  constexpr int kSteps = kTuneSteps;
   const WsLayout W = ws_layout(h, 3, B, kSteps + 1, 0);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
@@ -1186,35 +1192,46 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  float best = 0.0f;
-  int best_v = h->variant_code();
-  const int lb = Handle::log2B(B);
-  const int n_var = h->d_units[lb] ? 4 : 2;
-  if (times_us)
-    for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
-  // the Hermitian moment step (the one most calls run) of one variant and cap;
-  // returns milliseconds for kSteps / 2 launches
-  auto time_one = [&](int v, int cap, float* ms) -> gpuqt_status {
-    h->nt = v & 1;
-    h->banded = v >> 1;
-    h->per_cu_cap = cap;
+  // milliseconds of one run (after one untimed run of the same work)
+  auto time_run = [&](auto&& run, float* ms) -> gpuqt_status {
     gpuqt_status q;
-    if ((q = run_moments(h, B, phi, phi, 4, part, A, Bf, s, true))) return q;   // warm
+    if ((q = run())) return q;
     if (hipEventRecord(e0, s) != hipSuccess) return fail(GPUQT_ERR_HIP, "hipEventRecord failed");
-    if ((q = run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true))) return q;
+    if ((q = run())) return q;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(ms, e0, e1) != hipSuccess)
       return fail(GPUQT_ERR_HIP, "event timing failed");
     return GPUQT_OK;
   };
+  // the Hermitian moment step (the one most calls run) of one variant and cap
+  auto time_one = [&](int v, int cap, float* ms) -> gpuqt_status {
+    h->nt = v & 1;
+    h->banded = v >> 1;
+    h->per_cu_cap = cap;
+    return time_run([&] { return run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true); }, ms);
+  };
+  const int lb = Handle::log2B(B);
+  // caps below a family's occupancy limit at the current load variant, then none
+  auto caps_of = [&](int fam, std::vector<int>* out) {
+    const int occ = std::max<int>(1, h->occ[fam][lb][h->nt ? 1 : 0]);
+    out->clear();
+    for (int cap : {2, 3, 4, 5, 6})
+      if (cap < occ) out->push_back(cap);
+    out->push_back(0);
+  };
+  for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
+  float best = 0.0f;
+  int best_v = h->variant_code() & 63;
+  const int n_var = h->d_units[lb] ? 4 : 2;
+  if (times_us)
+    for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
   float ms = 0.0f;
   st = time_one(0, 0, &ms);   // settle clocks and caches before the sweep
+  std::vector<int> caps;
   for (int v = 0; v < n_var && !st; ++v) {
-    // caps below the occupancy limit of this variant's Hermitian step, then none
-    const int occ = std::max<int>(1, h->occ[FAM_SYM][lb][v & 1]);
-    const int caps[] = {2, 3, 4, 5, 6, 0};
+    h->nt = v & 1;
+    caps_of(FAM_SYM, &caps);
     for (int cap : caps) {
-      if (cap != 0 && cap >= occ) continue;
       if ((st = time_one(v, cap, &ms))) break;
       const double us = 1e3 * ms / (kSteps / 2);   // per launch
       if (times_us && (times_us[v] == 0.0 || us < times_us[v])) times_us[v] = us;
@@ -1224,11 +1241,46 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   h->nt = best_v & 1;
   h->banded = (best_v >> 1) & 1;
-  h->per_cu_cap = best_v >> 2;
+  h->per_cu_cap = (best_v >> 2) & 15;
+  // with room for their vectors, each of the two-chain moment, two-vector
+  // evolution and MSD families also gets its own cap at this load variant
+  const WsLayout WF = ws_layout(h, kTuneVectors, B, kSteps + 1, kTuneNp);
+  if (!st && ws_bytes >= WF.total) {
+    double2* v[kTuneVectors];
+    for (int i = 0; i < kTuneVectors; ++i) v[i] = reinterpret_cast<double2*>(base + i * WF.vec_bytes);
+    double2* partF = reinterpret_cast<double2*>(base + WF.off_part);
+    double* J = reinterpret_cast<double*>(base + WF.off_J);
+    HIP_TRY(launch_fill_phase(h->view(B), B, v[1], s));
+    const double dt = 1.0;
+    const int fams[] = {FAM_PAIR, FAM_EVOLVE_PAIR, FAM_MSD};
+    for (int f : fams) {
+      auto run = [&]() -> gpuqt_status {
+        if (f == FAM_PAIR) return run_moments(h, B, v[0], v[1], kSteps + 1, partF, v[2], v[3], s, false, v[4], v[5]);
+        if (f == FAM_EVOLVE_PAIR)
+          return run_evolve_pair(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], J, s);
+        return run_evolve(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], nullptr, J, s);
+      };
+      caps_of(f, &caps);
+      float fbest = 0.0f;
+      int fcap = -1;
+      for (int cap : caps) {
+        h->fam_cap[f] = (int8_t)cap;
+        if ((st = time_run(run, &ms))) break;
+        if (fbest == 0.0f || ms < fbest) {
+          fbest = ms;
+          fcap = cap;
+        }
+      }
+      if (st) break;
+      h->fam_cap[f] = (int8_t)fcap;
+    }
+  }
+  if (st)
+    for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return st;
 }
 
@@ -1279,11 +1331,15 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
 gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
-  if (variant < 0 || (variant >> 2) > kPerCU)
-    return fail(GPUQT_ERR_ARG, "variant must be bits 0-1 plus a per-CU cap of 0..8 in bits 2-5");
+  if (variant < 0 || ((variant >> 2) & 15) > kPerCU || (variant & (3 << 6)) ||
+      (variant >> (8 + 3 * kFamilies)))
+    return fail(GPUQT_ERR_ARG,
+                "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bits 6-7 zero "
+                "and 3 bits per kernel family from bit 8");
   h->nt = variant & 1;
   h->banded = (variant >> 1) & 1;
-  h->per_cu_cap = variant >> 2;
+  h->per_cu_cap = (variant >> 2) & 15;
+  for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = (int8_t)(((variant >> (8 + 3 * f)) & 7) - 1);
   return GPUQT_OK;
 }
 

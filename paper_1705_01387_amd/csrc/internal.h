@@ -126,6 +126,8 @@ struct Handle {
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
   int32_t per_cu_cap = 0;
+  // per kernel family: -1 = use per_cu_cap, else that family's own cap (0: none)
+  int8_t fam_cap[kFamilies] = {-1, -1, -1, -1, -1, -1};
   // banded orders per block width (index log2 B); NULL where the plain row order
   // already keeps the neighbour window within the cache budget
   int32_t* d_units[kNumB] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -169,10 +171,18 @@ struct Handle {
   int plan_index(int B, int family) const {
     int p = occ[family][log2B(B)][nt ? 1 : 0];
     if (p < 1 || p > kPerCU) p = kPerCU;
-    if (per_cu_cap > 0 && per_cu_cap < p) p = per_cu_cap;
+    const int cap = fam_cap[family] >= 0 ? fam_cap[family] : per_cu_cap;
+    if (cap > 0 && cap < p) p = cap;
     return p - 1;
   }
-  int32_t variant_code() const { return nt | (banded << 1) | (per_cu_cap << 2); }
+  // per family f, bits 3f..3f+2: fam_cap[f] + 1 (0: the handle's cap; family caps are 0..6)
+  int32_t family_caps_code() const {
+    int32_t c = 0;
+    for (int f = 0; f < kFamilies; ++f) c |= (int32_t)(fam_cap[f] + 1) << (3 * f);
+    return c;
+  }
+  // nt | banded << 1 | per_cu_cap << 2 | (fam_cap[f] + 1) << (8 + 3 f)
+  int32_t variant_code() const { return nt | (banded << 1) | (per_cu_cap << 2) | (family_caps_code() << 8); }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
   DevMat view(int B, int family) const {

@@ -112,11 +112,25 @@ def test_autotune_keeps_results(gpu):
     phi = dev(I.random_phase(m.n, 4, 66))
     t = P.gpuqt_autotune(H, 4)
     assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:] == 0)   # no banded order
-    assert H.info.kernel_variant & 3 in (0, 1) and (H.info.kernel_variant >> 2) <= 8
+    code = H.info.kernel_variant
+    assert code & 3 in (0, 1) and (code >> 2) & 15 <= 8 and (code >> 6) & 3 == 0
+    fc = H.info.family_caps   # the pair (2), msd (4) and evolve pair (5) families got their own cap
+    assert fc == code >> 8
+    assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 1, 3))
     a = host(P.gpuqt_moments(H, phi, phi, 200))
     Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     ref = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(phi), 200).T
     assert err(a[0], ref) < TOL
+    psi = dev(I.random_phase(m.n, 4, 67))
+    ref2 = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(psi), 200).T
+    assert err(host(P.gpuqt_moments(H, phi, psi, 200))[0], ref2) < TOL
+    P.gpuqt_set_variant(H, code & 63)
+    assert H.info.family_caps == 0 and H.info.kernel_variant == code & 63
+    P.gpuqt_set_variant(H, code)                       # the tuned code round-trips
+    assert H.info.kernel_variant == code
+    for bad in (code | (1 << 6), 1 << 26, 9 << 2):
+        with pytest.raises(P.GpuqtError):
+            P.gpuqt_set_variant(H, bad)
     Hb = P.gpuqt_build_h_from_model(m, band_rows=64)                      # period 121 > 64
     tb = P.gpuqt_autotune(Hb, 4)
     assert np.all(np.isfinite(tb)) and np.all(tb > 0)
