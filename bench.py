@@ -398,14 +398,16 @@ def train_workload(args):
     gU = torch.zeros(m.n, dtype=torch.float64, device=dev)
     gC = torch.zeros(2, dtype=torch.float64, device=dev)
     np_list = [P.gpuqt_auto_terms(dE * abs(t)) for t in dts]
+    # the VAC forward keeps its states and moment chains (the tape) for the backward
+    tape = torch.empty(P.gpuqt_vac_tape_size(H, 1, len(dts), M), dtype=torch.uint8, device=dev)
 
     def fwd():
         P.gpuqt_moments(H, phi, phi, M)
-        P.gpuqt_vac(H, phi, dts, M)
+        P.gpuqt_vac_record(H, phi, dts, M, tape=tape)
 
     def bwd():
         P.gpuqt_moments_backward(H, phi, phi, wd, gU, gC)
-        P.gpuqt_vac_backward(H, phi, dts, wv, gU, gC)
+        P.gpuqt_vac_backward_tape(H, phi, dts, wv, tape, gU, gC)
 
     for f in (fwd, bwd):
         f()
@@ -425,7 +427,8 @@ def train_workload(args):
                 config={"workload": "square 512^2 (262,144 orbitals), NN + NNN hopping classes, DeltaE=6, "
                                     "DOS M=512 + VAC 10 x dt=1; forward + adjoint (all on-site and class "
                                     "gradients; every forward vector kept, moment sets reversed in "
-                                    "the two-chain form)", "orbitals": int(m.n), "moments": M},
+                                    "the two-chain form, the VAC forward's states and chains recorded "
+                                    "for the adjoint)", "orbitals": int(m.n), "moments": M},
                 adjoint_vs_forward={"forward_ms": tf * 1e3, "adjoint_ms": tb * 1e3, "ratio": tb / tf},
                 roofline=None, cpu_baseline=None)
 

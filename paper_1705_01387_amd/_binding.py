@@ -106,6 +106,20 @@ _SIGS = {
     "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_vac_tape_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_vac_record": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p]),
+    "gpuqt_vac_backward_tape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_vac_backward_tape_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                                ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_kpm_reconstruct_adjoint": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                                        ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
@@ -484,6 +498,62 @@ def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: in
     _check(lib().gpuqt_vac_backward_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np, int(ckpt_stride),
                                                    ctypes.byref(out)), "gpuqt_vac_backward_workspace_size")
     return int(out.value)
+
+
+def gpuqt_vac_tape_size(H: Hamiltonian, B: int, n_t: int, M: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().gpuqt_vac_tape_size(H.handle, B, int(n_t), int(M), ctypes.byref(out)), "gpuqt_vac_tape_size")
+    return int(out.value)
+
+
+def gpuqt_vac_record(H: Hamiltonian, phi, dt: Sequence[float], M: int, Np: int = 0, tape=None, out=None,
+                     ws=None, stream=None):
+    """gpuqt_vac that also keeps the states and moment chains in `tape` (a uint8 CUDA tensor of
+    at least gpuqt_vac_tape_size bytes; allocated when None).  Returns (rows, tape)."""
+    import torch
+    _dev_vec(phi, "phi")
+    B = _cols(phi)
+    dtn = np.ascontiguousarray(dt, dtype=np.float64)
+    if tape is None:
+        tape = torch.empty(max(gpuqt_vac_tape_size(H, B, dtn.shape[0], M), 16), dtype=torch.uint8,
+                           device=phi.device)
+    tb = int(tape.numel() * tape.element_size())
+    fn = lambda h, b, p, n, d, m, npp, o, w_, nb, st: lib().gpuqt_vac_record(h, b, p, n, d, m, npp, o, w_, nb,
+                                                                           _ptr(tape), tb, st)
+    rows = _series(fn, "gpuqt_vac_record", OP_VAC, H, phi, dtn, M, Np, out, ws, stream)
+    return rows, tape
+
+
+def gpuqt_vac_backward_tape_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0) -> int:
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    out = ctypes.c_size_t()
+    _check(lib().gpuqt_vac_backward_tape_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np,
+                                                        ctypes.byref(out)), "gpuqt_vac_backward_tape_workspace_size")
+    return int(out.value)
+
+
+def gpuqt_vac_backward_tape(H: Hamiltonian, phi, dt, w, tape, grad_onsite=None, grad_class=None, Np: int = 0,
+                            ws=None, stream=None):
+    """gpuqt_vac_backward from the tape of gpuqt_vac_record (same phi, dt, M, Np): no state
+    re-evolution and no forward pass of the rows' moments."""
+    import torch
+    _dev_vec(phi, "phi")
+    B = _cols(phi)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    w = w.contiguous()
+    M = int(w.shape[-1])
+    if grad_onsite is None:
+        grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
+    if ws is None:
+        ws = torch.empty(max(gpuqt_vac_backward_tape_workspace_size(H, B, dt, M, Np), 16), dtype=torch.uint8,
+                         device=phi.device)
+    nb = int(ws.numel() * ws.element_size())
+    tb = int(tape.numel() * tape.element_size())
+    _check(lib().gpuqt_vac_backward_tape(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
+                                         _ptr(grad_onsite), _ptr(grad_class), _ptr(tape), tb, _ptr(ws), nb,
+                                         _stream(stream)),
+           "gpuqt_vac_backward_tape")
+    return grad_onsite, grad_class
 
 
 def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=None, Np: int = 0,

@@ -44,13 +44,26 @@ class Moments(torch.autograd.Function):
 
 
 class VAC(torch.autograd.Function):
-    """C_n^VAC(t_k) rows, shape [n_t, n_seg, B, M]."""
+    """C_n^VAC(t_k) rows, shape [n_t, n_seg, B, M].
+
+    When a gradient is needed and the recorded forward (states and moment chains,
+    gpuqt_vac_tape_size) fits in Bd.KEEP_ALL_FRACTION of the free device memory, the
+    forward keeps it and the backward recomputes nothing; otherwise the backward
+    re-evolves and recomputes as gpuqt_vac_backward does."""
 
     @staticmethod
     def forward(ctx, onsite, scales, H, phi, dt, M, Np):
         _set(H, onsite, scales)
-        out = Bd.gpuqt_vac(H, phi, dt, M, Np)
-        ctx.H, ctx.dt, ctx.Np = H, np.asarray(dt, dtype=np.float64), Np
+        dtn = np.asarray(dt, dtype=np.float64)
+        ctx.tape = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            need = Bd.gpuqt_vac_tape_size(H, Bd._cols(phi), dtn.shape[0], M)
+            free, _ = torch.cuda.mem_get_info(phi.device)
+            if need <= Bd.KEEP_ALL_FRACTION * free:
+                out, ctx.tape = Bd.gpuqt_vac_record(H, phi, dtn, M, Np)
+        if ctx.tape is None:
+            out = Bd.gpuqt_vac(H, phi, dtn, M, Np)
+        ctx.H, ctx.dt, ctx.Np = H, dtn, Np
         ctx.save_for_backward(onsite, scales, phi)
         return out
 
@@ -61,7 +74,11 @@ class VAC(torch.autograd.Function):
         _set(H, onsite, scales)
         gU = torch.zeros_like(onsite)
         gC = torch.zeros(scales.shape[0], dtype=torch.float64, device=onsite.device)
-        Bd.gpuqt_vac_backward(H, phi, ctx.dt, g.contiguous(), gU, gC, Np=ctx.Np)
+        if ctx.tape is not None:
+            Bd.gpuqt_vac_backward_tape(H, phi, ctx.dt, g.contiguous(), ctx.tape, gU, gC, Np=ctx.Np)
+            ctx.tape = None
+        else:
+            Bd.gpuqt_vac_backward(H, phi, ctx.dt, g.contiguous(), gU, gC, Np=ctx.Np)
         return gU, (gC.to(scales.device) / scales), None, None, None, None, None
 
 

@@ -190,20 +190,25 @@ struct TimeScope {
 // in symmetric mode turns into the moments.
 gpuqt_status run_moments(const Handle* h, int B, const double2* phiL, const double2* phiR, int M,
                          double2* part, double2* A, double2* Bf, hipStream_t s, bool sym = false,
-                         double2* A2 = nullptr, double2* B2 = nullptr) {
-  const int fam = A2 ? FAM_PAIR : sym ? FAM_SYM : FAM_MOMENT;
+                         double2* A2 = nullptr, double2* B2 = nullptr, double2* const* keep = nullptr) {
+  const int fam = A2 || keep ? FAM_PAIR : sym ? FAM_SYM : FAM_MOMENT;
   const DevMat D = h->view(B, fam);
   const int64_t row = (int64_t)D.G * B;   // partial rows: one per logical workgroup of this plan
-  if (A2) {   // pair: chains phiL (A, Bf) and phiR (A2, B2), product identities
+  if (A2 || keep) {   // pair: chains phiL (A, Bf) and phiR (A2, B2), product identities
     const int K = std::max(1, M / 2);
+    // keep: every chain vector goes to its own buffer, a_k to keep[k-1], b_k to keep[K+k-1]
+    if (keep) {
+      A = keep[0];
+      A2 = keep[K];
+    }
     TimeScope ts(h, s, 2, K);
     ChainIO io{phiL, nullptr, A, phiR, nullptr, A2, 1, 1};
     HIP_TRY(launch_moment_step_pair(D, h->hop_mode, B, io, part, part + row, part + 2 * row, s));
     const double2 *pa = phiL, *pb = phiR;
     double2 *ca = A, *cb = A2;
     for (int k = 2; k <= K; ++k) {
-      double2* oa = (pa == phiL) ? Bf : const_cast<double2*>(pa);
-      double2* ob = (pb == phiR) ? B2 : const_cast<double2*>(pb);
+      double2* oa = keep ? keep[k - 1] : (pa == phiL) ? Bf : const_cast<double2*>(pa);
+      double2* ob = keep ? keep[K + k - 1] : (pb == phiR) ? B2 : const_cast<double2*>(pb);
       ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
       HIP_TRY(launch_moment_step_pair(D, h->hop_mode, B, st, part + row * (2 * k - 1), nullptr,
                                       part + row * (2 * k), s));
@@ -472,13 +477,15 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
 gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                                const double* wts, double* gU, double* gcp, int nc, double2* outA,
                                bool accA, double2* outB, bool accB, double2* const* vec, double* om,
-                               double2* scratch, hipStream_t sm) {
+                               double2* scratch, hipStream_t sm, double2* const* recorded = nullptr) {
   const int K = pair_steps(M);
   const int R = 2 * K + 2;
   HIP_TRY(launch_raw_weights(wts, h->n_seg * B, M, R, om, sm));
-  auto fa = [&](int k) -> const double2* { return k == 0 ? pL : vec[k - 1]; };
-  auto fb = [&](int k) -> const double2* { return k == 0 ? pR : vec[K + k - 1]; };
-  {
+  // forward chains a_1..a_K, b_1..b_K: recorded by the forward call, or computed here into vec
+  double2* const* ch = recorded ? recorded : vec;
+  auto fa = [&](int k) -> const double2* { return k == 0 ? pL : ch[k - 1]; };
+  auto fb = [&](int k) -> const double2* { return k == 0 ? pR : ch[K + k - 1]; };
+  if (!recorded) {
     TimeScope ts(h, sm, FAM_PAIR, K);
     const DevMat F = h->view(B, FAM_PAIR);
     const int64_t row = (int64_t)F.G * B;
@@ -488,8 +495,8 @@ gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const 
       HIP_TRY(launch_moment_step_pair(F, h->hop_mode, B, io, scratch, scratch + row, scratch + 2 * row, sm));
     }
   }
-  double2* const* La = vec + 2 * K;       // rotating abar
-  double2* const* Lb = vec + 2 * K + 3;   // rotating bbar
+  double2* const* La = recorded ? vec : vec + 2 * K;   // rotating abar
+  double2* const* Lb = La + 3;                         // rotating bbar
   const DevMat D = h->view(B);            // class partials over the primary plan
   for (int k = K; k >= 0; --k) {
     if (k == 0 && !outA && !outB) break;
@@ -916,12 +923,50 @@ static int max_terms(const Handle* h, int32_t n_t, const double* dt, int32_t Np)
   return best;
 }
 
-gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
-                       int32_t M, int32_t Np, double* out, void* ws, size_t ws_bytes, void* stream) {
-  const Handle* h = reinterpret_cast<const Handle*>(hh);
+// Recorded VAC forward ("tape"), for a backward pass that recomputes nothing:
+// vector slots of n x B complex128 (256-byte aligned) holding psi_L(k) for
+// k = 1 .. n_t-1 (slot k-1), psi_R(k) for k = 0 .. n_t-1 (slot n_t-1+k), and
+// for each row k from slot 2 n_t - 1 + 2 K k the two moment chains a_1..a_K,
+// b_1..b_K of <V psi_L(k)| T_n |psi_R(k)> (K = max(1, M/2)).
+static int64_t vac_tape_vectors(int n_t, int M) {
+  return n_t > 0 ? 2 * (int64_t)n_t - 1 + 2 * (int64_t)pair_steps(M) * n_t : 0;
+}
+
+struct VacTape {
+  char* base = nullptr;
+  size_t vec_bytes = 0;
+  int n_t = 0, K = 0;
+  double2* slot(int64_t i) const { return reinterpret_cast<double2*>(base + vec_bytes * (size_t)i); }
+  double2* psiL(int k) const { return slot(k - 1); }
+  double2* psiR(int k) const { return slot(n_t - 1 + k); }
+  // a_1..a_K, b_1..b_K of row k
+  std::vector<double2*> chains(int k) const {
+    std::vector<double2*> c(2 * (size_t)K);
+    for (int j = 0; j < 2 * K; ++j) c[j] = slot(2 * (int64_t)n_t - 1 + 2 * (int64_t)K * k + j);
+    return c;
+  }
+};
+
+static gpuqt_status vac_tape_check(const Handle* h, int B, int n_t, int M, void* tape, size_t tape_bytes,
+                            VacTape* T) {
+  T->vec_bytes = round_up((size_t)h->n * (size_t)B * 16u, 256);
+  T->n_t = n_t;
+  T->K = pair_steps(M);
+  T->base = static_cast<char*>(tape);
+  if (!tape || tape_bytes < T->vec_bytes * (size_t)vac_tape_vectors(n_t, M))
+    return fail(GPUQT_ERR_WORKSPACE, "tape too small");
+  if (!aligned16(tape)) return fail(GPUQT_ERR_ARG, "tape is not 16-byte aligned");
+  return GPUQT_OK;
+}
+
+static gpuqt_status vac_impl(const Handle* h, int32_t B, const double* phi, int32_t n_t, const double* dt, int32_t M,
+                      int32_t Np, double* out, void* ws, size_t ws_bytes, void* tape, size_t tape_bytes,
+                      void* stream) {
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, out);
   if (st) return st;
   if (n_t == 0 || M == 0) return GPUQT_OK;
+  VacTape T;
+  if (tape && (st = vac_tape_check(h, B, n_t, M, tape, tape_bytes, &T))) return st;
   const int np = max_terms(h, n_t - 1, dt, Np);
   const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_VAC), B, moment_rows(M), np);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
@@ -939,18 +984,25 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
   double2* Rbuf[2] = {V(2), V(3)};
   double2* phiL = V(4);
   int ri = 0;
-  HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, Rbuf[0], s));
-  const double2* psiR = Rbuf[0];
+  HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, tape ? T.psiR(0) : Rbuf[0], s));
+  const double2* psiR = tape ? T.psiR(0) : Rbuf[0];
   const int64_t row = (int64_t)h->n_seg * B * M;
   for (int k = 0; k < n_t; ++k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL, phiL, s));
-    if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s, false, V(7), V(8)))) return st;
+    if (tape) {
+      const std::vector<double2*> keep = T.chains(k);
+      if ((st = run_moments(h, B, phiL, psiR, M, part, nullptr, nullptr, s, false, nullptr, nullptr,
+                            keep.data())))
+        return st;
+    } else if ((st = run_moments(h, B, phiL, psiR, M, part, V(5), V(6), s, false, V(7), V(8)))) {
+      return st;
+    }
     HIP_TRY(launch_reduce_moments(part, M, h->G_of(B, FAM_PAIR), B, h->n_seg, h->blk0_of(B, FAM_PAIR), 1,
                                   nullptr, out + row * k, s));
     if (k + 1 < n_t) {
       const int np_k = terms_for(h, dt[k], Np);
-      double2* Ln = (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
-      double2* Rn = Rbuf[ri ^ 1];
+      double2* Ln = tape ? T.psiL(k + 1) : (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
+      double2* Rn = tape ? T.psiR(k + 1) : Rbuf[ri ^ 1];
       // both states advance with the same U(-dt): one two-chain series
       if ((st = run_evolve_pair(h, B, -dt[k], np_k, psiL, Ln, psiR, Rn, V(5), V(6), V(7), V(8), J, s)))
         return st;
@@ -960,6 +1012,29 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
     }
   }
   return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
+                       int32_t M, int32_t Np, double* out, void* ws, size_t ws_bytes, void* stream) {
+  return vac_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, out, ws, ws_bytes, nullptr, 0,
+                  stream);
+}
+
+gpuqt_status gpuqt_vac_tape_size(gpuqt_h hh, int32_t B, int32_t n_t, int32_t M, size_t* bytes) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (n_t < 0 || M < 0) return fail(GPUQT_ERR_ARG, "n_t and M must be >= 0");
+  *bytes = round_up((size_t)h->n * (size_t)B * 16u, 256) * (size_t)vac_tape_vectors(n_t, M);
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_vac_record(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
+                              int32_t M, int32_t Np, double* out, void* ws, size_t ws_bytes, void* tape,
+                              size_t tape_bytes, void* stream) {
+  if (!tape) return fail(GPUQT_ERR_ARG, "tape is NULL");
+  return vac_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, out, ws, ws_bytes, tape,
+                  tape_bytes, stream);
 }
 
 gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
@@ -1068,23 +1143,24 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_
   return GPUQT_OK;
 }
 
-gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
-                                const double* dt, int32_t M, int32_t Np, const double* w,
-                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, void* ws,
-                                size_t ws_bytes, void* stream) {
-  const Handle* h = reinterpret_cast<const Handle*>(hh);
+static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* phi, int32_t n_t,
+                                      const double* dt, int32_t M, int32_t Np, const double* w,
+                                      double* grad_onsite, double* grad_class, int32_t ckpt_stride,
+                                      void* tape, size_t tape_bytes, void* ws, size_t ws_bytes, void* stream) {
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, w);
   if (st) return st;
   if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
-  const bool keep = ckpt_stride == 1;
+  const bool keep = ckpt_stride == 1 || tape;
   if (!grad_onsite) return fail(GPUQT_ERR_ARG, "grad_onsite is NULL");
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   if (n_t == 0 || M == 0) return GPUQT_OK;
+  VacTape T;
+  if (tape && (st = vac_tape_check(h, B, n_t, M, tape, tape_bytes, &T))) return st;
   const int np = max_terms(h, n_t - 1, dt, Np);
-  const int L = std::max(M, np);
+  const int L = tape ? np : std::max(M, np);
   const int s = keep ? 1 : backward_stride(L, 0);
-  const int nv = vac_backward_vectors(n_t, M, np, keep);
+  const int nv = tape ? 6 + backward_vectors(np, 1) : vac_backward_vectors(n_t, M, np, keep);
   const WsLayout W = ws_layout(h, nv, B, keep ? 5 : 2, np + (keep ? raw_weight_len(B, M) : 0));
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
@@ -1097,25 +1173,29 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   const DevMat D = h->view(B);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   const double2* ph = reinterpret_cast<const double2*>(phi);
-  // states psi_L(k) (k >= 1) and psi_R(k), adjoints, scratch
-  auto psiL = [&](int k) -> const double2* { return k == 0 ? ph : V(k - 1); };
-  auto psiR = [&](int k) { return V(n_t - 1 + k); };
-  double2* gL[2] = {V(2 * n_t - 1), V(2 * n_t)};
-  double2* gR[2] = {V(2 * n_t + 1), V(2 * n_t + 2)};
-  double2* gphiL = V(2 * n_t + 3);
-  double2* phiL = V(2 * n_t + 4);
+  // states psi_L(k) (k >= 1) and psi_R(k) (workspace, or the recorded tape),
+  // adjoints, scratch
+  const int o = tape ? 0 : 2 * n_t - 1;
+  auto psiL = [&](int k) -> const double2* { return k == 0 ? ph : tape ? T.psiL(k) : V(k - 1); };
+  auto psiR = [&](int k) { return tape ? T.psiR(k) : V(n_t - 1 + k); };
+  double2* gL[2] = {V(o), V(o + 1)};
+  double2* gR[2] = {V(o + 2), V(o + 3)};
+  double2* gphiL = V(o + 4);
+  double2* phiL = V(o + 5);
   std::vector<double2*> pool(backward_vectors(L, s));
-  for (size_t i = 0; i < pool.size(); ++i) pool[i] = V(2 * n_t + 5 + (int)i);
+  for (size_t i = 0; i < pool.size(); ++i) pool[i] = V(o + 6 + (int)i);
   double2* e0 = pool[0];   // evolution scratch during the forward pass
   double2* e1 = pool[1];
   if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
-  // forward: psi_R(0) = V phi; psi_{L,R}(k+1) = U(-dt_k) psi_{L,R}(k)
-  HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, psiR(0), sm));
-  for (int k = 0; k + 1 < n_t; ++k) {
-    const int npk = terms_for(h, dt[k], Np);
-    if ((st = run_evolve_pair(h, B, -dt[k], npk, psiL(k), V(k), psiR(k), psiR(k + 1), e0, e1, pool[2],
-                              pool[3], J, sm)))
-      return st;
+  // forward (unless recorded): psi_R(0) = V phi; psi_{L,R}(k+1) = U(-dt_k) psi_{L,R}(k)
+  if (!tape) {
+    HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, psiR(0), sm));
+    for (int k = 0; k + 1 < n_t; ++k) {
+      const int npk = terms_for(h, dt[k], Np);
+      if ((st = run_evolve_pair(h, B, -dt[k], npk, psiL(k), V(k), psiR(k), psiR(k + 1), e0, e1, pool[2],
+                                pool[3], J, sm)))
+        return st;
+    }
   }
   // reverse over the rows
   int cl = 0, cr = 0;
@@ -1127,9 +1207,11 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
     if (keep) {
       // moments of row k by the two-chain reverse: parameter terms,
       // gphiL = sum_n w_n T_n psi_R(k) and gR += sum_n w_n T_n phiL in one pass
+      const std::vector<double2*> rec = tape ? T.chains(k) : std::vector<double2*>();
       if ((st = run_backward_pair(h, B, phiL, psiR(k), M, w + row * k, grad_onsite, gcp, nc, gphiL, false,
                                   gR[cr], true, pool.data(), J + (int64_t)h->n_seg * np,
-                                  reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm)))
+                                  reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm,
+                                  tape ? rec.data() : nullptr)))
         return st;
     } else {
       BwdSource src;
@@ -1168,6 +1250,34 @@ gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_
   if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gR[cr], ph, h->d_cls, gcp, sm));
   if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
   return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
+                                const double* dt, int32_t M, int32_t Np, const double* w,
+                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, void* ws,
+                                size_t ws_bytes, void* stream) {
+  return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
+                           grad_class, ckpt_stride, nullptr, 0, ws, ws_bytes, stream);
+}
+
+gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
+                                                    int32_t M, int32_t Np, size_t* bytes) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (n_t < 0 || M < 0 || Np < 0 || (n_t > 0 && !dt)) return fail(GPUQT_ERR_ARG, "bad sizes");
+  const int np = max_terms(h, std::max(n_t - 1, 0), dt, Np);
+  *bytes = ws_layout(h, 6 + backward_vectors(np, 1), B, 5, np + raw_weight_len(B, M)).total;
+  return GPUQT_OK;
+}
+
+gpuqt_status gpuqt_vac_backward_tape(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, const double* dt,
+                                     int32_t M, int32_t Np, const double* w, double* grad_onsite,
+                                     double* grad_class, const void* tape, size_t tape_bytes, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  if (!tape) return fail(GPUQT_ERR_ARG, "tape is NULL");
+  return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
+                           grad_class, 1, const_cast<void*>(tape), tape_bytes, ws, ws_bytes, stream);
 }
 
 gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, void* stream,

@@ -113,6 +113,40 @@ def test_vac_backward(gpu, name, B, ckpt):
     assert err(host(gC), rC) < TOL
 
 
+@pytest.mark.parametrize("name", list(VAC_CASES))
+@pytest.mark.parametrize("B,M", [(1, 40), (2, 41), (1, 2)])
+def test_vac_record_and_backward_from_tape(gpu, name, B, M):
+    """The recorded forward returns gpuqt_vac's rows and the backward from its tape
+    gpuqt_vac_backward's gradients, bit for bit (same kernels on the same vectors), and
+    both match the oracle."""
+    import torch
+    from oracle.adjoint import vac_gradient, velocity_class_parts
+    say(f"case: VAC tape {name} B={B} M={M}")
+    mk, n_class = VAC_CASES[name]
+    m = mk()
+    H = P.gpuqt_build_h_from_model(m)
+    dE = float(H.energy_max[0])
+    phi = I.random_phase(m.n, B, 60)
+    dts = [0.3, 1.2, 0.0, 0.7]
+    rows = host(P.gpuqt_vac(H, dev(phi), dts, M))
+    rec, tape = P.gpuqt_vac_record(H, dev(phi), dts, M)
+    assert np.array_equal(host(rec), rows)
+    assert tape.numel() >= P.gpuqt_vac_tape_size(H, B, len(dts), M)
+    w = np.random.default_rng(61).normal(size=(len(dts), 1, B, M))
+    zc = lambda: torch.zeros(n_class, dtype=torch.float64, device="cuda")
+    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=1, grad_class=zc())
+    tU, tC = P.gpuqt_vac_backward_tape(H, dev(phi), dts, dev(w), tape, grad_class=zc())
+    assert np.array_equal(host(tU), host(gU)) and np.array_equal(host(tC), host(gC))
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
+    rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
+    assert err(host(tU), rU) < TOL and err(host(tC), rC) < TOL
+    # a tape that is too small is refused
+    with pytest.raises(P.GpuqtError):
+        P.gpuqt_vac_backward_tape(H, dev(phi), dts, dev(w), tape[:64], grad_class=zc())
+
+
 def test_backward_segments(gpu):
     import torch
     say("case: backward with segments")
