@@ -87,11 +87,12 @@ typedef struct {
                                    periods of 1024 rows or more that fit in one band); else a
                                    multiple of 64, used for every width and every segment whose
                                    row period exceeds it */
-  int32_t no_dictionary;        /* nonzero: keep one hopping per entry.  Otherwise, with one
-                                   hopping class, when the (hopping, position difference) pairs
-                                   take at most 65,535 distinct values (a uniform field, a few
-                                   bond types) each entry stores a 16-bit index into a table of
-                                   them (hop_mode 3 in gpuqt_h_info_t) */
+  int32_t no_dictionary;        /* nonzero: keep one hopping per entry.  Otherwise, with at
+                                   most 4 hopping classes, when the (column offset, hopping,
+                                   position difference, class) tuples take at most 65,535
+                                   distinct values (a uniform field, a few bond types) each
+                                   entry stores a 16-bit index into a table of them (hop_mode 3
+                                   in gpuqt_h_info_t) */
 } gpuqt_h_desc;
 
 /*

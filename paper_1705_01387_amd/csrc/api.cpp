@@ -751,7 +751,8 @@ gpuqt_status gpuqt_update_h_values(gpuqt_h hh, const double* onsite, const doubl
       HIP_TRY(hipMemcpyAsync(h->d_seg_hop, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
       HIP_TRY(hipStreamSynchronize(s));
     } else {
-      // per-entry hoppings, or (HOP_DICT, one class) the table of distinct values
+      // per-entry hoppings, or (HOP_DICT) the table of distinct values; classes per
+      // entry, or per table entry
       const bool dict = h->hop_mode == HOP_DICT;
       const int64_t count = dict ? h->dict_size : h->entries;
       const bool cplx = dict || h->hop_mode == HOP_COMPLEX;
@@ -768,7 +769,7 @@ gpuqt_status gpuqt_update_h_values(gpuqt_h hh, const double* onsite, const doubl
       }
       ClassScale sc{};
       for (int c = 0; c < h->n_class; ++c) sc.s[c] = class_scale[c];
-      HIP_TRY(launch_scale_hops(count, cplx ? 1 : 0, orig, cur, (!dict && h->n_class > 1) ? h->d_cls : nullptr,
+      HIP_TRY(launch_scale_hops(count, cplx ? 1 : 0, orig, cur, h->n_class > 1 ? h->d_cls : nullptr,
                                 sc, s));
     }
     for (int c = 0; c < h->n_class; ++c) h->class_scale[c] = class_scale[c];

@@ -238,7 +238,7 @@ struct HostLayout {
   std::vector<double> dxtab;   // HOP_DICT
   std::vector<int32_t> offtab; // HOP_DICT
   std::vector<double> diag;
-  std::vector<int32_t> cls;  // class per entry, -1 for padding (empty if one class)
+  std::vector<int32_t> cls;  // class per entry, -1 for padding (per table entry in HOP_DICT; empty if one class)
   std::vector<int64_t> seg_off;
   std::vector<double> seg_dE;
   std::vector<double> seg_gersh;
@@ -355,7 +355,7 @@ struct AdjIO {
   double f;              // 2 for n >= 2, 1 for n = 1
   double* gU;            // [n] accumulated
   double* gcp;           // [G][nc] accumulated per workgroup
-  const int32_t* cls;    // [entries] class of each entry (nc > 1)
+  const int32_t* cls;    // class of each entry, or (HOP_DICT) of each table entry (nc > 1)
   const double* Jtab;    // non-NULL: source coefficient J[seg*ldJ + n] * src_phase instead of wts
   int32_t ldJ;
   int32_t accumulate;    // 1: out += lam (instead of out = lam)

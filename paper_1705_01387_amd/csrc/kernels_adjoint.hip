@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
       if (NC > 0 && v) {
         const double2 vv = v[cc * B + b];
         const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vv) : cscale(he.x, vv);
-        const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
+        const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
           if (q == cls) hv[q] = cadd(hv[q], t);
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
         const double2 va = io.a_m1[cc * B + b], vb = io.b_m1[cc * B + b];
         const double2 ta = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, va) : cscale(he.x, va);
         const double2 tb = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vb) : cscale(he.x, vb);
-        const int cls = (NC > 1) ? (ok ? io.cls[e] : 0) : 0;
+        const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
           if (q == cls) {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
       const double s = e * dx_entry<HOP>(A, en);
       const double2 vt = make_double2(-s * t.y, s * t.x);      // i e dx H~ x
       const double contrib = ar.x * vt.x + ar.y * vt.y;        // Re conj(a) vt
-      const int q0 = (NC > 1) ? cls[en] : 0;
+      const int q0 = (NC > 1) ? cls[HOP == HOP_DICT ? (int64_t)A.hidx[en] : en] : 0;
 #pragma unroll
       for (int q = 0; q < NC; ++q)
         if (q == q0) gc[q] += contrib;

@@ -311,19 +311,23 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
     }
   }
 
-  // value table (one hopping class, few distinct (column offset, hopping, dx) triples)
-  // (not for one uniform hopping per segment: there the column array plus the
-  // per-segment value streams faster than the table's dependent index loads)
-  if ((mode == HOP_REAL || mode == HOP_COMPLEX) && n_class == 1 && !d->no_dictionary) {
+  // value table (at most 4 hopping classes, few distinct (column offset, hopping,
+  // dx, class) tuples); not for one uniform hopping per segment: there the column
+  // array plus the per-segment value streams faster than the table's dependent
+  // index loads
+  if ((mode == HOP_REAL || mode == HOP_COMPLEX) && n_class <= 4 && !d->no_dictionary) {
     struct Key {
       uint64_t a, b, c;
       int64_t off;
-      bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c && off == o.off; }
+      int32_t cls;
+      bool operator==(const Key& o) const {
+        return a == o.a && b == o.b && c == o.c && off == o.off && cls == o.cls;
+      }
     };
     struct KeyHash {
       size_t operator()(const Key& k) const {
         return std::hash<uint64_t>()(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x632BE59BD9B4E019ull) ^ (k.c << 1) ^
-                                     ((uint64_t)k.off * 0xC2B2AE3D27D4EB4Full));
+                                     ((uint64_t)k.off * 0xC2B2AE3D27D4EB4Full) ^ ((uint64_t)k.cls << 59));
       }
     };
     auto bits = [](double v) {
@@ -333,8 +337,8 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
     };
     std::unordered_map<Key, uint16_t, KeyHash> ids;
     std::vector<double> tab = {0.0, 0.0}, dtab = {0.0};
-    std::vector<int32_t> otab = {0};
-    ids[Key{bits(0.0), bits(0.0), bits(0.0), 0}] = 0;   // padding: offset 0, hopping 0
+    std::vector<int32_t> otab = {0}, ctab = {0};
+    ids[Key{bits(0.0), bits(0.0), bits(0.0), 0, 0}] = 0;   // padding: offset 0, hopping 0, class 0
     std::vector<uint16_t> hidx(entries, 0);
     bool fits = true;
     for (int64_t sl = 0; sl < n_slices && fits; ++sl) {
@@ -346,7 +350,8 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
           if (L->col[e] < 0) continue;
           const double re = mode == HOP_COMPLEX ? L->hop[2 * e] : L->hop[e];
           const double im = mode == HOP_COMPLEX ? L->hop[2 * e + 1] : 0.0;
-          const Key key{bits(re), bits(im), bits(L->dx[e]), (int64_t)L->col[e] - row};
+          const int32_t c = L->cls.empty() ? 0 : L->cls[e];
+          const Key key{bits(re), bits(im), bits(L->dx[e]), (int64_t)L->col[e] - row, c};
           auto it = ids.find(key);
           if (it == ids.end()) {
             if ((int64_t)dtab.size() >= kDictMax) {
@@ -358,6 +363,7 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
             tab.push_back(im);
             dtab.push_back(L->dx[e]);
             otab.push_back((int32_t)key.off);
+            ctab.push_back(c);
           }
           hidx[e] = it->second;
         }
@@ -369,6 +375,7 @@ gpuqt_status build_host_layout(const gpuqt_h_desc* d, HostLayout* L, std::string
       L->htab.swap(tab);
       L->dxtab.swap(dtab);
       L->offtab.swap(otab);
+      if (!L->cls.empty()) L->cls.swap(ctab);   // classes per table entry from now on
       std::vector<double>().swap(L->hop);
       std::vector<double>().swap(L->dx);
     }

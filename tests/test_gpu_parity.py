@@ -432,6 +432,31 @@ def test_value_table_class_update(torch_cuda):
     assert err(host(P.gpuqt_moments(H, phi, phi, 80)), a) < 1e-14
 
 
+def test_value_table_two_classes(torch_cuda):
+    """Two hopping classes (nearest and next-nearest neighbours) in the table: class updates
+    rescale the table by each entry's class, moments match per-entry storage and the oracle,
+    and the class gradients match per-entry storage."""
+    import torch
+    say("case: value table with two hopping classes")
+    m = I.square(23, 19, t1=-1.0, t2=-0.2, W=1.0, seed=102)
+    assert m.n_class == 2
+    Ht, Hp = build(m, 8.0), build(m, 8.0, no_dictionary=True)
+    assert Ht.info.hop_mode == 3 and Hp.info.hop_mode == 1
+    phi = dev(I.random_phase(m.n, 1, 103))
+    p = host(phi)
+    for H in (Ht, Hp):
+        P.gpuqt_update_h_values(H, class_scale=[1.1, 0.7])
+    hop = m.hop * np.where(m.hop_class == 0, 1.1, 0.7)
+    Hs, _, _ = ops(I.Model(m.nn, m.nbr, hop, m.onsite, m.x, m.length_x, m.volume))
+    a, b = (host(P.gpuqt_moments(H, phi, phi, 90))[0] for H in (Ht, Hp))
+    assert err(a, b) < 1e-14 and err(a, O.chebyshev_moments(Hs / 8.0, p, p, 90).T) < TOL
+    w = dev(np.random.default_rng(104).normal(size=(1, 1, 90)))
+    g = [P.gpuqt_moments_backward(H, phi, phi, w, grad_class=torch.zeros(2, dtype=torch.float64,
+                                                                        device="cuda"))
+         for H in (Ht, Hp)]
+    assert err(host(g[0][0]), host(g[1][0])) < 1e-12 and err(host(g[0][1]), host(g[1][1])) < 1e-12
+
+
 @pytest.mark.parametrize("name", list(MODELS))
 def test_per_entry_storage_modes(torch_cuda, name):
     """Layouts without the value table (one hopping per segment, real or complex per entry):
