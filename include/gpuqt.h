@@ -83,8 +83,9 @@ typedef struct {
   int32_t check_hermitian;      /* nonzero: require H_ji = conj(H_ij) (sums over duplicates) */
   int32_t slice_height;         /* sliced-ELL slice height: 0 = default (64), else 32..1024, 2^k */
   int32_t band_rows;            /* rows per band of the banded row order (see gpuqt_autotune):
-                                   0 = chosen per block width (and two bands per period for
-                                   periods of 1024 rows or more that fit in one band); else a
+                                   0 = chosen per block width (and, for B >= 2, two bands per
+                                   period for periods of 1024 rows or more that fit in one
+                                   band); else a
                                    multiple of 64, used for every width and every segment whose
                                    row period exceeds it */
   int32_t no_dictionary;        /* nonzero: keep one hopping per entry.  Otherwise, with at
@@ -322,9 +323,9 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * bit 0: non-temporal loads of the once-read streams; bit 1: the banded row
  * order (built when a segment's row period D would make the window between
  * the first and last use of a gathered element exceed about 2.5 MiB of
- * streamed data at this B, and with two bands per period for periods of 1024
- * rows or more: workgroups then sweep bands of W rows of the period one period
- * after another, so rows D apart are visited W rows apart);
+ * streamed data at this B, and for B >= 2 with two bands per period for
+ * periods of 1024 rows or more: workgroups then sweep bands of W rows of the
+ * period one period after another, so rows D apart are visited W rows apart);
  * bits 2-5: a cap on resident workgroups per compute unit (0: as many as the
  * kernel's registers allow).  Each of the four load/order variants is timed
  * uncapped and at every cap of 2..6 below its occupancy limit: fewer waves in

@@ -649,16 +649,18 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
     const int64_t W = desc->band_rows > 0 ? desc->band_rows
                                           : std::max<int64_t>(256, kBandBudget / (2 * row_bytes) / 64 * 64);
     h->band_rows[lb] = (int32_t)W;
-    // per segment: W where the period exceeds it; by default also two bands per
-    // period where the period is long (>= 1024 rows) but within W, since the
-    // plain order's 2 D window can still outgrow what stays cached while the
-    // whole chip's rows are in flight (the autotuner keeps whichever is faster)
+    // per segment: W where the period exceeds it; by default, for blocks of two
+    // or more vectors, also two bands per period where the period is long
+    // (>= 1024 rows) but within W, since the plain order's 2 D window of B-wide
+    // rows can still outgrow what stays cached while the whole chip's rows are
+    // in flight (the autotuner keeps whichever is faster; at B = 1 the window is
+    // small and the two-chain and series kernels lost with it)
     std::vector<int64_t> width(L.n_seg, 0);
     bool any = false;
     for (int sg = 0; sg < L.n_seg; ++sg) {
       const int64_t D = h->seg_period[sg];
       if (D > W) width[sg] = W;
-      else if (desc->band_rows == 0 && D >= 1024) width[sg] = D / 2 / 64 * 64;
+      else if (desc->band_rows == 0 && B >= 2 && D >= 1024) width[sg] = D / 2 / 64 * 64;
       any = any || width[sg] > 0;
     }
     if (!any) continue;

@@ -198,15 +198,15 @@ def test_variant_codes(cubic26):
 
 
 def test_default_two_bands_for_long_periods(gpu):
-    """Default band widths: a period of at least 1024 rows that fits in one band gets two
-    bands (D = 1100 here, bands of 512 rows); the moments match the oracle either way."""
+    """Default band widths: for B >= 2 a period of at least 1024 rows that fits in one band
+    gets two bands (D = 1100 here, bands of 512 rows); the moments match the oracle either way."""
     say("case: default two-band order, square 1100 x 24")
     m = I.square(1100, 24, W=2.0, seed=76)
     H = P.gpuqt_build_h_from_model(m)
-    assert H.info.row_period == 1100 and H.info.banded_mask & 1
+    assert H.info.row_period == 1100 and H.info.banded_mask == 0b11110
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     dE = float(H.energy_max[0])
-    phi = I.random_phase(m.n, 1, 77)
+    phi = I.random_phase(m.n, 2, 77)
     ref = O.chebyshev_moments(Hs / dE, phi, phi, 96).T
     for v in (0, 2, 3):
         P.gpuqt_set_variant(H, v)
