@@ -24,12 +24,12 @@ from .kpm import (chebyshev_moments, chebyshev_series, jackson, kpm_reconstruct,
 from .transport import (evolution_coefficients, evolve, commutator_evolve,
                         dos_moments, vac_moments, msd_moments, auto_terms)
 from .adjoint import moments_gradient
-from .postprocess import sigma_vac, sigma_msd
+from .postprocess import sigma_vac, sigma_msd, transport_lengths
 
 __all__ = [
     "operators", "position_differences", "gershgorin_bound",
     "chebyshev_moments", "chebyshev_series", "jackson", "kpm_reconstruct", "chebyshev_T",
     "evolution_coefficients", "evolve", "commutator_evolve",
     "dos_moments", "vac_moments", "msd_moments", "auto_terms",
-    "moments_gradient", "sigma_vac", "sigma_msd",
+    "moments_gradient", "sigma_vac", "sigma_msd", "transport_lengths",
 ]

@@ -43,3 +43,49 @@ def sigma_msd(rows, dt):
         prev = rows[k]
     t_mid = np.cumsum(dt) - 0.5 * dt
     return out, t_mid
+
+
+def transport_lengths(rho, vac0=None, sigma=None, msd=None):
+    """Transport regimes of Section 2.2 from reconstructed rows (e = hbar = 1).
+
+    rho [n_E] the DOS; vac0 [n_E] rho C_vv at t = 0 (VAC row 0); sigma [N_t, n_E] a
+    running conductivity (from sigma_vac or sigma_msd); msd [N_t, n_E] rho DeltaX^2.
+    Returns a dict with whatever the inputs allow:
+      sigma_sc = the maximum over the rows of sigma (the paper's choice of the semiclassical
+                 conductivity; NaN rows skipped),
+      v        = sqrt(C_vv(E, 0)), the group velocity (C_vv = rho C_vv / rho),
+      tau      = sigma_sc / (rho v^2)      (equation sigma_sc solved for tau),
+      mfp      = v tau                     (equation mfp),
+      L        = 2 sqrt(DeltaX^2(E, t))    (equation L, per row),
+      xi       = L(E, t_last) / (2 pi)     (equation xi, the last row standing for t -> inf).
+    Readings: NaN where rho <= 0, where C_vv(E, 0) < 0 (v), where rho v^2 <= 0 (tau, mfp)
+    and where DeltaX^2 < 0 (L, xi)."""
+    rho = np.asarray(rho, dtype=float)
+    ok = rho > 0
+    out = {}
+    if sigma is not None:
+        s = np.asarray(sigma, dtype=float)
+        sc = np.full(rho.shape, np.nan)
+        for e in range(rho.shape[0]):
+            col = s[:, e]
+            col = col[~np.isnan(col)]
+            if col.size:
+                sc[e] = col.max()
+        out["sigma_sc"] = sc
+    if vac0 is not None:
+        c0 = np.asarray(vac0, dtype=float)
+        cvv = np.where(ok, c0 / np.where(ok, rho, 1.0), np.nan)
+        v = np.where(cvv >= 0, np.sqrt(np.abs(cvv)), np.nan)
+        out["v"] = v
+        if sigma is not None:
+            good = ok & (c0 > 0)
+            tau = np.where(good, out["sigma_sc"] / np.where(good, c0, 1.0), np.nan)
+            out["tau"] = tau
+            out["mfp"] = v * tau
+    if msd is not None:
+        m = np.asarray(msd, dtype=float)
+        dx2 = np.where(ok[None, :], m / np.where(ok, rho, 1.0)[None, :], np.nan)
+        L = np.where(dx2 >= 0, 2.0 * np.sqrt(np.abs(dx2)), np.nan)
+        out["L"] = L
+        out["xi"] = L[-1] / (2.0 * np.pi)
+    return out

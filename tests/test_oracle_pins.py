@@ -436,3 +436,40 @@ def test_sigma_vac_equals_sigma_msd_on_clean_chain():
     slope = (sv[1] - sv[0]) / dts[0]
     assert rel(sv, tv[:, None] * slope[None, :]) < 1e-11
     assert rel(sm, t_mid[:, None] * slope[None, :]) < 1e-11
+
+
+def test_transport_lengths_recover_exponential_vac():
+    """Diffusive regime of Section 2.2: with C_vv(E, t) = v^2 exp(-t/tau) the running
+    conductivity rises to rho v^2 tau, so the summary returns v, tau (to the trapezoid rule's
+    error) and the mean free path v tau for each energy; rho <= 0 gives NaN."""
+    rho = np.array([0.3, 1.7, 0.05, 0.0])
+    v = np.array([1.2, 0.4, 2.5, 1.0])
+    tau = np.array([0.9, 3.0, 0.25, 1.0])
+    dt = np.full(6000, 0.005)
+    t = np.concatenate([[0.0], np.cumsum(dt)])[:len(dt)]          # VAC rows up to 30 s
+    rows = rho[None, :] * v[None, :] ** 2 * np.exp(-t[:, None] / tau[None, :])
+    out = O.transport_lengths(rho, rows[0], O.sigma_vac(rows, dt))
+    ok = slice(0, 3)
+    assert rel(out["v"][ok], v[ok]) < 1e-15
+    assert rel(out["tau"][ok], tau[ok]) < 1e-4                # dt^2 / (12 tau^2) <= 3.4e-5
+    assert rel(out["mfp"][ok], (v * tau)[ok]) < 1e-4
+    assert rel(out["sigma_sc"][ok], (rho * v ** 2 * tau)[ok]) < 1e-4
+    assert np.isnan(out["v"][3]) and np.isnan(out["tau"][3]) and np.isnan(out["mfp"][3])
+
+
+def test_transport_lengths_ballistic_msd_and_saturation():
+    """L = 2 sqrt(DeltaX^2): ballistic DeltaX^2 = v^2 t^2 gives L = 2 v t; a saturating
+    DeltaX^2 -> X_inf^2 gives xi = X_inf / pi from the last row.  The maximum of a running
+    conductivity skips NaN rows (a zero MSD time step)."""
+    rho = np.array([0.5, 2.0])
+    v = np.array([0.75, 1.5])
+    dt = np.array([0.5, 0.25, 1.0, 2.0])
+    t = np.cumsum(dt)
+    out = O.transport_lengths(rho, msd=rho[None, :] * (v[None, :] * t[:, None]) ** 2)
+    assert rel(out["L"], 2.0 * v[None, :] * t[:, None]) < 1e-15
+    assert rel(out["xi"], v * t[-1] / np.pi) < 1e-15
+    X = np.array([3.0, 0.2])
+    sat = rho[None, :] * (X[None, :] ** 2) * (1.0 - np.exp(-50.0 * t[:, None]))
+    assert rel(O.transport_lengths(rho, msd=sat)["xi"], X / np.pi) < 1e-15
+    s, _ = O.sigma_msd(np.array([[1.0], [1.0], [5.0]]), np.array([1.0, 0.0, 1.0]))
+    assert O.transport_lengths(np.ones(1), sigma=s)["sigma_sc"][0] == 2.0
