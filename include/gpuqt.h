@@ -378,6 +378,27 @@ enum { GPUQT_SIGMA_VAC = 0, GPUQT_SIGMA_MSD = 1 };
 gpuqt_status gpuqt_running_conductivity(int32_t mode, int32_t n_t, const double *dt, int32_t n_E,
                                         const double *y, double *sigma, void *stream);
 
+/* Transport regimes (Section 2.2, e = hbar = 1) per energy from reconstructed rows:
+ *   sigma_sc[e] = max over the rows k of sigma[k][e], the semiclassical conductivity taken, as
+ *                 in the paper, as the maximum of the running conductivity (NaN rows skipped);
+ *   v[e]   = sqrt(C_vv(E_e, 0)), the group velocity, C_vv(E, 0) = vac0[e] / rho[e];
+ *   tau[e] = sigma_sc / (rho v^2), the relaxation time (equation sigma_sc);
+ *   mfp[e] = v tau, the mean free path (equation mfp);
+ *   L[k][e] = 2 sqrt(DeltaX^2(E_e, t)), DeltaX^2 = msd[k][e] / rho[e] (equation L);
+ *   xi[e]  = L[n_t - 1][e] / (2 pi), the localization length, the last row standing for
+ *            t -> infinity (equation xi).
+ * rho : double [n_E] (the DOS of gpuqt_kpm_reconstruct); vac0 : [n_E] the VAC row at t = 0
+ * (rho C_vv), or NULL; sigma : [n_t][n_E] a running conductivity (gpuqt_running_conductivity),
+ * or NULL; msd : [n_t][n_E] rho DeltaX^2 rows, or NULL.  Outputs may be NULL; each one needs
+ * its inputs (sigma_sc: sigma; v: vac0; tau, mfp: sigma and vac0; L, xi: msd), must not overlap
+ * them, and is NaN where rho <= 0, C_vv(E, 0) < 0 (v), rho v^2 <= 0 (tau, mfp) or
+ * DeltaX^2 < 0 (L, xi).  All device; stream-ordered.
+ */
+gpuqt_status gpuqt_transport_lengths(int32_t n_t, int32_t n_E, const double *rho, const double *vac0,
+                                     const double *sigma, const double *msd, double *sigma_sc,
+                                     double *v, double *tau, double *mfp, double *L, double *xi,
+                                     void *stream);
+
 /* Transpose of gpuqt_kpm_reconstruct (for gradients of losses on the reconstructed
  * functions): out[r][n] = sum_e g[r][e] * d out_kpm[r][e] / d C[r][n], energies with
  * |E~| >= 1 contributing nothing.  g : double [R][n_E], energies : double [n_E],

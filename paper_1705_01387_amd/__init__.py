@@ -15,4 +15,5 @@ from ._binding import (  # noqa: F401
     gpuqt_vac_tape_size, gpuqt_vac_record, gpuqt_vac_backward_tape, gpuqt_vac_backward_tape_workspace_size,
     gpuqt_update_h_values, gpuqt_kpm_reconstruct_adjoint, gpuqt_set_timing, gpuqt_timing, K_FAMILIES, gpuqt_set_variant,
     gpuqt_schedule_rows, gpuqt_running_conductivity, SIGMA_VAC, SIGMA_MSD, gpuqt_model_load, InputFolder,
+    gpuqt_transport_lengths,
 )

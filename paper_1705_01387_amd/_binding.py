@@ -106,6 +106,7 @@ _SIGS = {
     "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_transport_lengths": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 11),
     "gpuqt_vac_tape_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_vac_record": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -439,6 +440,38 @@ def gpuqt_kpm_reconstruct(C, energies, energy_max: float, volume: float, jackson
 
 
 SIGMA_VAC, SIGMA_MSD = 0, 1
+
+
+def gpuqt_transport_lengths(rho, vac0=None, sigma=None, msd=None, stream=None) -> dict:
+    """Section 2.2 transport quantities per energy (float64 CUDA tensors): sigma_sc (max of the
+    running conductivity rows), v = sqrt(C_vv(E, 0)), tau, mean free path, L(E, t) and xi(E),
+    each returned when its inputs are given (rho [n_E]; vac0 [n_E] rho C_vv(t=0); sigma and msd
+    [n_t, n_E])."""
+    import torch
+    rho = rho.contiguous()
+    n_E = int(rho.shape[0])
+    rows = sigma if sigma is not None else msd
+    n_t = int(rows.shape[0]) if rows is not None else 0
+    vac0 = None if vac0 is None else vac0.contiguous()
+    sigma = None if sigma is None else sigma.contiguous()
+    msd = None if msd is None else msd.contiguous()
+    if sigma is not None and msd is not None and sigma.shape != msd.shape:
+        raise ValueError("sigma and msd rows must have the same shape")
+    new = lambda *shape: torch.empty(shape, dtype=torch.float64, device=rho.device)
+    out = {}
+    if sigma is not None:
+        out["sigma_sc"] = new(n_E)
+    if vac0 is not None:
+        out["v"] = new(n_E)
+        if sigma is not None:
+            out["tau"], out["mfp"] = new(n_E), new(n_E)
+    if msd is not None:
+        out["L"], out["xi"] = new(n_t, n_E), new(n_E)
+    g = lambda k: _ptr(out.get(k))
+    _check(lib().gpuqt_transport_lengths(n_t, n_E, _ptr(rho), _ptr(vac0), _ptr(sigma), _ptr(msd),
+                                         g("sigma_sc"), g("v"), g("tau"), g("mfp"), g("L"), g("xi"),
+                                         _stream(stream)), "gpuqt_transport_lengths")
+    return out
 
 
 def gpuqt_running_conductivity(mode: int, rows, dt, out=None, stream=None):

@@ -1480,6 +1480,34 @@ gpuqt_status gpuqt_running_conductivity(int32_t mode, int32_t n_t, const double*
   return GPUQT_OK;
 }
 
+gpuqt_status gpuqt_transport_lengths(int32_t n_t, int32_t n_E, const double* rho, const double* vac0,
+                                     const double* sigma, const double* msd, double* sigma_sc, double* v,
+                                     double* tau, double* mfp, double* L, double* xi, void* stream) {
+  if (n_t < 0 || n_E < 0) return fail(GPUQT_ERR_ARG, "n_t and n_E must be >= 0");
+  if (n_E == 0) return GPUQT_OK;
+  if (!rho) return fail(GPUQT_ERR_ARG, "rho is NULL");
+  if ((sigma_sc && !sigma) || (v && !vac0) || ((tau || mfp) && !(sigma && vac0)) || ((L || xi) && !msd))
+    return fail(GPUQT_ERR_ARG, "an output was asked for without the rows it is computed from");
+  if ((sigma || msd || L) && n_t == 0) return fail(GPUQT_ERR_ARG, "rows given or asked for with n_t = 0");
+  const size_t e8 = (size_t)n_E * 8, r8 = (size_t)n_t * n_E * 8;
+  const void* ins[][2] = {{rho, (const void*)e8}, {vac0, (const void*)e8}, {sigma, (const void*)r8},
+                          {msd, (const void*)r8}};
+  const void* outs[][2] = {{sigma_sc, (const void*)e8}, {v, (const void*)e8}, {tau, (const void*)e8},
+                           {mfp, (const void*)e8}, {L, (const void*)r8}, {xi, (const void*)e8}};
+  for (auto& o : outs) {
+    if (!o[0]) continue;
+    const char* a = static_cast<const char*>(o[0]);
+    for (auto& i : ins) {
+      const char* b = static_cast<const char*>(i[0]);
+      if (b && a < b + (size_t)i[1] && b < a + (size_t)o[1])
+        return fail(GPUQT_ERR_ARG, "outputs must not overlap the inputs");
+    }
+  }
+  TransportIO io{n_t, n_E, rho, vac0, sigma, msd, sigma_sc, v, tau, mfp, xi, L};
+  HIP_TRY(launch_transport(io, static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
+}
+
 gpuqt_status gpuqt_set_timing(gpuqt_h hh, int32_t enable) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");

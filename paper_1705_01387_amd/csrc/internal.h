@@ -281,6 +281,18 @@ void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
                   const std::vector<int64_t>& width, std::vector<int32_t>* out);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
+// Transport quantities of Section 2.2 from reconstructed rows (see gpuqt_transport_lengths).
+struct TransportIO {
+  int n_t, n_E;
+  const double* rho;     // [n_E]
+  const double* vac0;    // [n_E] rho C_vv at t = 0, or NULL
+  const double* sigma;   // [n_t][n_E] running conductivity, or NULL
+  const double* msd;     // [n_t][n_E] rho DeltaX^2, or NULL
+  double *sigma_sc, *v, *tau, *mfp, *xi;   // [n_E] each, or NULL
+  double* L;             // [n_t][n_E], or NULL
+};
+hipError_t launch_transport(const TransportIO& io, hipStream_t s);
+
 hipError_t launch_sigma(int mode, int n_t, const double* dt, int n_E, const double* y, double* out,
                         hipStream_t s);
 

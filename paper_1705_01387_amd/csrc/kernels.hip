@@ -427,6 +427,48 @@ __global__ __launch_bounds__(64) void k_reduce(const double2* __restrict__ part,
   }
 }
 
+// Transport regimes of Section 2.2 (e = hbar = 1), one energy per thread:
+// sigma_sc = max over the rows of the running conductivity (NaN rows skipped),
+// v = sqrt(C_vv(E, 0)), tau = sigma_sc / (rho v^2), mfp = v tau,
+// L(t) = 2 sqrt(DeltaX^2(t)), xi = L(t_last) / (2 pi); C_vv and DeltaX^2 are the
+// reconstructed rows (rho C_vv, rho DeltaX^2) divided by rho.  NaN where rho <= 0,
+// C_vv(E, 0) < 0 (v), rho v^2 <= 0 (tau, mfp) or DeltaX^2 < 0 (L, xi).
+__global__ __launch_bounds__(256) void k_transport(TransportIO io) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= io.n_E) return;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  const double r = io.rho[e];
+  const bool ok = r > 0.0;
+  double sc = nan;
+  if (io.sigma) {
+    for (int k = 0; k < io.n_t; ++k) {
+      const double x = io.sigma[(int64_t)k * io.n_E + e];
+      if (x == x && (sc != sc || x > sc)) sc = x;
+    }
+    if (io.sigma_sc) io.sigma_sc[e] = sc;
+  }
+  if (io.vac0) {
+    const double c0 = io.vac0[e];
+    const double cvv = ok ? c0 / r : nan;
+    const double v = cvv >= 0.0 ? sqrt(cvv) : nan;
+    if (io.v) io.v[e] = v;
+    if (io.sigma) {
+      const double tau = (ok && c0 > 0.0) ? sc / c0 : nan;
+      if (io.tau) io.tau[e] = tau;
+      if (io.mfp) io.mfp[e] = v * tau;
+    }
+  }
+  if (io.msd) {
+    double L = nan;
+    for (int k = 0; k < io.n_t; ++k) {
+      const double dx2 = ok ? io.msd[(int64_t)k * io.n_E + e] / r : nan;
+      L = dx2 >= 0.0 ? 2.0 * sqrt(dx2) : nan;
+      if (io.L) io.L[(int64_t)k * io.n_E + e] = L;
+    }
+    if (io.xi) io.xi[e] = io.n_t > 0 ? L / (2.0 * M_PI) : nan;
+  }
+}
+
 // Running conductivity (Section 2.2) over the time rows, one energy per thread:
 // mode 0 (VAC): trapezoid integral of rows at t_k = sum_{j<k} dt_j, sigma_0 = 0;
 // mode 1 (MSD): (y_k - y_{k-1}) / (2 dt_k), y_{-1} = 0 (NaN for dt_k = 0).
@@ -659,6 +701,12 @@ hipError_t launch_kpm_adjoint(int R, int M, const double* g, int n_E, const doub
   const double cot_pa = cos(M_PI * a) / sin(M_PI * a);
   k_kpm_adjoint<<<dim3((M + 255) / 256, R), 256, 0, s>>>(R, M, g, n_E, E, inv_dE, pref_base, jackson,
                                                          cot_pa, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transport(const TransportIO& io, hipStream_t s) {
+  if (io.n_E <= 0) return hipSuccess;
+  k_transport<<<dim3((io.n_E + 255) / 256), 256, 0, s>>>(io);
   return hipGetLastError();
 }
 

@@ -367,6 +367,54 @@ def test_running_conductivity(torch_cuda):
     assert np.all(np.isnan(gm[1])) and err(np.delete(gm, 1, 0), np.delete(om2, 1, 0)) < 1e-14
 
 
+def test_transport_lengths(torch_cuda):
+    """sigma_sc, v, tau, mean free path, L and xi (Section 2.2) on the GPU against the oracle:
+    from the square64 workload's reconstructed DOS, VAC and MSD rows, and from random rows with
+    negative and zero DOS, negative C_vv(0), negative DeltaX^2 and a NaN row (equal NaN
+    positions, values to rounding)."""
+    import torch
+    say("case: transport lengths square64")
+    w = I.workload_square64()
+    m, dE, M = w["model"], w["energy_max"], 256
+    H = build(m, dE)
+    E = np.linspace(-3.5, 3.5, 41)
+    dts = np.array([0.5, 1.0, 0.25, 2.0, 1.0])
+    d = dev(w["phi"])
+    rho = P.gpuqt_kpm_reconstruct(P.gpuqt_moments(H, d, d, M)[0, 0].real.contiguous(), E, dE, m.volume)[0]
+    rv = P.gpuqt_kpm_reconstruct(P.gpuqt_vac(H, d, dts, M)[:, 0, 0].contiguous(), E, dE, m.volume)
+    rm = P.gpuqt_kpm_reconstruct(P.gpuqt_msd(H, d, dts, M)[:, 0, 0].contiguous(), E, dE, m.volume)
+    sv = P.gpuqt_running_conductivity(P.SIGMA_VAC, rv, dts)
+    got = P.gpuqt_transport_lengths(rho, rv[0].contiguous(), sv, rm)
+    ref = O.transport_lengths(host(rho), host(rv[0]), host(sv), host(rm))
+    assert set(got) == set(ref) == {"sigma_sc", "v", "tau", "mfp", "L", "xi"}
+    for k in ref:
+        g = host(got[k])
+        assert np.array_equal(np.isnan(g), np.isnan(ref[k])), k
+        ok = ~np.isnan(ref[k])
+        assert err(g[ok], ref[k][ok]) < 1e-15, k
+    rng = np.random.default_rng(35)
+    rho2 = rng.normal(size=29)
+    rho2[3] = 0.0
+    vac0 = rng.normal(size=29)
+    sig = rng.normal(size=(4, 29))
+    sig[2] = np.nan
+    msd = rng.normal(size=(4, 29))
+    got = P.gpuqt_transport_lengths(dev(rho2), dev(vac0), dev(sig), dev(msd))
+    ref = O.transport_lengths(rho2, vac0, sig, msd)
+    for k in ref:
+        g = host(got[k])
+        assert np.array_equal(np.isnan(g), np.isnan(ref[k])), k
+        ok = ~np.isnan(ref[k])
+        assert ok.any() and err(g[ok], ref[k][ok]) < 1e-15, k
+    only = P.gpuqt_transport_lengths(dev(rho2), msd=dev(msd))
+    assert set(only) == {"L", "xi"}
+    r = dev(rho2)
+    L = torch.empty((4, 29), dtype=torch.float64, device="cuda")
+    # L asked for without the MSD rows: an argument error, nothing launched
+    assert P.lib().gpuqt_transport_lengths(4, 29, r.data_ptr(), None, None, None, None, None, None, None,
+                                           L.data_ptr(), None, None) == 1
+
+
 def _random_real_hops(m, seed, values):
     """A copy of m whose bonds carry hoppings drawn from `values` (Hermitian: each bond's two
     entries get the same value)."""
