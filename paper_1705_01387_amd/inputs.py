@@ -246,10 +246,16 @@ def concat_segments(models: List[Model]) -> Model:
         hops.append(h)
         Us.append(m.onsite if m.onsite is not None else np.zeros(m.n))
         xs.append(m.x)
+        c = np.zeros((m.n, k), dtype=np.int32)           # hopping classes (padding: class 0)
+        if m.hop_class is not None:
+            c[:, :m.max_nn] = m.hop_class
+        cls.append(c)
         off += m.n
+    n_class = max(m.n_class for m in models)
     return Model(np.concatenate(nns), np.concatenate(nbrs), np.concatenate(hops),
                  np.concatenate(Us), np.concatenate(xs), -1.0,
-                 float(sum(m.volume for m in models)), name="segments")
+                 float(sum(m.volume for m in models)),
+                 hop_class=np.concatenate(cls) if n_class > 1 else None, n_class=n_class, name="segments")
 
 
 def dense_hop(m: Model) -> np.ndarray:

@@ -173,3 +173,28 @@ def test_backward_segments(gpu):
         assert err(gU[offs[s]:offs[s + 1]], rU) < TOL
         tot += rC[0]
     assert abs(host(gC)[0] - tot) < TOL * abs(tot)
+
+
+def test_vac_tape_with_segments_and_block(gpu):
+    """The recorded forward and the backward from its tape on a handle of two segments
+    (different DeltaE) with a block of four vectors: bit for bit the same rows and gradients
+    as gpuqt_vac and gpuqt_vac_backward with every vector kept."""
+    import torch
+    say("case: VAC tape with segments, B=4")
+    mods = [I.square(10, 9, t1=-1.0, t2=-0.2, W=1.0, seed=62), I.square(13, 7, t1=-1.0, t2=-0.2, W=2.0, seed=63)]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        hop_class=cat.hop_class, n_class=2, seg_offsets=offs,
+                        seg_length_x=[mm.length_x for mm in mods])
+    phi = dev(I.random_phase(cat.n, 4, 64))
+    dts = [0.5, 0.9, 0.3]
+    M = 33
+    rows = host(P.gpuqt_vac(H, phi, dts, M))
+    rec, tape = P.gpuqt_vac_record(H, phi, dts, M)
+    assert np.array_equal(host(rec), rows)
+    w = dev(np.random.default_rng(65).normal(size=(len(dts), 2, 4, M)))
+    zc = lambda: torch.zeros(2, dtype=torch.float64, device="cuda")
+    gU, gC = P.gpuqt_vac_backward(H, phi, dts, w, ckpt_stride=1, grad_class=zc())
+    tU, tC = P.gpuqt_vac_backward_tape(H, phi, dts, w, tape, grad_class=zc())
+    assert np.array_equal(host(tU), host(gU)) and np.array_equal(host(tC), host(gC))

@@ -143,3 +143,29 @@ def test_update_h_values_roundtrip_and_spectrum_guard(gpu):
     with pytest.raises(P.GpuqtError) as e:
         P.gpuqt_update_h_values(H, None, [1.5, 1.0])        # 4*1.5 + 4*0.1 + 1 > 6
     assert e.value.status == 3
+
+
+def test_vac_autograd_recorded_and_recomputing_paths_agree(gpu, monkeypatch):
+    """The autograd VAC records its forward when the tape fits (the backward then recomputes
+    nothing) and otherwise re-evolves from checkpoints; both give the same gradients."""
+    import paper_1705_01387_amd._binding as Bd
+    say("case: VAC autograd recorded vs recomputing")
+    pb = Problem(20, M=96, n_E=201)
+    calls = []
+    rec = Bd.gpuqt_vac_record
+
+    def spy(*a, **k):
+        calls.append(1)
+        return rec(*a, **k)
+
+    monkeypatch.setattr(Bd, "gpuqt_vac_record", spy)
+    grads = []
+    for frac in (Bd.KEEP_ALL_FRACTION, 0.0):
+        monkeypatch.setattr(Bd, "KEEP_ALL_FRACTION", frac)
+        U = pb.U0.clone().requires_grad_(True)
+        s = pb.s0.clone().requires_grad_(True)
+        pb.loss(U, s).backward()
+        grads.append((U.grad.cpu().numpy(), s.grad.cpu().numpy()))
+    assert len(calls) == 1                      # only the first pass recorded
+    for a, b in zip(grads[0], grads[1]):
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
