@@ -245,7 +245,9 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
  * (Section 3.3 moments by the product identities T_2k = 2 T_k T_k - T_0,
  * T_2k-1 = 2 T_k T_k-1 - T_1): chains a_k = T_k phiL, b_k = T_k phiR over
  * K = max(1, M/2) steps, both adjoint chains in one launch per step, about
- * 2K vectors of workspace and no recomputation;
+ * 2K vectors of workspace and no recomputation; when phiL and phiR are the same
+ * pointer the two chains coincide and only their adjoints' sum enters, so one
+ * chain and one adjoint chain are run;
  * dL/dp = Re[ sum_{k>=2} 2 <lam_k| dH~/dp v_{k-1}> + <lam_1| dH~/dp v_0> ].
  *   phiL, phiR : c128 [n][B];  w : double [n_segments][B][M];  grad_onsite : double [n];
  *   grad_class : double [n_class] or NULL (at most 4 classes);  lam0 : c128 [n][B] or NULL.

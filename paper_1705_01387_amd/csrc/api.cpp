@@ -12,6 +12,13 @@
 
 using namespace gpuqt;
 
+namespace gpuqt {
+// Reverse step of a Hermitian moment set (kernels_adjoint.hip): the two-chain
+// step with both chains equal, one chain gathered; the b fields of io unused.
+hipError_t launch_adjoint_sym_step(const DevMat& A, int hop_mode, int B, int nc, const AdjPairIO& io,
+                                   hipStream_t s);
+}  // namespace gpuqt
+
 namespace {
 
 thread_local std::string g_err;
@@ -523,6 +530,52 @@ gpuqt_status run_backward_pair(const Handle* h, int B, const double2* pL, const 
     io.gcp = gcp;
     io.cls = h->d_cls;
     HIP_TRY(launch_adjoint_pair_step(D, h->hop_mode, B, gU ? nc : 0, io, sm));
+  }
+  return GPUQT_OK;
+}
+
+// Reverse of a Hermitian moment set (phiL = phiR = phi) in the product-identity
+// form: the chain a_k = T_k phi (k = 1..K) into vec[0..K-1], then the reverse
+// of cbar_k = abar_k + bbar_k in three rotating vectors vec[K..K+2]; lam0 (if
+// set) receives sum_n w_n T_n phi.  Half the vectors and half the gathers of
+// run_backward_pair with both arguments equal.
+gpuqt_status run_backward_sym(const Handle* h, int B, const double2* ph, int M, const double* wts, double* gU,
+                              double* gcp, int nc, double2* lam0, bool acc0, double2* const* vec, double* om,
+                              double2* scratch, hipStream_t sm) {
+  const int K = pair_steps(M);
+  const int R = 2 * K + 2;
+  HIP_TRY(launch_raw_weights(wts, h->n_seg * B, M, R, om, sm));
+  auto fa = [&](int k) -> const double2* { return k == 0 ? ph : vec[k - 1]; };
+  {
+    TimeScope ts(h, sm, FAM_SYM, K);
+    const DevMat F = h->view(B, FAM_SYM);
+    const int64_t row = (int64_t)F.G * B;
+    for (int k = 1; k <= K; ++k) {
+      StepIO io{fa(k - 1), k >= 2 ? fa(k - 2) : nullptr, vec[k - 1], k == 1 ? 1 : 0};
+      HIP_TRY(launch_moment_step_sym(F, h->hop_mode, B, io, scratch, scratch + row, scratch + 2 * row, sm));
+    }
+  }
+  double2* const* Lc = vec + K;   // rotating cbar
+  const DevMat D = h->view(B);     // class partials over the primary plan
+  for (int k = K; k >= 0; --k) {
+    if (k == 0 && !lam0) break;
+    AdjPairIO io{};
+    io.xa = k + 1 <= K ? Lc[(k + 1) % 3] : nullptr;
+    io.wa = k + 2 <= K ? Lc[(k + 2) % 3] : nullptr;
+    io.oa = (k == 0) ? lam0 : Lc[k % 3];
+    io.acc_a = (k == 0 && acc0) ? 1 : 0;
+    io.a_m1 = k >= 1 ? fa(k - 1) : nullptr;
+    io.a_k = fa(k);
+    io.a_p1 = k + 1 <= K ? fa(k + 1) : nullptr;
+    io.om = om;
+    io.R = R;
+    io.k = k;
+    io.f_rec = k >= 1 ? 2.0 : 1.0;
+    io.f = k >= 2 ? 2.0 : 1.0;
+    io.gU = gU;
+    io.gcp = gcp;
+    io.cls = h->d_cls;
+    HIP_TRY(launch_adjoint_sym_step(D, h->hop_mode, B, gU ? nc : 0, io, sm));
   }
   return GPUQT_OK;
 }
@@ -1106,7 +1159,13 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   double* gcp = reinterpret_cast<double*>(base + W.off_part);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
-  if (s == 1) {   // every forward vector kept: reverse of the two-chain form
+  if (s == 1 && phiL == phiR) {   // Hermitian set, every vector kept: one-chain reverse
+    if ((st = run_backward_sym(h, B, reinterpret_cast<const double2*>(phiL), M, w, grad_onsite, gcp, nc,
+                               reinterpret_cast<double2*>(lam0), false, vec.data(),
+                               reinterpret_cast<double*>(base + W.off_J),
+                               reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm)))
+      return st;
+  } else if (s == 1) {   // every forward vector kept: reverse of the two-chain form
     if ((st = run_backward_pair(h, B, reinterpret_cast<const double2*>(phiL),
                                 reinterpret_cast<const double2*>(phiR), M, w, grad_onsite, gcp, nc,
                                 nullptr, false, reinterpret_cast<double2*>(lam0), false, vec.data(),

@@ -213,6 +213,102 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
   }
 }
 
+// Reverse step of the Hermitian form (phiL = phiR, one chain a_k = T_k phi):
+// with both chains equal the two adjoints only enter through their sum
+// cbar_k = abar_k + bbar_k,
+//   cbar_k = 2 om_2k a_k + om_2k-1 a_{k-1} + om_2k+1 a_{k+1} + f_rec H~ cbar_{k+1} - cbar_{k+2},
+// and the parameter terms are Re sum_k f_k <cbar_k| dH~/dp a_{k-1}>: one chain
+// gathered instead of two.  At k = 0 the output is cbar_0 / 2 = sum_n w_n T_n phi
+// (abar_0 = bbar_0).  Fields of io: xa, wa, oa, acc_a, a_m1, a_k, a_p1 and the
+// weights; the b fields are unused.
+template <int B, int HOP, int K, int NC>
+__global__ __launch_bounds__(kBlock) void k_adjoint_sym_step(DevMat A, AdjPairIO io) {
+  const int lb = logical_block(A.G);
+  const BlkPlan P = A.plan[lb];
+  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
+  const double inv_dE = 1.0 / A.seg_dE[P.seg];
+  const int b = threadIdx.x & (B - 1);
+  const double* om = io.om + ((int64_t)P.seg * B + b) * io.R;
+  const int k2 = 2 * io.k;
+  const double w0 = 2.0 * om[k2];
+  const double wm = io.k >= 1 ? om[k2 - 1] : 0.0;
+  const double wp = (io.a_p1 && k2 + 1 < io.R) ? om[k2 + 1] : 0.0;
+  const double out_scale = io.k == 0 ? 0.5 : 1.0;
+  const bool grad = io.gU != nullptr && io.k >= 1;
+  const int S = 1 << A.S_log2;
+  double gc[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int c = 0; c < (NC > 0 ? NC : 1); ++c) gc[c] = 0.0;
+  for_rows<B>(A, P, [&](int64_t r) {
+    const int64_t idx = r * B + b;
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = K > 0 ? K : (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    double2 h = make_double2(0.0, 0.0);
+    double2 hv[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int c = 0; c < (NC > 0 ? NC : 1); ++c) hv[c] = make_double2(0.0, 0.0);
+    if (io.xa) h = cscale(A.diag[r], io.xa[idx]);
+    for (int j = 0; j < w; ++j) {
+      const int64_t e = e0 + (int64_t)j * S;
+      int64_t cc;
+      const bool ok = col_entry<HOP>(A, r, e, &cc);
+      const double2 he = hop_entry<HOP>(A, e, ok, hu);
+      if (io.xa) {
+        const double2 x = io.xa[cc * B + b];
+        h = cadd(h, (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, x) : cscale(he.x, x));
+      }
+      if (NC > 0 && grad) {
+        const double2 v = io.a_m1[cc * B + b];
+        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, v) : cscale(he.x, v);
+        const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
+#pragma unroll
+        for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+          if (q == cls) hv[q] = cadd(hv[q], t);
+      }
+    }
+    // direct sensitivities of the raw dots
+    double2 g = cscale(w0, io.a_k[idx]);
+    if (io.k >= 1) g = cadd(g, cscale(wm, io.a_m1[idx]));
+    if (io.a_p1) g = cadd(g, cscale(wp, io.a_p1[idx]));
+    double2 c = make_double2(fma(io.f_rec, h.x, g.x), fma(io.f_rec, h.y, g.y));
+    if (io.wa) {
+      const double2 u = io.wa[idx];
+      c = make_double2(c.x - u.x, c.y - u.y);
+    }
+    const double2 o = cscale(out_scale, c);
+    io.oa[idx] = io.acc_a ? cadd(io.oa[idx], o) : o;
+    if (grad) {
+      const double2 v = io.a_m1[idx];
+      double gu = io.f * (c.x * v.x + c.y * v.y);
+#pragma unroll
+      for (int off = 1; off < B; off <<= 1) gu += __shfl_xor(gu, off);
+      if (b == 0) io.gU[r] += gu * inv_dE;
+#pragma unroll
+      for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
+        if (NC > 0) gc[q] += io.f * (c.x * hv[q].x + c.y * hv[q].y);
+    }
+  });
+  if (NC == 0 || !grad) return;
+  __shared__ double sh[kBlock / 64][NC > 0 ? NC : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < (NC > 0 ? NC : 1); ++q) {
+    double s = gc[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) sh[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < (NC > 0 ? NC : 1)) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) s += sh[wv][threadIdx.x];
+    io.gcp[(int64_t)lb * NC + threadIdx.x] += s;
+  }
+}
+
 // Raw-dot weights of the product identities, one wavefront per (segment,
 // column) row: lane l sums w_n for n = 2 + l + 64 j (all of one parity, the
 // parity of l), a butterfly over lanes of equal parity gives the even and odd
@@ -408,6 +504,29 @@ hipError_t launch_adjoint_pair_step(const DevMat& A, int hop_mode, int B, int nc
         case 1: k_adjoint_pair_step<Bv, Hv, Kv, 1><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
         case 2: k_adjoint_pair_step<Bv, Hv, Kv, 2><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
         default: k_adjoint_pair_step<Bv, Hv, Kv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+      }
+    };
+    switch (A.K) {
+      case 3: go(IC<3>{}); break;
+      case 4: go(IC<4>{}); break;
+      case 6: go(IC<6>{}); break;
+      case 8: go(IC<8>{}); break;
+      default: go(IC<0>{}); break;
+    }
+  });
+}
+
+hipError_t launch_adjoint_sym_step(const DevMat& A, int hop_mode, int B, int nc, const AdjPairIO& io,
+                                   hipStream_t s) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    constexpr int Bv = decltype(Bc)::value, Hv = decltype(Hc)::value;
+    auto go = [&](auto Kc) {
+      constexpr int Kv = decltype(Kc)::value;
+      switch (nc) {
+        case 0: k_adjoint_sym_step<Bv, Hv, Kv, 0><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 1: k_adjoint_sym_step<Bv, Hv, Kv, 1><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        case 2: k_adjoint_sym_step<Bv, Hv, Kv, 2><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
+        default: k_adjoint_sym_step<Bv, Hv, Kv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, io); break;
       }
     };
     switch (A.K) {

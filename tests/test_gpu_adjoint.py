@@ -63,6 +63,32 @@ def test_moments_backward(gpu, name, B, M, stride):
     assert err(host(lam0), ref_l0) < TOL
 
 
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B,M,stride", [(1, 64, 1), (2, 97, 1), (1, 2, 1), (1, 3, 1), (4, 50, 1), (2, 97, 0)])
+def test_moments_backward_hermitian(gpu, name, B, M, stride):
+    """phiL = phiR (the same tensor): with every vector kept the one-chain reverse of the
+    product-identity form; against the oracle's reverse recurrence."""
+    import torch
+    say(f"case: Hermitian backward {name} B={B} M={M} stride={stride}")
+    mk, n_class = CASES[name]
+    m = mk()
+    H = P.gpuqt_build_h_from_model(m)
+    dE = float(H.energy_max[0])
+    Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    parts = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
+    phi = I.random_phase(m.n, B, 48)
+    d = dev(phi)
+    w = np.random.default_rng(49).normal(size=(1, B, M))
+    gU = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    gC = torch.zeros(n_class, dtype=torch.float64, device="cuda")
+    gU, gC, lam0 = P.gpuqt_moments_backward(H, d, d, dev(w), gU, gC, want_lam0=True, ckpt_stride=stride)
+    rU, rC = O.moments_gradient(Hs, phi, phi, dE, w[0].T, parts)
+    assert err(host(gU), rU) < TOL
+    assert err(host(gC), rC) < TOL
+    ref_l0 = np.stack([O.chebyshev_series(Hs / dE, w[0, b], phi[:, b]) for b in range(B)], axis=1)
+    assert err(host(lam0), ref_l0) < TOL
+
+
 def test_backward_accumulates_and_is_deterministic(gpu):
     import torch
     say("case: backward accumulation / determinism")
