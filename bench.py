@@ -399,7 +399,7 @@ def train_workload(args):
     gC = torch.zeros(2, dtype=torch.float64, device=dev)
     np_list = [P.gpuqt_auto_terms(dE * abs(t)) for t in dts]
     # the VAC forward keeps its states and moment chains (the tape) for the backward
-    tape = torch.empty(P.gpuqt_vac_tape_size(H, 1, len(dts), M), dtype=torch.uint8, device=dev)
+    tape = torch.empty(P.gpuqt_vac_tape_size(H, 1, dts, M), dtype=torch.uint8, device=dev)
 
     def fwd():
         P.gpuqt_moments(H, phi, phi, M)
@@ -427,8 +427,8 @@ def train_workload(args):
                 config={"workload": "square 512^2 (262,144 orbitals), NN + NNN hopping classes, DeltaE=6, "
                                     "DOS M=512 + VAC 10 x dt=1; forward + adjoint (all on-site and class "
                                     "gradients; every forward vector kept, moment sets reversed in "
-                                    "the two-chain form, the VAC forward's states and chains recorded "
-                                    "for the adjoint)", "orbitals": int(m.n), "moments": M},
+                                    "the two-chain form, the VAC forward's states, moment and "
+                                    "evolution chains recorded for the adjoint)", "orbitals": int(m.n), "moments": M},
                 adjoint_vs_forward={"forward_ms": tf * 1e3, "adjoint_ms": tb * 1e3, "ratio": tb / tf},
                 roofline=None, cpu_baseline=None)
 

@@ -296,17 +296,20 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t
  * gpuqt_vac_record computes the same rows as gpuqt_vac (same arguments,
  * workspace and results, bit for bit) and also writes into `tape` (device,
  * caller-owned, at least gpuqt_vac_tape_size bytes, 16-byte aligned) the states
- * psi_L(t_k), psi_R(t_k) and, per row, both moment chains T_j V psi_L(t_k) and
- * T_j psi_R(t_k) of the product-identity form (j = 1 .. max(1, M/2)):
- * (2 n_t - 1 + n_t * 2 * max(1, M/2)) vectors of n x B complex128.
+ * psi_L(t_k), psi_R(t_k), per row both moment chains T_j V psi_L(t_k) and
+ * T_j psi_R(t_k) of the product-identity form (j = 1 .. max(1, M/2)), and per
+ * time step both evolution chains T_m psi_L(t_k), T_m psi_R(t_k) (m = 1 .. P-1,
+ * P the largest number of terms over the steps): (2 n_t - 1 + n_t * 2 *
+ * max(1, M/2) + (n_t - 1) * 2 (P - 1)) vectors of n x B complex128.
  * gpuqt_vac_backward_tape then gives the gradients of gpuqt_vac_backward
- * (same arguments and results, bit for bit) from that tape, skipping the
- * re-evolution of the states and the forward pass of every row's moments; the
- * tape must come from gpuqt_vac_record with the same handle values, B, phi,
- * dt, M and Np.  Workspace: gpuqt_vac_backward_tape_workspace_size.
+ * (same arguments, results to rounding) from that tape, skipping the
+ * re-evolution of the states and every forward chain; the tape must come from
+ * gpuqt_vac_record with the same handle values, B, phi, dt, M and Np.
+ * Workspace: gpuqt_vac_backward_tape_workspace_size.
  * GPUQT_ERR_WORKSPACE for a tape or workspace that is too small.
  */
-gpuqt_status gpuqt_vac_tape_size(gpuqt_h h, int32_t B, int32_t n_t, int32_t M, size_t *bytes);
+gpuqt_status gpuqt_vac_tape_size(gpuqt_h h, int32_t B, int32_t n_t, const double *dt, int32_t M,
+                                 int32_t Np, size_t *bytes);
 gpuqt_status gpuqt_vac_record(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, const double *dt,
                               int32_t M, int32_t Np, double *out, void *ws, size_t ws_bytes,
                               void *tape, size_t tape_bytes, void *stream);

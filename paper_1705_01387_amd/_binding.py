@@ -107,8 +107,8 @@ _SIGS = {
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_transport_lengths": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 11),
-    "gpuqt_vac_tape_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "gpuqt_vac_tape_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_vac_record": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
@@ -533,9 +533,11 @@ def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: in
     return int(out.value)
 
 
-def gpuqt_vac_tape_size(H: Hamiltonian, B: int, n_t: int, M: int) -> int:
+def gpuqt_vac_tape_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0) -> int:
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
     out = ctypes.c_size_t()
-    _check(lib().gpuqt_vac_tape_size(H.handle, B, int(n_t), int(M), ctypes.byref(out)), "gpuqt_vac_tape_size")
+    _check(lib().gpuqt_vac_tape_size(H.handle, B, dt.shape[0], _ptr(dt), int(M), int(Np), ctypes.byref(out)),
+           "gpuqt_vac_tape_size")
     return int(out.value)
 
 
@@ -548,7 +550,7 @@ def gpuqt_vac_record(H: Hamiltonian, phi, dt: Sequence[float], M: int, Np: int =
     B = _cols(phi)
     dtn = np.ascontiguousarray(dt, dtype=np.float64)
     if tape is None:
-        tape = torch.empty(max(gpuqt_vac_tape_size(H, B, dtn.shape[0], M), 16), dtype=torch.uint8,
+        tape = torch.empty(max(gpuqt_vac_tape_size(H, B, dtn, M, Np), 16), dtype=torch.uint8,
                            device=phi.device)
     tb = int(tape.numel() * tape.element_size())
     fn = lambda h, b, p, n, d, m, npp, o, w_, nb, st: lib().gpuqt_vac_record(h, b, p, n, d, m, npp, o, w_, nb,

@@ -46,8 +46,8 @@ class Moments(torch.autograd.Function):
 class VAC(torch.autograd.Function):
     """C_n^VAC(t_k) rows, shape [n_t, n_seg, B, M].
 
-    When a gradient is needed and the recorded forward (states and moment chains,
-    gpuqt_vac_tape_size) fits in Bd.KEEP_ALL_FRACTION of the free device memory, the
+    When a gradient is needed and the recorded forward (states, moment and evolution
+    chains, gpuqt_vac_tape_size) fits in Bd.KEEP_ALL_FRACTION of the free device memory, the
     forward keeps it and the backward recomputes nothing; otherwise the backward
     re-evolves and recomputes as gpuqt_vac_backward does."""
 
@@ -57,7 +57,7 @@ class VAC(torch.autograd.Function):
         dtn = np.asarray(dt, dtype=np.float64)
         ctx.tape = None
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            need = Bd.gpuqt_vac_tape_size(H, Bd._cols(phi), dtn.shape[0], M)
+            need = Bd.gpuqt_vac_tape_size(H, Bd._cols(phi), dtn, M, Np)
             free, _ = torch.cuda.mem_get_info(phi.device)
             if need <= Bd.KEEP_ALL_FRACTION * free:
                 out, ctx.tape = Bd.gpuqt_vac_record(H, phi, dtn, M, Np)

@@ -331,7 +331,8 @@ gpuqt_status run_evolve(const Handle* h, int B, double dt, int Np, const double2
 // (scratch aA, aB, bA, bB; outputs must not alias the inputs).
 gpuqt_status run_evolve_pair(const Handle* h, int B, double dt, int Np, const double2* a_in, double2* a_out,
                              const double2* b_in, double2* b_out, double2* aA, double2* aB, double2* bA,
-                             double2* bB, double* Jtab, hipStream_t s) {
+                             double2* bB, double* Jtab, hipStream_t s, double2* const* keep = nullptr) {
+  // keep: every chain vector to its own buffer, a_m to keep[m-1], b_m to keep[Np-1+m-1]
   const double sgn = dt >= 0 ? 1.0 : -1.0;
   HIP_TRY(launch_bessel_table(h->d_seg_dE, h->n_seg, std::fabs(dt), Np, Np, Jtab, s));
   if (Np == 1) {
@@ -343,13 +344,17 @@ gpuqt_status run_evolve_pair(const Handle* h, int B, double dt, int Np, const do
   const double2 ph0 = phase_pow(0, sgn);
   TimeScope ts(h, s, FAM_EVOLVE_PAIR, Np - 1);
   const DevMat E = h->view(B, FAM_EVOLVE_PAIR);
+  if (keep) {
+    aA = keep[0];
+    bA = keep[Np - 1];
+  }
   ChainIO io{a_in, nullptr, aA, b_in, nullptr, bA, 1, 1};
   HIP_TRY(launch_evolve_pair_term(E, h->hop_mode, B, io, a_out, b_out, Jtab, Np, 1, phase_pow(1, sgn), ph0, s));
   const double2 *pa = a_in, *pb = b_in;
   double2 *ca = aA, *cb = bA;
   for (int m = 2; m < Np; ++m) {
-    double2* oa = (pa == a_in) ? aB : const_cast<double2*>(pa);
-    double2* ob = (pb == b_in) ? bB : const_cast<double2*>(pb);
+    double2* oa = keep ? keep[m - 1] : (pa == a_in) ? aB : const_cast<double2*>(pa);
+    double2* ob = keep ? keep[Np - 1 + m - 1] : (pb == b_in) ? bB : const_cast<double2*>(pb);
     ChainIO st{ca, pa, oa, cb, pb, ob, 0, 1};
     HIP_TRY(launch_evolve_pair_term(E, h->hop_mode, B, st, a_out, b_out, Jtab, Np, m, phase_pow(m, sgn), ph0, s));
     pa = ca;
@@ -377,7 +382,9 @@ struct BwdSource {
 // backward_vectors(M, s) workspace vectors.
 gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                           const BwdSource& src, double* gU, double* gcp, int nc, double2* lam0,
-                          bool acc0, int s, double2* const* vec, hipStream_t sm) {
+                          bool acc0, int s, double2* const* vec, hipStream_t sm,
+                          double2* const* recorded = nullptr) {
+  // recorded (s = 1 with parameter terms): v_1 .. v_{M-2} = T_n pR already computed
   const DevMat D = h->view(B);                  // adjoint steps: primary plan (class partials)
   const DevMat F = h->view(B, FAM_MOMENT);      // forward recomputation: no partials
   const bool grad = gU != nullptr;
@@ -409,18 +416,22 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
     return a;
   };
   if (grad && s == 1) {
-    // forward: v_1 .. v_{M-2}, every one kept (v_n in sb(n)); then the reverse
-    const double2* prev2 = nullptr;
-    const double2* prev1 = pR;
-    for (int n = 1; n <= M - 2; ++n) {
-      StepIO io{prev1, prev2, sb(n), n == 1 ? 1 : 0};
-      HIP_TRY(launch_moment_step(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
-      prev2 = prev1;
-      prev1 = sb(n);
+    // forward: v_1 .. v_{M-2}, every one kept (v_n in sb(n), unless recorded);
+    // then the reverse
+    auto fwd = [&](int n) -> const double2* { return n == 0 ? pR : recorded ? recorded[n - 1] : sb(n); };
+    if (!recorded) {
+      const double2* prev2 = nullptr;
+      const double2* prev1 = pR;
+      for (int n = 1; n <= M - 2; ++n) {
+        StepIO io{prev1, prev2, sb(n), n == 1 ? 1 : 0};
+        HIP_TRY(launch_moment_step(F, h->hop_mode, B, io, nullptr, nullptr, nullptr, sm));
+        prev2 = prev1;
+        prev1 = sb(n);
+      }
     }
     for (int n = M - 1; n >= 1; --n) {
       AdjIO a = make(n);
-      a.v = n == 1 ? pR : sb(n - 1);
+      a.v = fwd(n - 1);
       HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, nc, a, sm));
     }
   } else if (grad) {
@@ -981,17 +992,21 @@ static int max_terms(const Handle* h, int32_t n_t, const double* dt, int32_t Np)
 
 // Recorded VAC forward ("tape"), for a backward pass that recomputes nothing:
 // vector slots of n x B complex128 (256-byte aligned) holding psi_L(k) for
-// k = 1 .. n_t-1 (slot k-1), psi_R(k) for k = 0 .. n_t-1 (slot n_t-1+k), and
+// k = 1 .. n_t-1 (slot k-1), psi_R(k) for k = 0 .. n_t-1 (slot n_t-1+k),
 // for each row k from slot 2 n_t - 1 + 2 K k the two moment chains a_1..a_K,
-// b_1..b_K of <V psi_L(k)| T_n |psi_R(k)> (K = max(1, M/2)).
-static int64_t vac_tape_vectors(int n_t, int M) {
-  return n_t > 0 ? 2 * (int64_t)n_t - 1 + 2 * (int64_t)pair_steps(M) * n_t : 0;
+// b_1..b_K of <V psi_L(k)| T_n |psi_R(k)> (K = max(1, M/2)), and for each
+// time step k < n_t - 1 the two evolution chains T_m psi_L(k), T_m psi_R(k),
+// m = 1 .. P-1, in 2 (P - 1) slots, P the largest number of terms of the steps.
+static int64_t vac_tape_vectors(int n_t, int M, int P) {
+  return n_t > 0 ? 2 * (int64_t)n_t - 1 + 2 * (int64_t)pair_steps(M) * n_t +
+                       2 * (int64_t)std::max(P - 1, 0) * (n_t - 1)
+                 : 0;
 }
 
 struct VacTape {
   char* base = nullptr;
   size_t vec_bytes = 0;
-  int n_t = 0, K = 0;
+  int n_t = 0, K = 0, P = 1;
   double2* slot(int64_t i) const { return reinterpret_cast<double2*>(base + vec_bytes * (size_t)i); }
   double2* psiL(int k) const { return slot(k - 1); }
   double2* psiR(int k) const { return slot(n_t - 1 + k); }
@@ -1001,15 +1016,26 @@ struct VacTape {
     for (int j = 0; j < 2 * K; ++j) c[j] = slot(2 * (int64_t)n_t - 1 + 2 * (int64_t)K * k + j);
     return c;
   }
+  // time step k with np terms: T_m psi_L(k) at [m-1], T_m psi_R(k) at [np-1+m-1]
+  std::vector<double2*> evolution(int k, int np) const {
+    const int64_t base_k = 2 * (int64_t)n_t - 1 + 2 * (int64_t)K * n_t + 2 * (int64_t)(P - 1) * k;
+    std::vector<double2*> c(2 * (size_t)std::max(np - 1, 0));
+    for (int j = 0; j < np - 1; ++j) {
+      c[j] = slot(base_k + j);
+      c[np - 1 + j] = slot(base_k + (P - 1) + j);
+    }
+    return c;
+  }
 };
 
-static gpuqt_status vac_tape_check(const Handle* h, int B, int n_t, int M, void* tape, size_t tape_bytes,
-                            VacTape* T) {
+static gpuqt_status vac_tape_check(const Handle* h, int B, int n_t, int M, int P, void* tape,
+                                   size_t tape_bytes, VacTape* T) {
   T->vec_bytes = round_up((size_t)h->n * (size_t)B * 16u, 256);
   T->n_t = n_t;
   T->K = pair_steps(M);
+  T->P = P;
   T->base = static_cast<char*>(tape);
-  if (!tape || tape_bytes < T->vec_bytes * (size_t)vac_tape_vectors(n_t, M))
+  if (!tape || tape_bytes < T->vec_bytes * (size_t)vac_tape_vectors(n_t, M, P))
     return fail(GPUQT_ERR_WORKSPACE, "tape too small");
   if (!aligned16(tape)) return fail(GPUQT_ERR_ARG, "tape is not 16-byte aligned");
   return GPUQT_OK;
@@ -1021,9 +1047,9 @@ static gpuqt_status vac_impl(const Handle* h, int32_t B, const double* phi, int3
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, out);
   if (st) return st;
   if (n_t == 0 || M == 0) return GPUQT_OK;
-  VacTape T;
-  if (tape && (st = vac_tape_check(h, B, n_t, M, tape, tape_bytes, &T))) return st;
   const int np = max_terms(h, n_t - 1, dt, Np);
+  VacTape T;
+  if (tape && (st = vac_tape_check(h, B, n_t, M, np, tape, tape_bytes, &T))) return st;
   const WsLayout W = ws_layout(h, op_vectors(GPUQT_OP_VAC), B, moment_rows(M), np);
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
@@ -1060,7 +1086,9 @@ static gpuqt_status vac_impl(const Handle* h, int32_t B, const double* phi, int3
       double2* Ln = tape ? T.psiL(k + 1) : (psiL == Lbuf[0]) ? Lbuf[1] : Lbuf[0];
       double2* Rn = tape ? T.psiR(k + 1) : Rbuf[ri ^ 1];
       // both states advance with the same U(-dt): one two-chain series
-      if ((st = run_evolve_pair(h, B, -dt[k], np_k, psiL, Ln, psiR, Rn, V(5), V(6), V(7), V(8), J, s)))
+      const std::vector<double2*> ev = tape ? T.evolution(k, np_k) : std::vector<double2*>();
+      if ((st = run_evolve_pair(h, B, -dt[k], np_k, psiL, Ln, psiR, Rn, V(5), V(6), V(7), V(8), J, s,
+                                tape ? ev.data() : nullptr)))
         return st;
       psiL = Ln;
       psiR = Rn;
@@ -1076,12 +1104,15 @@ gpuqt_status gpuqt_vac(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
                   stream);
 }
 
-gpuqt_status gpuqt_vac_tape_size(gpuqt_h hh, int32_t B, int32_t n_t, int32_t M, size_t* bytes) {
+gpuqt_status gpuqt_vac_tape_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt, int32_t M, int32_t Np,
+                                 size_t* bytes) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
   if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
   if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
-  if (n_t < 0 || M < 0) return fail(GPUQT_ERR_ARG, "n_t and M must be >= 0");
-  *bytes = round_up((size_t)h->n * (size_t)B * 16u, 256) * (size_t)vac_tape_vectors(n_t, M);
+  if (n_t < 0 || M < 0 || Np < 0) return fail(GPUQT_ERR_ARG, "n_t, M and Np must be >= 0");
+  if (n_t > 1 && !dt) return fail(GPUQT_ERR_ARG, "dt is NULL");
+  const int np = n_t > 1 ? max_terms(h, n_t - 1, dt, Np) : 1;
+  *bytes = round_up((size_t)h->n * (size_t)B * 16u, 256) * (size_t)vac_tape_vectors(n_t, M, np);
   return GPUQT_OK;
 }
 
@@ -1217,9 +1248,9 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   if (n_t == 0 || M == 0) return GPUQT_OK;
-  VacTape T;
-  if (tape && (st = vac_tape_check(h, B, n_t, M, tape, tape_bytes, &T))) return st;
   const int np = max_terms(h, n_t - 1, dt, Np);
+  VacTape T;
+  if (tape && (st = vac_tape_check(h, B, n_t, M, np, tape, tape_bytes, &T))) return st;
   const int L = tape ? np : std::max(M, np);
   const int s = keep ? 1 : backward_stride(L, 0);
   const int nv = tape ? 6 + backward_vectors(np, 1) : vac_backward_vectors(n_t, M, np, keep);
@@ -1299,11 +1330,14 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
     ev.Jtab = J;
     ev.ldJ = npk;
     ev.sgn = d >= 0 ? 1.0 : -1.0;
+    // the chains T_m psi_{L,R}(k-1) were recorded by the forward's evolution
+    const std::vector<double2*> rec = tape ? T.evolution(k - 1, npk) : std::vector<double2*>();
+    const bool have = tape && npk >= 3;
     if ((st = run_backward(h, B, gL[cl], psiL(k - 1), npk, ev, grad_onsite, gcp, nc, gL[cl ^ 1], false,
-                           s, pool.data(), sm)))
+                           s, pool.data(), sm, have ? rec.data() : nullptr)))
       return st;
     if ((st = run_backward(h, B, gR[cr], psiR(k - 1), npk, ev, grad_onsite, gcp, nc, gR[cr ^ 1], false,
-                           s, pool.data(), sm)))
+                           s, pool.data(), sm, have ? rec.data() + (npk - 1) : nullptr)))
       return st;
     cl ^= 1;
     cr ^= 1;

@@ -142,9 +142,9 @@ def test_vac_backward(gpu, name, B, ckpt):
 @pytest.mark.parametrize("name", list(VAC_CASES))
 @pytest.mark.parametrize("B,M", [(1, 40), (2, 41), (1, 2)])
 def test_vac_record_and_backward_from_tape(gpu, name, B, M):
-    """The recorded forward returns gpuqt_vac's rows and the backward from its tape
-    gpuqt_vac_backward's gradients, bit for bit (same kernels on the same vectors), and
-    both match the oracle."""
+    """The recorded forward returns gpuqt_vac's rows bit for bit and the backward from its
+    tape gpuqt_vac_backward's gradients to rounding (the evolution chains come from the
+    two-vector evolution kernel instead of a recomputation), and both match the oracle."""
     import torch
     from oracle.adjoint import vac_gradient, velocity_class_parts
     say(f"case: VAC tape {name} B={B} M={M}")
@@ -157,12 +157,12 @@ def test_vac_record_and_backward_from_tape(gpu, name, B, M):
     rows = host(P.gpuqt_vac(H, dev(phi), dts, M))
     rec, tape = P.gpuqt_vac_record(H, dev(phi), dts, M)
     assert np.array_equal(host(rec), rows)
-    assert tape.numel() >= P.gpuqt_vac_tape_size(H, B, len(dts), M)
+    assert tape.numel() >= P.gpuqt_vac_tape_size(H, B, dts, M)
     w = np.random.default_rng(61).normal(size=(len(dts), 1, B, M))
     zc = lambda: torch.zeros(n_class, dtype=torch.float64, device="cuda")
     gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=1, grad_class=zc())
     tU, tC = P.gpuqt_vac_backward_tape(H, dev(phi), dts, dev(w), tape, grad_class=zc())
-    assert np.array_equal(host(tU), host(gU)) and np.array_equal(host(tC), host(gC))
+    assert err(host(tU), host(gU)) < 1e-13 and err(host(tC), host(gC)) < 1e-13
     Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
     Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
@@ -203,8 +203,8 @@ def test_backward_segments(gpu):
 
 def test_vac_tape_with_segments_and_block(gpu):
     """The recorded forward and the backward from its tape on a handle of two segments
-    (different DeltaE) with a block of four vectors: bit for bit the same rows and gradients
-    as gpuqt_vac and gpuqt_vac_backward with every vector kept."""
+    (different DeltaE) with a block of four vectors: the same rows (bit for bit) and
+    gradients (to rounding) as gpuqt_vac and gpuqt_vac_backward with every vector kept."""
     import torch
     say("case: VAC tape with segments, B=4")
     mods = [I.square(10, 9, t1=-1.0, t2=-0.2, W=1.0, seed=62), I.square(13, 7, t1=-1.0, t2=-0.2, W=2.0, seed=63)]
@@ -223,4 +223,4 @@ def test_vac_tape_with_segments_and_block(gpu):
     zc = lambda: torch.zeros(2, dtype=torch.float64, device="cuda")
     gU, gC = P.gpuqt_vac_backward(H, phi, dts, w, ckpt_stride=1, grad_class=zc())
     tU, tC = P.gpuqt_vac_backward_tape(H, phi, dts, w, tape, grad_class=zc())
-    assert np.array_equal(host(tU), host(gU)) and np.array_equal(host(tC), host(gC))
+    assert err(host(tU), host(gU)) < 1e-13 and err(host(tC), host(gC)) < 1e-13
