@@ -552,21 +552,13 @@ __global__ __launch_bounds__(256) void k_kpm_adjoint(int R, int M, const double*
   out[(int64_t)r * M + n] = wn * s;
 }
 
+// Bandwidth probe: one 16-byte element per thread over a grid that covers the
+// whole buffer (every element's load is in flight at once, as far as the chip
+// holds them; no loop-carried address arithmetic).
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                               size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const double2 a = ld2<true>(src + i);
-    const double2 b = ld2<true>(src + i + stride);
-    const double2 c = ld2<true>(src + i + 2 * stride);
-    const double2 d = ld2<true>(src + i + 3 * stride);
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n; i += stride) dst[i] = src[i];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 }  // namespace
@@ -719,8 +711,8 @@ hipError_t launch_sigma(int mode, int n_t, const double* dt, int n_E, const doub
 
 hipError_t launch_copy(const double2* src, double2* dst, size_t n16, hipStream_t s) {
   if (n16 == 0) return hipSuccess;
-  size_t blocks = (n16 + 255) / 256;
-  if (blocks > 256 * 16) blocks = 256 * 16;
+  const size_t blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
   k_copy<<<dim3((unsigned)blocks), 256, 0, s>>>(src, dst, n16);
   return hipGetLastError();
 }

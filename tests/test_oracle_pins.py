@@ -105,6 +105,41 @@ def test_exact_diagonalisation_moments_complex_hoppings():
     assert rel(mu, ref) < 1e-12
 
 
+def test_gershgorin_bound_hand_values():
+    """The Gershgorin bound that fixes DeltaE where the paper leaves it to the user (Section 3.2:
+    the spectrum of H / DeltaE must lie in [-1, 1]).  A 4-site open chain with hand-chosen
+    hoppings and potentials, row sums of |H_ij| written out by hand:
+      row 0: |1.5| + |-0.25|                 = 1.75
+      row 1: |-0.25| + |2| + |0.5 - 0.5 i|   = 2.25 + 0.7071...
+      row 2: |0.5 + 0.5 i| + |-3.0| + |1|    = 4 + 0.7071...
+      row 3: |1| + |-0.75|                   = 1.75
+    so the bound is 4 + 1/sqrt(2); a diagonal-only matrix gives max |U_i| exactly, and the
+    largest eigenvalue magnitude stays within the bound."""
+    n = 4
+    nbr = np.array([[1, -1], [0, 2], [1, 3], [2, -1]], np.int32)
+    nn = np.array([1, 2, 2, 1], np.int32)
+    hop = np.zeros((4, 2), np.complex128)
+    hop[0, 0] = -0.25
+    hop[1, 0], hop[1, 1] = -0.25, 0.5 - 0.5j
+    hop[2, 0], hop[2, 1] = 0.5 + 0.5j, 1.0
+    hop[3, 0] = 1.0
+    U = np.array([1.5, 2.0, -3.0, -0.75])
+    m = I.Model(nn, nbr, hop, U, np.arange(n, dtype=float), 0.0, float(n))
+    H, _, _ = ops(m)
+    assert abs(O.gershgorin_bound(H) - (4.0 + 1.0 / math.sqrt(2.0))) < 1e-15
+    assert np.max(np.abs(np.linalg.eigvalsh(H.toarray()))) <= O.gershgorin_bound(H)
+    # diagonal only: max |U_i| (a dropped diagonal would give 0)
+    Ud = np.array([0.3, -2.5, 1.0, 2.25])
+    md = I.Model(np.zeros(n, np.int32), np.full((n, 1), -1, np.int32), None, Ud,
+                 np.arange(n, dtype=float), 0.0, float(n))
+    Hd, _, _ = ops(md)
+    assert O.gershgorin_bound(Hd) == 2.5
+    # hoppings only (U = 0): a clean ring of 9 sites with t = -1 gives 2, and a square
+    # lattice with next-nearest t2 = -0.2 gives 4 + 4 * 0.2
+    assert abs(O.gershgorin_bound(ops(I.chain(9))[0]) - 2.0) < 1e-15
+    assert abs(O.gershgorin_bound(ops(I.square(6, 5, t2=-0.2))[0]) - 4.8) < 1e-15
+
+
 def test_honeycomb_flux_per_hexagon():
     """Input generator: every hexagon encloses 2 pi f (Peierls phases, uniform field)."""
     nx, ny, f = 4, 6, 1.0 / 24.0
