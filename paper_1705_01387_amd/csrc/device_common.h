@@ -107,11 +107,14 @@ __device__ __forceinline__ bool col_entry(const DevMat& A, int64_t r, int64_t e,
 // K > 0: every slice has exactly K entries per row, so the row's first entry
 // follows from r alone (no slice-offset load) and the loop is fully unrolled
 // with all index loads issued before the gathers.  K == 0: runtime slice width.
+// pk (K > 0 only): the row's keys, already loaded by for_rows_pf one tile
+// ahead (NULL: load them here).
 template <int B, int HOP, int K, bool NT, bool TWO, bool DX, bool DIAG>
 __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, double hu,
                                           const double2* __restrict__ xa,
                                           const double2* __restrict__ xb, double2 xra, double2 xrb,
-                                          double2& ha, double2& hb, double2& da) {
+                                          double2& ha, double2& hb, double2& da,
+                                          const int32_t* pk = nullptr) {
   const int S = 1 << A.S_log2;
   const int64_t sl = r >> A.S_log2;
   const int64_t e0 = (K > 0 ? sl * ((int64_t)K << A.S_log2) : A.slice_ptr[sl]) + (r & (S - 1));
@@ -159,7 +162,7 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
   if constexpr (K > 0) {
     int32_t c[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) c[j] = key_at(e0 + (int64_t)j * S);
+    for (int j = 0; j < K; ++j) c[j] = pk ? pk[j] : key_at(e0 + (int64_t)j * S);
 #pragma unroll
     for (int j = 0; j < K; ++j) body(c[j], e0 + (int64_t)j * S);
   } else {
@@ -204,6 +207,84 @@ __device__ __forceinline__ void for_rows(const DevMat& A, const BlkPlan& P, F&& 
     if (pos < total) {
       const int64_t r = a + (pos & ((int64_t(1) << kUnitLog2) - 1));
       if (r < (((a >> kUnitLog2) + 1) << kUnitLog2) && r < P.se) f(r);
+    }
+  }
+}
+
+// Keys of the K entries of row r (fixed slice width K): column indices, or
+// (HOP_DICT) table indices.
+template <int HOP, int K, bool NT>
+__device__ __forceinline__ void load_keys(const DevMat& A, int64_t r, int32_t* k) {
+  const int S = 1 << A.S_log2;
+  const int64_t e0 = (r >> A.S_log2) * ((int64_t)K << A.S_log2) + (r & (S - 1));
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if constexpr (HOP == HOP_DICT) {
+      k[j] = (int32_t)ldg<NT>(A.hidx + e0 + (int64_t)j * S);
+    } else {
+      k[j] = ldg<NT>(A.col + e0 + (int64_t)j * S);
+    }
+  }
+}
+
+// The rows of for_rows, with the keys of each thread's next row loaded while
+// the current row is processed: f(r, keys) gets keys already in registers, so
+// a row waits for one memory trip (its gathers, issued together with its own
+// per-row loads) instead of two (keys, then gathers).  Lanes past the end
+// prefetch the keys of a valid row (the last row of the range, or the start
+// of the unit) and discard them.  K == 0 (runtime slice widths): for_rows with
+// keys = NULL.
+template <int B, int HOP, int K, bool NT, typename F>
+__device__ __forceinline__ void for_rows_pf(const DevMat& A, const BlkPlan& P, F&& f) {
+  if constexpr (K == 0) {
+    for_rows<B>(A, P, [&](int64_t r) { f(r, (const int32_t*)nullptr); });
+  } else {
+    constexpr int RPI = kBlock / B;
+    const int64_t step = (int64_t)P.g * RPI;
+    int32_t kc[K], kn[K];
+    if (A.units == nullptr) {
+      if (P.r1 <= P.r0) return;
+      const int64_t last = P.r1 - 1;
+      int64_t r = P.r0 + (int64_t)P.j * RPI + threadIdx.x / B;
+      load_keys<HOP, K, NT>(A, r < last ? r : last, kc);
+      for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step, r += step) {
+        const int64_t rn = r + step;
+        load_keys<HOP, K, NT>(A, rn < last ? rn : last, kn);
+        if (r < P.r1) f(r, (const int32_t*)kc);
+#pragma unroll
+        for (int j = 0; j < K; ++j) kc[j] = kn[j];
+      }
+      return;
+    }
+    // banded: unit starts are loaded two tiles ahead, keys one tile ahead
+    const int64_t total = row_seq_len(P, A.units);
+    if (total <= 0) return;
+    const int32_t* __restrict__ units = A.units + P.u0;
+    const int64_t lastu = (total - 1) >> kUnitLog2;
+    constexpr int64_t um = (int64_t(1) << kUnitLog2) - 1;
+    auto unit_of = [&](int64_t p) -> int64_t { const int64_t u = p >> kUnitLog2; return u < lastu ? u : lastu; };
+    // row at position p of a tile whose unit starts at a, or -1 (past the unit or segment end)
+    auto row_in = [&](int64_t p, int64_t a) -> int64_t {
+      const int64_t r = a + (p & um);
+      return (p < total && r < (((a >> kUnitLog2) + 1) << kUnitLog2) && r < P.se) ? r : -1;
+    };
+    int64_t pos = (int64_t)P.j * RPI + threadIdx.x / B;
+    int64_t a0 = units[unit_of(pos)];
+    int64_t a1 = units[unit_of(pos + step)];
+    {
+      const int64_t r = row_in(pos, a0);
+      load_keys<HOP, K, NT>(A, r >= 0 ? r : a0, kc);
+    }
+    for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += step, pos += step) {
+      const int64_t a2 = units[unit_of(pos + 2 * step)];
+      const int64_t rn = row_in(pos + step, a1);
+      load_keys<HOP, K, NT>(A, rn >= 0 ? rn : a1, kn);
+      const int64_t r = row_in(pos, a0);
+      if (r >= 0) f(r, (const int32_t*)kc);
+#pragma unroll
+      for (int j = 0; j < K; ++j) kc[j] = kn[j];
+      a0 = a1;
+      a1 = a2;
     }
   }
 }

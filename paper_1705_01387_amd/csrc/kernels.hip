@@ -61,14 +61,14 @@ __global__ __launch_bounds__(kBlock) void k_moment_step(DevMat A, StepIO io,
   // from x on the first step, where it is unused, to keep the load unconditional)
   const double2* __restrict__ wsrc = first ? x : w;
   double dr = 0.0, di = 0.0, zr = 0.0, zi = 0.0;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xr = x[idx];
     const double2 wv = ld2<NT>(wsrc + idx);
     double2 p = make_double2(0.0, 0.0);
     if (phiL) p = ld2<NT>(phiL + idx);   // plain recurrence step (no moment) when phiL is NULL
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da, kc);
     const double2 y = first ? ha : twice_minus(ha, wv);
     out[idx] = y;
     if (phiL) {
@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
   // first: a = <v0|v0>, b = <v0|v1>, c = <v1|v1>;  else: a = <vk|vk-1>, c = <vk|vk>
   const double2* __restrict__ wsrc = first ? x : w;   // w unused on the first step
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xr = x[idx];
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da, kc);
     const double2 wv = ld2<NT>(wsrc + idx);
     const double2 y = first ? ha : twice_minus(ha, wv);
     out[idx] = y;
@@ -155,14 +155,14 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_pair(DevMat A, ChainIO i
   const double2* __restrict__ wa = first ? io.xa : io.wa;   // unused on the first step
   const double2* __restrict__ wb = first ? io.xb : io.wb;
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xa = io.xa[idx];
     const double2 xb = io.xb[idx];
     const double2 wav = ld2<NT>(wa + idx);
     const double2 wbv = ld2<NT>(wb + idx);
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da, kc);
     const double2 ya = first ? ha : twice_minus(ha, wav);
     const double2 yb = first ? hb : twice_minus(hb, wbv);
     io.oa[idx] = ya;
@@ -206,13 +206,13 @@ __global__ __launch_bounds__(kBlock) void k_evolve_term(DevMat A, StepIO io, dou
   // loads stay unconditional and ahead of the gathers
   const double2* __restrict__ wsrc = first ? x : w;
   const double2* __restrict__ asrc = first ? x : acc;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xr = x[idx];
     const double2 wv = ld2<NT>(wsrc + idx);
     const double2 av = ld2<NT>(asrc + idx);
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da);
+    row_apply<B, HOP, K, NT, false, false, true>(A, r, b, hu, x, nullptr, xr, xr, ha, hb, da, kc);
     if (first) {
       out[idx] = ha;
       acc[idx] = cadd(cmul(c0, xr), cmul(cm, ha));
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_pair_term(DevMat A, ChainIO i
   const double2* __restrict__ wb = first ? io.xb : io.wb;
   const double2* __restrict__ sa = first ? io.xa : acc_a;
   const double2* __restrict__ sb = first ? io.xb : acc_b;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xa = io.xa[idx];
     const double2 xb = io.xb[idx];
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_evolve_pair_term(DevMat A, ChainIO i
     const double2 aav = ld2<NT>(sa + idx);
     const double2 abv = ld2<NT>(sb + idx);
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
+    row_apply<B, HOP, K, NT, true, false, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da, kc);
     if (first) {
       io.oa[idx] = ha;
       io.ob[idx] = hb;
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
   const double2* __restrict__ wb = first ? io.xb : io.wb;
   const double2* __restrict__ sa = first ? io.xa : acc_a;
   const double2* __restrict__ sb = first ? io.xb : acc_b;
-  for_rows<B>(A, P, [&](int64_t r) {
+  for_rows_pf<B, HOP, K, NT>(A, P, [&](int64_t r, const int32_t* kc) {
     const int64_t idx = r * B + b;
     const double2 xa = io.xa[idx];
     const double2 xb = io.xb[idx];
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_msd_term(DevMat A, ChainIO io, doubl
     const double2 aav = ld2<NT>(sa + idx);
     const double2 abv = ld2<NT>(sb + idx);
     double2 ha, hb, da;
-    row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da);
+    row_apply<B, HOP, K, NT, true, true, true>(A, r, b, hu, io.xa, io.xb, xa, xb, ha, hb, da, kc);
     const double2 g = make_double2(hb.x - da.x, hb.y - da.y);   // [X,H~] a + H~ b
     if (first) {
       io.oa[idx] = ha;

@@ -12,6 +12,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
+def oracle_dE(Hs):
+    """DeltaE as the oracle derives it from its own H: 1.01 x the Gershgorin bound."""
+    return 1.01 * O.gershgorin_bound(Hs)
+
+
 def say(*a):
     print(*a, flush=True)
 
@@ -45,9 +50,9 @@ def test_moments_backward(gpu, name, B, M, stride):
     say(f"case: backward {name} B={B} M={M} stride={stride}")
     mk, n_class = CASES[name]
     m = mk()
-    H = P.gpuqt_build_h_from_model(m)
-    dE = float(H.energy_max[0])
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
     parts = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
     phiL = I.random_phase(m.n, B, 45)
     phiR = I.random_phase(m.n, B, 46)
@@ -72,9 +77,9 @@ def test_moments_backward_hermitian(gpu, name, B, M, stride):
     say(f"case: Hermitian backward {name} B={B} M={M} stride={stride}")
     mk, n_class = CASES[name]
     m = mk()
-    H = P.gpuqt_build_h_from_model(m)
-    dE = float(H.energy_max[0])
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
     parts = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
     phi = I.random_phase(m.n, B, 48)
     d = dev(phi)
@@ -123,9 +128,9 @@ def test_vac_backward(gpu, name, B, ckpt):
     say(f"case: VAC backward {name} B={B} ckpt_stride={ckpt}")
     mk, n_class = VAC_CASES[name]
     m = mk()
-    H = P.gpuqt_build_h_from_model(m)
-    dE = float(H.energy_max[0])
     Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
     Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
     Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
     phi = I.random_phase(m.n, B, 58)
@@ -150,8 +155,9 @@ def test_vac_record_and_backward_from_tape(gpu, name, B, M):
     say(f"case: VAC tape {name} B={B} M={M}")
     mk, n_class = VAC_CASES[name]
     m = mk()
-    H = P.gpuqt_build_h_from_model(m)
-    dE = float(H.energy_max[0])
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
     phi = I.random_phase(m.n, B, 60)
     dts = [0.3, 1.2, 0.0, 0.7]
     rows = host(P.gpuqt_vac(H, dev(phi), dts, M))
@@ -163,7 +169,6 @@ def test_vac_record_and_backward_from_tape(gpu, name, B, M):
     gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=1, grad_class=zc())
     tU, tC = P.gpuqt_vac_backward_tape(H, dev(phi), dts, dev(w), tape, grad_class=zc())
     assert err(host(tU), host(gU)) < 1e-13 and err(host(tC), host(gC)) < 1e-13
-    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
     Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
     rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
@@ -193,7 +198,8 @@ def test_backward_segments(gpu):
     tot = 0.0
     for s, mm in enumerate(mods):
         Hs, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
-        dE = float(H.energy_max[s])
+        dE = oracle_dE(Hs)
+        assert abs(float(H.energy_max[s]) - dE) <= 1e-15 * dE
         ph = phi[offs[s]:offs[s + 1]]
         rU, rC = O.moments_gradient(Hs, ph, ph, dE, w[s].T, class_parts(mm.nn, mm.nbr, mm.hop, None, 1))
         assert err(gU[offs[s]:offs[s + 1]], rU) < TOL

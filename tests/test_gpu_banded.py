@@ -17,6 +17,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
+def oracle_dE(Hs):
+    """DeltaE as the oracle derives it from its own H: 1.01 x the Gershgorin bound."""
+    return 1.01 * O.gershgorin_bound(Hs)
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -40,8 +45,8 @@ def err(got, ref):
 @pytest.fixture(scope="module")
 def cubic26(gpu):
     m = I.cubic(26, W=4.0, seed=71)             # 17,576 rows, period 676 (not a multiple of 64)
-    H = P.gpuqt_build_h_from_model(m, band_rows=128)
     Hs, V, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    H = P.gpuqt_build_h_from_model(m, energy_max=oracle_dE(Hs), band_rows=128)
     return m, H, Hs, V, XH
 
 
@@ -57,7 +62,7 @@ def test_banded_order_exists(cubic26):
 def test_banded_moments(cubic26, variant, B):
     say(f"case: banded moments variant={variant} B={B}")
     m, H, Hs, _, _ = cubic26
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
     P.gpuqt_set_variant(H, variant)
     phi = I.random_phase(m.n, B, 72)
     psi = I.random_phase(m.n, B, 73)
@@ -74,7 +79,7 @@ def test_banded_moments(cubic26, variant, B):
 def test_banded_rowwise_results_bit_identical(cubic26, B):
     say(f"case: banded evolve/commutator bit-identical B={B}")
     m, H, Hs, _, XH = cubic26
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
     psi = dev(I.random_phase(m.n, B, 74))
     outs = []
     for v in (0, 2, 3, 2 | (3 << 2), 1 << 2):   # row-wise results do not depend on the schedule
@@ -95,7 +100,7 @@ def test_banded_rowwise_results_bit_identical(cubic26, B):
 def test_banded_vac_msd(cubic26):
     say("case: banded VAC/MSD B=2")
     m, H, Hs, V, XH = cubic26
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
     P.gpuqt_set_variant(H, 2)
     phi = I.random_phase(m.n, 2, 75)
     dts = [0.5, 1.5, 1.0]
@@ -113,7 +118,7 @@ def test_banded_backward(cubic26):
     say("case: banded moments backward B=1")
     m, H, Hs, _, _ = cubic26
     import torch
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
     P.gpuqt_set_variant(H, 3)
     phi = I.random_phase(m.n, 1, 76)
     M = 40
@@ -146,7 +151,9 @@ def test_banded_segments_mixed(gpu):
         for s, mm in enumerate(mods):
             Hs, _, _ = O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)
             ph = phi[offs[s]:offs[s + 1]]
-            ref = O.chebyshev_moments(Hs / float(H.energy_max[s]), ph, ph, 90).T
+            dE = oracle_dE(Hs)
+            assert abs(float(H.energy_max[s]) - dE) <= 1e-15 * dE
+            ref = O.chebyshev_moments(Hs / dE, ph, ph, 90).T
             assert err(mu[s], ref) < TOL, (v, s)
 
 
@@ -162,10 +169,10 @@ def test_banded_with_value_table(gpu):
     hop[:, 2] = -np.exp(1j * theta * ix)       # +y bond of site i
     hop[:, 3] = -np.exp(-1j * theta * ix)      # -y bond (same x): the conjugate
     m = I.Model(m.nn, m.nbr, hop, m.onsite, m.x, m.length_x, m.volume, name="cubic26_phases")
-    H = P.gpuqt_build_h_from_model(m, band_rows=128, check_hermitian=True)
-    assert H.info.hop_mode == 3 and H.info.banded_mask == 0b11111
     Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
-    dE = float(H.energy_max[0])
+    H = P.gpuqt_build_h_from_model(m, energy_max=oracle_dE(Hs), band_rows=128, check_hermitian=True)
+    assert H.info.hop_mode == 3 and H.info.banded_mask == 0b11111
+    dE = oracle_dE(Hs)
     phi = I.random_phase(m.n, 2, 103)
     psi = I.random_phase(m.n, 2, 104)
     d = dev(phi)
@@ -182,7 +189,7 @@ def test_banded_with_value_table(gpu):
 def test_variant_codes(cubic26):
     say("case: variant codes with a per-CU cap")
     m, H, Hs, _, _ = cubic26
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
     phi = I.random_phase(m.n, 4, 75)
     ref = O.chebyshev_moments(Hs / dE, phi, phi, 64).T
     G = H.info.grid_blocks
@@ -202,10 +209,10 @@ def test_default_two_bands_for_long_periods(gpu):
     gets two bands (D = 1100 here, bands of 512 rows); the moments match the oracle either way."""
     say("case: default two-band order, square 1100 x 24")
     m = I.square(1100, 24, W=2.0, seed=76)
-    H = P.gpuqt_build_h_from_model(m)
-    assert H.info.row_period == 1100 and H.info.banded_mask == 0b11110
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
-    dE = float(H.energy_max[0])
+    H = P.gpuqt_build_h_from_model(m, energy_max=oracle_dE(Hs))
+    assert H.info.row_period == 1100 and H.info.banded_mask == 0b11110
+    dE = oracle_dE(Hs)
     phi = I.random_phase(m.n, 2, 77)
     ref = O.chebyshev_moments(Hs / dE, phi, phi, 96).T
     for v in (0, 2, 3):

@@ -11,6 +11,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
+def oracle_dE(Hs):
+    """DeltaE as the oracle derives it from its own H: 1.01 x the Gershgorin bound."""
+    return 1.01 * O.gershgorin_bound(Hs)
+
+
 def say(*a):
     print(*a, flush=True)
 
@@ -119,10 +124,12 @@ def test_autotune_keeps_results(gpu):
     assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 1, 3))
     a = host(P.gpuqt_moments(H, phi, phi, 200))
     Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
-    ref = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(phi), 200).T
+    dE = oracle_dE(Ho)
+    assert abs(float(H.energy_max[0]) - dE) <= 1e-15 * dE
+    ref = O.chebyshev_moments(Ho / dE, host(phi), host(phi), 200).T
     assert err(a[0], ref) < TOL
     psi = dev(I.random_phase(m.n, 4, 67))
-    ref2 = O.chebyshev_moments(Ho / float(H.energy_max[0]), host(phi), host(psi), 200).T
+    ref2 = O.chebyshev_moments(Ho / dE, host(phi), host(psi), 200).T
     assert err(host(P.gpuqt_moments(H, phi, psi, 200))[0], ref2) < TOL
     P.gpuqt_set_variant(H, code & 63)
     assert H.info.family_caps == 0 and H.info.kernel_variant == code & 63

@@ -45,6 +45,12 @@ def build(m, dE=0.0, **kw):
     return P.gpuqt_build_h_from_model(m, energy_max=dE, **kw)
 
 
+def oracle_dE(Hs):
+    """DeltaE as the oracle derives it: 1.01 x the Gershgorin bound of H (the scaling rule of the
+    design, applied to the oracle's own H); the library is handed this value explicitly."""
+    return 1.01 * O.gershgorin_bound(Hs)
+
+
 def diag_model(n=777, seed=3):
     U = np.random.default_rng(seed).uniform(-2, 2, n)
     return I.Model(np.zeros(n, np.int32), np.full((n, 1), -1, np.int32), None, U,
@@ -88,9 +94,9 @@ def test_moments_square64_dos(torch_cuda):
 def test_moments_lattices(torch_cuda, name, B):
     say(f"case: moments {name} B={B}")
     m = MODELS[name]()
-    H = build(m)
     Hs, _, _ = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     phiL = I.random_phase(m.n, B, 10)
     phiR = I.random_phase(m.n, B, 11)
     M = 300
@@ -99,12 +105,25 @@ def test_moments_lattices(torch_cuda, name, B):
     assert err(mu, ref) < TOL
 
 
+@pytest.mark.parametrize("name", list(MODELS))
+def test_default_energy_max_matches_oracle(torch_cuda, name):
+    """With no DeltaE given the library takes 1.01 x its own Gershgorin bound; the oracle's bound
+    of its own H gives the same value to a few ulp (the two sum the row magnitudes in different
+    orders)."""
+    say(f"case: default DeltaE {name}")
+    m = MODELS[name]()
+    Hs, _, _ = ops(m)
+    H = build(m)
+    assert abs(float(H.energy_max[0]) - oracle_dE(Hs)) <= 1e-15 * oracle_dE(Hs)
+    assert abs(float(H.gershgorin[0]) - O.gershgorin_bound(Hs)) <= 1e-15 * O.gershgorin_bound(Hs)
+
+
 def test_moments_B16_and_small_M(torch_cuda):
     say("case: moments B=16, M in {1,2,3}")
     m = I.square(33, 31, W=2.0, seed=8)
-    H = build(m)
     Hs, _, _ = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     phi = I.random_phase(m.n, 16, 12)
     mu = host(P.gpuqt_moments(H, dev(phi), dev(phi), 200))[0]
     assert err(mu, O.chebyshev_moments(Hs / dE, phi, phi, 200).T) < TOL
@@ -120,9 +139,9 @@ def test_moments_sym_and_pair_forms(torch_cuda, name, B):
     two buffers: the two-chain form; both against the plain definition for odd and even M."""
     say(f"case: moments sym/pair {name} B={B}")
     m = MODELS[name]()
-    H = build(m)
     Hs, _, _ = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     phi = I.random_phase(m.n, B, 15)
     same = dev(phi)
     for M in (1, 2, 3, 4, 5, 6, 299, 300):
@@ -149,9 +168,9 @@ def test_moments_bit_identical_reruns(torch_cuda):
 def test_evolve(torch_cuda, dt, Np, B):
     say(f"case: evolve dt={dt} Np={Np} B={B}")
     m = I.honeycomb(20, 14, flux=1.0 / 140.0, W=1.0, seed=14)
-    H = build(m)
     Hs, _, _ = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     psi = I.random_phase(m.n, B, 15)
     out = host(P.gpuqt_evolve(H, dev(psi), dt, Np))
     ref = O.evolve(Hs / dE, psi, dt, dE, Np)
@@ -166,9 +185,9 @@ def test_evolve(torch_cuda, dt, Np, B):
 def test_evolve_commutator(torch_cuda, with_chi, name):
     say(f"case: evolve+commutator {name} chi={with_chi}")
     m = MODELS[name]()
-    H = build(m)
     Hs, V, XH = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     psi = I.random_phase(m.n, 2, 16)
     chi = I.random_phase(m.n, 2, 17) * 0.3 if with_chi else None
     dt = 1.7
@@ -225,9 +244,9 @@ def test_msd_square64(torch_cuda):
 def test_vac_msd_nonuniform_steps_complex(torch_cuda, B):
     say(f"case: VAC/MSD honeycomb flux non-uniform steps B={B}")
     m = I.honeycomb(24, 16, flux=1.0 / 192.0, W=1.5, seed=19)
-    H = build(m)
     Hs, V, XH = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE)
     phi = I.random_phase(m.n, B, 20)
     dts = [0.1, 0.5, 2.0, 0.0, 3.5]
     v = host(P.gpuqt_vac(H, dev(phi), dts, 128))[:, 0]
@@ -257,8 +276,8 @@ def test_segments_uneven_realisations(torch_cuda):
     vc = host(P.gpuqt_vac(H, dev(phi), dts, 64))
     for s, mm in enumerate(mods):
         Hs, V, XH = ops(mm)
-        dE = float(H.energy_max[s])
-        assert abs(dE - 1.01 * O.gershgorin_bound(Hs)) < 1e-12 * dE
+        dE = oracle_dE(Hs)
+        assert abs(float(H.energy_max[s]) - dE) <= 1e-15 * dE   # the library's own per-segment rule
         ph = phi[offs[s]:offs[s + 1]]
         assert err(mu[s], O.chebyshev_moments(Hs / dE, ph, ph, M).T) < TOL
         rm = O.msd_moments(Hs, XH, ph, dts, dE, 64)
@@ -326,9 +345,9 @@ def test_full_size_honeycomb_sampled(torch_cuda):
     mu = host(P.gpuqt_moments(H, dev(phi), dev(phi), 64))[0, 0]
     assert err(mu, O.dos_moments(Hs, phi, dE, 64)[:, 0]) < TOL
     dt = -float(w["dt"][0])
-    Np = P.gpuqt_auto_terms(dE * abs(dt))
-    assert 260 <= Np <= 290
-    out = host(P.gpuqt_evolve(H, dev(phi), dt, 0))
+    Np = O.auto_terms(dE * abs(dt))                      # the oracle's own term count
+    assert 260 <= Np <= 290 and P.gpuqt_auto_terms(dE * abs(dt)) == Np
+    out = host(P.gpuqt_evolve(H, dev(phi), dt, 0))       # the library's automatic count
     ref = O.evolve(Hs / dE, phi, dt, dE, Np)
     assert err(out, ref) < TOL
     assert abs(np.sum(np.abs(out) ** 2) / m.n - 1) < 1e-12
@@ -439,12 +458,11 @@ def test_value_table_matches_per_entry_storage(torch_cuda, name):
         m = _random_real_hops(I.cubic(12, W=2.0, seed=96), 2, [-1.0, -0.9])
     else:
         m = MODELS[name]()
-    Ht = build(m)
-    Hp = build(m, no_dictionary=True)
-    assert Ht.info.hop_mode == 3 and Hp.info.hop_mode in (1, 2)
     Hs, V, XH = ops(m)
-    dE = float(Ht.energy_max[0])
-    assert dE == float(Hp.energy_max[0])
+    dE = oracle_dE(Hs)
+    Ht = build(m, dE)
+    Hp = build(m, dE, no_dictionary=True)
+    assert Ht.info.hop_mode == 3 and Hp.info.hop_mode in (1, 2)
     psi = dev(I.random_phase(m.n, 2, 97))
     for H in (Ht, Hp):
         P.gpuqt_autotune(H, 2)
@@ -511,10 +529,10 @@ def test_per_entry_storage_modes(torch_cuda, name):
     moments and the evolution + commutator series against the oracle."""
     say(f"case: per-entry storage {name}")
     m = MODELS[name]()
-    H = build(m, no_dictionary=True)
-    assert H.info.hop_mode in (0, 1, 2)
     Hs, _, XH = ops(m)
-    dE = float(H.energy_max[0])
+    dE = oracle_dE(Hs)
+    H = build(m, dE, no_dictionary=True)
+    assert H.info.hop_mode in (0, 1, 2)
     phi = I.random_phase(m.n, 2, 101)
     d = dev(phi)
     assert err(host(P.gpuqt_moments(H, d, d, 120))[0], O.chebyshev_moments(Hs / dE, phi, phi, 120).T) < TOL
