@@ -1,51 +1,48 @@
-"""Benchmark: Chebyshev H*psi steps per second of the linear-scaling Kubo path.
+"""Benchmark: Chebyshev H*psi steps per second of the linear-scaling Kubo path on one MI355X.
 
-Default workload (--workload honeycomb): honeycomb lattice, 1000 x 1000 unit
-cells = 2,000,000 orbitals, 3 neighbours, hopping -2.7 eV with Peierls phases
-for a flux of 1/2000 per hexagon (complex128 hoppings), Anderson disorder U
-in [-1, 1] eV, DeltaE = 1.01 x Gershgorin bound.  One step = the whole
-calculation for one random-phase vector (vectors seeded 2002, 2003, ...):
-DOS moments (M = 3000), VAC moments and MSD moments over 20 time steps of
-15 fs (M = 3000 per row, 275 Chebyshev-Bessel terms per step, chosen
-automatically).
+Default workload (--workload cubic): simple cubic lattice 200^3 = 8,000,000 orbitals,
+6 neighbours, t = -1, Anderson disorder U in [-8, 8] (W = 16), DeltaE = 1.01 (6 + W/2),
+a block of 4 random-phase vectors advanced together.  The MSD of this block over time steps
+of dt = 2 with 60 Chebyshev-Bessel terms per step and M = 1000 moments per row is the
+workload; one bench step is one time step of it: the fused evolution + commutator series
+(psi <- U(dt) psi, chi <- [X, U(dt)] psi + U(dt) chi, Section 3.2, product rule) followed
+by the M moments of the new chi (Section 3.3, C_n^MSD).  The state carries over from step
+to step (warmup steps included), so K steps are K consecutive MSD rows.  The DOS moments
+of the block (M = 1000) are timed once beside it, and the whole calculation of one block
+(DOS + 40 rows) is reported as the sum.  Every input is resident in HBM before timing.
 
-Other workloads (each prints its own line):
-  cubic    simple cubic 200^3 = 8,000,000 orbitals, W = 16, a block of 4 vectors;
-           one step = DOS moments (M = 1000) and MSD over 40 steps of dt = 2
-           (M = 1000, 63 terms) for the block.  Its working set is several GB,
-           far beyond the 256 MB last-level cache: the HBM roofline case.
-  batched  8 square-lattice realisations 200^2 .. 2000^2 (8,255,182 orbitals in
-           all, W_r uniform in [0.5, 3]) x a block of 16 vectors, all in one
-           launch per Chebyshev step; one step = M = 2000 moments of every
-           (realisation, vector) pair.  Also times the same moments one vector
-           at a time (B = 1) and reports the ratio.
-  paper    the paper's two examples (2000^2 square, VAC + MSD; 4e6 chain, MSD over 30
-           non-uniform steps) end to end: moments, KPM sums on the energy grids and
-           running conductivities; reports the seconds per pass beside the paper's
-           "about 3 minutes on a Tesla K40" (context, not the same measurement).
-  train    square 512^2 with two trainable hopping classes; one step = forward
-           (DOS moments M = 512, VAC 10 rows of dt = 1) + adjoint (gradients of a
-           loss on both w.r.t. all on-site energies and both classes); reports
-           the adjoint/forward time ratio.
+value = sparse H*psi applications per second actually launched, counted per vector (a step
+on a block of B vectors counts B): a fused evolution + commutator term counts 2 (its two
+chains), a step of a moment set 1 (the library reaches M moments in max(1, M/2) steps by the
+Chebyshev product identities).  config.plain_equivalent_steps_per_s counts the same results
+as the paper's one-moment-per-step recurrence would need them (M - 1 per set).
 
-Every input is resident on the GPU before the timed region.  The value counts
-Chebyshev recurrence steps on one vector as the plain recurrence of the method
-needs them for the same results: a set of M moments counts M - 1, an evolution
-term and a velocity application 1, a fused evolution + commutator term 2 (two
-chains), a reverse (adjoint) step 1; a step on a block of B vectors counts B.
-The library computes a moment set with the Chebyshev product identities in
-about half those launches; config.launched_steps_per_s gives the rate of the
-steps actually launched.
+Also on the line:
+  roofline      the kernel family with the most time (HIP events the library records on its
+                own stream around each run of launches, gpuqt_set_timing): algorithmic bytes
+                per launch / average launch time, against the 8 TB/s HBM peak, with the HBM
+                bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record
+                when it was taken on the same kernel sources and variant;
+  single_vector the single-vector (B = 1) Chebyshev step on the same lattice, both the
+                Hermitian product-identity step the library uses and the paper's plain
+                one-moment-per-step recurrence (gpuqt_moments_plain);
+  cpu_baseline  the CPU oracle's moment recurrence on the same lattice, one host thread and
+                all host cores (median of 5 runs of 20 steps each);
+  paper_examples the paper's two examples (Section 5) end to end, once;
+  copy_probe_GBs a full-grid 16-byte copy kernel over 2 x 1 GiB.
 
-Also reported: per kernel family, launches, average launch time and the
-bandwidth its algorithmic bytes imply, from HIP events the library records on
-its own stream around every run of launches of that family in the timed
-region (gpuqt_set_timing); the roofline line is the family with the most
-time.  And the CPU oracle timed on a bounded sample of the same recurrence.
+Other workloads (--workload): honeycomb (2,000,000-orbital honeycomb with Peierls phases, one
+vector, DOS + VAC + MSD at M = 3000: its working set fits the 256 MB last-level cache, so
+the roofline is labelled "llc"); honeycomb-general (the same with every hopping stored per
+entry, as an arbitrary hopping.in gives); batched (8 uneven square realisations x 16 vectors
+in one launch per step, eager vs graph-captured, and vs one vector at a time); small (square
+64 x 64: DOS + VAC + MSD, launch-bound, eager vs graph-captured); paper; train.
 """
 import argparse
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -54,8 +51,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Chebyshev H·psi steps/s, HBM GB/s %peak; batched & adjoint vs plain @1e-10 err"
+UNIT = "Chebyshev H*psi steps/s"
 HBM_PEAK_GBS = 8000.0
-
+LLC_BYTES = 256 << 20
 
 # vector bytes per row and block column of one launch of each kernel family (16-byte complex
 # elements, each stream counted once): gathered inputs, v_{n-2} reads, outputs, dot partners
@@ -71,6 +69,11 @@ FAMILY_VECTOR_BYTES = {
 FAMILY_KERNEL = {"moment": "k_moment_step", "moment_sym": "k_moment_step_sym",
                  "moment_pair": "k_moment_step_pair", "evolve": "k_evolve_term", "msd": "k_msd_term",
                  "evolve_pair": "k_evolve_pair_term"}
+KERNEL_SOURCES = ("device_common.h", "internal.h", "kernels.hip")   # what the step kernels are built from
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def family_bytes(info, B, family="moment"):
@@ -80,51 +83,45 @@ def family_bytes(info, B, family="moment"):
     segment), 8 (real) or 16 (complex) B, plus the position difference 8 B for the
     commutator chain; in table mode (3) one 2-byte index into the table of distinct
     (column offset, hopping, dx) triples, which stays in cache.  Per row the on-site term
-    8 B; per slice the 8-byte slice offset.  Vector part: FAMILY_VECTOR_BYTES per row and
-    block column.
+    8 B.  Vector part: FAMILY_VECTOR_BYTES per row and block column.
     """
     mode = int(info.hop_mode)
     n = int(info.n)
-    if mode == 3:        # one 16-bit index into the table of (column offset, hopping, dx)
+    if mode == 3:
         per_entry = 2
     else:
         per_entry = 4 + {0: 0, 1: 8, 2: 16}[mode] + (8 if family == "msd" else 0)
-    return int(info.nnz) * per_entry + n * 8 + int(info.n_slices) * 8 + n * FAMILY_VECTOR_BYTES[family] * B
-
-
-def pick_variant(P, H, B, ws, args):
-    """Autotune the kernel variant of H at block width B, or pin the one given by --variant
-    (for profiling runs whose counters must all come from one configuration).  Returns the
-    autotune times per load variant (zeros when pinned)."""
-    if args.variant >= 0:
-        P.gpuqt_set_variant(H, args.variant)
-        return [0.0] * 4
-    return P.gpuqt_autotune(H, B, ws=ws)
+    return int(info.entries) * per_entry + n * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 
 def variant_text(v, family=None):
-    """The autotuned kernel variant code v: load variant (bit 0 non-temporal, bit 1 banded
-    order), the cap on resident workgroups per CU (bits 2-5, 0 = none), or the family's own
-    cap (3 bits per family from bit 8: 0 = the per-CU cap, 1 + c = cap c) when it has one."""
+    """The kernel variant code v: load variant (bit 0 non-temporal, bit 1 banded order), the
+    cap on resident workgroups per CU (bits 2-5, 0 = none), or the family's own cap (3 bits
+    per family from bit 8: 0 = the per-CU cap, 1 + c = cap c) when it has one."""
     from paper_1705_01387_amd._binding import K_FAMILIES
     cap = (v >> 2) & 15
     if family is not None:
         c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
         if c:
             cap = c - 1
-    return "code %d: variant %d, %s" % (v, v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
+    return "code %d: load/order variant %d, %s" % (v, v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
 
 
-def moment_step_bytes(info, B):
-    """Algorithmic HBM bytes of one plain moment-step launch."""
-    return family_bytes(info, B, "moment")
+def pick_variant(P, H, B, ws, args):
+    """Autotune the kernel variant of H at block width B (through the tuning cache, so that
+    the benchmark and its profiles run the same variant), or pin the one given by --variant.
+    Returns (autotune times per load variant or zeros, whether the choice came from the cache)."""
+    if args.variant >= 0:
+        P.gpuqt_set_variant(H, args.variant)
+        return [0.0] * 4, False
+    t, cached = P.gpuqt_autotune_cached(H, B, ws=ws)
+    return [float(x) for x in t], bool(cached)
 
 
 def kernel_table(info, B, fam, elapsed_s):
     """Per family: launches, average launch time (event time of its runs / launches; the
     runs are back-to-back launches, so this includes the small gaps between them),
-    algorithmic bytes per launch and the bandwidth they imply.  Returns (table, dominant
-    family = the one with the most time)."""
+    algorithmic bytes per launch and the bandwidth they imply.  Returns (table, dominant)."""
     table = {}
     for f, (ms, nl) in fam.items():
         if nl <= 0:
@@ -138,28 +135,40 @@ def kernel_table(info, B, fam, elapsed_s):
     return table, dominant
 
 
-def count_steps(M, dts, np_list, vac=True, msd=True, applied=False):
-    """Chebyshev H*psi steps of one vector's DOS (+ VAC) (+ MSD) calculation.
+def measured_traffic(name, family, bytes_launch, variant):
+    """HBM bytes per launch of the dominant kernel from the committed counter record, if it was
+    taken on that kernel family, on the kernel sources built now and with the same variant
+    code (else None: a record of another variant does not describe this run's kernel)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1705_01387_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        with open(os.path.join(src, fn), "rb") as g:
+            h.update(g.read())
+    e = rec.get(name)
+    if (not e or e.get("kernel_source_sha256") != h.hexdigest() or e.get("family") != family
+            or e.get("variant") != int(variant)):
+        return None
+    return {"bytes": e["bytes_per_launch"], "ratio_to_algorithmic": e["bytes_per_launch"] / bytes_launch,
+            "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"],
+            "variant": e["variant"], "profile": e.get("profile")}
 
-    applied=False: as the plain recurrence of the method counts them (a set of M moments
-    is M - 1 steps), the unit of the reported throughput.  applied=True: the steps the
-    library actually launches, where a Hermitian moment set takes max(1, M // 2) steps
-    and an off-diagonal one two chains of max(1, M // 2) steps (product identities).
-    """
-    n_t = len(dts)
-    K = max(1, M // 2)
-    mom_sym = K if applied else M - 1
-    mom_pair = 2 * K if applied else M - 1
-    total = mom_sym
-    if vac:
-        total += 1 + n_t * (1 + mom_pair) + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))
-    if msd:
-        total += sum(2 * (np_list[k] - 1) for k in range(n_t)) + n_t * mom_sym
-    return total
 
-
-def log(msg):
-    print("[bench] " + msg, file=sys.stderr, flush=True)
+def roofline_of(name, info, B, kernels, dominant, bound="hbm"):
+    d = kernels[dominant]
+    tr = measured_traffic(name, dominant, d["bytes_per_launch"], info.kernel_variant)
+    return {"bound": bound, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": None if tr is None else tr["bytes"] / 1e9,
+            "traffic_detail": tr,
+            "kernel": "%s (B=%d, hop mode %d, K=%d, %s)" % (FAMILY_KERNEL[dominant], B, info.hop_mode,
+                                                          info.uniform_width,
+                                                          variant_text(info.kernel_variant, dominant)),
+            "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"]}
 
 
 def copy_probe_gbs(P, torch, dev):
@@ -175,34 +184,119 @@ def copy_probe_gbs(P, torch, dev):
         P.gpuqt_copy_probe(src, dst)
     c1.record()
     torch.cuda.synchronize()
-    return 2 * nb * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    out = 2 * nb * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
-def cpu_oracle_sample(m, phi, dE, B, Mc, seconds=15.0):
-    """The oracle's DOS recurrence on the full lattice, sized to about `seconds` of CPU work,
-    with every BLAS / OpenMP pool held to one thread (the figure is per host thread)."""
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        return _cpu_oracle_sample(m, phi, dE, B, Mc, seconds)
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle, in a fresh process that never touches the GPU
+# --------------------------------------------------------------------------
+
+def cpu_baseline(workload, timeout=600):
+    """Run this file with --cpu-baseline in a child process (the oracle's worker processes are
+    forked there, from a process with no GPU context) and return its JSON."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline", workload]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=timeout)
+    if r.returncode != 0:
+        log("cpu baseline failed: " + r.stderr[-400:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def _cpu_oracle_sample(m, phi, dE, B, Mc, seconds):
+_CPU = {}
+
+
+def _cpu_runs(seed, reps, steps):
+    """reps timed runs of the oracle's DOS recurrence (steps sparse steps each) on one random-phase
+    vector; BLAS / OpenMP pools held to one thread."""
     import oracle as O
+    from threadpoolctl import threadpool_limits
+    from paper_1705_01387_amd import inputs as I
+    Hs, dE, n = _CPU["H"], _CPU["dE"], _CPU["n"]
+    phi = I.random_phase(n, 1, seed)
+    out = []
+    with threadpool_limits(limits=1):
+        for _ in range(reps):
+            t = time.perf_counter()
+            O.dos_moments(Hs, phi, dE, steps + 1)
+            out.append(time.perf_counter() - t)
+    return out
+
+
+def cpu_baseline_main(workload):
+    import multiprocessing as mp
+
+    import oracle as O
+    from paper_1705_01387_amd import inputs as I
+    if workload == "cubic":
+        w = I.workload_cubic(L=200, W=16.0, B=4)
+        m, dE = w["model"], w["energy_max"]
+    else:
+        w = I.workload_honeycomb(n_vectors=1)
+        m, dE = w["model"], w["energy_max"]
+    t = time.perf_counter()
     Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
-    if Mc <= 0:
-        tc = time.perf_counter()
-        O.dos_moments(Hs, phi, dE, 8)
-        per = (time.perf_counter() - tc) / 7
-        Mc = int(max(16, min(4000, seconds / max(per, 1e-6))))
-    tc = time.perf_counter()
-    O.dos_moments(Hs, phi, dE, Mc)
-    tcpu = time.perf_counter() - tc
-    return {"value": (Mc - 1) * B / tcpu, "unit": "Chebyshev H*psi steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle DOS moment recurrence, M={Mc}, B={B}, on the full {m.n}-orbital lattice "
-                      f"of this workload ({tcpu:.1f} s; scipy CSR products and numpy, one thread)"}
+    setup = time.perf_counter() - t
+    _CPU.update(H=Hs, dE=dE, n=m.n)
+    reps, steps = 5, 20
+    one = _cpu_runs(4200, reps, steps)
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        res = pool.starmap(_cpu_runs, [(4300 + i, reps, steps) for i in range(procs)])
+    all_rate = sum(steps / statistics.median(r) for r in res)
+    one_rate = steps / statistics.median(one)
+    sample = (f"oracle DOS moment recurrence (scipy CSR products, numpy dots; Section 3.2) on the full "
+              f"{m.n}-orbital lattice of this workload, one vector per process, {reps} runs of {steps} "
+              f"steps each, median run")
+    print(json.dumps({"value": all_rate, "unit": UNIT, "cores": procs, "kind": "oracle", "sample": sample,
+                      "single_thread": {"value": one_rate, "cores": 1, "median_run_s": statistics.median(one)},
+                      "all_cores": {"value": all_rate, "cores": procs,
+                                    "median_run_s": statistics.median([statistics.median(r) for r in res])},
+                      "operator_setup_s": setup}))
 
 
-def transport_workload(args, name):
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def single_vector_steps(P, torch, H, n, dev, args, seed=4200):
+    """The single-vector Chebyshev step on this lattice: 100 Hermitian product-identity steps
+    (the library's DOS form) and 100 steps of the paper's plain recurrence, autotuned at B = 1."""
+    from paper_1705_01387_amd import inputs as I
+    ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MOMENTS, 1, 201, 0),
+                         P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, 1, 0, 0)), dtype=torch.uint8, device=dev)
+    tune, cached = pick_variant(P, H, 1, ws, args)
+    phi = torch.from_numpy(I.random_phase(n, 1, seed)).to(dev)
+    mu = torch.empty((H.n_segments, 1, 201), dtype=torch.complex128, device=dev)
+    out = {}
+    for name, call, M in (("hermitian_step", P.gpuqt_moments, 201), ("plain_recurrence", P.gpuqt_moments_plain, 101)):
+        call(H, phi, phi, M, mu=mu[:, :, :M].contiguous() if M != 201 else mu, ws=ws)
+        torch.cuda.synchronize()
+        P.gpuqt_set_timing(H, True)
+        for _ in range(3):
+            call(H, phi, phi, M, mu=mu, ws=ws) if M == 201 else call(H, phi, phi, M, ws=ws)
+        torch.cuda.synchronize()
+        P.gpuqt_set_timing(H, False)
+        fam = P.gpuqt_timing(H)
+        f = "moment_sym" if name == "hermitian_step" else "moment"
+        ms, nl = fam[f]
+        avg = ms / 1e3 / nl
+        b = family_bytes(H.info, 1, f)
+        out[name] = {"kernel": FAMILY_KERNEL[f], "B": 1, "launches": nl, "avg_us": avg * 1e6,
+                     "bytes_per_launch": b, "GBs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS,
+                     "variant": variant_text(H.info.kernel_variant, f),
+                     "traffic": measured_traffic("cubic_b1" if f == "moment_sym" else "cubic_b1_plain", f, b,
+                                                 H.info.kernel_variant)}
+    out["autotune_us"] = tune
+    out["from_cache"] = cached
+    del ws, phi, mu
+    return out
+
+
+def cubic_workload(args):
     import numpy as np
     import torch
 
@@ -210,103 +304,221 @@ def transport_workload(args, name):
     from paper_1705_01387_amd import inputs as I
 
     dev = torch.device("cuda:0")
-    n_vec = args.warmup + args.steps
-    if name == "honeycomb":
-        w = I.workload_honeycomb(n_vectors=n_vec)
-        m, dE, M, dts, B = w["model"], w["energy_max"], w["M"], w["dt"], 1
-        phis_np, do_vac = w["phis"], True
-        desc = ("honeycomb 1000x1000 cells (2,000,000 orbitals), Peierls flux 1/2000, W=2 eV; "
-                "per vector: DOS M=3000 + VAC and MSD 20 x 15 fs, M=3000")
-    else:
-        w = I.workload_cubic(L=200, W=16.0, B=4)
-        m, dE, M, dts, B = w["model"], w["energy_max"], w["M"], w["dt"], 4
-        phis_np = [I.random_phase(m.n, 4, 4100 + r) for r in range(n_vec)]
-        do_vac = False
-        desc = "cubic 200^3 (8,000,000 orbitals), W=16, block of 4 vectors; per block: DOS M=1000 + MSD 40 x dt=2, M=1000"
+    B, W, Np, M, dt = 4, 16.0, 60, 1000, 2.0
+    w = I.workload_cubic(L=200, W=W, B=B)
+    m, dE = w["model"], w["energy_max"]
     H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    phi = torch.from_numpy(w["phi"]).to(dev)
+    ws_m = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0),
+                           P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
+    ws_e = torch.empty(P.gpuqt_workspace_size(H, P.OP_EVOLVE_COMMUTATOR, B, 0, Np), dtype=torch.uint8,
+                       device=dev)
+    tune_us, cached = pick_variant(P, H, B, ws_m, args)
+    mu = torch.empty((1, B, M), dtype=torch.complex128, device=dev)
+    psi = [phi.clone(), torch.empty_like(phi)]
+    chi = [torch.zeros_like(phi), torch.empty_like(phi)]
+    state = {"i": 0}
+
+    def step():
+        i = state["i"]
+        P.gpuqt_evolve(H, psi[i], dt, Np, psi_out=psi[i ^ 1], chi=chi[i], chi_out=chi[i ^ 1], ws=ws_e)
+        P.gpuqt_moments(H, chi[i ^ 1], chi[i ^ 1], M, mu=mu, ws=ws_m)
+        state["i"] = i ^ 1
+
+    log("setup done (%d orbitals, B=%d, variant %d%s)" % (m.n, B, H.info.kernel_variant,
+                                                          " from the tuning cache" if cached else ""))
+    # the DOS moments of the block, once (warm) and timed
+    P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws_m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws_m)
+    torch.cuda.synchronize()
+    dos_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    P.gpuqt_set_timing(H, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.gpuqt_set_timing(H, False)
+    log("timed steps done")
+    fam = P.gpuqt_timing(H)
+    K = max(1, M // 2)
+    launched = (2 * (Np - 1) + K) * B               # per step: series terms (two chains) + moment steps
+    plain = (2 * (Np - 1) + (M - 1)) * B
+    kernels, dominant = kernel_table(H.info, B, fam, elapsed)
+    per_step = elapsed / args.steps
+    out = dict(value=launched * args.steps / elapsed, ms_per_step=per_step * 1e3,
+               config={"workload": "cubic 200^3 (8,000,000 orbitals, 6 neighbours, t=-1), Anderson W=16, "
+                                   "DeltaE=1.01*(6+W/2), block of 4 random-phase vectors; one step = one MSD "
+                                   "time step dt=2 (fused evolution + commutator series, 60 terms) + the "
+                                   "M=1000 moments of the new chi",
+                       "orbitals": int(m.n), "block": B, "moments": M, "terms_per_step": Np, "dt": dt,
+                       "launched_steps_per_step": launched, "plain_equivalent_steps_per_step": plain,
+                       "plain_equivalent_steps_per_s": plain * args.steps / elapsed,
+                       "dos_moments_s": dos_s, "full_block_calculation_s": dos_s + 40 * per_step,
+                       "steps_timed": args.steps, "variant_from_tuning_cache": cached,
+                       "autotune_us_per_step": tune_us},
+               roofline=roofline_of("cubic", H.info, B, kernels, dominant),
+               kernels=kernels)
+    del ws_m, ws_e, psi, chi, mu, phi
+    torch.cuda.empty_cache()
+    log("single-vector steps")
+    out["single_vector"] = single_vector_steps(P, torch, H, m.n, dev, args)
+    H.close()
+    out["roofline"]["copy_probe_GBs"] = copy_probe_gbs(P, torch, dev)
+    if not args.no_paper:
+        log("paper examples")
+        out["paper_examples"] = paper_examples(args, passes=1)
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline("cubic")
+    return out
+
+
+def honeycomb_workload(args, general=False):
+    import torch
+
+    import paper_1705_01387_amd as P
+    from paper_1705_01387_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    n_vec = args.warmup + args.steps
+    w = I.workload_honeycomb(n_vectors=n_vec)
+    m, dE, M, dts, B = w["model"], w["energy_max"], w["M"], w["dt"], 1
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE, no_dictionary=general)
     np_list = [P.gpuqt_auto_terms(dE * abs(t)) for t in dts]
-    phis = [torch.from_numpy(p).to(dev) for p in phis_np]
+    phis = [torch.from_numpy(p).to(dev) for p in w["phis"]]
     ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_VAC, B, M, max(np_list)),
                          P.gpuqt_workspace_size(H, P.OP_MSD, B, M, max(np_list)),
-                         P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0)),
-                     dtype=torch.uint8, device=dev)
-    tune_us = pick_variant(P, H, B, ws, args)          # untimed: pick the kernel variant
+                         P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0),
+                         P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
+    tune_us, cached = pick_variant(P, H, B, ws, args)
     mu = torch.empty((1, B, M), dtype=torch.complex128, device=dev)
     vac = torch.empty((len(dts), 1, B, M), dtype=torch.float64, device=dev)
     msd = torch.empty_like(vac)
 
     def one_step(phi):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
-        if do_vac:
-            P.gpuqt_vac(H, phi, dts, M, 0, out=vac, ws=ws)
+        P.gpuqt_vac(H, phi, dts, M, 0, out=vac, ws=ws)
         P.gpuqt_msd(H, phi, dts, M, 0, out=msd, ws=ws)
 
-    log("setup done (%d orbitals, B=%d)" % (m.n, B))
+    log("setup done (%d orbitals, hop mode %d)" % (m.n, H.info.hop_mode))
     for i in range(args.warmup):
         one_step(phis[i])
     torch.cuda.synchronize()
-    log("warmup done")
-    P.gpuqt_set_timing(H, True)       # HIP events around each run of one kernel family
+    P.gpuqt_set_timing(H, True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         one_step(phis[args.warmup + i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     P.gpuqt_set_timing(H, False)
-    log("timed steps done")
     fam = P.gpuqt_timing(H)
-
-    steps_per = count_steps(M, dts, np_list, do_vac, True) * B
-    applied_per = count_steps(M, dts, np_list, do_vac, True, applied=True) * B
+    K = max(1, M // 2)
+    n_t = len(dts)
+    launched = K + (1 + n_t * (1 + 2 * K) + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))) \
+        + (sum(2 * (np_list[k] - 1) for k in range(n_t)) + n_t * K)
+    plain = (M - 1) + (1 + n_t * M + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))) \
+        + (sum(2 * (np_list[k] - 1) for k in range(n_t)) + n_t * (M - 1))
     kernels, dominant = kernel_table(H.info, B, fam, elapsed)
-    d = kernels[dominant]
-    out = dict(value=steps_per * args.steps / elapsed, ms_per_step=elapsed / args.steps * 1e3,
-               config={"workload": desc + ", Np=auto (%d)" % np_list[0], "orbitals": int(m.n), "block": B,
-                       "moments": M, "time_steps": len(dts), "cheb_steps_per_step": steps_per,
-                       "launched_steps_per_step": applied_per,
-                       "launched_steps_per_s": applied_per * args.steps / elapsed,
-                       "steps_timed": args.steps},
-               roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": d["GBs"] / HBM_PEAK_GBS,
-                         "traffic": measured_traffic(name, dominant, d["bytes_per_launch"],
-                                                     H.info.kernel_variant),
-                         "kernel": "%s (B=%d, hop mode %d, K=%d, %s)"
-                                   % (FAMILY_KERNEL[dominant], B, H.info.hop_mode, H.info.uniform_width,
-                                      variant_text(H.info.kernel_variant, dominant)),
-                         "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
-                         "autotune_us_per_step": [float(t) for t in tune_us]},
+    # working set of the dominant launch: everything it streams
+    ws_bytes = kernels[dominant]["bytes_per_launch"]
+    bound = "llc" if ws_bytes <= LLC_BYTES else "hbm"
+    name = "honeycomb_general" if general else "honeycomb"
+    desc = ("honeycomb 1000x1000 cells (2,000,000 orbitals), Peierls flux 1/2000, W=2 eV, %s; per vector: "
+            "DOS M=3000 + VAC and MSD 20 x 15 fs, M=3000, Np=auto (%d)"
+            % ("hoppings stored per entry (complex128)" if general else "value-table layout", np_list[0]))
+    out = dict(value=launched * args.steps / elapsed, ms_per_step=elapsed / args.steps * 1e3,
+               config={"workload": desc, "orbitals": int(m.n), "block": B, "moments": M, "hop_mode": H.info.hop_mode,
+                       "time_steps": n_t, "launched_steps_per_step": launched,
+                       "plain_equivalent_steps_per_s": plain * args.steps / elapsed, "steps_timed": args.steps,
+                       "dominant_working_set_MB": ws_bytes / 1e6, "variant_from_tuning_cache": cached,
+                       "autotune_us_per_step": tune_us},
+               roofline=roofline_of(name, H.info, B, kernels, dominant, bound),
                kernels=kernels)
+    if bound == "llc":
+        out["roofline"]["note"] = ("the dominant launch streams %.0f MB, within the 256 MB last-level "
+                                   "cache: achieved bandwidth is not an HBM figure" % (ws_bytes / 1e6))
     del ws
     out["roofline"]["copy_probe_GBs"] = copy_probe_gbs(P, torch, dev)
-    out["cpu_baseline"] = None if args.no_cpu else cpu_oracle_sample(m, phis_np[0], dE, B, args.cpu_moments)
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline("honeycomb")
     return out
 
 
-KERNEL_SOURCES = ("device_common.h", "internal.h", "kernels.hip")   # what the moment step is built from
+def _graph_vs_eager(torch, fn, reps):
+    """Seconds per call of fn eagerly and as one captured HIP graph replay."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / reps
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / reps
+    return eager, graph
 
 
-def measured_traffic(name, family, bytes_launch, variant):
-    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
-    was taken on that kernel family and on the kernel source that is built now (else None).
-    The record names the kernel variant it was taken with (pinned by --variant); the
-    autotuner of this run may have chosen another one (variant_matches)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    src = os.path.join(ROOT, "paper_1705_01387_amd", "csrc")
-    h = hashlib.sha256()
-    for fn in KERNEL_SOURCES:
-        with open(os.path.join(src, fn), "rb") as g:
-            h.update(g.read())
-    e = rec.get(name)
-    if not e or e.get("kernel_source_sha256") != h.hexdigest() or e.get("family") != family:
-        return None
-    return {"bytes": e["bytes_per_launch"], "ratio_to_algorithmic": e["bytes_per_launch"] / bytes_launch,
-            "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"],
-            "variant": e.get("variant"), "variant_matches": e.get("variant") == int(variant)}
+def small_workload(args):
+    """Square 64 x 64 (4096 orbitals): DOS M=1000 + VAC and MSD over 10 steps of dt=1 (100 terms);
+    every launch is a few microseconds, so the launch path decides the rate: eager calls vs
+    the same calls captured once into a HIP graph and replayed."""
+    import torch
+
+    import paper_1705_01387_amd as P
+    from paper_1705_01387_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    w = I.workload_square64()
+    m, dE, M, dts, Np = w["model"], w["energy_max"], w["M"], list(w["dt"]), w["Np"]
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    B = 1
+    phi = torch.from_numpy(w["phi"]).to(dev)
+    ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_VAC, B, M, Np),
+                         P.gpuqt_workspace_size(H, P.OP_MSD, B, M, Np),
+                         P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
+    tune_us, cached = pick_variant(P, H, B, ws, args)
+    mu = torch.empty((1, B, M), dtype=torch.complex128, device=dev)
+    vac = torch.empty((len(dts), 1, B, M), dtype=torch.float64, device=dev)
+    msd = torch.empty_like(vac)
+
+    def calc():
+        P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
+        P.gpuqt_vac(H, phi, dts, M, Np, out=vac, ws=ws)
+        P.gpuqt_msd(H, phi, dts, M, Np, out=msd, ws=ws)
+
+    eager, graph = _graph_vs_eager(torch, calc, max(1, args.steps))
+    K = max(1, M // 2)
+    n_t = len(dts)
+    launched = K + (1 + n_t * (1 + 2 * K) + (n_t - 1) * 2 * (Np - 1)) + (n_t * 2 * (Np - 1) + n_t * K)
+    return dict(value=launched / graph, ms_per_step=graph * 1e3,
+                config={"workload": "square 64x64 (4096 orbitals), W=1, DeltaE=4.5, one vector: DOS M=1000 + VAC "
+                                    "and MSD over 10 steps of dt=1 with 100 terms; value from the graph replay",
+                        "orbitals": int(m.n), "launched_steps_per_step": launched, "steps_timed": args.steps,
+                        "variant_from_tuning_cache": cached},
+                graph_vs_eager={"eager_ms": eager * 1e3, "graph_ms": graph * 1e3, "speedup": eager / graph,
+                                "eager_steps_per_s": launched / eager, "graph_steps_per_s": launched / graph,
+                                "launches_per_step": launched + 2 * n_t + 1},
+                roofline=None, cpu_baseline=None)
 
 
 def batched_workload(args):
@@ -321,13 +533,16 @@ def batched_workload(args):
     mods, B, M = w["models"], w["B"], w["M"]
     cat = I.concat_segments(mods)
     offs = np.cumsum([0] + [mm.n for mm in mods])
-    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
-                        seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
-                        seg_length_x=[mm.length_x for mm in mods])
+
+    def build():
+        return P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                               seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
+                               seg_length_x=[mm.length_x for mm in mods])
+    H = build()
     phi = torch.from_numpy(w["phi"]).to(dev)
     ws = torch.empty(max(P.gpuqt_workspace_size(H, P.OP_MOMENTS, B, M, 0),
                          P.gpuqt_workspace_size(H, P.OP_AUTOTUNE, B, 0, 0)), dtype=torch.uint8, device=dev)
-    tune_us = pick_variant(P, H, B, ws, args)
+    tune_us, cached = pick_variant(P, H, B, ws, args)
     mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=dev)
     for _ in range(args.warmup):
         P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws)
@@ -340,14 +555,24 @@ def batched_workload(args):
     elapsed = time.perf_counter() - t0
     P.gpuqt_set_timing(H, False)
     kernels, dominant = kernel_table(H.info, B, P.gpuqt_timing(H), elapsed)
-    d = kernels[dominant]
+    eager, graph = _graph_vs_eager(torch, lambda: P.gpuqt_moments(H, phi, phi, M, mu=mu, ws=ws), 2)
+    K = max(1, M // 2)
+    value = B * K * args.steps / elapsed
+    out = dict(value=value, ms_per_step=elapsed / args.steps * 1e3,
+               config={"workload": "8 square realisations 200^2..2000^2 (8,255,182 orbitals), W_r in [0.5,3], "
+                                   "per-realisation DeltaE, block of 16 vectors, M=2000, one launch per step",
+                       "orbitals": int(H.n), "block": B, "moments": M, "segments": H.n_segments,
+                       "plain_equivalent_steps_per_s": B * (M - 1) * args.steps / elapsed,
+                       "steps_timed": args.steps, "variant_from_tuning_cache": cached,
+                       "autotune_us_per_step": tune_us},
+               roofline=roofline_of("batched", H.info, B, kernels, dominant), kernels=kernels,
+               graph_vs_eager={"eager_ms": eager * 1e3, "graph_ms": graph * 1e3, "speedup": eager / graph})
+    del ws
     # the same moments one vector at a time (B = 1): two vectors, same M
-    H1 = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
-                         seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
-                         seg_length_x=[mm.length_x for mm in mods])
+    H1 = build()
     ws1 = torch.empty(max(P.gpuqt_workspace_size(H1, P.OP_MOMENTS, 1, M, 0),
                           P.gpuqt_workspace_size(H1, P.OP_AUTOTUNE, 1, 0, 0)), dtype=torch.uint8, device=dev)
-    tune1 = P.gpuqt_autotune(H1, 1, ws=ws1)
+    pick_variant(P, H1, 1, ws1, args)
     v1 = [phi[:, b].contiguous() for b in range(2)]
     P.gpuqt_moments(H1, v1[0], v1[0], M, ws=ws1)
     torch.cuda.synchronize()
@@ -355,28 +580,11 @@ def batched_workload(args):
     for v in v1:
         P.gpuqt_moments(H1, v, v, M, ws=ws1)
     torch.cuda.synchronize()
-    plain_vs = 2 * (M - 1) / (time.perf_counter() - t1)
-    value = B * (M - 1) * args.steps / elapsed
-    return dict(value=value, ms_per_step=elapsed / args.steps * 1e3,
-                config={"workload": "8 square realisations 200^2..2000^2 (8,255,182 orbitals), W_r in [0.5,3], "
-                                    "per-realisation DeltaE, block of 16 vectors, M=2000, one launch per step",
-                        "orbitals": int(H.n), "block": B, "moments": M, "segments": H.n_segments,
-                        "steps_timed": args.steps},
-                roofline={"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": d["GBs"] / HBM_PEAK_GBS,
-                          "traffic": measured_traffic("batched", dominant, d["bytes_per_launch"],
-                                                      H.info.kernel_variant),
-                          "kernel": "%s (B=16, hop mode %d, K=%d, %s)"
-                                    % (FAMILY_KERNEL[dominant], H.info.hop_mode, H.info.uniform_width,
-                                       variant_text(H.info.kernel_variant, dominant)),
-                          "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
-                          "autotune_us_per_step": [float(t) for t in tune_us]},
-                kernels=kernels,
-                batched_vs_plain={"plain_vector_steps_per_s": plain_vs, "batched_vector_steps_per_s": value,
-                                  "speedup": value / plain_vs,
-                                  "plain_autotune_us": [float(t) for t in tune1]},
-                cpu_baseline=None if args.no_cpu else cpu_oracle_sample(
-                    cat, w["phi"][:, :1], float(np.max(w["seg_energy_max"])), 1, args.cpu_moments))
+    plain_vs = 2 * K / (time.perf_counter() - t1)
+    out["batched_vs_single"] = {"single_vector_steps_per_s": plain_vs, "batched_vector_steps_per_s": value,
+                                "speedup": value / plain_vs}
+    out["cpu_baseline"] = None
+    return out
 
 
 def train_workload(args):
@@ -398,7 +606,6 @@ def train_workload(args):
     gU = torch.zeros(m.n, dtype=torch.float64, device=dev)
     gC = torch.zeros(2, dtype=torch.float64, device=dev)
     np_list = [P.gpuqt_auto_terms(dE * abs(t)) for t in dts]
-    # the VAC forward keeps its states and moment chains (the tape) for the backward
     tape = torch.empty(P.gpuqt_vac_tape_size(H, 1, dts, M), dtype=torch.uint8, device=dev)
 
     def fwd():
@@ -422,21 +629,22 @@ def train_workload(args):
         bwd()
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
-    fwd_steps = count_steps(M, dts, np_list, True, False)   # forward steps served per (fwd + adjoint)
+    K = max(1, M // 2)
+    n_t = len(dts)
+    fwd_steps = K + 1 + n_t * (1 + 2 * K) + sum(2 * (np_list[k] - 1) for k in range(n_t - 1))
     return dict(value=fwd_steps / (tf + tb), ms_per_step=(tf + tb) * 1e3,
                 config={"workload": "square 512^2 (262,144 orbitals), NN + NNN hopping classes, DeltaE=6, "
                                     "DOS M=512 + VAC 10 x dt=1; forward + adjoint (all on-site and class "
-                                    "gradients; every forward vector kept, moment sets reversed in "
-                                    "the two-chain form, the VAC forward's states, moment and "
-                                    "evolution chains recorded for the adjoint)", "orbitals": int(m.n), "moments": M},
+                                    "gradients; VAC forward recorded for the adjoint)", "orbitals": int(m.n),
+                        "moments": M},
                 adjoint_vs_forward={"forward_ms": tf * 1e3, "adjoint_ms": tb * 1e3, "ratio": tb / tf},
                 roofline=None, cpu_baseline=None)
 
 
-def paper_workload(args):
-    """The paper's two examples end to end on resident inputs: moments, KPM sums on the
-    energy grid and running conductivities (the paper reports about 3 minutes for both on
-    a Tesla K40, input and output included)."""
+def paper_examples(args, passes=None):
+    """The paper's two examples end to end on resident inputs: moments, KPM sums on the energy
+    grid and running conductivities (the paper reports about 3 minutes for both on a Tesla
+    K40, input and output included)."""
     import torch
 
     import paper_1705_01387_amd as P
@@ -449,24 +657,21 @@ def paper_workload(args):
         m = w["model"]
         H = P.gpuqt_build_h_from_model(m, energy_max=w["energy_max"])
         B = w["phi"].shape[1]
-        np_list = [P.gpuqt_auto_terms(w["energy_max"] * abs(t)) for t in w["dt"]]
-        runs.append(dict(w=w, H=H, B=B, np_list=np_list, phi=torch.from_numpy(w["phi"]).to(dev),
-                         E=w["energies"]))
+        runs.append(dict(w=w, H=H, B=B, phi=torch.from_numpy(w["phi"]).to(dev), E=w["energies"]))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    log("setup done (%.1f s)" % setup_s)
     for r in runs:
-        P.gpuqt_autotune(r["H"], r["B"])
+        P.gpuqt_autotune_cached(r["H"], r["B"])
 
     def example(r):
         w, H, B, phi, E = r["w"], r["H"], r["B"], r["phi"], r["E"]
         dE, M, dts, vol = w["energy_max"], w["M"], w["dt"], float(w["model"].volume)
-        mu = P.gpuqt_moments(H, phi, phi, M)[0].real.contiguous()              # [B, M]
+        mu = P.gpuqt_moments(H, phi, phi, M)[0].real.contiguous()
         out = {"dos": P.gpuqt_kpm_reconstruct(mu, E, dE, vol)}
         for kind, call, mode in (("vac", P.gpuqt_vac, P.SIGMA_VAC), ("msd", P.gpuqt_msd, P.SIGMA_MSD)):
             if not w[kind]:
                 continue
-            c = call(H, phi, dts, M)[:, 0]                                      # [N_t, B, M]
+            c = call(H, phi, dts, M)[:, 0]
             rows = P.gpuqt_kpm_reconstruct(c.reshape(-1, M), E, dE, vol).reshape(len(dts), B, -1)
             out[kind] = rows
             out["sigma_" + kind] = [P.gpuqt_running_conductivity(mode, rows[:, b].contiguous(), dts)
@@ -476,63 +681,63 @@ def paper_workload(args):
     for r in runs:
         example(r)
     torch.cuda.synchronize()
-    log("warmup done")
+    n = passes if passes is not None else args.steps
     per = [0.0, 0.0]
-    for _ in range(args.steps):
+    for _ in range(n):
         for i, r in enumerate(runs):
             ta = time.perf_counter()
             example(r)
             torch.cuda.synchronize()
             per[i] += time.perf_counter() - ta
-    per = [p / args.steps for p in per]
-    steps = [count_steps(r["w"]["M"], r["w"]["dt"], r["np_list"], r["w"]["vac"], r["w"]["msd"]) * r["B"]
-             for r in runs]
-    total = sum(per)
-    return dict(value=sum(steps) / total, ms_per_step=total * 1e3,
-                config={"workload": "the paper's two examples (Section 5): 2000^2 square W=4, DeltaE=6.1, "
-                                    "M=1000, VAC+MSD 20 x 0.2, 601 energies, 1 vector; 4e6 chain W=4, "
-                                    "DeltaE=4.1, M=500, MSD over 30 non-uniform steps 0.1..100, 401 "
-                                    "energies, 2 vectors as one block; moments, KPM sums and running "
-                                    "conductivities", "orbitals": [int(r["H"].n) for r in runs],
-                        "cheb_steps_per_step": sum(steps), "steps_timed": args.steps},
-                paper_examples={"diffusive_s": per[0], "localized_s": per[1], "total_s": total,
-                                "setup_s": setup_s,
-                                "paper_k40_total_s_context": 180.0,
-                                "note": "the paper's about 3 minutes on a Tesla K40 includes reading "
-                                        "inputs and writing outputs; here inputs are resident"},
-                roofline=None, cpu_baseline=None)
+    per = [p / n for p in per]
+    for r in runs:
+        r["H"].close()
+    return {"diffusive_s": per[0], "localized_s": per[1], "total_s": sum(per), "setup_s": setup_s,
+            "passes": n, "paper_k40_total_s_context": 180.0,
+            "workload": "2000^2 square W=4, DeltaE=6.1, M=1000, VAC+MSD 20 x 0.2, 601 energies, 1 vector; "
+                        "4e6 chain W=4, DeltaE=4.1, M=500, MSD over 30 non-uniform steps 0.1..100, 401 "
+                        "energies, 2 vectors as one block",
+            "note": "the paper's about 3 minutes on a Tesla K40 include reading inputs and writing outputs; "
+                    "here inputs are resident"}
+
+
+def paper_workload(args):
+    r = paper_examples(args)
+    return dict(value=None, ms_per_step=r["total_s"] * 1e3,
+                config={"workload": "the paper's two examples (Section 5): " + r["workload"],
+                        "steps_timed": args.steps},
+                paper_examples=r, roofline=None, cpu_baseline=None)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="honeycomb",
-                    choices=["honeycomb", "cubic", "batched", "train", "paper"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cubic",
+                    choices=["cubic", "honeycomb", "honeycomb-general", "batched", "small", "train", "paper"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper examples on the default line")
     ap.add_argument("--variant", type=int, default=-1,
                     help="pin the kernel variant code of the timed handle instead of autotuning "
                          "(as gpuqt_h_info reports it: bits 0-1 load variant, 2-5 per-CU cap, 3 bits "
-                         "per kernel family from bit 8; honeycomb, cubic, batched)")
-    ap.add_argument("--cpu-moments", type=int, default=0,
-                    help="moments in the CPU oracle sample (0: sized to about 15 s)")
+                         "per kernel family from bit 8)")
+    ap.add_argument("--cpu-baseline", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline:
+        cpu_baseline_main(args.cpu_baseline)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the workload shards over random vectors "
                                    "and realisations with no communication, but only --gpus 1 is run"}))
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    if args.workload in ("honeycomb", "cubic"):
-        r = transport_workload(args, args.workload)
-    elif args.workload == "batched":
-        r = batched_workload(args)
-    elif args.workload == "paper":
-        r = paper_workload(args)
-    else:
-        r = train_workload(args)
-    out = {"metric": METRIC, "value": r.pop("value"), "unit": "Chebyshev H*psi steps/s", "n_gpus": 1,
+    fn = {"cubic": cubic_workload, "honeycomb": honeycomb_workload,
+          "honeycomb-general": lambda a: honeycomb_workload(a, general=True), "batched": batched_workload,
+          "small": small_workload, "train": train_workload, "paper": paper_workload}[args.workload]
+    r = fn(args)
+    out = {"metric": METRIC, "value": r.pop("value"), "unit": UNIT, "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
            "data": "synthetic"}

@@ -181,6 +181,17 @@ gpuqt_status gpuqt_moments(gpuqt_h h, int32_t B, const double *phiL, const doubl
                            int32_t M, double *mu, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * The same moments as gpuqt_moments by the one-moment-per-step recurrence of Sections 3.2-3.3
+ * as the paper runs it: v_0 = phiR, v_1 = H~ v_0, v_k = 2 H~ v_{k-1} - v_{k-2}, mu_k = <phiL|v_k>,
+ * M - 1 sparse steps whatever phiL and phiR are (gpuqt_moments needs about M/2 steps through
+ * the product identities).  Same arguments, layouts, workspace (GPUQT_OP_MOMENTS) and errors
+ * as gpuqt_moments; the fixed reduction order makes reruns bit-identical.  For comparisons
+ * with the product-identity forms and for timing the single Chebyshev step.
+ */
+gpuqt_status gpuqt_moments_plain(gpuqt_h h, int32_t B, const double *phiL, const double *phiR,
+                                 int32_t M, double *mu, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Time evolution by the Chebyshev-Bessel series of Section 3.2:
  *   psi_out = U(dt) psi_in,  U(dt) = exp(-i H dt) for dt > 0 and exp(+i H |dt|) for dt < 0,
  *   U(+-dt) psi = sum_{m<Np} (2 - delta_m0) (-+i)^m J_m(DeltaE_s |dt|) T_m(H~) psi.
@@ -359,6 +370,52 @@ gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, voi
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*
+ * Tuning cache (process-wide, thread-safe).  A kernel variant measured by gpuqt_autotune is
+ * kept under a key of everything the choice depends on: the device architecture, the
+ * orbital count (log2 bucket), the row structure (fixed width K or widest slice, slice
+ * height), the hopping storage, the segment count, the row period (log2 bucket), which
+ * block widths have a banded row order, and B (gpuqt_tune_cache_key writes it, at most
+ * len bytes with the terminating NUL).
+ * gpuqt_autotune_cached applies the cached code for the handle's key, or runs
+ * gpuqt_autotune (same arguments) and caches its choice; *from_cache (may be NULL) tells
+ * which.  A cached code leaves times_us zero and needs no workspace (ws may be NULL then).
+ * gpuqt_tune_cache_load merges a text file of "<key>TAB<code>" lines ('#' starts a
+ * comment line; GPUQT_ERR_ARG if it cannot be opened, GPUQT_ERR_LAYOUT with file:line for a
+ * malformed line, nothing merged then); gpuqt_tune_cache_save writes every entry.
+ */
+gpuqt_status gpuqt_tune_cache_key(gpuqt_h h, int32_t B, char *buf, size_t len);
+gpuqt_status gpuqt_autotune_cached(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
+                                   double *times_us, int32_t *from_cache);
+gpuqt_status gpuqt_tune_cache_load(const char *path);
+gpuqt_status gpuqt_tune_cache_save(const char *path);
+void gpuqt_tune_cache_clear(void);
+
+/*
+ * Block width for n_vectors independent random vectors (Section 4.2.7: the random vectors
+ * are independent, so they may be advanced in blocks of B columns sharing each matrix read):
+ * for every B in {1, 2, 4, 8, 16} with B <= n_vectors whose autotuning workspace
+ * (gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0)) fits in ws_bytes, autotunes the
+ * handle at B (caching each choice) and measures the Hermitian moment step; writes the B
+ * with the least time per vector and step to *best_B, the microseconds per vector-step of
+ * each width to us_per_vector_step (HOST [5], index log2 B, 0 where not tried; may be NULL),
+ * and leaves the handle tuned for best_B.  Synchronises the stream.
+ */
+gpuqt_status gpuqt_autotune_block(gpuqt_h h, int32_t n_vectors, void *ws, size_t ws_bytes, void *stream,
+                                  int32_t *best_B, double *us_per_vector_step);
+
+/*
+ * gpuqt_build_h with the sliced-ELL slice height chosen by measurement: the layout of desc
+ * (its slice_height ignored) is built at heights 32, 64, 128 and 256, each autotuned at
+ * block width B (allocating and freeing its own autotuning workspace), and the handle whose
+ * Hermitian moment step is fastest is returned in *out (the others are destroyed).
+ * *slice_height (may be NULL) receives its height, us_per_step (HOST [4] or NULL) the best
+ * microseconds per step at each height.  Errors as gpuqt_build_h, plus GPUQT_ERR_NOMEM when
+ * a workspace cannot be allocated.
+ */
+gpuqt_status gpuqt_build_h_tuned(const gpuqt_h_desc *desc, int32_t B, void *stream, gpuqt_h *out,
+                                 int32_t *slice_height, double *us_per_step);
+
+/*
  * KPM reconstruction (Section 3.3, same prefactor for DOS, rho*C_vv, rho*DeltaX^2):
  *   out[r][e] = 2 / (pi Omega DeltaE sqrt(1 - E~^2)) sum_{n<M} g_n (2 - delta_n0) T_n(E~) C[r][n],
  *   E~ = energies[e] / DeltaE, g_n the Jackson damping (jackson != 0) or 1.
@@ -485,8 +542,11 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t *seg_offsets,
  * a = 1/(M+1).  g: HOST [M]. */
 gpuqt_status gpuqt_jackson(int32_t M, double *g);
 
-/* Bessel functions of the first kind J_m(tau), m < Np, tau >= 0 (Miller's backward
- * recurrence normalised by J_0 + 2 sum_k J_2k = 1).  J: HOST [Np]. */
+/* Bessel functions of the first kind J_m(tau), m < Np, tau >= 0: the coefficients of the
+ * Chebyshev expansion of the evolution operator, U(dt) = sum_m (2 - delta_m0) (-i)^m
+ * J_m(DeltaE dt) T_m(H~) (Section 3.2, the first Chebyshev expansion), evaluated by Miller's
+ * backward recurrence normalised by J_0 + 2 sum_k J_2k = 1.  J: HOST [Np].
+ * GPUQT_ERR_ARG for tau < 0 or not finite, Np < 0, or J NULL with Np > 0. */
 gpuqt_status gpuqt_bessel(double tau, int32_t Np, double *J);
 
 /* Number of Chebyshev terms for U(dt): the smallest m > tau with |J_m(tau)| < 1e-16,

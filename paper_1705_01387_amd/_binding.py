@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpuqt.so")
 
 GPUQT_OK = 0
+GPUQT_ERR_WORKSPACE = 4
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_LAYOUT", 3: "ERR_SPECTRUM", 4: "ERR_WORKSPACE",
                 5: "ERR_HIP", 6: "ERR_NOMEM", 7: "ERR_UNSUPPORTED"}
 OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD, OP_AUTOTUNE = range(7)
@@ -73,6 +74,9 @@ _SIGS = {
     "gpuqt_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_moments": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p]),
+    "gpuqt_moments_plain": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p]),
     "gpuqt_evolve": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
@@ -141,7 +145,20 @@ _SIGS = {
                                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_tune_cache_key": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
+    "gpuqt_autotune_cached": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "gpuqt_tune_cache_load": (ctypes.c_int32, [ctypes.c_char_p]),
+    "gpuqt_tune_cache_save": (ctypes.c_int32, [ctypes.c_char_p]),
+    "gpuqt_tune_cache_clear": (None, []),
+    "gpuqt_autotune_block": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "gpuqt_build_h_tuned": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
 }
+
+# kernel variants measured on the MI355X for the workloads of this package (see gpuqt_autotune_cached)
+TUNE_CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.tsv")
 
 
 def lib():
@@ -156,6 +173,8 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if os.path.exists(TUNE_CACHE_PATH) and L.gpuqt_tune_cache_load(os.fsencode(TUNE_CACHE_PATH)) != GPUQT_OK:
+            raise RuntimeError(f"{TUNE_CACHE_PATH}: {L.gpuqt_last_error().decode()}")
         _lib = L
     return _lib
 
@@ -174,8 +193,9 @@ def _ptr(a) -> Optional[int]:
 
 
 def _stream(stream):
+    """The raw hipStream_t of a torch stream, of a raw handle, or of torch's current stream."""
     if stream is not None:
-        return stream
+        return getattr(stream, "cuda_stream", stream)
     import torch
     return torch.cuda.current_stream().cuda_stream
 
@@ -263,8 +283,11 @@ class Hamiltonian:
 def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1.0,
                   energy_max=0.0, hop_class=None, n_class=1, seg_offsets=None,
                   seg_energy_max=None, seg_length_x=None, check_hermitian=False,
-                  slice_height=0, band_rows=0, no_dictionary=False, stream=None) -> Hamiltonian:
-    """Build the device layout of H from a neighbour list (the paper's input files)."""
+                  slice_height=0, band_rows=0, no_dictionary=False, tune_block=0,
+                  stream=None) -> Hamiltonian:
+    """Build the device layout of H from a neighbour list (the paper's input files).
+    tune_block > 0: choose the slice height by measurement at that block width
+    (gpuqt_build_h_tuned; the result's slice_tuning holds the height and the times)."""
     nn = np.ascontiguousarray(nn, dtype=np.int32)
     n = nn.shape[0]
     nbr = np.ascontiguousarray(nbr, dtype=np.int32).reshape(n, -1)
@@ -319,8 +342,22 @@ def gpuqt_build_h(nn, nbr, hop=None, onsite=None, x=None, length_x=0.0, volume=1
     d.band_rows = int(band_rows)
     d.no_dictionary = 1 if no_dictionary else 0
     out = ctypes.c_void_p()
+    if tune_block:
+        S = ctypes.c_int32()
+        us = np.zeros(4)
+        _check(lib().gpuqt_build_h_tuned(ctypes.byref(d), int(tune_block), _stream(stream) if stream else None,
+                                         ctypes.byref(out), ctypes.byref(S), _ptr(us)), "gpuqt_build_h_tuned")
+        H = Hamiltonian(out.value, None)
+        H.slice_tuning = {"slice_height": int(S.value), "us_per_step": dict(zip((32, 64, 128, 256), us.tolist()))}
+        return H
     _check(lib().gpuqt_build_h(ctypes.byref(d), stream, ctypes.byref(out)), "gpuqt_build_h")
     return Hamiltonian(out.value, None)
+
+
+def gpuqt_build_h_tuned(*args, B: int = 1, **kw) -> Hamiltonian:
+    """gpuqt_build_h with the slice height chosen by measurement at block width B."""
+    kw["tune_block"] = int(B)
+    return gpuqt_build_h(*args, **kw)
 
 
 def gpuqt_build_h_from_model(m, energy_max=0.0, **kw) -> Hamiltonian:
@@ -335,11 +372,29 @@ def gpuqt_workspace_size(H: Hamiltonian, op: int, B: int, M: int = 0, Np: int = 
     return int(out.value)
 
 
-def _workspace(H, op, B, M, Np, ws):
+def _scratch(nbytes, like, stream):
+    """A uint8 device buffer of nbytes on the device of `like`.  When the call runs on a stream
+    other than torch's current one, the buffer is recorded on that stream, so the caching
+    allocator does not hand its memory out again before the enqueued kernels have finished."""
+    import torch
+    ws = torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=like.device)
+    if stream is not None:
+        with torch.cuda.device(like.device):
+            raw = _stream(stream)
+            if raw != torch.cuda.current_stream().cuda_stream:
+                ts = stream if isinstance(stream, torch.cuda.Stream) else \
+                    torch.cuda.ExternalStream(raw, device=like.device)
+                ws.record_stream(ts)
+    return ws
+
+
+def _workspace(H, op, B, M, Np, ws, like=None, stream=None):
     import torch
     need = gpuqt_workspace_size(H, op, B, M, Np)
     if ws is None:
-        ws = torch.empty(max(need, 16), dtype=torch.uint8, device="cuda")
+        if like is None:
+            like = torch.empty(0, device=torch.device("cuda", torch.cuda.current_device()))
+        ws = _scratch(need, like, stream)
     return ws, int(ws.numel() * ws.element_size())
 
 
@@ -355,9 +410,23 @@ def gpuqt_moments(H: Hamiltonian, phiL, phiR, M: int, mu=None, ws=None, stream=N
     B = _cols(phiR)
     if mu is None:
         mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=phiR.device)
-    ws, nb = _workspace(H, OP_MOMENTS, B, M, 0, ws)
+    ws, nb = _workspace(H, OP_MOMENTS, B, M, 0, ws, phiR, stream)
     _check(lib().gpuqt_moments(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(mu), _ptr(ws), nb,
                                _stream(stream)), "gpuqt_moments")
+    return mu
+
+
+def gpuqt_moments_plain(H: Hamiltonian, phiL, phiR, M: int, mu=None, ws=None, stream=None):
+    """gpuqt_moments by the one-moment-per-step recurrence (M - 1 sparse steps)."""
+    import torch
+    _dev_vec(phiL, "phiL")
+    _dev_vec(phiR, "phiR")
+    B = _cols(phiR)
+    if mu is None:
+        mu = torch.empty((H.n_segments, B, M), dtype=torch.complex128, device=phiR.device)
+    ws, nb = _workspace(H, OP_MOMENTS, B, M, 0, ws, phiR, stream)
+    _check(lib().gpuqt_moments_plain(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(mu), _ptr(ws), nb,
+                                     _stream(stream)), "gpuqt_moments_plain")
     return mu
 
 
@@ -376,7 +445,7 @@ def gpuqt_evolve(H: Hamiltonian, psi, dt: float, Np: int = 0, psi_out=None, chi=
         Np_ws = max(gpuqt_auto_terms(e * abs(dt)) for e in H.energy_max)
     else:
         Np_ws = Np
-    ws, nb = _workspace(H, op, B, 0, Np_ws, ws)
+    ws, nb = _workspace(H, op, B, 0, Np_ws, ws, psi, stream)
     _check(lib().gpuqt_evolve(H.handle, B, float(dt), Np, _ptr(psi), _ptr(psi_out), _ptr(chi),
                               _ptr(chi_out), _ptr(ws), nb, _stream(stream)), "gpuqt_evolve")
     return (psi_out, chi_out) if chi_out is not None else psi_out
@@ -405,7 +474,7 @@ def _series(fn, name, op, H, phi, dt, M, Np, out, ws, stream):
         Np_ws = max([1] + [gpuqt_auto_terms(e * abs(t)) for e in H.energy_max for t in dt])
     else:
         Np_ws = Np
-    ws, nb = _workspace(H, op, B, M, Np_ws, ws)
+    ws, nb = _workspace(H, op, B, M, Np_ws, ws, phi, stream)
     _check(fn(H.handle, B, _ptr(phi), n_t, _ptr(dt), M, Np, _ptr(out), _ptr(ws), nb, _stream(stream)), name)
     return out
 
@@ -517,7 +586,7 @@ def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phiR.device)
     lam0 = torch.empty_like(phiR) if want_lam0 else None
-    ws, nb = _workspace(H, OP_MOMENTS_BACKWARD, B, M, ckpt_stride, ws)
+    ws, nb = _workspace(H, OP_MOMENTS_BACKWARD, B, M, ckpt_stride, ws, phiR, stream)
     _check(lib().gpuqt_moments_backward(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(w),
                                         _ptr(grad_onsite), _ptr(grad_class), _ptr(lam0), ckpt_stride,
                                         _ptr(ws), nb, _stream(stream)), "gpuqt_moments_backward")
@@ -580,8 +649,7 @@ def gpuqt_vac_backward_tape(H: Hamiltonian, phi, dt, w, tape, grad_onsite=None, 
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
     if ws is None:
-        ws = torch.empty(max(gpuqt_vac_backward_tape_workspace_size(H, B, dt, M, Np), 16), dtype=torch.uint8,
-                         device=phi.device)
+        ws = _scratch(gpuqt_vac_backward_tape_workspace_size(H, B, dt, M, Np), phi, stream)
     nb = int(ws.numel() * ws.element_size())
     tb = int(tape.numel() * tape.element_size())
     _check(lib().gpuqt_vac_backward_tape(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
@@ -614,8 +682,7 @@ def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
     if ws is None:
-        ws = torch.empty(max(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride), 16),
-                         dtype=torch.uint8, device=phi.device)
+        ws = _scratch(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride), phi, stream)
     nb = int(ws.numel() * ws.element_size())
     _check(lib().gpuqt_vac_backward(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
                                     _ptr(grad_onsite), _ptr(grad_class), int(ckpt_stride), _ptr(ws), nb,
@@ -691,6 +758,68 @@ def gpuqt_set_variant(H: Hamiltonian, variant: int):
     info = HInfo()
     _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")
     H.info = info
+
+
+def _refresh_info(H: Hamiltonian):
+    info = HInfo()
+    _check(lib().gpuqt_h_info(H.handle, ctypes.byref(info), None, None), "gpuqt_h_info")
+    H.info = info
+
+
+def gpuqt_tune_cache_key(H: Hamiltonian, B: int) -> str:
+    """The configuration key under which variants for H at block width B are cached."""
+    buf = ctypes.create_string_buffer(256)
+    _check(lib().gpuqt_tune_cache_key(H.handle, int(B), buf, 256), "gpuqt_tune_cache_key")
+    return buf.value.decode()
+
+
+def gpuqt_autotune_cached(H: Hamiltonian, B: int = 1, ws=None, stream=None):
+    """The cached variant for H's configuration at B, or gpuqt_autotune (then cached).  The
+    autotuning workspace is only allocated on a miss.  Returns (times per load variant,
+    whether the choice came from the cache)."""
+    t = np.zeros(4)
+    hit = ctypes.c_int32()
+    if ws is None:
+        st = lib().gpuqt_autotune_cached(H.handle, int(B), None, 0, _stream(stream), _ptr(t), ctypes.byref(hit))
+        if st == GPUQT_ERR_WORKSPACE:
+            ws, _ = _workspace(H, OP_AUTOTUNE, B, 0, 0, None, None, stream)
+        else:
+            _check(st, "gpuqt_autotune_cached")
+            _refresh_info(H)
+            return t, bool(hit.value)
+    nb = int(ws.numel() * ws.element_size())
+    _check(lib().gpuqt_autotune_cached(H.handle, int(B), _ptr(ws), nb, _stream(stream), _ptr(t),
+                                       ctypes.byref(hit)), "gpuqt_autotune_cached")
+    _refresh_info(H)
+    return t, bool(hit.value)
+
+
+def gpuqt_tune_cache_load(path):
+    _check(lib().gpuqt_tune_cache_load(os.fsencode(str(path))), "gpuqt_tune_cache_load")
+
+
+def gpuqt_tune_cache_save(path):
+    _check(lib().gpuqt_tune_cache_save(os.fsencode(str(path))), "gpuqt_tune_cache_save")
+
+
+def gpuqt_tune_cache_clear():
+    lib().gpuqt_tune_cache_clear()
+
+
+def gpuqt_autotune_block(H: Hamiltonian, n_vectors: int, max_B: int = 16, ws=None, stream=None):
+    """Block width for n_vectors random vectors by measurement: (best B, microseconds per vector
+    and Hermitian moment step for B = 1, 2, 4, 8, 16; 0 where not tried).  The workspace (the
+    autotuning workspace of the widest block tried, max_B) bounds the widths tried."""
+    B = 1
+    while B * 2 <= min(max_B, n_vectors, 16):
+        B *= 2
+    ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws, None, stream)
+    best = ctypes.c_int32()
+    us = np.zeros(5)
+    _check(lib().gpuqt_autotune_block(H.handle, int(n_vectors), _ptr(ws), nb, _stream(stream), ctypes.byref(best),
+                                      _ptr(us)), "gpuqt_autotune_block")
+    _refresh_info(H)
+    return int(best.value), us
 
 
 def gpuqt_schedule_rows(seg_offsets, period=None, band_rows=0, cus=256, B=1):

@@ -920,6 +920,33 @@ gpuqt_status gpuqt_moments(gpuqt_h hh, int32_t B, const double* phiL, const doub
   return GPUQT_OK;
 }
 
+gpuqt_status gpuqt_moments_plain(gpuqt_h hh, int32_t B, const double* phiL, const double* phiR, int32_t M,
+                                 double* mu, void* ws, size_t ws_bytes, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
+  if (M < 0) return fail(GPUQT_ERR_ARG, "M must be >= 0");
+  if (M == 0) return GPUQT_OK;
+  gpuqt_status st;
+  if ((st = check_vec(phiL, "phiL")) || (st = check_vec(phiR, "phiR")) || (st = check_vec(mu, "mu")))
+    return st;
+  const WsLayout W = ws_layout(h, 4, B, moment_rows(M), 0);
+  if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
+  if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
+  if ((st = check_device(h))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double2* A = reinterpret_cast<double2*>(base);
+  double2* Bf = reinterpret_cast<double2*>(base + W.vec_bytes);
+  double2* part = reinterpret_cast<double2*>(base + W.off_part);
+  if ((st = run_moments(h, B, reinterpret_cast<const double2*>(phiL), reinterpret_cast<const double2*>(phiR), M,
+                        part, A, Bf, s)))
+    return st;
+  HIP_TRY(launch_reduce_moments(part, M, h->G_of(B, FAM_MOMENT), B, h->n_seg, h->blk0_of(B, FAM_MOMENT), 0,
+                                reinterpret_cast<double2*>(mu), nullptr, s));
+  return GPUQT_OK;
+}
+
 gpuqt_status gpuqt_evolve(gpuqt_h hh, int32_t B, double dt, int32_t Np, const double* psi_in,
                           double* psi_out, const double* chi_in, double* chi_out, void* ws,
                           size_t ws_bytes, void* stream) {
