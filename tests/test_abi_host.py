@@ -128,3 +128,45 @@ def test_ctypes_mirrors_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(mirror)
         for f, _ in mirror._fields_:
             assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)
+
+
+def test_tune_cache_file_format(tmp_path):
+    """The tuning cache file: '<key>TAB<code>' lines and '#' comments; a missing file is an
+    argument error, a malformed line a layout error naming file:line with nothing merged,
+    and a saved cache reloads to the same entries."""
+    P.lib()
+    try:
+        P.gpuqt_tune_cache_clear()
+        with pytest.raises(P.GpuqtError) as e:
+            P.gpuqt_tune_cache_load(tmp_path / "missing.tsv")
+        assert e.value.status == 1
+        bad = tmp_path / "bad.tsv"
+        bad.write_text("# comment\ngfx950 n10 K4 B1\t12\ngfx950 n11 K4 B1 no-code\n")
+        with pytest.raises(P.GpuqtError) as e:
+            P.gpuqt_tune_cache_load(bad)
+        assert e.value.status == 2 and "bad.tsv:3" in str(e.value)
+        empty = tmp_path / "empty.tsv"
+        P.gpuqt_tune_cache_save(empty)
+        assert [ln for ln in empty.read_text().splitlines() if not ln.startswith("#")] == []
+        good = tmp_path / "good.tsv"
+        good.write_text("# comment\ngfx950 n10 K4 w4 S64 h0 s1 p5 m0 B1\t12\ngfx950 n11 K4 w4 S64 h0 s1 p5 m0 B2\t77\n")
+        P.gpuqt_tune_cache_load(good)
+        out = tmp_path / "out.tsv"
+        P.gpuqt_tune_cache_save(out)
+        lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+        assert lines == ["gfx950 n10 K4 w4 S64 h0 s1 p5 m0 B1\t12", "gfx950 n11 K4 w4 S64 h0 s1 p5 m0 B2\t77"]
+    finally:
+        P.gpuqt_tune_cache_clear()
+        P.gpuqt_tune_cache_load(P.TUNE_CACHE_PATH)
+
+
+def test_committed_tune_cache_is_well_formed():
+    """The package's cache of MI355X choices: every line a gfx950 key and a variant code that
+    gpuqt_set_variant accepts (load variant, a per-CU cap of at most 8, family caps)."""
+    lines = [ln for ln in open(P.TUNE_CACHE_PATH).read().splitlines() if ln and not ln.startswith("#")]
+    assert lines
+    for ln in lines:
+        key, code = ln.split("\t")
+        code = int(code)
+        assert key.startswith("gfx950 ") and key.split()[-1].startswith("B")
+        assert ((code >> 2) & 15) <= 8 and (code >> 6) & 3 == 0 and code >> (8 + 18) == 0
