@@ -181,6 +181,22 @@ gpuqt_status gpuqt_moments(gpuqt_h h, int32_t B, const double *phiL, const doubl
                            int32_t M, double *mu, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): gpuqt_moments with its workspace in a fixed array
+ * the library holds on every GPU it runs on (gpuqt_noalloc_scratch_bytes() bytes, 64 MiB), so
+ * the call allocates nothing.  Same arguments, layouts and results as gpuqt_moments (bit for
+ * bit under the same kernel variant), without ws / ws_bytes; GPUQT_ERR_WORKSPACE when
+ * gpuqt_workspace_size(h, GPUQT_OP_MOMENTS, B, M, 0) exceeds the array (for B = 1, about
+ * 4 x 16 n bytes plus the per-workgroup partials: n up to about 10^6).  All calls on one GPU
+ * share that GPU's array: calls that overlap in time on one GPU (other streams, threads or
+ * handles) race and must be serialised by the caller.  Nothing in the array needs to start
+ * at zero; it keeps the last call's contents.
+ */
+gpuqt_status gpuqt_moments_noalloc(gpuqt_h h, int32_t B, const double *phiL, const double *phiR,
+                                   int32_t M, double *mu, void *stream);
+size_t gpuqt_noalloc_scratch_bytes(void);
+
+/*
  * The same moments as gpuqt_moments by the one-moment-per-step recurrence of Sections 3.2-3.3
  * as the paper runs it: v_0 = phiR, v_1 = H~ v_0, v_k = 2 H~ v_{k-1} - v_{k-2}, mu_k = <phiL|v_k>,
  * M - 1 sparse steps whatever phiL and phiR are (gpuqt_moments needs about M/2 steps through

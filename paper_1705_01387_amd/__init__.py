@@ -8,7 +8,7 @@ from ._binding import (  # noqa: F401
     GpuqtError, Hamiltonian, HInfo, LIB_PATH, lib,
     OP_MOMENTS, OP_EVOLVE, OP_EVOLVE_COMMUTATOR, OP_VAC, OP_MSD, OP_MOMENTS_BACKWARD, OP_AUTOTUNE,
     VELOCITY, COMMUTATOR_XH,
-    gpuqt_build_h, gpuqt_build_h_from_model, gpuqt_workspace_size, gpuqt_moments, gpuqt_moments_plain,
+    gpuqt_build_h, gpuqt_build_h_from_model, gpuqt_workspace_size, gpuqt_moments, gpuqt_moments_plain, gpuqt_moments_noalloc, gpuqt_noalloc_scratch_bytes,
     gpuqt_evolve, gpuqt_apply_commutator, gpuqt_vac, gpuqt_msd, gpuqt_kpm_reconstruct,
     gpuqt_jackson, gpuqt_bessel, gpuqt_auto_terms, gpuqt_last_error, gpuqt_copy_probe,
     gpuqt_autotune, gpuqt_moments_backward, gpuqt_vac_backward, gpuqt_vac_backward_workspace_size,

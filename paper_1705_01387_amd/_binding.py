@@ -145,6 +145,9 @@ _SIGS = {
                                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_moments_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpuqt_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "gpuqt_tune_cache_key": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
     "gpuqt_autotune_cached": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
@@ -428,6 +431,21 @@ def gpuqt_moments_plain(H: Hamiltonian, phiL, phiR, M: int, mu=None, ws=None, st
     _check(lib().gpuqt_moments_plain(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(mu), _ptr(ws), nb,
                                      _stream(stream)), "gpuqt_moments_plain")
     return mu
+
+
+def gpuqt_moments_noalloc(H: Hamiltonian, phiL, phiR, M: int, mu, stream=None):
+    """gpuqt_moments with the library's fixed per-GPU workspace: the C call allocates nothing
+    (mu, complex128 [n_seg, B, M] on the GPU, must be given).  Calls that overlap on one GPU
+    race; the workspace limit is gpuqt_noalloc_scratch_bytes()."""
+    _dev_vec(phiL, "phiL")
+    _dev_vec(phiR, "phiR")
+    _check(lib().gpuqt_moments_noalloc(H.handle, _cols(phiR), _ptr(phiL), _ptr(phiR), int(M), _ptr(mu),
+                                       _stream(stream)), "gpuqt_moments_noalloc")
+    return mu
+
+
+def gpuqt_noalloc_scratch_bytes() -> int:
+    return int(lib().gpuqt_noalloc_scratch_bytes())
 
 
 def gpuqt_evolve(H: Hamiltonian, psi, dt: float, Np: int = 0, psi_out=None, chi=None,

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgpuqt.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "kernels_adjoint.hip", "api.cpp", "layout.cpp", "io.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "kernels_adjoint.hip", "api.cpp", "layout.cpp", "io.cpp", "tune.cpp", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
