@@ -293,28 +293,33 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h h, int32_t B, const double *phiL, co
  * with DeltaE held fixed, with respect to the on-site energies (grad_onsite[i] += dL/dU_i)
  * and the hopping classes (grad_class[c] += dL/deps_c, H_ij -> (1 + eps_c) H_ij; this also
  * scales the velocity V = i[H, X] on those bonds).
- * Method: the forward VAC series with every state psi_L(t_k), psi_R(t_k) kept, then the
- * reverse over the rows: per row the adjoints of both moment arguments (as
- * gpuqt_moments_backward), back through phi_L = V psi_L (V is Hermitian), and back
- * through each evolution U(-dt) = sum_m c_m T_m(H~) by the reverse recurrence with
- * sources conj(c_m) g, whose lam_0 is U(+dt) g.
+ * Method: the forward VAC series (the states psi_L(t_k), psi_R(t_k) advanced by
+ * U(-dt_k), Section 3.2), then the reverse over the rows: per row the adjoints of both
+ * moment arguments (as gpuqt_moments_backward), back through phi_L = V psi_L (V is
+ * Hermitian), and back through each evolution U(-dt) = sum_m c_m T_m(H~) by the reverse
+ * recurrence with sources conj(c_m) g, whose lam_0 is U(+dt) g.
  *   ckpt_stride 0: the moment and evolution reverses recompute forward vectors from
  *   checkpoints every ceil(sqrt(L)) steps (L = max(M, Np)); 1: every forward vector is
  *   kept and each row's moments are reversed in the two-chain form (one pass gives both
  *   adjoints and the parameter terms); needs about L vectors more workspace.
+ *   time_stride 1: every state psi_L(t_k), psi_R(t_k) is kept (2 n_t - 1 vectors);
+ *   s >= 2: only the states of rows 0, s, 2s, ... are kept and each segment of s rows is
+ *   re-evolved from its checkpoint when the reverse reaches it (2 ceil(n_t / s) - 1 +
+ *   2 (s - 1) vectors, one more forward evolution of every step); 0: s = ceil(sqrt(n_t))
+ *   (1 when that is n_t).  The gradients agree to rounding whatever the strides.
  *   phi : c128 [n][B];  dt : HOST [n_t];  w : double [n_t][n_segments][B][M];
  *   grad_onsite : double [n];  grad_class : double [n_class] or NULL (at most 4 classes).
- *   Workspace: gpuqt_vac_backward_workspace_size with the same ckpt_stride.
+ *   Workspace: gpuqt_vac_backward_workspace_size with the same strides.
  */
 gpuqt_status gpuqt_vac_backward(gpuqt_h h, int32_t B, const double *phi, int32_t n_t,
                                 const double *dt, int32_t M, int32_t Np, const double *w,
                                 double *grad_onsite, double *grad_class, int32_t ckpt_stride,
-                                void *ws, size_t ws_bytes, void *stream);
+                                int32_t time_stride, void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes of gpuqt_vac_backward (dt: HOST [n_t], needed for the automatic Np). */
 gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t, const double *dt,
                                                int32_t M, int32_t Np, int32_t ckpt_stride,
-                                               size_t *bytes);
+                                               int32_t time_stride, size_t *bytes);
 
 /*
  * Recorded VAC forward, for a backward pass that recomputes nothing (the

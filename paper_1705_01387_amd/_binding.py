@@ -105,11 +105,12 @@ _SIGS = {
                                                 ctypes.c_void_p]),
     "gpuqt_vac_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_size_t, ctypes.c_void_p]),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+                                                           ctypes.c_int32, ctypes.c_int32,
+                                                           ctypes.POINTER(ctypes.c_size_t)]),
     "gpuqt_transport_lengths": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 11),
     "gpuqt_vac_tape_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -612,11 +613,12 @@ def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad
 
 
 def gpuqt_vac_backward_workspace_size(H: Hamiltonian, B: int, dt, M: int, Np: int = 0,
-                                      ckpt_stride: int = 0) -> int:
+                                      ckpt_stride: int = 0, time_stride: int = 1) -> int:
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     out = ctypes.c_size_t()
     _check(lib().gpuqt_vac_backward_workspace_size(H.handle, B, dt.shape[0], _ptr(dt), M, Np, int(ckpt_stride),
-                                                   ctypes.byref(out)), "gpuqt_vac_backward_workspace_size")
+                                                   int(time_stride), ctypes.byref(out)),
+           "gpuqt_vac_backward_workspace_size")
     return int(out.value)
 
 
@@ -678,33 +680,46 @@ def gpuqt_vac_backward_tape(H: Hamiltonian, phi, dt, w, tape, grad_onsite=None, 
 
 
 def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=None, Np: int = 0,
-                       ckpt_stride=None, ws=None, stream=None):
+                       ckpt_stride=None, time_stride=None, ws=None, stream=None):
     """Accumulate dL/dU and dL/deps_c for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M]).
 
     ckpt_stride: 1 keeps every forward vector (two-chain reverse of each row's moments), 0
     recomputes from checkpoints; None (default) takes 1 when its workspace fits in
-    KEEP_ALL_FRACTION of the free device memory (or 0 when ws is given)."""
+    KEEP_ALL_FRACTION of the free device memory (or 0 when ws is given).
+    time_stride: 1 keeps every state psi_{L,R}(t_k), s >= 2 only every s-th (segments are
+    re-evolved in the reverse), 0 every ceil(sqrt(n_t))-th; None (default) takes 1 when the
+    workspace with every state fits in KEEP_ALL_FRACTION of the free memory (or 1 when ws is
+    given), else 0."""
     import torch
     _dev_vec(phi, "phi")
     B = _cols(phi)
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     w = w.contiguous()
     M = int(w.shape[-1])
+    free = None
+    if time_stride is None:
+        if ws is not None:
+            time_stride = 1
+        else:
+            need = gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, 0, 1)
+            free, _ = torch.cuda.mem_get_info(phi.device)
+            time_stride = 1 if need <= KEEP_ALL_FRACTION * free else 0
     if ckpt_stride is None:
         if ws is not None:
             ckpt_stride = 0
         else:
-            need = gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, 1)
-            free, _ = torch.cuda.mem_get_info(phi.device)
+            need = gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, 1, time_stride)
+            if free is None:
+                free, _ = torch.cuda.mem_get_info(phi.device)
             ckpt_stride = 1 if need <= KEEP_ALL_FRACTION * free else 0
     if grad_onsite is None:
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phi.device)
     if ws is None:
-        ws = _scratch(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride), phi, stream)
+        ws = _scratch(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride, time_stride), phi, stream)
     nb = int(ws.numel() * ws.element_size())
     _check(lib().gpuqt_vac_backward(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
-                                    _ptr(grad_onsite), _ptr(grad_class), int(ckpt_stride), _ptr(ws), nb,
-                                    _stream(stream)),
+                                    _ptr(grad_onsite), _ptr(grad_class), int(ckpt_stride), int(time_stride),
+                                    _ptr(ws), nb, _stream(stream)),
            "gpuqt_vac_backward")
     return grad_onsite, grad_class
 

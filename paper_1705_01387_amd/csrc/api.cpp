@@ -1242,23 +1242,44 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   return GPUQT_OK;
 }
 
+// Time checkpoints of the VAC adjoint: stride 1 keeps every state
+// psi_{L,R}(t_k); s >= 2 keeps the states of rows 0, s, 2s, ... and
+// re-evolves one segment of s rows at a time during the reverse pass; 0
+// chooses ceil(sqrt(n_t)).
+static int vac_time_stride(int n_t, int time_stride) {
+  if (time_stride >= 1) return std::min(time_stride, std::max(n_t, 1));
+  const int st = (int)std::ceil(std::sqrt((double)std::max(n_t, 1)));
+  return st >= n_t ? 1 : std::max(2, st);
+}
+
+// state vectors the forward part of gpuqt_vac_backward keeps: every psi_L(k)
+// (k >= 1) and psi_R(k) at stride 1; else the checkpoints (psi_L of row 0 is
+// phi itself) and the s - 1 later states of one segment per chain
+static int vac_state_vectors(int n_t, int ts) {
+  if (ts <= 1) return 2 * n_t - 1;
+  const int nck = (n_t + ts - 1) / ts;
+  return 2 * nck - 1 + 2 * (ts - 1);
+}
+
 // number of workspace vectors of gpuqt_vac_backward (keep: every forward vector
 // kept, two-chain reverse of the rows; else checkpoints every ceil(sqrt(L)) steps)
-static int vac_backward_vectors(int n_t, int M, int Np, bool keep) {
+static int vac_backward_vectors(int n_t, int M, int Np, bool keep, int ts) {
   const int L = std::max(M, Np);
-  return 2 * n_t + 6 + backward_vectors(L, keep ? 1 : backward_stride(L, 0));
+  return vac_state_vectors(n_t, ts) + 6 + backward_vectors(L, keep ? 1 : backward_stride(L, 0));
 }
 
 gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
-                                               int32_t M, int32_t Np, int32_t ckpt_stride, size_t* bytes) {
+                                               int32_t M, int32_t Np, int32_t ckpt_stride, int32_t time_stride,
+                                               size_t* bytes) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
   if (!h || !bytes) return fail(GPUQT_ERR_ARG, "NULL handle or bytes");
   if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
   if (n_t < 0 || M < 0 || Np < 0 || (n_t > 0 && !dt)) return fail(GPUQT_ERR_ARG, "bad sizes");
   if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
+  if (time_stride < 0) return fail(GPUQT_ERR_ARG, "time_stride must be >= 0");
   const bool keep = ckpt_stride == 1;
   const int np = max_terms(h, std::max(n_t - 1, 0), dt, Np);
-  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np, keep), B, keep ? 5 : 2,
+  *bytes = ws_layout(h, vac_backward_vectors(n_t, M, np, keep, vac_time_stride(n_t, time_stride)), B, keep ? 5 : 2,
                      np + (keep ? raw_weight_len(B, M) : 0)).total;
   return GPUQT_OK;
 }
@@ -1266,10 +1287,12 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_
 static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* phi, int32_t n_t,
                                       const double* dt, int32_t M, int32_t Np, const double* w,
                                       double* grad_onsite, double* grad_class, int32_t ckpt_stride,
-                                      void* tape, size_t tape_bytes, void* ws, size_t ws_bytes, void* stream) {
+                                      int32_t time_stride, void* tape, size_t tape_bytes, void* ws,
+                                      size_t ws_bytes, void* stream) {
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, w);
   if (st) return st;
   if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
+  if (time_stride < 0) return fail(GPUQT_ERR_ARG, "time_stride must be >= 0");
   const bool keep = ckpt_stride == 1 || tape;
   if (!grad_onsite) return fail(GPUQT_ERR_ARG, "grad_onsite is NULL");
   if (grad_class && h->n_class > 4)
@@ -1280,7 +1303,8 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
   if (tape && (st = vac_tape_check(h, B, n_t, M, np, tape, tape_bytes, &T))) return st;
   const int L = tape ? np : std::max(M, np);
   const int s = keep ? 1 : backward_stride(L, 0);
-  const int nv = tape ? 6 + backward_vectors(np, 1) : vac_backward_vectors(n_t, M, np, keep);
+  const int ts = tape ? 1 : vac_time_stride(n_t, time_stride);
+  const int nv = tape ? 6 + backward_vectors(np, 1) : vac_backward_vectors(n_t, M, np, keep, ts);
   const WsLayout W = ws_layout(h, nv, B, keep ? 5 : 2, np + (keep ? raw_weight_len(B, M) : 0));
   if (!ws || ws_bytes < W.total) return fail(GPUQT_ERR_WORKSPACE, "workspace too small");
   if (!aligned16(ws)) return fail(GPUQT_ERR_ARG, "workspace is not 16-byte aligned");
@@ -1293,22 +1317,52 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
   const DevMat D = h->view(B);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   const double2* ph = reinterpret_cast<const double2*>(phi);
-  // states psi_L(k) (k >= 1) and psi_R(k) (workspace, or the recorded tape),
-  // adjoints, scratch
-  const int o = tape ? 0 : 2 * n_t - 1;
-  auto psiL = [&](int k) -> const double2* { return k == 0 ? ph : tape ? T.psiL(k) : V(k - 1); };
-  auto psiR = [&](int k) { return tape ? T.psiR(k) : V(n_t - 1 + k); };
+  // states: the recorded tape; every psi_L(k) (k >= 1) and psi_R(k); or (time
+  // checkpoints) psi_L, psi_R of rows 0, ts, 2 ts, ... and the states of one
+  // segment of ts rows, re-evolved from its checkpoint when the reverse needs it
+  const int o = tape ? 0 : vac_state_vectors(n_t, ts);
+  const int nck = ts > 1 ? (n_t + ts - 1) / ts : 0;
+  auto ckL = [&](int c) -> const double2* { return c == 0 ? ph : V(c - 1); };      // checkpoint c, chain L
+  auto ckR = [&](int c) -> double2* { return V(nck - 1 + c); };                    // checkpoint c, chain R
+  auto segL = [&](int i) -> double2* { return V(2 * nck - 1 + (i - 1)); };          // i = 1 .. ts-1
+  auto segR = [&](int i) -> double2* { return V(2 * nck - 1 + (ts - 1) + (i - 1)); };
+  int seg = -1;   // the segment whose states segL / segR hold (time checkpoints)
+  auto psiL = [&](int k) -> const double2* {
+    if (k == 0) return ph;
+    if (tape) return T.psiL(k);
+    if (ts <= 1) return V(k - 1);
+    const int i = k - seg * ts;
+    return i == 0 ? ckL(seg) : segL(i);
+  };
+  auto psiR = [&](int k) -> double2* {
+    if (tape) return T.psiR(k);
+    if (ts <= 1) return V(n_t - 1 + k);
+    const int i = k - seg * ts;
+    return i == 0 ? ckR(seg) : segR(i);
+  };
   double2* gL[2] = {V(o), V(o + 1)};
   double2* gR[2] = {V(o + 2), V(o + 3)};
   double2* gphiL = V(o + 4);
   double2* phiL = V(o + 5);
   std::vector<double2*> pool(backward_vectors(L, s));
   for (size_t i = 0; i < pool.size(); ++i) pool[i] = V(o + 6 + (int)i);
-  double2* e0 = pool[0];   // evolution scratch during the forward pass
+  double2* e0 = pool[0];   // evolution scratch (forward pass and segment re-evolution)
   double2* e1 = pool[1];
   if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
+  // states of segment c from its checkpoint: psi(k+1) = U(-dt_k) psi(k), k in the segment
+  auto load_segment = [&](int c) -> gpuqt_status {
+    seg = c;
+    const int k0 = c * ts, k1 = std::min(k0 + ts, n_t);
+    for (int k = k0; k + 1 < k1; ++k) {
+      const int i = k - k0;
+      gpuqt_status q = run_evolve_pair(h, B, -dt[k], terms_for(h, dt[k], Np), i == 0 ? ckL(c) : segL(i), segL(i + 1),
+                                       i == 0 ? ckR(c) : segR(i), segR(i + 1), e0, e1, pool[2], pool[3], J, sm);
+      if (q) return q;
+    }
+    return GPUQT_OK;
+  };
   // forward (unless recorded): psi_R(0) = V phi; psi_{L,R}(k+1) = U(-dt_k) psi_{L,R}(k)
-  if (!tape) {
+  if (!tape && ts <= 1) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, psiR(0), sm));
     for (int k = 0; k + 1 < n_t; ++k) {
       const int npk = terms_for(h, dt[k], Np);
@@ -1316,12 +1370,36 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
                                 pool[3], J, sm)))
         return st;
     }
+  } else if (!tape) {
+    // keep only the checkpoints; a state between checkpoints goes to segment
+    // slot 1 or 2 by the parity of its row (ts >= 3), or to slot 1 (ts = 2,
+    // where it always follows a checkpoint), so it never overwrites its input
+    HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, ph, ckR(0), sm));
+    const double2* aL = ph;
+    const double2* aR = ckR(0);
+    for (int k = 0; k + 1 < n_t; ++k) {
+      const int npk = terms_for(h, dt[k], Np);
+      double2* oL;
+      double2* oR;
+      if ((k + 1) % ts == 0) {
+        oL = const_cast<double2*>(ckL((k + 1) / ts));
+        oR = ckR((k + 1) / ts);
+      } else {
+        const int slot = ts >= 3 ? ((k + 1) % 2) + 1 : 1;
+        oL = segL(slot);
+        oR = segR(slot);
+      }
+      if ((st = run_evolve_pair(h, B, -dt[k], npk, aL, oL, aR, oR, e0, e1, pool[2], pool[3], J, sm))) return st;
+      aL = oL;
+      aR = oR;
+    }
   }
   // reverse over the rows
   int cl = 0, cr = 0;
   HIP_TRY(launch_scale(D, B, nullptr, gL[0], nullptr, 0, sm));
   HIP_TRY(launch_scale(D, B, nullptr, gR[0], nullptr, 0, sm));
   const int64_t row = (int64_t)h->n_seg * B * M;
+  if (!tape && ts > 1 && (st = load_segment((n_t - 1) / ts))) return st;
   for (int k = n_t - 1; k >= 0; --k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL(k), phiL, sm));
     if (keep) {
@@ -1349,6 +1427,8 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY | kAccumulate, gphiL, gL[cl], sm));
     if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gphiL, psiL(k), h->d_cls, gcp, sm));
     if (k == 0) break;
+    // the reverse through U(-dt_{k-1}) needs the states of row k - 1
+    if (!tape && ts > 1 && (k - 1) / ts != seg && (st = load_segment((k - 1) / ts))) return st;
     // back through psi(k) = U(-dt) psi(k-1): parameter terms and g <- U(+dt) g
     const double d = -dt[k - 1];
     const int npk = terms_for(h, d, Np);
@@ -1377,10 +1457,10 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
 
 gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
                                 const double* dt, int32_t M, int32_t Np, const double* w,
-                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, void* ws,
-                                size_t ws_bytes, void* stream) {
+                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, int32_t time_stride,
+                                void* ws, size_t ws_bytes, void* stream) {
   return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
-                           grad_class, ckpt_stride, nullptr, 0, ws, ws_bytes, stream);
+                           grad_class, ckpt_stride, time_stride, nullptr, 0, ws, ws_bytes, stream);
 }
 
 gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
@@ -1400,7 +1480,7 @@ gpuqt_status gpuqt_vac_backward_tape(gpuqt_h hh, int32_t B, const double* phi, i
                                      size_t ws_bytes, void* stream) {
   if (!tape) return fail(GPUQT_ERR_ARG, "tape is NULL");
   return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
-                           grad_class, 1, const_cast<void*>(tape), tape_bytes, ws, ws_bytes, stream);
+                           grad_class, 1, 1, const_cast<void*>(tape), tape_bytes, ws, ws_bytes, stream);
 }
 
 gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, void* stream,

@@ -137,11 +137,66 @@ def test_vac_backward(gpu, name, B, ckpt):
     dts = [0.3, 1.2, 0.0, 0.7]
     M = 40
     w = np.random.default_rng(59).normal(size=(len(dts), 1, B, M))
-    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=ckpt,
+    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=ckpt, time_stride=1,
                                   grad_class=torch.zeros(n_class, dtype=torch.float64, device="cuda"))
     rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
     assert err(host(gU), rU) < TOL
     assert err(host(gC), rC) < TOL
+
+
+@pytest.mark.parametrize("name", ["square_nnn_2class", "honeycomb_flux"])
+@pytest.mark.parametrize("time_stride,ckpt", [(0, 0), (0, 1), (3, 1), (5, 0), (2, 1), (16, 0)])
+def test_vac_backward_time_checkpoints(gpu, name, time_stride, ckpt):
+    """Sixteen VAC rows (non-uniform steps, one of them zero) reversed with the states kept only
+    every time_stride rows (0: every ceil(sqrt(16)) = 4) and each segment re-evolved from its
+    checkpoint: the gradients match the oracle's (every state stored) and the run that keeps
+    every state, to rounding."""
+    import torch
+    from oracle.adjoint import vac_gradient, velocity_class_parts
+    say(f"case: VAC backward time checkpoints {name} time_stride={time_stride} ckpt={ckpt}")
+    mk, n_class = VAC_CASES[name]
+    m = mk()
+    Hs, V, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class)
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, n_class, m.x, m.length_x)
+    B, M = 2, 24
+    phi = I.random_phase(m.n, B, 141)
+    dts = list(np.random.default_rng(142).uniform(0.1, 0.9, size=16))
+    dts[6] = 0.0
+    w = np.random.default_rng(143).normal(size=(len(dts), 1, B, M))
+    zc = lambda: torch.zeros(n_class, dtype=torch.float64, device="cuda")
+    gU, gC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=ckpt, time_stride=time_stride,
+                                  grad_class=zc())
+    aU, aC = P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=ckpt, time_stride=1, grad_class=zc())
+    assert err(host(gU), host(aU)) < 1e-13 and err(host(gC), host(aC)) < 1e-13
+    rU, rC = vac_gradient(Hs, V, phi, dts, dE, M, np.transpose(w[:, 0], (0, 2, 1)), 0, Hc, Vc)
+    assert err(host(gU), rU) < TOL and err(host(gC), rC) < TOL
+
+
+def test_vac_backward_workspace_grows_as_sqrt_steps(gpu):
+    """State vectors of the VAC adjoint: 2 n_t - 1 when every state is kept; with the default
+    time checkpoints 2 ceil(n_t / s) - 1 + 2 (s - 1), s = ceil(sqrt(n_t)), about 4 sqrt(n_t)."""
+    import math
+    say("case: VAC adjoint workspace vs time steps")
+    m = I.square(64, 64, W=1.0, seed=144)
+    H = P.gpuqt_build_h_from_model(m)
+    B, M = 1, 16
+    # two state vectors more from n_t = 1 (psi_R(0)) to n_t = 2 (plus psi_L(1), psi_R(1))
+    vec = P.gpuqt_vac_backward_workspace_size(H, B, [0.5] * 2, M, 8, 0, 1) \
+        - P.gpuqt_vac_backward_workspace_size(H, B, [0.5], M, 8, 0, 1)
+    assert vec == 2 * m.n * B * 16
+    base = P.gpuqt_vac_backward_workspace_size(H, B, [0.5], M, 8, 0, 1)
+    for n_t in (16, 64, 400):
+        dts = [0.5] * n_t
+        s = math.ceil(math.sqrt(n_t))
+        keep = P.gpuqt_vac_backward_workspace_size(H, B, dts, M, 8, 0, 1)
+        ck = P.gpuqt_vac_backward_workspace_size(H, B, dts, M, 8, 0, 0)
+        assert keep - base == (2 * n_t - 2) * vec // 2
+        assert ck - base == (2 * math.ceil(n_t / s) - 1 + 2 * (s - 1) - 1) * vec // 2
+    assert P.gpuqt_vac_backward_workspace_size(H, B, [0.5] * 400, M, 8, 0, 0) < \
+        P.gpuqt_vac_backward_workspace_size(H, B, [0.5] * 400, M, 8, 0, 1) / 5
 
 
 @pytest.mark.parametrize("name", list(VAC_CASES))
