@@ -23,7 +23,7 @@ from .operators import operators, position_differences, gershgorin_bound
 from .kpm import (chebyshev_moments, chebyshev_series, jackson, kpm_reconstruct, chebyshev_T)
 from .transport import (evolution_coefficients, evolve, commutator_evolve,
                         dos_moments, vac_moments, msd_moments, auto_terms)
-from .adjoint import moments_gradient
+from .adjoint import moments_gradient, vac_gradient, entry_list, tie_hermitian
 from .postprocess import sigma_vac, sigma_msd, transport_lengths
 
 __all__ = [
@@ -31,5 +31,6 @@ __all__ = [
     "chebyshev_moments", "chebyshev_series", "jackson", "kpm_reconstruct", "chebyshev_T",
     "evolution_coefficients", "evolve", "commutator_evolve",
     "dos_moments", "vac_moments", "msd_moments", "auto_terms",
-    "moments_gradient", "sigma_vac", "sigma_msd", "transport_lengths",
+    "moments_gradient", "vac_gradient", "entry_list", "tie_hermitian", "sigma_vac", "sigma_msd",
+    "transport_lengths",
 ]

@@ -15,7 +15,13 @@ Parameters:
   * on-site U_i:  dH~/dU_i = e_i e_i^T / DeltaE;
   * hopping class c, as the relative change H_ij -> (1 + eps_c) H_ij on every
     bond of class c, at eps_c = 0:  dH~/deps_c = H_c / DeltaE, and the velocity
-    V = i dx H changes by V_c = i dx H_c.
+    V = i dx H changes by V_c = i dx H_c;
+  * one stored entry H_ij on its own (complex): a change dH_ij = delta changes L
+    by Re(delta g_ij) with g_ij = sum_n f_n <lam_n|e_i> <e_j|v_{n-1}> / DeltaE
+    (+ i dx_ij conj(a_i) x_j for every velocity application a^+ V x), so
+    dL/dRe H_ij = Re g_ij and dL/dIm H_ij = -Im g_ij.  For a Hermitian H whose
+    bond carries h = H_ij = conj(H_ji), dL/dRe h and dL/dIm h add the two
+    entries' values with the sign of Im flipped on the partner (tie_hermitian).
 
 The VAC gradient reverses the whole computation of vac_moments (the reading
 C_n(t_k) = Re <V psi_L(k)|T_n|psi_R(k)>, psi_{L,R}(k+1) = U(-dt_k) psi_{L,R}(k),
@@ -66,8 +72,58 @@ def _as_cols(a):
     return a[:, None] if a.ndim == 1 else a
 
 
-def moments_gradient(H, phiL, phiR, energy_max, weights, H_classes=()):
-    """Gradient of L = sum_{n,b} Re(w[n,b] mu[n,b]) w.r.t. on-site energies and class scales.
+def entry_list(nn, nbr, x=None, length_x=0.0):
+    """The stored entries of a neighbour list in the input layout: (rows, cols, slots, dx),
+    slot s of row i at flat index i * max_nn + s."""
+    n, k = nbr.shape
+    slot = np.broadcast_to(np.arange(k)[None, :], (n, k))
+    valid = slot < np.asarray(nn)[:, None]
+    rows = np.broadcast_to(np.arange(n)[:, None], (n, k))[valid]
+    cols = np.asarray(nbr)[valid].astype(np.int64)
+    flat = (rows * k + slot[valid]).astype(np.int64)
+    dx = None if x is None else position_differences(x, rows, cols, length_x)
+    return rows, cols, flat, dx
+
+
+def tie_hermitian(nn, nbr, g):
+    """Per-entry gradient pairs (dL/dRe, dL/dIm) [n, max_nn, 2] of independent entries ->
+    the gradient of each Hermitian bond h = H_ij = conj(H_ji), stored at both entries of
+    the pair (the partner's Im with the opposite sign).  The q-th entry of row i that
+    points to j pairs with the q-th entry of row j that points to i; an entry without a
+    partner keeps its own value."""
+    n, k = nbr.shape
+    out = np.array(g, dtype=np.float64, copy=True)
+    for i in range(n):
+        for s in range(nn[i]):
+            j = nbr[i, s]
+            q = sum(1 for t in range(s) if nbr[i, t] == j)
+            hits = [t for t in range(nn[j]) if nbr[j, t] == i]
+            if q < len(hits):
+                p = hits[q]
+                out[i, s, 0] = g[i, s, 0] + g[j, p, 0]
+                out[i, s, 1] = g[i, s, 1] - g[j, p, 1]
+    return out
+
+
+def _add_entries(gH, entries, lam, v, f, scale):
+    """gH[flat] += f (Re g, -Im g), g = sum_b conj(lam[i, b]) v[j, b] * scale."""
+    rows, cols, flat, _ = entries
+    g = np.sum(np.conj(lam[rows]) * v[cols], axis=1) * scale * f
+    gH[flat, 0] += np.real(g)
+    gH[flat, 1] += -np.imag(g)
+
+
+def _add_velocity_entries(gH, entries, a, xv):
+    """The velocity's share a^+ V x (V_ij = i dx_ij H_ij, unscaled): g_ij = i dx_ij conj(a_i) x_j."""
+    rows, cols, flat, dx = entries
+    g = 1j * dx * np.sum(np.conj(a[rows]) * xv[cols], axis=1)
+    gH[flat, 0] += np.real(g)
+    gH[flat, 1] += -np.imag(g)
+
+
+def moments_gradient(H, phiL, phiR, energy_max, weights, H_classes=(), entries=None, gH=None):
+    """Gradient of L = sum_{n,b} Re(w[n,b] mu[n,b]) w.r.t. on-site energies and class scales,
+    and (entries = entry_list(...), gH [n * max_nn, 2] accumulated) w.r.t. each stored entry.
 
     Returns (grad_onsite [n], grad_class [len(H_classes)]).
     """
@@ -94,11 +150,15 @@ def moments_gradient(H, phiL, phiR, energy_max, weights, H_classes=()):
         gU += f * np.sum(np.real(np.conj(lam[n]) * v[n - 1]), axis=1)
         for c, Hc in enumerate(H_classes):
             gC[c] += f * np.sum(np.real(np.conj(lam[n]) * (Hc @ v[n - 1])))
+        if entries is not None:
+            _add_entries(gH, entries, lam[n], v[n - 1], f, 1.0 / energy_max)
     return gU / energy_max, gC / energy_max
 
 
-def vac_gradient(H, V, phi, dts, energy_max, M, weights, Np=0, H_classes=(), V_classes=()):
-    """Gradient of L = sum_{k,n,b} w[k,n,b] C_n^VAC(t_k)[b] w.r.t. on-site energies and class scales."""
+def vac_gradient(H, V, phi, dts, energy_max, M, weights, Np=0, H_classes=(), V_classes=(), entries=None,
+                 gH=None):
+    """Gradient of L = sum_{k,n,b} w[k,n,b] C_n^VAC(t_k)[b] w.r.t. on-site energies and class scales,
+    and (entries with dx, gH accumulated) w.r.t. each stored entry."""
     Ht = H / energy_max
     phi = _as_cols(phi)
     w = np.asarray(weights, dtype=np.float64)
@@ -114,7 +174,7 @@ def vac_gradient(H, V, phi, dts, energy_max, M, weights, Np=0, H_classes=(), V_c
     gR = np.zeros_like(phi)
     for k in range(n_t - 1, -1, -1):
         phiL = V @ psiL[k]
-        u, c = moments_gradient(H, phiL, psiR[k], energy_max, w[k], H_classes)
+        u, c = moments_gradient(H, phiL, psiR[k], energy_max, w[k], H_classes, entries, gH)
         gU += u
         gC += c
         gR = gR + np.stack([chebyshev_series(Ht, w[k][:, b], phiL[:, b]) for b in range(phi.shape[1])], 1)
@@ -122,16 +182,20 @@ def vac_gradient(H, V, phi, dts, energy_max, M, weights, Np=0, H_classes=(), V_c
         gL = gL + V @ gphiL
         for q, Vc in enumerate(V_classes):
             gC[q] += np.sum(np.real(np.conj(gphiL) * (Vc @ psiL[k])))
+        if entries is not None:
+            _add_velocity_entries(gH, entries, gphiL, psiL[k])
         if k > 0:
             dt = -dts[k - 1]
             coef = evolution_coefficients(dt, energy_max, _np_for(dt, energy_max, Np))
             cw = np.repeat(coef[:, None], phi.shape[1], axis=1)
             for g_, psi_ in ((gL, psiL[k - 1]), (gR, psiR[k - 1])):
-                u, c = moments_gradient(H, g_, psi_, energy_max, cw, H_classes)
+                u, c = moments_gradient(H, g_, psi_, energy_max, cw, H_classes, entries, gH)
                 gU += u
                 gC += c
             gL = evolve(Ht, gL, -dt, energy_max, len(coef))     # U(-dt)^+ = U(+dt)
             gR = evolve(Ht, gR, -dt, energy_max, len(coef))
     for q, Vc in enumerate(V_classes):
         gC[q] += np.sum(np.real(np.conj(gR) * (Vc @ phi)))
+    if entries is not None:
+        _add_velocity_entries(gH, entries, gR, phi)
     return gU, gC

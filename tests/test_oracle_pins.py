@@ -508,3 +508,132 @@ def test_transport_lengths_ballistic_msd_and_saturation():
     assert rel(O.transport_lengths(rho, msd=sat)["xi"], X / np.pi) < 1e-15
     s, _ = O.sigma_msd(np.array([[1.0], [1.0], [5.0]]), np.array([1.0, 0.0, 1.0]))
     assert O.transport_lengths(np.ones(1), sigma=s)["sigma_sc"][0] == 2.0
+
+
+def _bond_perturbation(m, i, s, delta):
+    """H and V of m with the bond (i, s) -> j and its Hermitian partner moved: H_ij += delta,
+    H_ji += conj(delta) (the partner found as in tie_hermitian); V = i dx H follows."""
+    hop = np.array(I.dense_hop(m), dtype=np.complex128)
+    j = m.nbr[i, s]
+    q = sum(1 for t in range(s) if m.nbr[i, t] == j)
+    p = [t for t in range(m.nn[j]) if m.nbr[j, t] == i][q]
+    hop[i, s] += delta
+    hop[j, p] += np.conj(delta)
+    return O.operators(m.nn, m.nbr, hop, m.onsite, m.x, m.length_x)
+
+
+def test_entry_gradient_finite_differences_moments():
+    """Per-entry gradient of a moment loss on a small flux honeycomb lattice (complex hoppings)
+    against central differences (h = 1e-6): one entry moved alone (untied: dL/dRe H_ij, dL/dIm
+    H_ij), and a Hermitian bond h = H_ij = conj(H_ji) moved as a whole (tie_hermitian)."""
+    import scipy.sparse as sp
+    m = I.honeycomb(3, 4, flux=1.0 / 12.0, W=1.0, seed=150)
+    H, _, _ = ops(m)
+    dE = 1.01 * O.gershgorin_bound(H)
+    phiL = I.random_phase(m.n, 2, 151)
+    phiR = I.random_phase(m.n, 2, 152)
+    M = 30
+    w = np.random.default_rng(153).normal(size=(M, 2))
+
+    def loss(Hm):
+        return float(np.sum(w * O.chebyshev_moments(Hm / dE, phiL, phiR, M).real))
+
+    ent = O.entry_list(m.nn, m.nbr)
+    gH = np.zeros((m.n * m.max_nn, 2))
+    O.moments_gradient(H, phiL, phiR, dE, w, (), ent, gH)
+    g = gH.reshape(m.n, m.max_nn, 2)
+    tied = O.tie_hermitian(m.nn, m.nbr, g)
+    h = 1e-6
+    scale = np.max(np.abs(g))
+    for i, s in ((0, 0), (5, 2), (17, 1), (23, 0)):
+        j = m.nbr[i, s]
+        for part, d in ((0, h), (1, 1j * h)):
+            e = sp.csr_matrix(([d], ([i], [j])), shape=H.shape)
+            fd = (loss(H + e) - loss(H - e)) / (2 * h)
+            assert abs(fd - g[i, s, part]) < 1e-6 * scale, (i, s, part)
+            Hp, _, _ = _bond_perturbation(m, i, s, d)
+            Hm, _, _ = _bond_perturbation(m, i, s, -d)
+            fd = (loss(Hp) - loss(Hm)) / (2 * h)
+            assert abs(fd - tied[i, s, part]) < 1e-6 * scale, (i, s, part, "tied")
+
+
+def test_entry_gradient_sums_to_class_gradient():
+    """A class scale moves every entry of the class in proportion to its value, so the class
+    gradient is sum_e (dL/dRe H_e Re H_e + dL/dIm H_e Im H_e) over its entries: the per-entry
+    and the class paths of the oracle are separate code (sparse class matrices vs entry lists)."""
+    m = I.square(6, 5, t1=-1.0, t2=-0.2, W=1.0, seed=154)
+    H, V, _ = ops(m)
+    Hc = class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2)
+    from oracle.adjoint import velocity_class_parts
+    Vc = velocity_class_parts(m.nn, m.nbr, m.hop, m.hop_class, 2, m.x, m.length_x)
+    dE = 6.0
+    phi = I.random_phase(m.n, 2, 155)
+    M = 20
+    ent = O.entry_list(m.nn, m.nbr, m.x, m.length_x)
+    hop = np.asarray(I.dense_hop(m), dtype=np.complex128)
+    cls = m.hop_class
+    # moments
+    w = np.random.default_rng(156).normal(size=(M, 2))
+    gH = np.zeros((m.n * m.max_nn, 2))
+    _, gC = O.moments_gradient(H, phi, I.random_phase(m.n, 2, 157), dE, w, Hc, ent, gH)
+    g = gH.reshape(m.n, m.max_nn, 2)
+    for c in range(2):
+        sel = (cls == c)
+        s = np.sum(g[..., 0][sel] * hop.real[sel] + g[..., 1][sel] * hop.imag[sel])
+        assert abs(s - gC[c]) < 1e-12 * max(1.0, abs(gC[c]))
+    # VAC (the velocity's share included)
+    dts = [0.4, 0.8]
+    wv = np.random.default_rng(158).normal(size=(len(dts), M, 2))
+    gH = np.zeros((m.n * m.max_nn, 2))
+    _, gC = O.vac_gradient(H, V, phi, dts, dE, M, wv, 0, Hc, Vc, ent, gH)
+    g = gH.reshape(m.n, m.max_nn, 2)
+    for c in range(2):
+        sel = (cls == c)
+        s = np.sum(g[..., 0][sel] * hop.real[sel] + g[..., 1][sel] * hop.imag[sel])
+        assert abs(s - gC[c]) < 1e-11 * max(1.0, abs(gC[c]))
+
+
+def test_entry_gradient_finite_differences_vac():
+    """Per-entry gradient of a VAC loss (H and the velocity V = i dx H move together) on a small
+    flux honeycomb lattice, against central differences (h = 1e-6) on whole Hermitian bonds."""
+    m = I.honeycomb(3, 4, flux=1.0 / 12.0, W=1.0, seed=159)
+    H, V, _ = ops(m)
+    dE = 1.01 * O.gershgorin_bound(H)
+    phi = I.random_phase(m.n, 1, 160)
+    dts = [0.5, 1.1, 0.3]
+    M, Np = 16, 40
+    w = np.random.default_rng(161).normal(size=(len(dts), M, 1))
+
+    def loss(Hm, Vm):
+        return float(np.sum(w * O.vac_moments(Hm, Vm, phi, dts, dE, M, Np)))
+
+    ent = O.entry_list(m.nn, m.nbr, m.x, m.length_x)
+    gH = np.zeros((m.n * m.max_nn, 2))
+    O.vac_gradient(H, V, phi, dts, dE, M, w, Np, (), (), ent, gH)
+    tied = O.tie_hermitian(m.nn, m.nbr, gH.reshape(m.n, m.max_nn, 2))
+    h = 1e-6
+    scale = np.max(np.abs(tied))
+    for i, s in ((1, 0), (6, 2), (14, 1)):
+        for part, d in ((0, h), (1, 1j * h)):
+            Hp, Vp, _ = _bond_perturbation(m, i, s, d)
+            Hm, Vm, _ = _bond_perturbation(m, i, s, -d)
+            fd = (loss(Hp, Vp) - loss(Hm, Vm)) / (2 * h)
+            assert abs(fd - tied[i, s, part]) < 1e-6 * scale, (i, s, part)
+
+
+def test_tie_hermitian_pairs_duplicates_in_order():
+    """Hand-made neighbour lists: a duplicated bond pairs its occurrences in order, an entry
+    without a partner keeps its value, and the partner's imaginary part enters with the
+    opposite sign."""
+    nn = np.array([3, 2, 0], np.int32)
+    nbr = np.array([[1, 1, 2], [0, 0, -1], [-1, -1, -1]], np.int32)
+    g = np.zeros((3, 3, 2))
+    g[0, 0] = (1.0, 10.0)
+    g[0, 1] = (2.0, 20.0)
+    g[0, 2] = (3.0, 30.0)     # 0 -> 2 has no partner (row 2 is empty)
+    g[1, 0] = (0.5, 5.0)
+    g[1, 1] = (0.25, 2.5)
+    t = O.tie_hermitian(nn, nbr, g)
+    assert tuple(t[0, 0]) == (1.5, 5.0) and tuple(t[1, 0]) == (1.5, -5.0)
+    assert tuple(t[0, 1]) == (2.25, 17.5) and tuple(t[1, 1]) == (2.25, -17.5)
+    assert tuple(t[0, 2]) == (3.0, 30.0)
