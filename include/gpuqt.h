@@ -145,6 +145,8 @@ typedef struct {
   int32_t banded_mask;       /* bit log2(B) set: block width B has a banded row order */
   int32_t family_caps;       /* per kernel family f (GPUQT_K_*), bits 4f..4f+3: 0 = the per-CU
                                 cap of kernel_variant, else 1 + that family's own cap (1: none) */
+  int32_t max_nn;            /* neighbour slots per row of the build descriptor: the row stride
+                                of per-entry hopping gradients */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -261,9 +263,16 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
  *   L = sum_{s,b,k} w[s][b][k] Re mu[s][b][k],  mu[s][b][k] = <phiL_b| T_k(H/DeltaE_s) |phiR_b>,
  * with DeltaE held fixed, with respect to
  *   - the on-site energies:   grad_onsite[i] += dL/dU_i,
- *   - the hopping classes:    grad_class[c]  += dL/deps_c, where every hopping of class c
- *                             is scaled as H_ij -> (1 + eps_c) H_ij (at eps = 0),
+ *   - the hopping classes:    grad_class[c]  += dL/ds_c, where s_c is the class scale of
+ *                             gpuqt_update_h_values (class-c hoppings = s_c x their values
+ *                             at build time; defined, and finite, at every s_c, also 0),
+ *   - each stored hopping:    grad_hop[i][slot] += (dL/dRe H_ij, dL/dIm H_ij), entry `slot`
+ *                             of row i of the neighbour list (j = nbr[i][slot]), every
+ *                             entry an independent complex number (no Hermitian tie: see
+ *                             gpuqt_tie_entry_gradient),
  * and optionally lam0 = sum_k w_k T_k(H~) phiL (the adjoint of phiR).
+ * The entry gradient is sum_k f_k conj(lam_k)_i (v_{k-1})_j / DeltaE (f_1 = 1, else 2),
+ * stored as (Re, -Im) of that sum.
  * Method: the recurrence of Section 3.2 run forwards with checkpoints of
  * (v_{js}, v_{js+1}) every s = ckpt_stride steps (0: ceil(sqrt(M))), then the
  * adjoint recurrence lam_k = w_k phiL + 2 H~ lam_{k+1} - lam_{k+2} run backwards,
@@ -276,23 +285,30 @@ gpuqt_status gpuqt_msd(gpuqt_h h, int32_t B, const double *phi, int32_t n_t, con
  * pointer the two chains coincide and only their adjoints' sum enters, so one
  * chain and one adjoint chain are run;
  * dL/dp = Re[ sum_{k>=2} 2 <lam_k| dH~/dp v_{k-1}> + <lam_1| dH~/dp v_0> ].
+ * With grad_hop set the plain recurrence is reversed at every stride (ckpt_stride = 1
+ * then keeps the M - 2 vectors v_1 .. v_{M-2}): the product identities hold for a
+ * Hermitian H, which a change of one entry alone does not keep.
  *   phiL, phiR : c128 [n][B];  w : double [n_segments][B][M];  grad_onsite : double [n];
- *   grad_class : double [n_class] or NULL (at most 4 classes);  lam0 : c128 [n][B] or NULL.
+ *   grad_class : double [n_class] or NULL (at most 4 classes);
+ *   grad_hop : double [n][max_nn][2] (max_nn of the descriptor) or NULL;
+ *   lam0 : c128 [n][B] or NULL.  grad_class and grad_hop need grad_onsite.
  *   All device.  Workspace: gpuqt_workspace_size(h, GPUQT_OP_MOMENTS_BACKWARD, B, M,
  *   ckpt_stride) (its Np argument is the checkpoint stride).  Accumulation order is fixed:
  *   repeated calls give bit-identical gradients.
  */
 gpuqt_status gpuqt_moments_backward(gpuqt_h h, int32_t B, const double *phiL, const double *phiR,
                                     int32_t M, const double *w, double *grad_onsite,
-                                    double *grad_class, double *lam0, int32_t ckpt_stride,
-                                    void *ws, size_t ws_bytes, void *stream);
+                                    double *grad_class, double *grad_hop, double *lam0,
+                                    int32_t ckpt_stride, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Gradient of a loss on the VAC moments of gpuqt_vac (Section 3.3, C_n^VAC; Section 2.2):
  *   L = sum_{k,s,b,n} w[k][s][b][n] out[k][s][b][n],  out as computed by gpuqt_vac,
- * with DeltaE held fixed, with respect to the on-site energies (grad_onsite[i] += dL/dU_i)
- * and the hopping classes (grad_class[c] += dL/deps_c, H_ij -> (1 + eps_c) H_ij; this also
- * scales the velocity V = i[H, X] on those bonds).
+ * with DeltaE held fixed, with respect to the on-site energies (grad_onsite[i] += dL/dU_i),
+ * the hopping class scales (grad_class[c] += dL/ds_c as in gpuqt_moments_backward; s_c also
+ * scales the velocity V = i[H, X] on those bonds) and each stored hopping (grad_hop as in
+ * gpuqt_moments_backward, plus the velocity's share: V_ij = i dx_ij H_ij, so every
+ * application a^+ V x adds i dx_ij conj(a_i) x_j to entry (i, j)).
  * Method: the forward VAC series (the states psi_L(t_k), psi_R(t_k) advanced by
  * U(-dt_k), Section 3.2), then the reverse over the rows: per row the adjoints of both
  * moment arguments (as gpuqt_moments_backward), back through phi_L = V psi_L (V is
@@ -308,13 +324,31 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h h, int32_t B, const double *phiL, co
  *   2 (s - 1) vectors, one more forward evolution of every step); 0: s = ceil(sqrt(n_t))
  *   (1 when that is n_t).  The gradients agree to rounding whatever the strides.
  *   phi : c128 [n][B];  dt : HOST [n_t];  w : double [n_t][n_segments][B][M];
- *   grad_onsite : double [n];  grad_class : double [n_class] or NULL (at most 4 classes).
+ *   grad_onsite : double [n];  grad_class : double [n_class] or NULL (at most 4 classes);
+ *   grad_hop : double [n][max_nn][2] or NULL (with it, the rows' moments are reversed by
+ *   the plain recurrence also at ckpt_stride 1).
  *   Workspace: gpuqt_vac_backward_workspace_size with the same strides.
  */
 gpuqt_status gpuqt_vac_backward(gpuqt_h h, int32_t B, const double *phi, int32_t n_t,
                                 const double *dt, int32_t M, int32_t Np, const double *w,
-                                double *grad_onsite, double *grad_class, int32_t ckpt_stride,
-                                int32_t time_stride, void *ws, size_t ws_bytes, void *stream);
+                                double *grad_onsite, double *grad_class, double *grad_hop,
+                                int32_t ckpt_stride, int32_t time_stride, void *ws, size_t ws_bytes,
+                                void *stream);
+
+/*
+ * Hermitian tie of per-entry gradients (of gpuqt_moments_backward / gpuqt_vac_backward).
+ * A Hermitian H stores each bond h = H_ij = conj(H_ji) twice; the gradient of L with
+ * respect to (Re h, Im h) is the sum of the two entries' gradients with the sign of the
+ * Im part flipped on the partner:
+ *   tied[i][s] = (g[i][s].re + g[j][p].re, g[i][s].im - g[j][p].im),
+ * where entry s of row i points to j and p is its partner in row j: the q-th entry of
+ * row j that points to i when s is the q-th entry of row i that points to j.  An entry
+ * without a partner, and every padding slot, is copied.  Each bond's value then sits at
+ * both of its entries (the partner holding (re, -im)).
+ *   untied, tied : double [n][max_nn][2], device, distinct buffers (no in-place).
+ * Enqueued on `stream`; GPUQT_ERR_ARG for NULL, equal or misaligned pointers.
+ */
+gpuqt_status gpuqt_tie_entry_gradient(gpuqt_h h, const double *untied, double *tied, void *stream);
 
 /* Workspace bytes of gpuqt_vac_backward (dt: HOST [n_t], needed for the automatic Np). */
 gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h h, int32_t B, int32_t n_t, const double *dt,

@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     gpuqt_evolve, gpuqt_apply_commutator, gpuqt_vac, gpuqt_msd, gpuqt_kpm_reconstruct,
     gpuqt_jackson, gpuqt_bessel, gpuqt_auto_terms, gpuqt_last_error, gpuqt_copy_probe,
     gpuqt_autotune, gpuqt_moments_backward, gpuqt_vac_backward, gpuqt_vac_backward_workspace_size,
+    gpuqt_tie_entry_gradient,
     gpuqt_vac_tape_size, gpuqt_vac_record, gpuqt_vac_backward_tape, gpuqt_vac_backward_tape_workspace_size,
     gpuqt_update_h_values, gpuqt_kpm_reconstruct_adjoint, gpuqt_set_timing, gpuqt_timing, K_FAMILIES, gpuqt_set_variant,
     gpuqt_schedule_rows, gpuqt_running_conductivity, SIGMA_VAC, SIGMA_MSD, gpuqt_model_load, InputFolder,

@@ -53,7 +53,7 @@ class HInfo(ctypes.Structure):
         ("max_width", ctypes.c_int32), ("uniform_width", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
-        ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32),
+        ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32), ("max_nn", ctypes.c_int32),
     ]
 
 
@@ -101,12 +101,14 @@ _SIGS = {
     "gpuqt_moments_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
-                                                ctypes.c_void_p]),
+                                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_size_t, ctypes.c_void_p]),
     "gpuqt_vac_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gpuqt_tie_entry_gradient": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "gpuqt_vac_backward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                            ctypes.c_int32, ctypes.c_int32,
@@ -582,9 +584,11 @@ KEEP_ALL_FRACTION = 0.25   # keep every forward vector when that needs at most t
 
 
 def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad_class=None,
-                           want_lam0=False, ckpt_stride=None, ws=None, stream=None):
-    """Accumulate dL/dU (grad_onsite, float64 [n]) and dL/deps_c (grad_class, float64 [n_class])
-    for L = sum w[s,b,k] Re mu[s,b,k]; returns (grad_onsite, grad_class, lam0 or None).
+                           want_lam0=False, ckpt_stride=None, ws=None, stream=None, grad_hop=None):
+    """Accumulate dL/dU (grad_onsite, float64 [n]), dL/ds_c (grad_class, float64 [n_class], s_c
+    the class scales) and, with grad_hop (float64 [n, max_nn, 2]), (dL/dRe H_ij, dL/dIm H_ij) of
+    every stored entry on its own, for L = sum w[s,b,k] Re mu[s,b,k]; returns
+    (grad_onsite, grad_class, lam0 or None).
 
     ckpt_stride: 1 keeps every forward vector (no recomputation), >= 2 checkpoints every that
     many steps, 0 every ceil(sqrt(M)); None (default) takes 1 when its workspace fits in
@@ -606,9 +610,10 @@ def gpuqt_moments_backward(H: Hamiltonian, phiL, phiR, w, grad_onsite=None, grad
         grad_onsite = torch.zeros(H.n, dtype=torch.float64, device=phiR.device)
     lam0 = torch.empty_like(phiR) if want_lam0 else None
     ws, nb = _workspace(H, OP_MOMENTS_BACKWARD, B, M, ckpt_stride, ws, phiR, stream)
+    _entry_grad_check(H, grad_hop)
     _check(lib().gpuqt_moments_backward(H.handle, B, _ptr(phiL), _ptr(phiR), M, _ptr(w),
-                                        _ptr(grad_onsite), _ptr(grad_class), _ptr(lam0), ckpt_stride,
-                                        _ptr(ws), nb, _stream(stream)), "gpuqt_moments_backward")
+                                        _ptr(grad_onsite), _ptr(grad_class), _ptr(grad_hop), _ptr(lam0),
+                                        ckpt_stride, _ptr(ws), nb, _stream(stream)), "gpuqt_moments_backward")
     return grad_onsite, grad_class, lam0
 
 
@@ -680,8 +685,9 @@ def gpuqt_vac_backward_tape(H: Hamiltonian, phi, dt, w, tape, grad_onsite=None, 
 
 
 def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=None, Np: int = 0,
-                       ckpt_stride=None, time_stride=None, ws=None, stream=None):
-    """Accumulate dL/dU and dL/deps_c for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M]).
+                       ckpt_stride=None, time_stride=None, ws=None, stream=None, grad_hop=None):
+    """Accumulate dL/dU, dL/ds_c and (grad_hop, float64 [n, max_nn, 2]) the per-entry hopping
+    gradients for L = sum w[k,s,b,n] C^VAC rows (w float64 [n_t,n_seg,B,M]).
 
     ckpt_stride: 1 keeps every forward vector (two-chain reverse of each row's moments), 0
     recomputes from checkpoints; None (default) takes 1 when its workspace fits in
@@ -717,11 +723,35 @@ def gpuqt_vac_backward(H: Hamiltonian, phi, dt, w, grad_onsite=None, grad_class=
     if ws is None:
         ws = _scratch(gpuqt_vac_backward_workspace_size(H, B, dt, M, Np, ckpt_stride, time_stride), phi, stream)
     nb = int(ws.numel() * ws.element_size())
+    _entry_grad_check(H, grad_hop)
     _check(lib().gpuqt_vac_backward(H.handle, B, _ptr(phi), dt.shape[0], _ptr(dt), M, Np, _ptr(w),
-                                    _ptr(grad_onsite), _ptr(grad_class), int(ckpt_stride), int(time_stride),
-                                    _ptr(ws), nb, _stream(stream)),
+                                    _ptr(grad_onsite), _ptr(grad_class), _ptr(grad_hop), int(ckpt_stride),
+                                    int(time_stride), _ptr(ws), nb, _stream(stream)),
            "gpuqt_vac_backward")
     return grad_onsite, grad_class
+
+
+def _entry_grad_check(H: Hamiltonian, g):
+    if g is None:
+        return
+    import torch
+    shape = (H.n, int(H.info.max_nn), 2)
+    if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.float64 and g.is_contiguous()
+            and tuple(g.shape) == shape):
+        raise ValueError(f"per-entry gradients must be a contiguous float64 CUDA tensor of shape {shape}")
+
+
+def gpuqt_tie_entry_gradient(H: Hamiltonian, untied, out=None, stream=None):
+    """Hermitian tie of per-entry gradients [n, max_nn, 2]: each bond's gradient with respect to
+    (Re h, Im h), h = H_ij = conj(H_ji), stored at both of its entries (the partner as (re, -im))."""
+    import torch
+    _entry_grad_check(H, untied)
+    if out is None:
+        out = torch.empty_like(untied)
+    _entry_grad_check(H, out)
+    _check(lib().gpuqt_tie_entry_gradient(H.handle, _ptr(untied), _ptr(out), _stream(stream)),
+           "gpuqt_tie_entry_gradient")
+    return out
 
 
 def gpuqt_kpm_reconstruct_adjoint(g, energies, M: int, energy_max: float, volume: float,

@@ -5,9 +5,8 @@ hopping-class scales s (float64 tensor [n_class]; every hopping of class c
 is s_c times the hopping given when the handle was built).  DeltaE stays fixed.
 Forward and backward both set the handle to the given parameter values
 (gpuqt_update_h_values) before running, so interleaved calls stay consistent.
-
-The library returns dL/deps_c for the relative change H -> (1 + eps_c) H on
-class c; at scale s_c this is s_c dL/ds_c, hence the division below.
+The library's class gradients are dL/ds_c themselves (taken against the
+build-time hoppings), so they are finite at every scale, s_c = 0 included.
 """
 from __future__ import annotations
 
@@ -40,7 +39,7 @@ class Moments(torch.autograd.Function):
         gU = torch.zeros_like(onsite)
         gC = torch.zeros(scales.shape[0], dtype=torch.float64, device=onsite.device)
         Bd.gpuqt_moments_backward(H, phi, phi, g.contiguous(), gU, gC)
-        return gU, (gC.to(scales.device) / scales), None, None, None
+        return gU, gC.to(scales.device), None, None, None
 
 
 class VAC(torch.autograd.Function):
@@ -79,7 +78,7 @@ class VAC(torch.autograd.Function):
             ctx.tape = None
         else:
             Bd.gpuqt_vac_backward(H, phi, ctx.dt, g.contiguous(), gU, gC, Np=ctx.Np)
-        return gU, (gC.to(scales.device) / scales), None, None, None, None, None
+        return gU, gC.to(scales.device), None, None, None, None, None
 
 
 class KPM(torch.autograd.Function):

@@ -376,14 +376,15 @@ struct BwdSource {
 };
 
 // Reverse of the M-step recurrence started at phiR, with phiL the adjoint
-// source: when gU is set, parameter terms go to gU and (nc > 0) gcp, with the
+// source: when gU is set, parameter terms go to gU, (nc > 0) gcp and (gH set)
+// the per-entry gradients [n][max_nn] (re, im), with the
 // forward vectors recomputed from checkpoints every s steps; lam0 (if set)
 // receives sum_n conj(c_n) T_n phiL (accumulated when acc0).  vec: at least
 // backward_vectors(M, s) workspace vectors.
 gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const double2* pR, int M,
                           const BwdSource& src, double* gU, double* gcp, int nc, double2* lam0,
                           bool acc0, int s, double2* const* vec, hipStream_t sm,
-                          double2* const* recorded = nullptr) {
+                          double2* const* recorded = nullptr, double* gH = nullptr) {
   // recorded (s = 1 with parameter terms): v_1 .. v_{M-2} = T_n pR already computed
   const DevMat D = h->view(B);                  // adjoint steps: primary plan (class partials)
   const DevMat F = h->view(B, FAM_MOMENT);      // forward recomputation: no partials
@@ -408,6 +409,8 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
     a.gU = gU;
     a.gcp = gcp;
     a.cls = h->d_cls;
+    a.gH = gU ? gH : nullptr;
+    a.ldH = h->max_nn_in;
     a.Jtab = src.Jtab;
     a.ldJ = src.ldJ;
     a.accumulate = 0;
@@ -476,6 +479,7 @@ gpuqt_status run_backward(const Handle* h, int B, const double2* pL, const doubl
     a.f_rec = 1.0;
     a.gU = nullptr;
     a.gcp = nullptr;
+    a.gH = nullptr;
     a.accumulate = acc0 ? 1 : 0;
     HIP_TRY(launch_adjoint_step(D, h->hop_mode, B, 0, a, sm));
   }
@@ -677,6 +681,8 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_blk0, seg_blk0.data(), seg_blk0.size() * 4);
   up((void**)&h->d_seg_dE, L.seg_dE.data(), L.seg_dE.size() * 8);
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
+  up((void**)&h->d_seg_hop0, L.seg_hop.data(), L.seg_hop.size() * 8);
+  h->max_nn_in = desc->max_nn;
   // plans for fewer resident workgroups per CU, and each hot family's occupancy
   h->d_plans[kPerCU - 1] = h->d_plan;
   h->d_blk0s[kPerCU - 1] = h->d_seg_blk0;
@@ -746,7 +752,7 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
-                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_hop0, h->d_bound,
+                  h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_seg_hop0, h->d_hop0, h->d_bound,
                   h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab, h->d_offtab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -781,6 +787,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->device_bytes = h->device_bytes;
   info->kernel_variant = h->variant_code();
   info->family_caps = h->family_caps_code();
+  info->max_nn = h->max_nn_in;
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -1191,8 +1198,8 @@ gpuqt_status gpuqt_msd(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t, co
 
 gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, const double* phiR,
                                     int32_t M, const double* w, double* grad_onsite,
-                                    double* grad_class, double* lam0, int32_t ckpt_stride,
-                                    void* ws, size_t ws_bytes, void* stream) {
+                                    double* grad_class, double* grad_hop, double* lam0,
+                                    int32_t ckpt_stride, void* ws, size_t ws_bytes, void* stream) {
   const Handle* h = reinterpret_cast<const Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
   if (!valid_B(B)) return fail(GPUQT_ERR_UNSUPPORTED, "B must be 1, 2, 4, 8 or 16");
@@ -1201,7 +1208,10 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   gpuqt_status st;
   if ((st = check_vec(phiL, "phiL")) || (st = check_vec(phiR, "phiR"))) return st;
   if (!w) return fail(GPUQT_ERR_ARG, "w is NULL");
-  if (!grad_onsite && grad_class) return fail(GPUQT_ERR_ARG, "grad_class needs grad_onsite");
+  if (!grad_onsite && (grad_class || grad_hop))
+    return fail(GPUQT_ERR_ARG, "grad_class and grad_hop need grad_onsite");
+  if (grad_hop && (reinterpret_cast<uintptr_t>(grad_hop) & 7u))
+    return fail(GPUQT_ERR_ARG, "grad_hop is not 8-byte aligned");
   if (lam0 && !aligned16(lam0)) return fail(GPUQT_ERR_ARG, "lam0 is not 16-byte aligned");
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
@@ -1217,13 +1227,15 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
   double* gcp = reinterpret_cast<double*>(base + W.off_part);
   const int nc = grad_class ? class_stride(h->n_class) : 0;
   if (nc) HIP_TRY(launch_zero(gcp, (int64_t)h->G * nc, sm));
-  if (s == 1 && phiL == phiR) {   // Hermitian set, every vector kept: one-chain reverse
+  // per-entry gradients: the reverse of the plain recurrence (the product-identity
+  // forms use H^+ = H, which an entry on its own does not keep)
+  if (s == 1 && !grad_hop && phiL == phiR) {   // Hermitian set, every vector kept: one-chain reverse
     if ((st = run_backward_sym(h, B, reinterpret_cast<const double2*>(phiL), M, w, grad_onsite, gcp, nc,
                                reinterpret_cast<double2*>(lam0), false, vec.data(),
                                reinterpret_cast<double*>(base + W.off_J),
                                reinterpret_cast<double2*>(base + W.off_part) + 2 * (int64_t)h->G * B, sm)))
       return st;
-  } else if (s == 1) {   // every forward vector kept: reverse of the two-chain form
+  } else if (s == 1 && !grad_hop) {   // every forward vector kept: reverse of the two-chain form
     if ((st = run_backward_pair(h, B, reinterpret_cast<const double2*>(phiL),
                                 reinterpret_cast<const double2*>(phiR), M, w, grad_onsite, gcp, nc,
                                 nullptr, false, reinterpret_cast<double2*>(lam0), false, vec.data(),
@@ -1235,7 +1247,7 @@ gpuqt_status gpuqt_moments_backward(gpuqt_h hh, int32_t B, const double* phiL, c
     src.wts = w;
     if ((st = run_backward(h, B, reinterpret_cast<const double2*>(phiL),
                            reinterpret_cast<const double2*>(phiR), M, src, grad_onsite, gcp, nc,
-                           reinterpret_cast<double2*>(lam0), false, s, vec.data(), sm)))
+                           reinterpret_cast<double2*>(lam0), false, s, vec.data(), sm, nullptr, grad_hop)))
       return st;
   }
   if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
@@ -1286,15 +1298,17 @@ gpuqt_status gpuqt_vac_backward_workspace_size(gpuqt_h hh, int32_t B, int32_t n_
 
 static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* phi, int32_t n_t,
                                       const double* dt, int32_t M, int32_t Np, const double* w,
-                                      double* grad_onsite, double* grad_class, int32_t ckpt_stride,
-                                      int32_t time_stride, void* tape, size_t tape_bytes, void* ws,
-                                      size_t ws_bytes, void* stream) {
+                                      double* grad_onsite, double* grad_class, double* grad_hop,
+                                      int32_t ckpt_stride, int32_t time_stride, void* tape, size_t tape_bytes,
+                                      void* ws, size_t ws_bytes, void* stream) {
   gpuqt_status st = check_series(h, B, phi, n_t, dt, M, Np, w);
   if (st) return st;
   if (ckpt_stride != 0 && ckpt_stride != 1) return fail(GPUQT_ERR_ARG, "ckpt_stride must be 0 or 1");
   if (time_stride < 0) return fail(GPUQT_ERR_ARG, "time_stride must be >= 0");
   const bool keep = ckpt_stride == 1 || tape;
   if (!grad_onsite) return fail(GPUQT_ERR_ARG, "grad_onsite is NULL");
+  if (grad_hop && (reinterpret_cast<uintptr_t>(grad_hop) & 7u))
+    return fail(GPUQT_ERR_ARG, "grad_hop is not 8-byte aligned");
   if (grad_class && h->n_class > 4)
     return fail(GPUQT_ERR_UNSUPPORTED, "class gradients support at most 4 hopping classes");
   if (n_t == 0 || M == 0) return GPUQT_OK;
@@ -1402,7 +1416,7 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
   if (!tape && ts > 1 && (st = load_segment((n_t - 1) / ts))) return st;
   for (int k = n_t - 1; k >= 0; --k) {
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY, psiL(k), phiL, sm));
-    if (keep) {
+    if (keep && !grad_hop) {
       // moments of row k by the two-chain reverse: parameter terms,
       // gphiL = sum_n w_n T_n psi_R(k) and gR += sum_n w_n T_n phiL in one pass
       const std::vector<double2*> rec = tape ? T.chains(k) : std::vector<double2*>();
@@ -1414,9 +1428,11 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
     } else {
       BwdSource src;
       src.wts = w + row * k;
-      // moments of row k: parameter terms, and gR += sum_n w_n T_n phiL
+      // moments of row k: parameter terms, and gR += sum_n w_n T_n phiL (with
+      // per-entry gradients also when every vector is kept: the plain
+      // recurrence, not the two-chain form, whose pool it fits)
       if ((st = run_backward(h, B, phiL, psiR(k), M, src, grad_onsite, gcp, nc, gR[cr], true, s,
-                             pool.data(), sm)))
+                             pool.data(), sm, nullptr, grad_hop)))
         return st;
       // gphiL = sum_n w_n T_n psi_R(k) (no parameter terms)
       if ((st = run_backward(h, B, psiR(k), phiL, M, src, nullptr, nullptr, 0, gphiL, false, s,
@@ -1426,6 +1442,8 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
     // phiL = V psi_L: gL += V gphiL, class terms of V
     HIP_TRY(launch_commutator(D, h->hop_mode, B, GPUQT_VELOCITY | kAccumulate, gphiL, gL[cl], sm));
     if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gphiL, psiL(k), h->d_cls, gcp, sm));
+    if (grad_hop)
+      HIP_TRY(launch_velocity_entry_grad(D, h->hop_mode, B, gphiL, psiL(k), grad_hop, h->max_nn_in, sm));
     if (k == 0) break;
     // the reverse through U(-dt_{k-1}) needs the states of row k - 1
     if (!tape && ts > 1 && (k - 1) / ts != seg && (st = load_segment((k - 1) / ts))) return st;
@@ -1441,26 +1459,41 @@ static gpuqt_status vac_backward_impl(const Handle* h, int32_t B, const double* 
     const std::vector<double2*> rec = tape ? T.evolution(k - 1, npk) : std::vector<double2*>();
     const bool have = tape && npk >= 3;
     if ((st = run_backward(h, B, gL[cl], psiL(k - 1), npk, ev, grad_onsite, gcp, nc, gL[cl ^ 1], false,
-                           s, pool.data(), sm, have ? rec.data() : nullptr)))
+                           s, pool.data(), sm, have ? rec.data() : nullptr, grad_hop)))
       return st;
     if ((st = run_backward(h, B, gR[cr], psiR(k - 1), npk, ev, grad_onsite, gcp, nc, gR[cr ^ 1], false,
-                           s, pool.data(), sm, have ? rec.data() + (npk - 1) : nullptr)))
+                           s, pool.data(), sm, have ? rec.data() + (npk - 1) : nullptr, grad_hop)))
       return st;
     cl ^= 1;
     cr ^= 1;
   }
   // psi_R(0) = V phi: class terms of V
   if (nc) HIP_TRY(launch_velocity_class_grad(D, h->hop_mode, B, nc, gR[cr], ph, h->d_cls, gcp, sm));
+  if (grad_hop) HIP_TRY(launch_velocity_entry_grad(D, h->hop_mode, B, gR[cr], ph, grad_hop, h->max_nn_in, sm));
   if (nc) HIP_TRY(launch_reduce_classes(gcp, h->G, nc, h->n_class, grad_class, sm));
   return GPUQT_OK;
 }
 
 gpuqt_status gpuqt_vac_backward(gpuqt_h hh, int32_t B, const double* phi, int32_t n_t,
                                 const double* dt, int32_t M, int32_t Np, const double* w,
-                                double* grad_onsite, double* grad_class, int32_t ckpt_stride, int32_t time_stride,
-                                void* ws, size_t ws_bytes, void* stream) {
+                                double* grad_onsite, double* grad_class, double* grad_hop, int32_t ckpt_stride,
+                                int32_t time_stride, void* ws, size_t ws_bytes, void* stream) {
   return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
-                           grad_class, ckpt_stride, time_stride, nullptr, 0, ws, ws_bytes, stream);
+                           grad_class, grad_hop, ckpt_stride, time_stride, nullptr, 0, ws, ws_bytes, stream);
+}
+
+gpuqt_status gpuqt_tie_entry_gradient(gpuqt_h hh, const double* untied, double* tied, void* stream) {
+  const Handle* h = reinterpret_cast<const Handle*>(hh);
+  if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
+  if (!untied || !tied) return fail(GPUQT_ERR_ARG, "untied or tied is NULL");
+  if (untied == tied) return fail(GPUQT_ERR_ARG, "untied and tied must be distinct buffers");
+  if ((reinterpret_cast<uintptr_t>(untied) & 7u) || (reinterpret_cast<uintptr_t>(tied) & 7u))
+    return fail(GPUQT_ERR_ARG, "untied or tied is not 8-byte aligned");
+  gpuqt_status st;
+  if ((st = check_device(h))) return st;
+  HIP_TRY(launch_tie_entries(h->view(1), h->hop_mode, h->n, h->max_nn_in, untied, tied,
+                             static_cast<hipStream_t>(stream)));
+  return GPUQT_OK;
 }
 
 gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h hh, int32_t B, int32_t n_t, const double* dt,
@@ -1480,7 +1513,7 @@ gpuqt_status gpuqt_vac_backward_tape(gpuqt_h hh, int32_t B, const double* phi, i
                                      size_t ws_bytes, void* stream) {
   if (!tape) return fail(GPUQT_ERR_ARG, "tape is NULL");
   return vac_backward_impl(reinterpret_cast<const Handle*>(hh), B, phi, n_t, dt, M, Np, w, grad_onsite,
-                           grad_class, 1, 1, const_cast<void*>(tape), tape_bytes, ws, ws_bytes, stream);
+                           grad_class, nullptr, 1, 1, const_cast<void*>(tape), tape_bytes, ws, ws_bytes, stream);
 }
 
 gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, void* stream,

@@ -76,6 +76,20 @@ __device__ __forceinline__ double2 hop_entry(const DevMat& A, int64_t e, bool ok
     return A.htab[ldg<NT>(A.hidx + e)];
   }
 }
+// The build-time hopping of entry e (before class scales): class gradients are
+// derivatives with respect to the scale s_c of H_c = s_c x (build-time H_c).
+template <int HOP>
+__device__ __forceinline__ double2 hop0_entry(const DevMat& A, int64_t e, bool ok, int seg) {
+  if constexpr (HOP == HOP_UNIFORM) {
+    return make_double2(ok ? A.seg_hop0[seg] : 0.0, 0.0);
+  } else if constexpr (HOP == HOP_REAL) {
+    return make_double2(A.hop0[e], 0.0);
+  } else if constexpr (HOP == HOP_COMPLEX) {
+    return reinterpret_cast<const double2*>(A.hop0)[e];
+  } else {
+    return A.htab0[A.hidx[e]];
+  }
+}
 template <int HOP, bool NT = false>
 __device__ __forceinline__ double dx_entry(const DevMat& A, int64_t e) {
   if constexpr (HOP == HOP_DICT) {
@@ -285,6 +299,44 @@ __device__ __forceinline__ void for_rows_pf(const DevMat& A, const BlkPlan& P, F
       for (int j = 0; j < K; ++j) kc[j] = kn[j];
       a0 = a1;
       a1 = a2;
+    }
+  }
+}
+
+// Sum of v over the B lanes of one row (adjacent lanes, B a power of two).
+template <int B>
+__device__ __forceinline__ double row_lanes_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < B; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Per-entry gradients of row r: for every entry j (column c, not padding),
+// g = f * sum over the row's B lanes of conj(lam) u_c, accumulated as
+// (Re g, -Im g) at gH[r*ldH + j] by the row's first lane.  Every lane of the
+// row calls this (the lane sums are shuffles).  Slot j of the sliced layout is
+// slot j of the row in the input neighbour list.
+template <int B, int HOP, int K>
+__device__ __forceinline__ void row_entry_grads(const DevMat& A, int64_t r, int b, double2 lam,
+                                                const double2* __restrict__ u, double f, double* gH, int ldH) {
+  const int S = 1 << A.S_log2;
+  const int64_t sl = r >> A.S_log2;
+  const int64_t p0 = K > 0 ? sl * ((int64_t)K << A.S_log2) : A.slice_ptr[sl];
+  const int64_t e0 = p0 + (r & (S - 1));
+  const int w = K > 0 ? K : (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+  for (int j = 0; j < w; ++j) {
+    const int64_t e = e0 + (int64_t)j * S;
+    int64_t cc;
+    const bool ok = col_entry<HOP>(A, r, e, &cc);
+    const double2 x = u[cc * B + b];
+    double gr = lam.x * x.x + lam.y * x.y;   // conj(lam) x
+    double gi = lam.x * x.y - lam.y * x.x;
+    gr = row_lanes_sum<B>(gr);
+    gi = row_lanes_sum<B>(gi);
+    if (ok && b == 0) {
+      double* p = gH + 2 * (r * (int64_t)ldH + j);
+      p[0] += f * gr;
+      p[1] -= f * gi;
     }
   }
 }

@@ -87,6 +87,11 @@ struct DevMat {
   const int32_t* units;      // banded unit order for this block width (first row of each unit), or NULL
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
+  // the hoppings given at build time (before class scales), for class gradients
+  // dL/ds_c: hop0 like hop, htab0 like htab, seg_hop0 like seg_hop
+  const double* hop0;
+  const double2* htab0;
+  const double* seg_hop0;
   int64_t n;
   int32_t S_log2;
   int32_t G;
@@ -144,12 +149,14 @@ struct Handle {
   double* d_dxtab = nullptr;       // HOP_DICT [T]
   int32_t* d_offtab = nullptr;     // HOP_DICT [T]
   int32_t dict_size = 0;
+  int32_t max_nn_in = 0;           // neighbour slots per orbital of the descriptor (per-entry gradients)
   double* d_diag = nullptr;
   int32_t* d_cls = nullptr;
   BlkPlan* d_plan = nullptr;
   int32_t* d_seg_blk0 = nullptr;   // [n_seg + 1] first logical workgroup of each segment
   double* d_seg_dE = nullptr;
   double* d_seg_hop = nullptr;
+  double* d_seg_hop0 = nullptr;    // [n_seg] build-time uniform hopping / DeltaE
   // parameter updates: build-time hoppings (allocated on the first class update),
   // current class scales, per-workgroup spectrum bounds
   double* d_hop0 = nullptr;
@@ -208,6 +215,9 @@ struct Handle {
     m.plan = d_plan;
     m.seg_dE = d_seg_dE;
     m.seg_hop = d_seg_hop;
+    m.hop0 = d_hop0 ? d_hop0 : d_hop;
+    m.htab0 = reinterpret_cast<const double2*>(d_htab0 ? d_htab0 : d_htab);
+    m.seg_hop0 = d_seg_hop0;
     m.n = n;
     m.S_log2 = S_log2;
     m.G = G;
@@ -372,6 +382,8 @@ struct AdjIO {
   int32_t ldJ;
   int32_t accumulate;    // 1: out += lam (instead of out = lam)
   double2 src_phase;
+  double* gH;            // NULL, or per-entry gradients [n][ldH] (re, im) pairs, accumulated
+  int32_t ldH;           // entry slots per row of gH (the descriptor's max_nn)
 };
 // Reverse of the two-chain (product identity) moment computation: chains
 // a_k = T_k a_0, b_k = T_k b_0 and L = sum_n om_n Re r_n over the raw dots
@@ -420,6 +432,15 @@ hipError_t launch_row_bound(const DevMat& A, int hop_mode, double* bound, hipStr
 // gcp[lb][c] += Re sum_i conj(a_i) (V_c x)_i, V_c = i dx H_c (unscaled)
 hipError_t launch_velocity_class_grad(const DevMat& A, int hop_mode, int B, int nc, const double2* a,
                                       const double2* x, const int32_t* cls, double* gcp, hipStream_t s);
+// per-entry share of the velocity V = i dx H (unscaled): g_ij = i dx_ij sum_b conj(a_ib) x_jb,
+// gH[i*ldH + slot] += (Re g, -Im g)
+hipError_t launch_velocity_entry_grad(const DevMat& A, int hop_mode, int B, const double2* a, const double2* x,
+                                      double* gH, int ldH, hipStream_t s);
+// Hermitian tie of per-entry gradients [n][ldH] (re, im): an entry (i, s) -> j and the
+// q-th entry of row j pointing back to i (q = its occurrence among row i's entries to j)
+// give out = (re_is + re_jp, im_is - im_jp); entries without a partner are copied
+hipError_t launch_tie_entries(const DevMat& A, int hop_mode, int64_t n, int ldH, const double* in, double* out,
+                              hipStream_t s);
 hipError_t launch_adjoint_step(const DevMat& A, int hop_mode, int B, int nc, const AdjIO& io,
                                hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
       }
       if (NC > 0 && v) {
         const double2 vv = v[cc * B + b];
-        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vv) : cscale(he.x, vv);
+        const double2 he0 = hop0_entry<HOP>(A, e, ok, P.seg);
+        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he0, vv) : cscale(he0.x, vv);
         const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(DevMat A, AdjIO io) {
 #pragma unroll
       for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
         if (NC > 0) gc[q] += io.f * (lam.x * hv[q].x + lam.y * hv[q].y);
+      if (io.gH) row_entry_grads<B, HOP, K>(A, r, b, lam, v, io.f * inv_dE, io.gH, io.ldH);
     }
   });
   if (NC == 0 || !v) return;
@@ -157,8 +159,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_pair_step(DevMat A, AdjPairI
       }
       if (NC > 0 && grad) {
         const double2 va = io.a_m1[cc * B + b], vb = io.b_m1[cc * B + b];
-        const double2 ta = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, va) : cscale(he.x, va);
-        const double2 tb = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, vb) : cscale(he.x, vb);
+        const double2 he0 = hop0_entry<HOP>(A, e, ok, P.seg);
+        const double2 ta = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he0, va) : cscale(he0.x, va);
+        const double2 tb = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he0, vb) : cscale(he0.x, vb);
         const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
@@ -261,7 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_sym_step(DevMat A, AdjPairIO
       }
       if (NC > 0 && grad) {
         const double2 v = io.a_m1[cc * B + b];
-        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he, v) : cscale(he.x, v);
+        const double2 he0 = hop0_entry<HOP>(A, e, ok, P.seg);
+        const double2 t = (HOP == HOP_COMPLEX || HOP == HOP_DICT) ? cmul(he0, v) : cscale(he0.x, v);
         const int cls = (NC > 1) ? (ok ? io.cls[HOP == HOP_DICT ? (int64_t)A.hidx[e] : e] : 0) : 0;
 #pragma unroll
         for (int q = 0; q < (NC > 0 ? NC : 1); ++q)
@@ -343,7 +347,6 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
                                                                 double* __restrict__ gcp) {
   const int lb = logical_block(A.G);
   const BlkPlan P = A.plan[lb];
-  const double hu = (HOP == HOP_UNIFORM) ? A.seg_hop[P.seg] : 0.0;
   const double e = A.seg_dE[P.seg];
   const int b = threadIdx.x & (B - 1);
   const int S = 1 << A.S_log2;
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
       const int64_t en = e0 + (int64_t)j * S;
       int64_t c;
       if (!col_entry<HOP>(A, r, en, &c)) continue;
-      const double2 he = hop_entry<HOP>(A, en, true, hu);
+      const double2 he = hop0_entry<HOP>(A, en, true, P.seg);
       const double2 t = cmul(he, x[c * B + b]);
       const double s = e * dx_entry<HOP>(A, en);
       const double2 vt = make_double2(-s * t.y, s * t.x);      // i e dx H~ x
@@ -388,6 +391,83 @@ __global__ __launch_bounds__(kBlock) void k_velocity_class_grad(DevMat A, const 
     for (int wv = 0; wv < kBlock / 64; ++wv) s += sh[wv][threadIdx.x];
     gcp[(int64_t)lb * NC + threadIdx.x] += s;
   }
+}
+
+// Per-entry share of a^+ V x, V_ij = i dx_ij H_ij (unscaled):
+// g_ij = i dx_ij sum_b conj(a_ib) x_jb, gH[i*ldH + slot] += (Re g, -Im g).
+template <int B, int HOP>
+__global__ __launch_bounds__(kBlock) void k_velocity_entry_grad(DevMat A, const double2* __restrict__ a,
+                                                                const double2* __restrict__ x,
+                                                                double* __restrict__ gH, int ldH) {
+  const BlkPlan P = A.plan[logical_block(A.G)];
+  const int b = threadIdx.x & (B - 1);
+  const int S = 1 << A.S_log2;
+  for_rows<B>(A, P, [&](int64_t r) {
+    const double2 ar = a[r * B + b];
+    const int64_t sl = r >> A.S_log2;
+    const int64_t p0 = A.slice_ptr[sl];
+    const int64_t e0 = p0 + (r & (S - 1));
+    const int w = (int)((A.slice_ptr[sl + 1] - p0) >> A.S_log2);
+    for (int j = 0; j < w; ++j) {
+      const int64_t en = e0 + (int64_t)j * S;
+      int64_t c;
+      const bool ok = col_entry<HOP>(A, r, en, &c);
+      const double2 xv = x[c * B + b];
+      double zr = ar.x * xv.x + ar.y * xv.y;   // z = conj(a) x
+      double zi = ar.x * xv.y - ar.y * xv.x;
+      zr = row_lanes_sum<B>(zr);
+      zi = row_lanes_sum<B>(zi);
+      if (ok && b == 0) {
+        const double d = dx_entry<HOP>(A, en);   // g = i d z: (Re g, -Im g) = (-d Im z, -d Re z)
+        double* p = gH + 2 * (r * (int64_t)ldH + j);
+        p[0] -= d * zi;
+        p[1] -= d * zr;
+      }
+    }
+  });
+}
+
+// Hermitian tie of per-entry gradients, one thread per (row i, slot s): entry
+// (i, s) -> j is the q-th of row i's entries pointing to j; its partner is the
+// q-th entry of row j pointing to i.  out = (re_is + re_jp, im_is - im_jp), or
+// the entry's own value without a partner (and for padding slots).
+template <int HOP>
+__global__ __launch_bounds__(256) void k_tie_entries(DevMat A, int64_t n, int ldH, const double* __restrict__ in,
+                                                     double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ldH) return;
+  const int64_t i = t / ldH;
+  const int s = (int)(t - i * ldH);
+  const int S = 1 << A.S_log2;
+  auto width = [&](int64_t r) { const int64_t sl = r >> A.S_log2; return (int)((A.slice_ptr[sl + 1] - A.slice_ptr[sl]) >> A.S_log2); };
+  auto entry = [&](int64_t r, int j) { return A.slice_ptr[r >> A.S_log2] + (int64_t)j * S + (r & (S - 1)); };
+  double re = in[2 * t], im = in[2 * t + 1];
+  int64_t j = -1;
+  if (s < width(i)) {
+    int64_t c;
+    if (col_entry<HOP>(A, i, entry(i, s), &c)) j = c;
+  }
+  if (j >= 0) {
+    int q = 0;
+    for (int u = 0; u < s; ++u) {
+      int64_t c;
+      if (col_entry<HOP>(A, i, entry(i, u), &c) && c == j) ++q;
+    }
+    const int wj = width(j);
+    for (int u = 0; u < wj && u < ldH; ++u) {
+      int64_t c;
+      if (col_entry<HOP>(A, j, entry(j, u), &c) && c == i) {
+        if (q == 0) {
+          re += in[2 * (j * ldH + u)];
+          im -= in[2 * (j * ldH + u) + 1];
+          break;
+        }
+        --q;
+      }
+    }
+  }
+  out[2 * t] = re;
+  out[2 * t + 1] = im;
 }
 
 // diag[r] = onsite[r] / DeltaE_seg (new on-site energies)
@@ -555,6 +635,28 @@ hipError_t launch_velocity_class_grad(const DevMat& A, int hop_mode, int B, int 
       default: k_velocity_class_grad<Bv, Hv, 4><<<dim3(A.G), kBlock, 0, s>>>(A, a, x, cls, gcp); break;
     }
   });
+}
+
+hipError_t launch_velocity_entry_grad(const DevMat& A, int hop_mode, int B, const double2* a, const double2* x,
+                                      double* gH, int ldH, hipStream_t s) {
+  return dispatch_bh(B, hop_mode, [&](auto Bc, auto Hc) {
+    k_velocity_entry_grad<decltype(Bc)::value, decltype(Hc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, a, x, gH,
+                                                                                                  ldH);
+  });
+}
+
+hipError_t launch_tie_entries(const DevMat& A, int hop_mode, int64_t n, int ldH, const double* in, double* out,
+                              hipStream_t s) {
+  const int64_t total = n * (int64_t)ldH;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g((unsigned)blocks);
+  if (hop_mode == HOP_UNIFORM) k_tie_entries<HOP_UNIFORM><<<g, 256, 0, s>>>(A, n, ldH, in, out);
+  else if (hop_mode == HOP_REAL) k_tie_entries<HOP_REAL><<<g, 256, 0, s>>>(A, n, ldH, in, out);
+  else if (hop_mode == HOP_COMPLEX) k_tie_entries<HOP_COMPLEX><<<g, 256, 0, s>>>(A, n, ldH, in, out);
+  else k_tie_entries<HOP_DICT><<<g, 256, 0, s>>>(A, n, ldH, in, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_onsite(const DevMat& A, const double* onsite, double* diag, hipStream_t s) {

@@ -258,6 +258,30 @@ def concat_segments(models: List[Model]) -> Model:
                  hop_class=np.concatenate(cls) if n_class > 1 else None, n_class=n_class, name="segments")
 
 
+def bond_disorder(m: Model, spread: float, seed: int, max_phase: float = 0.0) -> Model:
+    """m with every bond's hopping multiplied by (1 + spread * u), u uniform in [-1, 1], and
+    (max_phase > 0) a phase exp(i phi), phi uniform in [-max_phase, max_phase], drawn once per
+    bond so that H stays Hermitian: the q-th entry of row i pointing to j and the q-th entry
+    of row j pointing to i hold h and conj(h)."""
+    rng = np.random.default_rng(seed)
+    base = dense_hop(m)
+    cplx = max_phase > 0 or np.iscomplexobj(base)
+    hop = np.array(base, dtype=np.complex128 if cplx else np.float64, copy=True)
+    seen = {}
+    for i in range(m.n):
+        for s in range(int(m.nn[i])):
+            j = int(m.nbr[i, s])
+            q = sum(1 for t in range(s) if m.nbr[i, t] == j)
+            key = (min(i, j), max(i, j), q)
+            if key not in seen:
+                f = 1.0 + spread * rng.uniform(-1.0, 1.0)
+                ph = np.exp(1j * rng.uniform(-max_phase, max_phase)) if max_phase > 0 else 1.0
+                seen[key] = (i, f * ph)
+            first, g = seen[key]
+            hop[i, s] = hop[i, s] * (g if (first == i or not cplx) else np.conj(g))
+    return dataclasses.replace(m, hop=hop, name=m.name + "_bond")
+
+
 def dense_hop(m: Model) -> np.ndarray:
     """The hopping array with the paper's default (-1) filled in."""
     if m.hop is None:
