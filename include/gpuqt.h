@@ -147,6 +147,7 @@ typedef struct {
                                 cap of kernel_variant, else 1 + that family's own cap (1: none) */
   int32_t max_nn;            /* neighbour slots per row of the build descriptor: the row stride
                                 of per-entry hopping gradients */
+  int32_t pencil_mask;       /* bit log2(B) set: block width B has a pencil row order */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -397,6 +398,11 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * streamed data at this B, and for B >= 2 with two bands per period for
  * periods of 1024 rows or more: workgroups then sweep bands of W rows of the
  * period one period after another, so rows D apart are visited W rows apart);
+ * bit 6 (with bit 1): the pencil order instead (built for segments with a row
+ * period of at least 128 rows: the four wavefronts of a workgroup take the
+ * same rows of four consecutive periods at once, so a row's neighbours one
+ * period away are the rows a sibling wavefront on the same compute unit is
+ * loading, and the L1 serves them);
  * bits 2-5: a cap on resident workgroups per compute unit (0: as many as the
  * kernel's registers allow).  Each of the four load/order variants is timed
  * uncapped and at every cap of 2..6 below its occupancy limit: fewer waves in
@@ -409,19 +415,23 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  *   ws : device workspace of gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0) bytes
  *        (eight vectors); one of three vectors plus the partial sums tunes the
  *        Hermitian step only.
- *   times_us : NULL or HOST [4], microseconds per step of load/order variants 0..3, each at
- *              its best cap (0 for a banded variant when this B has no banded order).
+ *   times_us : NULL or HOST [6], microseconds per step of load/order variants 0..3 and of
+ *              the pencil order with plain (4) and non-temporal (5) loads, each at its best
+ *              cap (0 for an order this B does not have).
  * Not safe while other calls on the handle are in flight.
  */
 gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
                             double *times_us);
 
 /* Set the kernel variant without measuring, with the bits of gpuqt_h_info_t.kernel_variant:
- * load variant in bits 0-1, per-CU cap 0..8 in bits 2-5, bits 6-7 zero, and from bit 8 three
- * bits per kernel family (0: the per-CU cap, 1 + c: cap c of 0..6), so a code read from
- * gpuqt_h_info after gpuqt_autotune reproduces the tuned configuration.  The banded bit only
- * takes effect for block widths that have a banded order (gpuqt_h_info_t.banded_mask).
- * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8 or bits set above the families. */
+ * load variant in bits 0-1, per-CU cap 0..8 in bits 2-5, the pencil order in bit 6 (with
+ * bit 1), bit 7 zero, and from bit 8 three bits per kernel family (0: the per-CU cap, 1 + c:
+ * cap c of 0..6), so a code read from gpuqt_h_info after gpuqt_autotune reproduces the tuned
+ * configuration.  The banded and pencil bits only take effect for block widths that have
+ * such an order (gpuqt_h_info_t.banded_mask, pencil_mask); a pencil bit for a width without
+ * a pencil order falls back to the banded order.
+ * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8, bit 6 without bit 1, bit 7 or
+ * bits set above the families. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*
@@ -585,13 +595,15 @@ void gpuqt_model_free(gpuqt_model m);
  * and block width B (introspection; the kernels enumerate rows with the same host/device
  * rule): segments seg_offsets (HOST [n_segments+1], from 0, ascending), row period per
  * segment (HOST [n_segments] or NULL: plain order), band width band_rows (multiple of 64;
- * segments whose period exceeds it take the banded order).  Writes for every row the
+ * segments whose period exceeds it take the banded order; with pencil != 0 every segment
+ * whose period is at least 128 rows takes the pencil order of that band width instead, as
+ * gpuqt_autotune's bit 6 describes).  Writes for every row the
  * logical workgroup that visits it (block_of_row, HOST int32 [n]) and the workgroup's
  * iteration at that visit (iter_of_row, HOST int32 [n]); -1 for a row no workgroup visits.
  * GPUQT_ERR_LAYOUT if some row would be visited twice. */
 gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t *seg_offsets, const int64_t *period,
-                                 int32_t band_rows, int32_t cus, int32_t B, int32_t *block_of_row,
-                                 int32_t *iter_of_row);
+                                 int32_t band_rows, int32_t pencil, int32_t cus, int32_t B,
+                                 int32_t *block_of_row, int32_t *iter_of_row);
 
 /* Jackson damping g_n, n < M (Section 3.3):  g_n = (1 - n a) cos(pi n a) + a sin(pi n a) cot(pi a),
  * a = 1/(M+1).  g: HOST [M]. */

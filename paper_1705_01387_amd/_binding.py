@@ -54,6 +54,7 @@ class HInfo(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
         ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32), ("max_nn", ctypes.c_int32),
+        ("pencil_mask", ctypes.c_int32),
     ]
 
 
@@ -147,7 +148,8 @@ _SIGS = {
     "gpuqt_running_conductivity": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_schedule_rows": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
-                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "gpuqt_moments_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "gpuqt_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -798,12 +800,14 @@ def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=
 
 
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
-    """Time the kernel variants (plain / non-temporal loads, plain / banded row order, each
-    uncapped and at per-CU workgroup caps below its occupancy limit), keep the fastest; returns
-    us per moment step of load variants 0..3 at their best cap (0 where a variant does not
-    exist).  H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none),
-    from bit 8 the two-chain moment, MSD and two-vector evolution families' own caps."""
-    t = np.zeros(4)
+    """Time the kernel variants (plain / non-temporal loads, plain / banded / pencil row order,
+    each uncapped and at per-CU workgroup caps below its occupancy limit), keep the fastest;
+    returns us per moment step of load variants 0..3 and of the pencil order with plain and
+    non-temporal loads (entries 4, 5) at their best cap (0 where a variant does not exist).
+    H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none), bit 6 the
+    pencil order, from bit 8 the two-chain moment, MSD and two-vector evolution families'
+    own caps."""
+    t = np.zeros(6)
     ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
     info = HInfo()
@@ -814,7 +818,8 @@ def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
 
 def gpuqt_set_variant(H: Hamiltonian, variant: int):
     """Pin the kernel variant code (bit 0: non-temporal streams, bit 1: banded row order,
-    bits 2-5: resident workgroups per CU at most, 0 = no cap; from bit 8, 3 bits per kernel
+    bits 2-5: resident workgroups per CU at most, 0 = no cap; bit 6 (with bit 1): the pencil
+    order instead of the banded one; from bit 8, 3 bits per kernel
     family: 0 = that cap, 1 + c = the family's own cap c).  H.info.kernel_variant after
     gpuqt_autotune is such a code."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")
@@ -840,7 +845,7 @@ def gpuqt_autotune_cached(H: Hamiltonian, B: int = 1, ws=None, stream=None):
     """The cached variant for H's configuration at B, or gpuqt_autotune (then cached).  The
     autotuning workspace is only allocated on a miss.  Returns (times per load variant,
     whether the choice came from the cache)."""
-    t = np.zeros(4)
+    t = np.zeros(6)
     hit = ctypes.c_int32()
     if ws is None:
         st = lib().gpuqt_autotune_cached(H.handle, int(B), None, 0, _stream(stream), _ptr(t), ctypes.byref(hit))
@@ -885,15 +890,16 @@ def gpuqt_autotune_block(H: Hamiltonian, n_vectors: int, max_B: int = 16, ws=Non
     return int(best.value), us
 
 
-def gpuqt_schedule_rows(seg_offsets, period=None, band_rows=0, cus=256, B=1):
-    """Host-only: (workgroup, iteration) visiting each row under the library's row schedule."""
+def gpuqt_schedule_rows(seg_offsets, period=None, band_rows=0, cus=256, B=1, pencil=False):
+    """Host-only: (workgroup, iteration) visiting each row under the library's row schedule
+    (pencil: the pencil order of band width band_rows for segments with a period >= 128)."""
     off = np.ascontiguousarray(seg_offsets, dtype=np.int64)
     per = None if period is None else np.ascontiguousarray(period, dtype=np.int64)
     n = int(off[-1])
     blk = np.empty(n, dtype=np.int32)
     it = np.empty(n, dtype=np.int32)
-    _check(lib().gpuqt_schedule_rows(len(off) - 1, _ptr(off), _ptr(per), int(band_rows), int(cus), int(B),
-                                     _ptr(blk), _ptr(it)), "gpuqt_schedule_rows")
+    _check(lib().gpuqt_schedule_rows(len(off) - 1, _ptr(off), _ptr(per), int(band_rows), 1 if pencil else 0,
+                                     int(cus), int(B), _ptr(blk), _ptr(it)), "gpuqt_schedule_rows")
     return blk, it
 
 

@@ -733,9 +733,26 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
       else if (desc->band_rows == 0 && B >= 2 && D >= 1024) width[sg] = D / 2 / 64 * 64;
       any = any || width[sg] > 0;
     }
-    if (!any) continue;
-    banded_units(L.seg_off, h->seg_period, width, &unit_lists[lb]);
-    up((void**)&h->d_units[lb], unit_lists[lb].data(), unit_lists[lb].size() * 4);
+    if (any) {
+      banded_units(L.seg_off, h->seg_period, width, &unit_lists[lb]);
+      up((void**)&h->d_units[lb], unit_lists[lb].data(), unit_lists[lb].size() * 4);
+    }
+    // pencil order: the reuse window between a row and its neighbours one period
+    // on spans kPencil bands of units, so its band width is half the banded one
+    const int64_t Wp = desc->band_rows > 0 ? desc->band_rows
+                                           : std::max<int64_t>(256, kBandBudget / (4 * row_bytes) / 64 * 64);
+    h->pencil_rows[lb] = (int32_t)Wp;
+    std::vector<int64_t> pw(L.n_seg, 0);
+    bool anyp = false;
+    for (int sg = 0; sg < L.n_seg; ++sg) {
+      if (h->seg_period[sg] >= 128) pw[sg] = Wp;
+      anyp = anyp || pw[sg] > 0;
+    }
+    if (anyp) {
+      std::vector<int32_t> pl;
+      pencil_units(L.seg_off, h->seg_period, pw, &pl);
+      up((void**)&h->d_units_p[lb], pl.data(), pl.size() * 4);
+    }
   }
   h->seg_hop0 = L.seg_hop;
   h->class_scale.assign(h->n_class, 1.0);
@@ -757,6 +774,8 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int32_t* p : h->d_units)
+    if (p) (void)hipFree(p);
+  for (int32_t* p : h->d_units_p)
     if (p) (void)hipFree(p);
   for (int p = 0; p + 1 < kPerCU; ++p) {   // the last entries alias d_plan / d_seg_blk0
     if (h->d_plans[p]) (void)hipFree(h->d_plans[p]);
@@ -793,6 +812,9 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->banded_mask = 0;
   for (int b = 0; b < kNumB; ++b)
     if (h->d_units[b]) info->banded_mask |= 1 << b;
+  info->pencil_mask = 0;
+  for (int b = 0; b < kNumB; ++b)
+    if (h->d_units_p[b]) info->pencil_mask |= 1 << b;
   for (int s = 0; s < h->n_seg; ++s) {
     if (energy_max) energy_max[s] = h->seg_dE[s];
     if (gershgorin) gershgorin[s] = h->seg_gersh[s];
@@ -1550,9 +1572,11 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
     return GPUQT_OK;
   };
   // the Hermitian moment step (the one most calls run) of one variant and cap
+  // v: bit 0 non-temporal loads, bit 1 banded order, bit 2 the pencil order instead
   auto time_one = [&](int v, int cap, float* ms) -> gpuqt_status {
     h->nt = v & 1;
-    h->banded = v >> 1;
+    h->banded = (v >> 1) & 1;
+    h->pencil = (v >> 2) & 1;
     h->per_cu_cap = cap;
     return time_run([&] { return run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true); }, ms);
   };
@@ -1567,29 +1591,35 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   };
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
   float best = 0.0f;
-  int best_v = h->variant_code() & 63;
-  const int n_var = h->d_units[lb] ? 4 : 2;
+  int best_v = (h->nt | (h->banded << 1) | ((h->banded & h->pencil) << 2)), best_cap = h->per_cu_cap;
+  std::vector<int> vars = {0, 1};
+  if (h->d_units[lb]) vars.insert(vars.end(), {2, 3});
+  if (h->d_units_p[lb]) vars.insert(vars.end(), {6, 7});
   if (times_us)
-    for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
+    for (int v = 0; v < 6; ++v) times_us[v] = 0.0;
   float ms = 0.0f;
   st = time_one(0, 0, &ms);   // settle clocks and caches before the sweep
   std::vector<int> caps;
-  for (int v = 0; v < n_var && !st; ++v) {
+  for (int v : vars) {
+    if (st) break;
     h->nt = v & 1;
     caps_of(FAM_SYM, &caps);
+    const int slot = v < 4 ? v : v - 2;   // times_us: 0..3 load/order variants, 4, 5 pencil
     for (int cap : caps) {
       if ((st = time_one(v, cap, &ms))) break;
       const double us = 1e3 * ms / (kSteps / 2);   // per launch
-      if (times_us && (times_us[v] == 0.0 || us < times_us[v])) times_us[v] = us;
+      if (times_us && (times_us[slot] == 0.0 || us < times_us[slot])) times_us[slot] = us;
       if (best == 0.0f || ms < best) {
         best = ms;
-        best_v = v | (cap << 2);
+        best_v = v;
+        best_cap = cap;
       }
     }
   }
   h->nt = best_v & 1;
   h->banded = (best_v >> 1) & 1;
-  h->per_cu_cap = (best_v >> 2) & 15;
+  h->pencil = (best_v >> 2) & 1;
+  h->per_cu_cap = best_cap;
   // with room for their vectors, each of the two-chain moment, two-vector
   // evolution and MSD families also gets its own cap at this load variant
   const WsLayout WF = ws_layout(h, kTuneVectors, B, kSteps + 1, kTuneNp);
@@ -1631,7 +1661,7 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
 }
 
 gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets, const int64_t* period,
-                                 int32_t band_rows, int32_t cus, int32_t B, int32_t* block_of_row,
+                                 int32_t band_rows, int32_t pencil, int32_t cus, int32_t B, int32_t* block_of_row,
                                  int32_t* iter_of_row) {
   if (n_segments < 1 || !seg_offsets || !block_of_row || !iter_of_row || cus < 1 || !valid_B(B))
     return fail(GPUQT_ERR_ARG, "bad arguments to gpuqt_schedule_rows");
@@ -1651,19 +1681,31 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
     D[s] = period[s];
     banded = banded || (band_rows > 0 && D[s] > band_rows);
   }
-  if (banded) banded_units(off, D, std::vector<int64_t>(n_segments, band_rows), &units);
+  if (banded && pencil) {
+    std::vector<int64_t> pw(n_segments, 0);
+    banded = false;
+    for (int s = 0; s < n_segments; ++s)
+      if (D[s] >= 128) {
+        pw[s] = band_rows;
+        banded = true;
+      }
+    if (banded) pencil_units(off, D, pw, &units);
+  } else if (banded) {
+    banded_units(off, D, std::vector<int64_t>(n_segments, band_rows), &units);
+  }
+  const bool pen = banded && pencil;
   const int32_t* U = banded ? units.data() : nullptr;
   for (int64_t r = 0; r < n; ++r) block_of_row[r] = iter_of_row[r] = -1;
   const int RPI = kBlock / B;
   for (size_t lb = 0; lb < plan.size(); ++lb) {
     const BlkPlan& P = plan[lb];
-    const int64_t total = row_seq_len(P, U);
+    const int64_t total = pen ? pencil_seq_len(P) : row_seq_len(P, U);
     int32_t it = 0;
     for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += (int64_t)P.g * RPI, ++it) {
       for (int i = 0; i < RPI; ++i) {
         const int64_t pos = pos0 + i;
         if (pos >= total) break;
-        const int64_t r = row_at(P, U, pos);
+        const int64_t r = pen ? row_at_pencil(P, U, pos, B) : row_at(P, U, pos);
         if (r < 0) continue;
         if (r >= n || block_of_row[r] != -1) return fail(GPUQT_ERR_LAYOUT, "schedule visits a row twice");
         block_of_row[r] = (int32_t)lb;
@@ -1677,13 +1719,14 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
 gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
-  if (variant < 0 || ((variant >> 2) & 15) > kPerCU || (variant & (3 << 6)) ||
-      (variant >> (8 + 3 * kFamilies)))
+  if (variant < 0 || ((variant >> 2) & 15) > kPerCU || (variant & (1 << 7)) ||
+      ((variant >> 6) & 1 && !((variant >> 1) & 1)) || (variant >> (8 + 3 * kFamilies)))
     return fail(GPUQT_ERR_ARG,
-                "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bits 6-7 zero "
-                "and 3 bits per kernel family from bit 8");
+                "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bit 6 the pencil "
+                "order (with bit 1), bit 7 zero and 3 bits per kernel family from bit 8");
   h->nt = variant & 1;
   h->banded = (variant >> 1) & 1;
+  h->pencil = (variant >> 6) & 1;
   h->per_cu_cap = (variant >> 2) & 15;
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = (int8_t)(((variant >> (8 + 3 * f)) & 7) - 1);
   return GPUQT_OK;

@@ -195,13 +195,28 @@ __device__ __forceinline__ void row_apply(const DevMat& A, int64_t r, int b, dou
 
 // Visit the rows of this workgroup in tiles of RPI = 256/B rows: tiles j,
 // j + g, j + 2g, ... of its group's row sequence (the contiguous range
-// [r0, r1), or the units u0 .. u0 + nu of the banded order when the view has
-// one).  f(r) for each row r of the thread; all threads of the workgroup
-// iterate the same number of times.
+// [r0, r1), or the units u0 .. u0 + nu of the banded or pencil order when the
+// view has one).  f(r) for each row r of the thread; all threads of the
+// workgroup iterate the same number of times.
 template <int B, typename F>
 __device__ __forceinline__ void for_rows(const DevMat& A, const BlkPlan& P, F&& f) {
   constexpr int RPI = kBlock / B;
   const int64_t step = (int64_t)P.g * RPI;
+  if (A.pencil) {   // the same rule as row_at_pencil, per tile t
+    constexpr int RPW = 64 / B;
+    const int64_t total = pencil_seq_len(P);
+    const int32_t* __restrict__ units = A.units + P.u0;
+    const int w = threadIdx.x >> 6, l = (threadIdx.x & 63) / B;
+    for (int64_t t = P.j; t * RPI < total; t += P.g) {
+      const int64_t u = (t / B) * kPencil + w;
+      if (u < P.nu) {
+        const int64_t a = units[u];
+        const int64_t r = a + (t % B) * RPW + l;
+        if (r < (((a >> kUnitLog2) + 1) << kUnitLog2) && r < P.se) f(r);
+      }
+    }
+    return;
+  }
   if (A.units == nullptr) {   // linear: the same rule as row_at, without the call
     for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step) {
       const int64_t r = base + threadIdx.x / B;
@@ -241,6 +256,46 @@ __device__ __forceinline__ void load_keys(const DevMat& A, int64_t r, int32_t* k
   }
 }
 
+// The keys of row r split over the row's B lanes: lane b loads keys b, b + B,
+// b + 2B, ... (k[i] = key b + i B, 0 past K), so a row's keys cost ceil(K / B)
+// load instructions per wavefront instead of K; expand_keys gathers them back.
+template <int HOP, int K, int B, bool NT>
+__device__ __forceinline__ void load_keys_split(const DevMat& A, int64_t r, int32_t* k) {
+  if constexpr (B == 1) {
+    load_keys<HOP, K, NT>(A, r, k);
+  } else {
+    const int b = threadIdx.x & (B - 1);
+    const int S = 1 << A.S_log2;
+    const int64_t e0 = (r >> A.S_log2) * ((int64_t)K << A.S_log2) + (r & (S - 1));
+#pragma unroll
+    for (int i = 0; i < (K + B - 1) / B; ++i) {
+      const int j = b + i * B;
+      k[i] = 0;
+      if (j < K) {
+        if constexpr (HOP == HOP_DICT) {
+          k[i] = (int32_t)ldg<NT>(A.hidx + e0 + (int64_t)j * S);
+        } else {
+          k[i] = ldg<NT>(A.col + e0 + (int64_t)j * S);
+        }
+      }
+    }
+  }
+}
+// All K keys of the row from the split of load_keys_split: key j sits in lane
+// j mod B of the row's lanes, in its register j / B.  Every lane of the row must
+// take part (cross-lane reads).
+template <int K, int B>
+__device__ __forceinline__ void expand_keys(const int32_t* kl, int32_t* keys) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if constexpr (B == 1) {
+      keys[j] = kl[j];
+    } else {
+      keys[j] = __shfl(kl[j / B], j % B, B);
+    }
+  }
+}
+
 // The rows of for_rows, with the keys of each thread's next row loaded while
 // the current row is processed: f(r, keys) gets keys already in registers, so
 // a row waits for one memory trip (its gathers, issued together with its own
@@ -254,19 +309,65 @@ __device__ __forceinline__ void for_rows_pf(const DevMat& A, const BlkPlan& P, F
     for_rows<B>(A, P, [&](int64_t r) { f(r, (const int32_t*)nullptr); });
   } else {
     constexpr int RPI = kBlock / B;
+    constexpr int KL = (K + B - 1) / B;   // keys each lane loads
     const int64_t step = (int64_t)P.g * RPI;
-    int32_t kc[K], kn[K];
+    int32_t kc[KL], kn[KL];
+    auto ldk = [&](int64_t r, int32_t* k) { load_keys_split<HOP, K, B, NT>(A, r, k); };
+    // expand the row's keys (every lane of the workgroup takes part), then f for a valid row
+    auto run = [&](int64_t r, bool ok) {
+      int32_t keys[K];
+      expand_keys<K, B>(kc, keys);
+      if (ok) f(r, (const int32_t*)keys);
+    };
     if (A.units == nullptr) {
       if (P.r1 <= P.r0) return;
       const int64_t last = P.r1 - 1;
       int64_t r = P.r0 + (int64_t)P.j * RPI + threadIdx.x / B;
-      load_keys<HOP, K, NT>(A, r < last ? r : last, kc);
+      ldk(r < last ? r : last, kc);
       for (int64_t base = P.r0 + (int64_t)P.j * RPI; base < P.r1; base += step, r += step) {
         const int64_t rn = r + step;
-        load_keys<HOP, K, NT>(A, rn < last ? rn : last, kn);
-        if (r < P.r1) f(r, (const int32_t*)kc);
+        ldk(rn < last ? rn : last, kn);
+        run(r, r < P.r1);
 #pragma unroll
-        for (int j = 0; j < K; ++j) kc[j] = kn[j];
+        for (int j = 0; j < KL; ++j) kc[j] = kn[j];
+      }
+      return;
+    }
+    if (A.pencil) {
+      // pencil: per tile t the unit of this wavefront (row_at_pencil); unit
+      // starts two tiles ahead, keys one tile ahead
+      constexpr int RPW = 64 / B;
+      const int64_t total = pencil_seq_len(P);
+      if (total <= 0) return;
+      const int32_t* __restrict__ units = A.units + P.u0;
+      const int w = threadIdx.x >> 6, l = (threadIdx.x & 63) / B;
+      const int64_t g = P.g, nu = P.nu;
+      auto unit_of = [&](int64_t t) -> int64_t {
+        const int64_t u = (t / B) * kPencil + w;
+        return u < nu ? u : nu - 1;
+      };
+      auto row_in = [&](int64_t t, int64_t a) -> int64_t {
+        const int64_t u = (t / B) * kPencil + w;
+        const int64_t r = a + (t % B) * RPW + l;
+        return (t * RPI < total && u < nu && r < (((a >> kUnitLog2) + 1) << kUnitLog2) && r < P.se) ? r : -1;
+      };
+      int64_t t = P.j;
+      int64_t a0 = units[unit_of(t)];
+      int64_t a1 = units[unit_of(t + g)];
+      {
+        const int64_t r = row_in(t, a0);
+        ldk(r >= 0 ? r : a0, kc);
+      }
+      for (; t * RPI < total; t += g) {
+        const int64_t a2 = units[unit_of(t + 2 * g)];
+        const int64_t rn = row_in(t + g, a1);
+        ldk(rn >= 0 ? rn : a1, kn);
+        const int64_t r = row_in(t, a0);
+        run(r, r >= 0);
+#pragma unroll
+        for (int j = 0; j < KL; ++j) kc[j] = kn[j];
+        a0 = a1;
+        a1 = a2;
       }
       return;
     }
@@ -287,16 +388,16 @@ __device__ __forceinline__ void for_rows_pf(const DevMat& A, const BlkPlan& P, F
     int64_t a1 = units[unit_of(pos + step)];
     {
       const int64_t r = row_in(pos, a0);
-      load_keys<HOP, K, NT>(A, r >= 0 ? r : a0, kc);
+      ldk(r >= 0 ? r : a0, kc);
     }
     for (int64_t pos0 = (int64_t)P.j * RPI; pos0 < total; pos0 += step, pos += step) {
       const int64_t a2 = units[unit_of(pos + 2 * step)];
       const int64_t rn = row_in(pos + step, a1);
-      load_keys<HOP, K, NT>(A, rn >= 0 ? rn : a1, kn);
+      ldk(rn >= 0 ? rn : a1, kn);
       const int64_t r = row_in(pos, a0);
-      if (r >= 0) f(r, (const int32_t*)kc);
+      run(r, r >= 0);
 #pragma unroll
-      for (int j = 0; j < K; ++j) kc[j] = kn[j];
+      for (int j = 0; j < KL; ++j) kc[j] = kn[j];
       a0 = a1;
       a1 = a2;
     }

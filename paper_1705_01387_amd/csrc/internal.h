@@ -36,7 +36,7 @@ constexpr int kMaxB = 16;           // widest vector block
 //   linear: the contiguous rows [r0, r1), or
 //   banded: the 64-row units units[u0 .. u0 + nu) of a banded unit order
 //           (each unit is the part of one 64-row slice inside the segment,
-//           whose rows end at se).
+//           whose rows end at se), or of a pencil order (see row_at_pencil).
 struct BlkPlan {
   int64_t r0, r1;
   int32_t j, g, seg, nu;
@@ -44,6 +44,7 @@ struct BlkPlan {
 };
 
 constexpr int kUnitLog2 = 6;        // rows per unit of a banded order: 64
+constexpr int kPencil = kBlock / 64;   // units per pencil: one per wavefront of a workgroup
 constexpr int kNumB = 5;            // block widths 1, 2, 4, 8, 16
 constexpr int64_t kBandBudget = int64_t(5) << 19;   // 2.5 MiB: bytes one row window may stream per XCD
 
@@ -67,6 +68,28 @@ GPUQT_PLAN_HD inline int64_t row_at(const BlkPlan& P, const int32_t* units, int6
   return (r < end && r < P.se) ? r : -1;
 }
 
+// Pencil order: the group's units are taken kPencil at a time, one per
+// wavefront.  Tile t (of kBlock / B rows) covers rows sub * RPW .. sub * RPW +
+// RPW - 1 of units kPencil * (t / B) + w (wavefront w), sub = t mod B, RPW =
+// 64 / B rows per wavefront, so the wavefronts of one workgroup (one CU and its
+// L1) work on the same rows of kPencil units at once: in a pencil unit order
+// those are units one lattice period apart, whose rows gather each other.
+// The sequence has kPencil * 64 * ceil(nu / kPencil) positions.
+GPUQT_PLAN_HD inline int64_t pencil_seq_len(const BlkPlan& P) {
+  return (int64_t)((P.nu + kPencil - 1) / kPencil) * kPencil << kUnitLog2;
+}
+GPUQT_PLAN_HD inline int64_t row_at_pencil(const BlkPlan& P, const int32_t* units, int64_t pos, int B) {
+  const int rpi = kBlock / B, rpw = 64 / B;
+  const int64_t t = pos / rpi;
+  const int q = (int)(pos % rpi);
+  const int64_t u = (t / B) * kPencil + q / rpw;
+  if (u >= P.nu) return -1;
+  const int64_t a = units[P.u0 + u];
+  const int64_t r = a + (t % B) * rpw + q % rpw;
+  const int64_t end = ((a >> kUnitLog2) + 1) << kUnitLog2;
+  return (r < end && r < P.se) ? r : -1;
+}
+
 // Device view of a Hamiltonian in sliced ELL.  Rows are cut into slices of S
 // rows; slice s stores width_s entries per row, slot-major (entry j of row
 // s*S + r sits at slice_ptr[s] + j*S + r), so a wavefront reading one slot of
@@ -84,7 +107,8 @@ struct DevMat {
   const int32_t* offtab;     // HOP_DICT: [T] column offset (column - row) of each table entry
   const double* diag;        // [n] U_i / DeltaE_seg
   const BlkPlan* plan;       // [G] row ranges of the logical workgroups
-  const int32_t* units;      // banded unit order for this block width (first row of each unit), or NULL
+  const int32_t* units;      // banded or pencil unit order for this block width (first row of each unit), or NULL
+  int32_t pencil;            // 1: units is a pencil order, visited as row_at_pencil says
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   // the hoppings given at build time (before class scales), for class gradients
@@ -127,6 +151,7 @@ struct Handle {
   // resident workgroups per CU of each hot family [family][log2 B][nt] (0: unknown)
   int8_t occ[kFamilies][kNumB][2] = {};
   int32_t banded = 0;             // 1: use the banded unit order where one exists
+  int32_t pencil = 0;             // with banded: the pencil unit order instead, where one exists
   // at most this many resident workgroups per CU (0: as many as fit).  Fewer
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
@@ -136,6 +161,9 @@ struct Handle {
   // banded orders per block width (index log2 B); NULL where the plain row order
   // already keeps the neighbour window within the cache budget
   int32_t* d_units[kNumB] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // pencil orders per block width; NULL where no segment has a period of at least 128 rows
+  int32_t* d_units_p[kNumB] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t pencil_rows[kNumB] = {0, 0, 0, 0, 0};
   std::vector<int64_t> seg_period;   // detected row period D per segment (0: none)
   int32_t band_rows[kNumB] = {0, 0, 0, 0, 0};
   // device allocations
@@ -188,8 +216,10 @@ struct Handle {
     for (int f = 0; f < kFamilies; ++f) c |= (int32_t)(fam_cap[f] + 1) << (3 * f);
     return c;
   }
-  // nt | banded << 1 | per_cu_cap << 2 | (fam_cap[f] + 1) << (8 + 3 f)
-  int32_t variant_code() const { return nt | (banded << 1) | (per_cu_cap << 2) | (family_caps_code() << 8); }
+  // nt | banded << 1 | per_cu_cap << 2 | pencil << 6 | (fam_cap[f] + 1) << (8 + 3 f)
+  int32_t variant_code() const {
+    return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (family_caps_code() << 8);
+  }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
   DevMat view(int B, int family) const {
@@ -202,7 +232,9 @@ struct Handle {
 
   DevMat view(int B) const {
     DevMat m;
-    m.units = banded ? d_units[log2B(B)] : nullptr;
+    const int lb = log2B(B);
+    m.pencil = (banded && pencil && d_units_p[lb]) ? 1 : 0;
+    m.units = m.pencil ? d_units_p[lb] : (banded ? d_units[lb] : nullptr);
     m.slice_ptr = d_slice_ptr;
     m.col = d_col;
     m.hop = d_hop;
@@ -288,6 +320,15 @@ int64_t row_period(const HostLayout& L, int s);
 // W is given per segment (width[s]); segments with W = 0, D = 0 or D <= W keep
 // the plain order.
 void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
+                  const std::vector<int64_t>& width, std::vector<int32_t>* out);
+
+// Pencil order of the units of each segment for band width W rows: unit at
+// offset a goes to (band (a mod D) / W, sweep group (a / D) / kPencil, 64-row
+// bucket of (a mod D) within the band, sweep (a / D) mod kPencil, a mod D), so
+// kPencil consecutive units are the same rows of kPencil consecutive periods
+// (as far as the 64-row units line up with the period).  Segments with W = 0 or
+// D < 128 keep the plain order.
+void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
                   const std::vector<int64_t>& width, std::vector<int32_t>* out);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).

@@ -457,7 +457,8 @@ void plan_blocks(const std::vector<int64_t>& seg_off, int cus, int per_cu,
       int64_t r = (k + 1 == groups.size()) ? b : a + (ns * done) / gs[s];
       r = std::min(b, std::max(prev, (r / 64) * 64));
       if (k + 1 == groups.size()) r = b;
-      const int64_t u = (k + 1 == groups.size()) ? U : (U * done) / gs[s];
+      // (a multiple of kPencil, so that every group's pencils start aligned)
+      const int64_t u = (k + 1 == groups.size()) ? U : std::max(uprev, (U * done) / gs[s] / kPencil * kPencil);
       for (int64_t q = 0; q < groups[k].second; ++q) {
         BlkPlan& P = (*plan)[groups[k].first + q];
         P.r0 = prev;
@@ -517,6 +518,35 @@ void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
       const int64_t qx = ox / D, qy = oy / D;
       if (qx != qy) return qx < qy;
       return ox % D < oy % D;
+    });
+  }
+}
+
+void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
+                  const std::vector<int64_t>& width, std::vector<int32_t>* out) {
+  std::vector<int64_t> unit_first;
+  segment_units(seg_off, &unit_first, out);
+  const int n_seg = (int)seg_off.size() - 1;
+  for (int s = 0; s < n_seg; ++s) {
+    const int64_t D = period[s], W = width[s];
+    if (W <= 0 || D < 128) continue;   // plain order for this segment
+    const int64_t a = seg_off[s];
+    auto first = out->begin() + unit_first[s], last = out->begin() + unit_first[s + 1];
+    auto key = [&](int32_t x, int64_t k[5]) {
+      const int64_t o = x - a, off = o % D, q = o / D;
+      k[0] = off / W;
+      k[1] = q / kPencil;
+      k[2] = (off % W) >> kUnitLog2;
+      k[3] = q % kPencil;
+      k[4] = off;
+    };
+    std::stable_sort(first, last, [&](int32_t x, int32_t y) {
+      int64_t kx[5], ky[5];
+      key(x, kx);
+      key(y, ky);
+      for (int i = 0; i < 5; ++i)
+        if (kx[i] != ky[i]) return kx[i] < ky[i];
+      return false;
     });
   }
 }

@@ -121,7 +121,7 @@ gpuqt_status gpuqt_autotune_cached(gpuqt_h hh, int32_t B, void* ws, size_t ws_by
   }
   if (code >= 0 && gpuqt_set_variant(hh, code) == GPUQT_OK) {
     if (times_us)
-      for (int v = 0; v < 4; ++v) times_us[v] = 0.0;
+      for (int v = 0; v < 6; ++v) times_us[v] = 0.0;
     if (from_cache) *from_cache = 1;
     return GPUQT_OK;
   }

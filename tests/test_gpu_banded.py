@@ -1,4 +1,5 @@
-"""GPU parity of the banded row order (kernel variants 2 and 3).
+"""GPU parity of the banded and pencil row orders (kernel variants 2 and 3, with bit 6 the
+pencil order).
 
 Small lattices get a banded order by a small band width (band_rows); every entry point
 then runs with the variant pinned and is compared with the oracle, and the per-row
@@ -53,11 +54,15 @@ def cubic26(gpu):
 def test_banded_order_exists(cubic26):
     m, H, *_ = cubic26
     assert H.info.row_period == 676
-    assert H.info.banded_mask == 0b11111
+    assert H.info.banded_mask == 0b11111 and H.info.pencil_mask == 0b11111
 
 
-# variant bits: 0 non-temporal loads, 1 banded order, 2-5 resident workgroups per CU at most
-@pytest.mark.parametrize("variant", [2, 3, 3 | (2 << 2)])
+# variant bits: 0 non-temporal loads, 1 banded order, 2-5 resident workgroups per CU at most,
+# 6 the pencil order instead of the banded one
+PEN = 1 << 6
+
+
+@pytest.mark.parametrize("variant", [2, 3, 3 | (2 << 2), 2 | PEN, 3 | PEN, 3 | PEN | (2 << 2)])
 @pytest.mark.parametrize("B", [1, 4, 16])
 def test_banded_moments(cubic26, variant, B):
     say(f"case: banded moments variant={variant} B={B}")
@@ -82,7 +87,7 @@ def test_banded_rowwise_results_bit_identical(cubic26, B):
     dE = oracle_dE(Hs)
     psi = dev(I.random_phase(m.n, B, 74))
     outs = []
-    for v in (0, 2, 3, 2 | (3 << 2), 1 << 2):   # row-wise results do not depend on the schedule
+    for v in (0, 2, 3, 2 | (3 << 2), 1 << 2, 2 | PEN, 3 | PEN | (3 << 2)):   # row-wise results do not depend on the schedule
         P.gpuqt_set_variant(H, v)
         a = host(P.gpuqt_evolve(H, psi, 1.3, 0))
         b = host(P.gpuqt_apply_commutator(H, psi, P.VELOCITY))
@@ -97,11 +102,12 @@ def test_banded_rowwise_results_bit_identical(cubic26, B):
     assert err(outs[1][2], O.commutator_evolve(Hs / dE, XH / dE, p, 0.7, dE)) < TOL
 
 
-def test_banded_vac_msd(cubic26):
-    say("case: banded VAC/MSD B=2")
+@pytest.mark.parametrize("variant", [2, 2 | PEN])
+def test_banded_vac_msd(cubic26, variant):
+    say(f"case: banded VAC/MSD B=2 variant={variant}")
     m, H, Hs, V, XH = cubic26
     dE = oracle_dE(Hs)
-    P.gpuqt_set_variant(H, 2)
+    P.gpuqt_set_variant(H, variant)
     phi = I.random_phase(m.n, 2, 75)
     dts = [0.5, 1.5, 1.0]
     v = host(P.gpuqt_vac(H, dev(phi), dts, 64))[:, 0]
@@ -114,12 +120,13 @@ def test_banded_vac_msd(cubic26):
         assert err(s[k], rs[k].T) < TOL, k
 
 
-def test_banded_backward(cubic26):
-    say("case: banded moments backward B=1")
+@pytest.mark.parametrize("variant", [3, 3 | PEN])
+def test_banded_backward(cubic26, variant):
+    say(f"case: banded moments backward B=1 variant={variant}")
     m, H, Hs, _, _ = cubic26
     import torch
     dE = oracle_dE(Hs)
-    P.gpuqt_set_variant(H, 3)
+    P.gpuqt_set_variant(H, variant)
     phi = I.random_phase(m.n, 1, 76)
     M = 40
     w = np.random.default_rng(77).normal(size=(1, 1, M))
@@ -141,11 +148,11 @@ def test_banded_segments_mixed(gpu):
     offs = np.cumsum([0] + [mm.n for mm in mods])
     H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
                         seg_offsets=offs, seg_length_x=[mm.length_x for mm in mods], band_rows=64)
-    assert H.info.banded_mask == 0b11111
+    assert H.info.banded_mask == 0b11111 and H.info.pencil_mask == 0b11111
     B = 4
     phi = I.random_phase(int(offs[-1]), B, 85)
     d = dev(phi)
-    for v in (2, 3):
+    for v in (2, 3, 2 | PEN, 3 | PEN):
         P.gpuqt_set_variant(H, v)
         mu = host(P.gpuqt_moments(H, d, d, 90))
         for s, mm in enumerate(mods):
@@ -176,7 +183,7 @@ def test_banded_with_value_table(gpu):
     phi = I.random_phase(m.n, 2, 103)
     psi = I.random_phase(m.n, 2, 104)
     d = dev(phi)
-    for v in (2, 3):
+    for v in (2, 3, 2 | PEN):
         P.gpuqt_set_variant(H, v)
         assert err(host(P.gpuqt_moments(H, d, d, 90))[0], O.chebyshev_moments(Hs / dE, phi, phi, 90).T) < TOL
         assert err(host(P.gpuqt_moments(H, d, dev(psi), 90))[0],

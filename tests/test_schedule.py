@@ -34,9 +34,26 @@ CASES = [
 @pytest.mark.parametrize("offs,period,band", CASES)
 @pytest.mark.parametrize("B", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("cus", [1, 3, 256])
-def test_schedule_visits_every_row_once(offs, period, band, B, cus):
-    blk, it = P.gpuqt_schedule_rows(offs, period, band, cus, B)
+@pytest.mark.parametrize("pencil", [False, True])
+def test_schedule_visits_every_row_once(offs, period, band, B, cus, pencil):
+    blk, it = P.gpuqt_schedule_rows(offs, period, band, cus, B, pencil=pencil)
     _check_cover(np.asarray(offs), blk, it)
+
+
+def test_pencil_order_puts_period_neighbours_in_one_tile():
+    """Cubic 200^3 in natural site order (period D = 200^2 = 625 units of 64 rows): in the
+    pencil order the four wavefronts of a workgroup take the same rows of four consecutive
+    periods, so for 3 of every 4 rows r the row r + D is visited by the same workgroup in
+    the same iteration (another wavefront of the same compute unit); in the plain and the
+    banded orders almost never."""
+    n, D = 200 ** 3, 40000
+    r = np.arange(n - D)
+    for B, W in [(1, 8192), (4, 2880), (16, 768)]:
+        blk, it = P.gpuqt_schedule_rows([0, n], [D], W, 256, B, pencil=True)
+        same = np.mean((blk[r + D] == blk[r]) & (it[r + D] == it[r]))
+        assert same >= 0.74, (B, same)
+        b0, i0 = P.gpuqt_schedule_rows([0, n], [D], W, 256, B)
+        assert np.mean((b0[r + D] == b0[r]) & (i0[r + D] == i0[r])) < 0.05, B
 
 
 def test_banded_order_brings_period_neighbours_together():
