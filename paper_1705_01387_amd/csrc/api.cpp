@@ -1596,7 +1596,7 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   if (h->d_units[lb]) vars.insert(vars.end(), {2, 3});
   if (h->d_units_p[lb]) vars.insert(vars.end(), {6, 7});
   if (times_us)
-    for (int v = 0; v < 6; ++v) times_us[v] = 0.0;
+    for (int v = 0; v < kTuneTimes; ++v) times_us[v] = 0.0;
   float ms = 0.0f;
   st = time_one(0, 0, &ms);   // settle clocks and caches before the sweep
   std::vector<int> caps;

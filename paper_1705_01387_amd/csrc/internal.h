@@ -45,6 +45,7 @@ struct BlkPlan {
 
 constexpr int kUnitLog2 = 6;        // rows per unit of a banded order: 64
 constexpr int kPencil = kBlock / 64;   // units per pencil: one per wavefront of a workgroup
+constexpr int kTuneTimes = 6;       // entries of gpuqt_autotune's times_us: 4 load/order variants + 2 pencil
 constexpr int kNumB = 5;            // block widths 1, 2, 4, 8, 16
 constexpr int64_t kBandBudget = int64_t(5) << 19;   // 2.5 MiB: bytes one row window may stream per XCD
 

@@ -121,7 +121,7 @@ gpuqt_status gpuqt_autotune_cached(gpuqt_h hh, int32_t B, void* ws, size_t ws_by
   }
   if (code >= 0 && gpuqt_set_variant(hh, code) == GPUQT_OK) {
     if (times_us)
-      for (int v = 0; v < 6; ++v) times_us[v] = 0.0;
+      for (int v = 0; v < kTuneTimes; ++v) times_us[v] = 0.0;
     if (from_cache) *from_cache = 1;
     return GPUQT_OK;
   }
@@ -149,7 +149,7 @@ gpuqt_status gpuqt_autotune_block(gpuqt_h hh, int32_t n_vectors, void* ws, size_
     gpuqt_status st = gpuqt_workspace_size(hh, GPUQT_OP_AUTOTUNE, B, 0, 0, &need);
     if (st) return st;
     if (ws_bytes < need) break;   // the workspace bounds the widest block tried
-    double t[4] = {0, 0, 0, 0};
+    double t[kTuneTimes] = {};
     if ((st = gpuqt_autotune(hh, B, ws, ws_bytes, stream, t))) return st;
     double us = 0.0;
     for (double x : t)
@@ -200,7 +200,7 @@ gpuqt_status gpuqt_build_h_tuned(const gpuqt_h_desc* desc, int32_t B, void* stre
     }
     size_t need = 0;
     void* ws = nullptr;
-    double t[4] = {0, 0, 0, 0};
+    double t[kTuneTimes] = {};
     if ((st = gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0, &need)) == GPUQT_OK) {
       if (hipMalloc(&ws, need) != hipSuccess) {
         ws = nullptr;

@@ -162,11 +162,13 @@ def test_tune_cache_file_format(tmp_path):
 
 def test_committed_tune_cache_is_well_formed():
     """The package's cache of MI355X choices: every line a gfx950 key and a variant code that
-    gpuqt_set_variant accepts (load variant, a per-CU cap of at most 8, family caps)."""
+    gpuqt_set_variant accepts (load variant, a per-CU cap of at most 8, the pencil bit, family
+    caps)."""
     lines = [ln for ln in open(P.TUNE_CACHE_PATH).read().splitlines() if ln and not ln.startswith("#")]
     assert lines
     for ln in lines:
         key, code = ln.split("\t")
         code = int(code)
         assert key.startswith("gfx950 ") and key.split()[-1].startswith("B")
-        assert ((code >> 2) & 15) <= 8 and (code >> 6) & 3 == 0 and code >> (8 + 18) == 0
+        assert ((code >> 2) & 15) <= 8 and (code >> 7) & 1 == 0 and code >> (8 + 18) == 0
+        assert not (code >> 6) & 1 or (code >> 1) & 1          # the pencil bit only with the banded bit

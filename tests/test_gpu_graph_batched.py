@@ -140,5 +140,17 @@ def test_autotune_keeps_results(gpu):
             P.gpuqt_set_variant(H, bad)
     Hb = P.gpuqt_build_h_from_model(m, band_rows=64)                      # period 121 > 64
     tb = P.gpuqt_autotune(Hb, 4)
-    assert np.all(np.isfinite(tb)) and np.all(tb > 0)
+    # banded variants timed; no pencil order below a period of 128 rows
+    assert np.all(np.isfinite(tb)) and np.all(tb[:4] > 0) and np.all(tb[4:] == 0)
     assert err(host(P.gpuqt_moments(Hb, phi, phi, 200))[0], ref) < TOL
+    m12 = I.cubic(12, W=4.0, seed=68)                                      # period 144: pencils too
+    Hp = P.gpuqt_build_h_from_model(m12, band_rows=64)
+    assert Hp.info.pencil_mask == 0b11111
+    tp = P.gpuqt_autotune(Hp, 4)
+    assert np.all(np.isfinite(tp)) and np.all(tp > 0)
+    H12, _, _ = O.operators(m12.nn, m12.nbr, m12.hop, m12.onsite, m12.x, m12.length_x)
+    ph12 = I.random_phase(m12.n, 4, 69)
+    ref12 = O.chebyshev_moments(H12 / oracle_dE(H12), ph12, ph12, 120).T
+    for v in (Hp.info.kernel_variant, 2 | (1 << 6), 3 | (1 << 6) | (2 << 2)):
+        P.gpuqt_set_variant(Hp, v)
+        assert err(host(P.gpuqt_moments(Hp, dev(ph12), dev(ph12), 120))[0], ref12) < TOL, v
