@@ -84,3 +84,40 @@ def test_errors(tmp_path):
     # missing required file
     os.remove(nb)
     _expect(d, 1, "neighbour.in")
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _with_golden(tmp_path, para, time_step=None):
+    """A small folder whose para.in (and time_step.in) are the paper's printed files."""
+    m = I.chain(12, W=4.0, seed=92)
+    write_input_folder(tmp_path, m, np.linspace(-4.0, 4.0, 5), [0.5])
+    import shutil
+    shutil.copy(os.path.join(GOLDEN, para), os.path.join(tmp_path, "para.in"))
+    if time_step:
+        shutil.copy(os.path.join(GOLDEN, time_step), os.path.join(tmp_path, "time_step.in"))
+    return P.gpuqt_model_load(tmp_path)
+
+
+def test_paper_para_in_of_the_diffusive_example(tmp_path):
+    """Section 5.1: the file means N_m = 1000 (default), DeltaE = 6.1, N_r = 1 (default),
+    VAC and MSD; the benchmark's replay of the example uses the same values."""
+    f = _with_golden(tmp_path, "para_diffusive.in")
+    assert (f.n_moments, f.energy_max, f.n_random_vectors) == (1000, 6.1, 1)
+    assert f.calculate_vac and f.calculate_msd
+    w = I.workload_paper_diffusive(L=20)
+    assert (w["M"], w["energy_max"], w["phi"].shape[1], w["vac"], w["msd"]) == (1000, 6.1, 1, True, True)
+
+
+def test_paper_para_and_time_steps_of_the_localized_example(tmp_path):
+    """Section 5.2: N_r = 2, N_m = 500, DeltaE = 4.1, MSD only, and the 30 time steps
+    0.1 .. 1.0, 1 .. 10, 10 .. 100 (total 610.5); the replay uses the same values."""
+    f = _with_golden(tmp_path, "para_localized.in", "time_step_localized.in")
+    assert (f.n_random_vectors, f.n_moments, f.energy_max) == (2, 500, 4.1)
+    assert f.calculate_msd and not f.calculate_vac
+    assert f.time_steps.shape == (30,) and abs(f.time_steps.sum() - 610.5) < 1e-9
+    assert np.allclose(f.time_steps[:10], 0.1 * np.arange(1, 11)) and np.array_equal(f.time_steps[10:20], np.arange(1, 11))
+    w = I.workload_paper_localized(L=1000)
+    assert np.allclose(w["dt"], f.time_steps, rtol=0, atol=1e-15)
+    assert (w["M"], w["energy_max"], w["phi"].shape[1], w["vac"], w["msd"]) == (500, 4.1, 2, False, True)
