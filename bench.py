@@ -22,7 +22,8 @@ Also on the line:
                 own stream around each run of launches, gpuqt_set_timing): algorithmic bytes
                 per launch / average launch time, against the 8 TB/s HBM peak, with the HBM
                 bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record
-                when it was taken on the same kernel sources and variant;
+                when it was taken on the same kernel sources and configuration of that
+                kernel family (family_config);
   single_vector the single-vector (B = 1) Chebyshev step on the same lattice, both the
                 Hermitian product-identity step the library uses and the paper's plain
                 one-moment-per-step recurrence (gpuqt_moments_plain);
@@ -94,17 +95,37 @@ def family_bytes(info, B, family="moment"):
     return int(info.entries) * per_entry + n * 8 + n * FAMILY_VECTOR_BYTES[family] * B
 
 
-def variant_text(v, family=None):
-    """The kernel variant code v: load variant (bit 0 non-temporal, bit 1 banded order), the
-    cap on resident workgroups per CU (bits 2-5, 0 = none), or the family's own cap (3 bits
-    per family from bit 8: 0 = the per-CU cap, 1 + c = cap c) when it has one."""
+SERIES_FAMILIES = ("evolve", "msd", "evolve_pair")
+
+
+def family_config(v, family):
+    """What the variant code v sets for one kernel family: (non-temporal loads, banded order,
+    pencil order, cap on resident workgroups per CU).  Bit 0 non-temporal loads (bit 7 flips it
+    for the evolution and MSD families), bit 1 banded order, bit 6 pencil order, bits 2-5 the
+    per-CU cap (0 = none) unless the family has its own (3 bits per family from bit 8: 0 = the
+    per-CU cap, 1 + c = cap c)."""
     from paper_1705_01387_amd._binding import K_FAMILIES
+    nt = v & 1
+    if family in SERIES_FAMILIES:
+        nt ^= (v >> 7) & 1
+    banded = (v >> 1) & 1
     cap = (v >> 2) & 15
-    if family is not None:
-        c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
-        if c:
-            cap = c - 1
-    return "code %d: load/order variant %d, %s" % (v, v & 3, "%d workgroups/CU" % cap if cap else "full occupancy")
+    c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
+    if c:
+        cap = c - 1
+    return nt, banded, banded & ((v >> 6) & 1), cap
+
+
+def variant_text(v, family=None):
+    """The kernel variant code v as it applies to one kernel family (family_config)."""
+    if family is None:
+        nt, banded, pencil, cap = v & 1, (v >> 1) & 1, ((v >> 1) & (v >> 6)) & 1, (v >> 2) & 15
+    else:
+        nt, banded, pencil = family_config(v, family)[:3]
+        cap = family_config(v, family)[3]
+    order = "pencil" if pencil else ("banded" if banded else "plain")
+    return "code %d: %s loads, %s row order, %s" % (v, "non-temporal" if nt else "plain", order,
+                                                   "%d workgroups/CU" % cap if cap else "full occupancy")
 
 
 def pick_variant(P, H, B, ws, args):
@@ -113,7 +134,7 @@ def pick_variant(P, H, B, ws, args):
     Returns (autotune times per load variant or zeros, whether the choice came from the cache)."""
     if args.variant >= 0:
         P.gpuqt_set_variant(H, args.variant)
-        return [0.0] * 4, False
+        return [0.0] * 6, False
     t, cached = P.gpuqt_autotune_cached(H, B, ws=ws)
     return [float(x) for x in t], bool(cached)
 
@@ -137,8 +158,9 @@ def kernel_table(info, B, fam, elapsed_s):
 
 def measured_traffic(name, family, bytes_launch, variant):
     """HBM bytes per launch of the dominant kernel from the committed counter record, if it was
-    taken on that kernel family, on the kernel sources built now and with the same variant
-    code (else None: a record of another variant does not describe this run's kernel)."""
+    taken on that kernel family, on the kernel sources built now and with the same
+    configuration of that family (family_config; else None: a record of another
+    configuration does not describe this run's kernel)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -152,7 +174,7 @@ def measured_traffic(name, family, bytes_launch, variant):
             h.update(g.read())
     e = rec.get(name)
     if (not e or e.get("kernel_source_sha256") != h.hexdigest() or e.get("family") != family
-            or e.get("variant") != int(variant)):
+            or family_config(int(e.get("variant")), family) != family_config(int(variant), family)):
         return None
     return {"bytes": e["bytes_per_launch"], "ratio_to_algorithmic": e["bytes_per_launch"] / bytes_launch,
             "fetch_kib": e["fetch_kib"], "write_kib": e["write_kib"], "scale": e["scale"],

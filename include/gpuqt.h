@@ -410,7 +410,9 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * which can outweigh the lost latency hiding.  The cap applies to every
  * kernel family on the handle; then, at the chosen load variant, the
  * two-chain moment step, the two-vector evolution term and the MSD term are
- * each timed at the same caps and get their own (kernel_variant bits 8-25).
+ * each timed at the same caps and get their own (kernel_variant bits 8-25),
+ * the two series terms also with the other load variant (bit 7 when that is
+ * faster for the pair of them).
  * Synchronises the stream.
  *   ws : device workspace of gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0) bytes
  *        (eight vectors); one of three vectors plus the partial sums tunes the
@@ -425,13 +427,14 @@ gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, voi
 
 /* Set the kernel variant without measuring, with the bits of gpuqt_h_info_t.kernel_variant:
  * load variant in bits 0-1, per-CU cap 0..8 in bits 2-5, the pencil order in bit 6 (with
- * bit 1), bit 7 zero, and from bit 8 three bits per kernel family (0: the per-CU cap, 1 + c:
+ * bit 1), in bit 7 the series families (evolution and MSD terms) on the other load variant
+ * than bit 0, and from bit 8 three bits per kernel family (0: the per-CU cap, 1 + c:
  * cap c of 0..6), so a code read from gpuqt_h_info after gpuqt_autotune reproduces the tuned
  * configuration.  The banded and pencil bits only take effect for block widths that have
  * such an order (gpuqt_h_info_t.banded_mask, pencil_mask); a pencil bit for a width without
  * a pencil order falls back to the banded order.
- * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8, bit 6 without bit 1, bit 7 or
- * bits set above the families. */
+ * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8, bit 6 without bit 1 or bits set
+ * above the families. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*

@@ -819,7 +819,8 @@ def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
 def gpuqt_set_variant(H: Hamiltonian, variant: int):
     """Pin the kernel variant code (bit 0: non-temporal streams, bit 1: banded row order,
     bits 2-5: resident workgroups per CU at most, 0 = no cap; bit 6 (with bit 1): the pencil
-    order instead of the banded one; from bit 8, 3 bits per kernel
+    order instead of the banded one; bit 7: the evolution and MSD terms on the other load
+    variant; from bit 8, 3 bits per kernel
     family: 0 = that cap, 1 + c = the family's own cap c).  H.info.kernel_variant after
     gpuqt_autotune is such a code."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")

@@ -1583,13 +1583,14 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   const int lb = Handle::log2B(B);
   // caps below a family's occupancy limit at the current load variant, then none
   auto caps_of = [&](int fam, std::vector<int>* out) {
-    const int occ = std::max<int>(1, h->occ[fam][lb][h->nt ? 1 : 0]);
+    const int occ = std::max<int>(1, h->occ[fam][lb][h->fam_nt(fam) ? 1 : 0]);
     out->clear();
     for (int cap : {2, 3, 4, 5, 6})
       if (cap < occ) out->push_back(cap);
     out->push_back(0);
   };
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
+  h->series_nt_flip = 0;
   float best = 0.0f;
   int best_v = (h->nt | (h->banded << 1) | ((h->banded & h->pencil) << 2)), best_cap = h->per_cu_cap;
   std::vector<int> vars = {0, 1};
@@ -1630,8 +1631,8 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
     double* J = reinterpret_cast<double*>(base + WF.off_J);
     HIP_TRY(launch_fill_phase(h->view(B), B, v[1], s));
     const double dt = 1.0;
-    const int fams[] = {FAM_PAIR, FAM_EVOLVE_PAIR, FAM_MSD};
-    for (int f : fams) {
+    // the best cap of family f at the current load variants (its time in *best_ms)
+    auto tune_family = [&](int f, float* best_ms) -> gpuqt_status {
       auto run = [&]() -> gpuqt_status {
         if (f == FAM_PAIR) return run_moments(h, B, v[0], v[1], kSteps + 1, partF, v[2], v[3], s, false, v[4], v[5]);
         if (f == FAM_EVOLVE_PAIR)
@@ -1643,18 +1644,42 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
       int fcap = -1;
       for (int cap : caps) {
         h->fam_cap[f] = (int8_t)cap;
-        if ((st = time_run(run, &ms))) break;
+        gpuqt_status q;
+        if ((q = time_run(run, &ms))) return q;
         if (fbest == 0.0f || ms < fbest) {
           fbest = ms;
           fcap = cap;
         }
       }
-      if (st) break;
       h->fam_cap[f] = (int8_t)fcap;
+      *best_ms = fbest;
+      return GPUQT_OK;
+    };
+    float t_pair = 0.0f;
+    st = tune_family(FAM_PAIR, &t_pair);
+    // the series families (two-vector evolution and MSD terms) with the handle's
+    // load variant and with the other one; the pair of caps of the faster total stays
+    float tot[2] = {0.0f, 0.0f};
+    int8_t cap_ev[2] = {-1, -1}, cap_msd[2] = {-1, -1};
+    for (int flip = 0; flip < 2 && !st; ++flip) {
+      h->series_nt_flip = flip;
+      float te = 0.0f, tm = 0.0f;
+      if ((st = tune_family(FAM_EVOLVE_PAIR, &te)) || (st = tune_family(FAM_MSD, &tm))) break;
+      tot[flip] = te + tm;
+      cap_ev[flip] = h->fam_cap[FAM_EVOLVE_PAIR];
+      cap_msd[flip] = h->fam_cap[FAM_MSD];
+    }
+    if (!st) {
+      const int fl = tot[1] < tot[0] ? 1 : 0;
+      h->series_nt_flip = fl;
+      h->fam_cap[FAM_EVOLVE_PAIR] = cap_ev[fl];
+      h->fam_cap[FAM_MSD] = cap_msd[fl];
     }
   }
-  if (st)
+  if (st) {
     for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
+    h->series_nt_flip = 0;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
@@ -1719,14 +1744,16 @@ gpuqt_status gpuqt_schedule_rows(int32_t n_segments, const int64_t* seg_offsets,
 gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
-  if (variant < 0 || ((variant >> 2) & 15) > kPerCU || (variant & (1 << 7)) ||
-      ((variant >> 6) & 1 && !((variant >> 1) & 1)) || (variant >> (8 + 3 * kFamilies)))
+  if (variant < 0 || ((variant >> 2) & 15) > kPerCU || ((variant >> 6) & 1 && !((variant >> 1) & 1)) ||
+      (variant >> (8 + 3 * kFamilies)))
     return fail(GPUQT_ERR_ARG,
                 "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bit 6 the pencil "
-                "order (with bit 1), bit 7 zero and 3 bits per kernel family from bit 8");
+                "order (with bit 1), bit 7 the series families' load flip and 3 bits per kernel family "
+                "from bit 8");
   h->nt = variant & 1;
   h->banded = (variant >> 1) & 1;
   h->pencil = (variant >> 6) & 1;
+  h->series_nt_flip = (variant >> 7) & 1;
   h->per_cu_cap = (variant >> 2) & 15;
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = (int8_t)(((variant >> (8 + 3 * f)) & 7) - 1);
   return GPUQT_OK;

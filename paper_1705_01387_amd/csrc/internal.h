@@ -153,6 +153,9 @@ struct Handle {
   int8_t occ[kFamilies][kNumB][2] = {};
   int32_t banded = 0;             // 1: use the banded unit order where one exists
   int32_t pencil = 0;             // with banded: the pencil unit order instead, where one exists
+  // 1: the series families (evolution terms, MSD term) use the other load variant
+  // (non-temporal <-> plain) than nt
+  int32_t series_nt_flip = 0;
   // at most this many resident workgroups per CU (0: as many as fit).  Fewer
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
@@ -204,8 +207,13 @@ struct Handle {
   static int log2B(int B) { return B <= 1 ? 0 : B == 2 ? 1 : B == 4 ? 2 : B == 8 ? 3 : 4; }
 
   // plan of a hot family at block width B and the current load variant
+  // load variant of a kernel family
+  int fam_nt(int family) const {
+    const bool series = family == FAM_EVOLVE || family == FAM_EVOLVE_PAIR || family == FAM_MSD;
+    return series ? (nt ^ series_nt_flip) : nt;
+  }
   int plan_index(int B, int family) const {
-    int p = occ[family][log2B(B)][nt ? 1 : 0];
+    int p = occ[family][log2B(B)][fam_nt(family) ? 1 : 0];
     if (p < 1 || p > kPerCU) p = kPerCU;
     const int cap = fam_cap[family] >= 0 ? fam_cap[family] : per_cu_cap;
     if (cap > 0 && cap < p) p = cap;
@@ -217,9 +225,10 @@ struct Handle {
     for (int f = 0; f < kFamilies; ++f) c |= (int32_t)(fam_cap[f] + 1) << (3 * f);
     return c;
   }
-  // nt | banded << 1 | per_cu_cap << 2 | pencil << 6 | (fam_cap[f] + 1) << (8 + 3 f)
+  // nt | banded << 1 | per_cu_cap << 2 | pencil << 6 | series_nt_flip << 7 | (fam_cap[f] + 1) << (8 + 3 f)
   int32_t variant_code() const {
-    return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (family_caps_code() << 8);
+    return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (series_nt_flip << 7) |
+           (family_caps_code() << 8);
   }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
@@ -228,6 +237,7 @@ struct Handle {
     const int i = plan_index(B, family);
     m.plan = d_plans[i];
     m.G = Gs[i];
+    m.nt = fam_nt(family);
     return m;
   }
 

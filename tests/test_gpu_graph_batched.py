@@ -118,7 +118,7 @@ def test_autotune_keeps_results(gpu):
     t = P.gpuqt_autotune(H, 4)
     assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:] == 0)   # no banded order
     code = H.info.kernel_variant
-    assert code & 3 in (0, 1) and (code >> 2) & 15 <= 8 and (code >> 6) & 3 == 0
+    assert code & 3 in (0, 1) and (code >> 2) & 15 <= 8 and (code >> 6) & 1 == 0
     fc = H.info.family_caps   # the pair (2), msd (4) and evolve pair (5) families got their own cap
     assert fc == code >> 8
     assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 1, 3))
