@@ -219,3 +219,47 @@ def test_autograd_at_zero_scale(gpu):
     rU, rC = O.moments_gradient(Hs, phi, phi, dE, wv[0].T, parts)
     assert np.all(np.isfinite(s.grad.numpy()))
     assert err(s.grad.numpy(), rC) < TOL and err(host(U.grad), rU) < TOL
+
+
+@pytest.mark.parametrize("kind", ["moments", "vac"])
+def test_entry_gradient_segments(gpu, kind):
+    """Two realisations of different lattices (4 and 3 neighbour slots, real and complex
+    hoppings, their own DeltaE) in one handle: each segment's per-entry gradients equal the
+    oracle's for that segment alone, placed at its rows; the other segment's slots and the
+    padding stay zero."""
+    import torch
+    say(f"case: entry gradients on two segments ({kind})")
+    mods = [I.bond_disorder(I.square(9, 8, W=1.0, seed=84), 0.3, 85),
+            I.bond_disorder(I.honeycomb(6, 4, flux=1.0 / 24.0, W=1.0, seed=86), 0.2, 87, 0.3)]
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    ops = [O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x) for mm in mods]
+    dEs = np.array([oracle_dE(o[0]) for o in ops])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=offs, seg_energy_max=dEs, seg_length_x=[mm.length_x for mm in mods])
+    B, M = 2, 30
+    phi = np.concatenate([I.random_phase(mm.n, B, 88 + s) for s, mm in enumerate(mods)], axis=0)
+    gH = zeros_entries(H)
+    ref = np.zeros((cat.n, cat.max_nn, 2))
+    if kind == "moments":
+        w = np.random.default_rng(90).normal(size=(2, B, M))
+        P.gpuqt_moments_backward(H, dev(phi), dev(phi), dev(w), ckpt_stride=0, grad_hop=gH)
+    else:
+        dts = [0.5, 0.9, 0.2]
+        w = np.random.default_rng(91).normal(size=(len(dts), 2, B, M))
+        P.gpuqt_vac_backward(H, dev(phi), dts, dev(w), ckpt_stride=0, time_stride=1, grad_hop=gH)
+    for s, mm in enumerate(mods):
+        Hs, V, _ = ops[s]
+        ph = phi[offs[s]:offs[s + 1]]
+        rs = np.zeros((mm.n * mm.max_nn, 2))
+        if kind == "moments":
+            O.moments_gradient(Hs, ph, ph, dEs[s], w[s].T, (), O.entry_list(mm.nn, mm.nbr), rs)
+        else:
+            O.vac_gradient(Hs, V, ph, dts, dEs[s], M, np.transpose(w[:, s], (0, 2, 1)), 0, (), (),
+                           O.entry_list(mm.nn, mm.nbr, mm.x, mm.length_x), rs)
+        ref[offs[s]:offs[s + 1], :mm.max_nn] = rs.reshape(mm.n, mm.max_nn, 2)
+    got = host(gH)
+    for s, mm in enumerate(mods):
+        sl = slice(offs[s], offs[s + 1])
+        assert err(got[sl], ref[sl]) < TOL, s
+    assert np.all(got[offs[1]:, mods[1].max_nn:] == 0.0)
