@@ -92,7 +92,16 @@ def family_bytes(info, B, family="moment"):
         per_entry = 2
     else:
         per_entry = 4 + {0: 0, 1: 8, 2: 16}[mode] + (8 if family == "msd" else 0)
+    if box_used(info, B, family):
+        per_entry = 0          # the box stencil reads no neighbour indices
     return int(info.entries) * per_entry + n * 8 + n * FAMILY_VECTOR_BYTES[family] * B
+
+
+def box_used(info, B, family):
+    """Whether the Hermitian moment step runs the periodic-box stencil kernel (variant bit 26 on
+    a handle whose matrix is a periodic box, blocks of B >= 2)."""
+    return (family == "moment_sym" and B >= 2 and int(info.box[0]) > 0
+            and (int(info.kernel_variant) >> 26) & 1 == 1)
 
 
 SERIES_FAMILIES = ("evolve", "msd", "evolve_pair")
@@ -113,7 +122,8 @@ def family_config(v, family):
     c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
     if c:
         cap = c - 1
-    return nt, banded, banded & ((v >> 6) & 1), cap
+    box = (v >> 26) & 1 if family == "moment_sym" else 0
+    return nt, banded, banded & ((v >> 6) & 1), cap, box
 
 
 def variant_text(v, family=None):
@@ -121,8 +131,9 @@ def variant_text(v, family=None):
     if family is None:
         nt, banded, pencil, cap = v & 1, (v >> 1) & 1, ((v >> 1) & (v >> 6)) & 1, (v >> 2) & 15
     else:
-        nt, banded, pencil = family_config(v, family)[:3]
-        cap = family_config(v, family)[3]
+        nt, banded, pencil, cap, box = family_config(v, family)
+        if box:
+            return "code %d: periodic-box stencil, %s" % (v, "%d workgroups/CU" % cap if cap else "full occupancy")
     order = "pencil" if pencil else ("banded" if banded else "plain")
     return "code %d: %s loads, %s row order, %s" % (v, "non-temporal" if nt else "plain", order,
                                                    "%d workgroups/CU" % cap if cap else "full occupancy")
@@ -149,7 +160,7 @@ def kernel_table(info, B, fam, elapsed_s):
             continue
         avg = ms / 1e3 / nl
         b = family_bytes(info, B, f)
-        table[f] = {"kernel": FAMILY_KERNEL[f], "launches": nl, "total_ms": ms,
+        table[f] = {"kernel": FAMILY_KERNEL[f] + ("_box" if box_used(info, B, f) else ""), "launches": nl, "total_ms": ms,
                     "share_of_elapsed": ms / 1e3 / elapsed_s, "avg_us": avg * 1e6,
                     "bytes_per_launch": b, "GBs": b / avg / 1e9}
     dominant = max(table, key=lambda f: table[f]["total_ms"])
@@ -187,7 +198,7 @@ def roofline_of(name, info, B, kernels, dominant, bound="hbm"):
     return {"bound": bound, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": None if tr is None else tr["bytes"] / 1e9,
             "traffic_detail": tr,
-            "kernel": "%s (B=%d, hop mode %d, K=%d, %s)" % (FAMILY_KERNEL[dominant], B, info.hop_mode,
+            "kernel": "%s (B=%d, hop mode %d, K=%d, %s)" % (FAMILY_KERNEL[dominant] + ("_box" if box_used(info, B, dominant) else ""), B, info.hop_mode,
                                                           info.uniform_width,
                                                           variant_text(info.kernel_variant, dominant)),
             "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"]}

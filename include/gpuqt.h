@@ -148,6 +148,9 @@ typedef struct {
   int32_t max_nn;            /* neighbour slots per row of the build descriptor: the row stride
                                 of per-entry hopping gradients */
   int32_t pencil_mask;       /* bit log2(B) set: block width B has a pencil row order */
+  int32_t box[3];            /* (Lx, Ly, Lz) when H is a periodic simple cubic box in natural
+                                order with one uniform hopping (see gpuqt_autotune, bit 26),
+                                else 0 */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -398,6 +401,13 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * streamed data at this B, and for B >= 2 with two bands per period for
  * periods of 1024 rows or more: workgroups then sweep bands of W rows of the
  * period one period after another, so rows D apart are visited W rows apart);
+ * bit 26: on a periodic simple cubic box (one segment, rows x + Lx (y + Ly z), each
+ * with its six periodic neighbours, one uniform hopping; gpuqt_h_info_t.box), the Hermitian
+ * moment step of blocks of B >= 2 vectors as a box stencil: a workgroup marches through
+ * a column of the box, keeps each lane's elements of three consecutive planes in
+ * registers and the current plane's tile in LDS, so x is read about once per step instead
+ * of once per neighbour and no neighbour indices are read (timed against the best other
+ * variant, kept when faster);
  * bit 6 (with bit 1): the pencil order instead (built for segments with a row
  * period of at least 128 rows: the four wavefronts of a workgroup take the
  * same rows of four consecutive periods at once, so a row's neighbours one
@@ -417,9 +427,10 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  *   ws : device workspace of gpuqt_workspace_size(h, GPUQT_OP_AUTOTUNE, B, 0, 0) bytes
  *        (eight vectors); one of three vectors plus the partial sums tunes the
  *        Hermitian step only.
- *   times_us : NULL or HOST [6], microseconds per step of load/order variants 0..3 and of
+ *   times_us : NULL or HOST [7], microseconds per step of load/order variants 0..3, of
  *              the pencil order with plain (4) and non-temporal (5) loads, each at its best
- *              cap (0 for an order this B does not have).
+ *              cap, and of the periodic-box stencil (6, at the chosen cap); 0 for what this
+ *              handle and B do not have.
  * Not safe while other calls on the handle are in flight.
  */
 gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, void *stream,
@@ -432,9 +443,10 @@ gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, voi
  * cap c of 0..6), so a code read from gpuqt_h_info after gpuqt_autotune reproduces the tuned
  * configuration.  The banded and pencil bits only take effect for block widths that have
  * such an order (gpuqt_h_info_t.banded_mask, pencil_mask); a pencil bit for a width without
- * a pencil order falls back to the banded order.
+ * a pencil order falls back to the banded order.  Bit 26 (the box stencil of the Hermitian
+ * step) takes effect on a periodic box (gpuqt_h_info_t.box) for blocks of B >= 2.
  * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8, bit 6 without bit 1 or bits set
- * above the families. */
+ * above bit 26. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*

@@ -54,7 +54,7 @@ class HInfo(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
         ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32), ("max_nn", ctypes.c_int32),
-        ("pencil_mask", ctypes.c_int32),
+        ("pencil_mask", ctypes.c_int32), ("box", ctypes.c_int32 * 3),
     ]
 
 
@@ -802,12 +802,14 @@ def gpuqt_update_h_values(H: Hamiltonian, onsite=None, class_scale=None, stream=
 def gpuqt_autotune(H: Hamiltonian, B: int = 1, ws=None, stream=None):
     """Time the kernel variants (plain / non-temporal loads, plain / banded / pencil row order,
     each uncapped and at per-CU workgroup caps below its occupancy limit), keep the fastest;
-    returns us per moment step of load variants 0..3 and of the pencil order with plain and
-    non-temporal loads (entries 4, 5) at their best cap (0 where a variant does not exist).
+    returns us per moment step of load variants 0..3, of the pencil order with plain and
+    non-temporal loads (entries 4, 5) at their best cap, and of the periodic-box stencil
+    (entry 6, at the chosen cap; blocks of B >= 2 on a periodic box), 0 where a variant does
+    not exist.
     H.info.kernel_variant: bits 0-1 the load variant, bits 2-5 the cap (0: none), bit 6 the
     pencil order, from bit 8 the two-chain moment, MSD and two-vector evolution families'
     own caps."""
-    t = np.zeros(6)
+    t = np.zeros(7)
     ws, nb = _workspace(H, OP_AUTOTUNE, B, 0, 0, ws)
     _check(lib().gpuqt_autotune(H.handle, B, _ptr(ws), nb, _stream(stream), _ptr(t)), "gpuqt_autotune")
     info = HInfo()
@@ -820,7 +822,8 @@ def gpuqt_set_variant(H: Hamiltonian, variant: int):
     """Pin the kernel variant code (bit 0: non-temporal streams, bit 1: banded row order,
     bits 2-5: resident workgroups per CU at most, 0 = no cap; bit 6 (with bit 1): the pencil
     order instead of the banded one; bit 7: the evolution and MSD terms on the other load
-    variant; from bit 8, 3 bits per kernel
+    variant; bit 26: the periodic-box Hermitian step (blocks of B >= 2); from bit 8, 3 bits
+    per kernel
     family: 0 = that cap, 1 + c = the family's own cap c).  H.info.kernel_variant after
     gpuqt_autotune is such a code."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")
@@ -846,7 +849,7 @@ def gpuqt_autotune_cached(H: Hamiltonian, B: int = 1, ws=None, stream=None):
     """The cached variant for H's configuration at B, or gpuqt_autotune (then cached).  The
     autotuning workspace is only allocated on a miss.  Returns (times per load variant,
     whether the choice came from the cache)."""
-    t = np.zeros(6)
+    t = np.zeros(7)
     hit = ctypes.c_int32()
     if ws is None:
         st = lib().gpuqt_autotune_cached(H.handle, int(B), None, 0, _stream(stream), _ptr(t), ctypes.byref(hit))

@@ -683,6 +683,7 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
   up((void**)&h->d_seg_hop0, L.seg_hop.data(), L.seg_hop.size() * 8);
   h->max_nn_in = desc->max_nn;
+  if (L.hop_mode == HOP_UNIFORM && L.n_seg == 1 && L.uniform_width == 6) detect_box(desc, h->box);
   // plans for fewer resident workgroups per CU, and each hot family's occupancy
   h->d_plans[kPerCU - 1] = h->d_plan;
   h->d_blk0s[kPerCU - 1] = h->d_seg_blk0;
@@ -807,6 +808,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->kernel_variant = h->variant_code();
   info->family_caps = h->family_caps_code();
   info->max_nn = h->max_nn_in;
+  for (int q = 0; q < 3; ++q) info->box[q] = h->box[q];
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -1591,6 +1593,7 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   };
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
   h->series_nt_flip = 0;
+  h->use_box = 0;
   float best = 0.0f;
   int best_v = (h->nt | (h->banded << 1) | ((h->banded & h->pencil) << 2)), best_cap = h->per_cu_cap;
   std::vector<int> vars = {0, 1};
@@ -1621,6 +1624,31 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   h->banded = (best_v >> 1) & 1;
   h->pencil = (best_v >> 2) & 1;
   h->per_cu_cap = best_cap;
+  // on a periodic box, the box stencil kernel of the Hermitian step, uncapped and at
+  // caps 2..6; when it beats the best general variant it is kept, with its cap as the
+  // Hermitian family's own
+  if (!st && h->box[0] > 0 && B >= 2 && h->hop_mode == HOP_UNIFORM) {
+    h->use_box = 1;
+    float bbest = 0.0f;
+    int bcap = 0;
+    for (int cap : {0, 2, 3, 4, 5, 6}) {
+      h->fam_cap[FAM_SYM] = (int8_t)cap;
+      float mb = 0.0f;
+      if ((st = time_run([&] { return run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true); }, &mb)))
+        break;
+      if (bbest == 0.0f || mb < bbest) {
+        bbest = mb;
+        bcap = cap;
+      }
+    }
+    if (times_us && !st) times_us[kTuneTimes - 1] = 1e3 * bbest / (kSteps / 2);
+    if (!st && bbest < best) {
+      h->fam_cap[FAM_SYM] = (int8_t)bcap;
+    } else {
+      h->use_box = 0;
+      h->fam_cap[FAM_SYM] = -1;
+    }
+  }
   // with room for their vectors, each of the two-chain moment, two-vector
   // evolution and MSD families also gets its own cap at this load variant
   const WsLayout WF = ws_layout(h, kTuneVectors, B, kSteps + 1, kTuneNp);
@@ -1745,15 +1773,16 @@ gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
   if (variant < 0 || ((variant >> 2) & 15) > kPerCU || ((variant >> 6) & 1 && !((variant >> 1) & 1)) ||
-      (variant >> (8 + 3 * kFamilies)))
+      (variant >> (8 + 3 * kFamilies + 1)))
     return fail(GPUQT_ERR_ARG,
                 "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bit 6 the pencil "
-                "order (with bit 1), bit 7 the series families' load flip and 3 bits per kernel family "
-                "from bit 8");
+                "order (with bit 1), bit 7 the series families' load flip, 3 bits per kernel family "
+                "from bit 8 and bit 26 the periodic-box Hermitian step");
   h->nt = variant & 1;
   h->banded = (variant >> 1) & 1;
   h->pencil = (variant >> 6) & 1;
   h->series_nt_flip = (variant >> 7) & 1;
+  h->use_box = (variant >> (8 + 3 * kFamilies)) & 1;
   h->per_cu_cap = (variant >> 2) & 15;
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = (int8_t)(((variant >> (8 + 3 * f)) & 7) - 1);
   return GPUQT_OK;

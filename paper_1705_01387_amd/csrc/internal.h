@@ -45,7 +45,7 @@ struct BlkPlan {
 
 constexpr int kUnitLog2 = 6;        // rows per unit of a banded order: 64
 constexpr int kPencil = kBlock / 64;   // units per pencil: one per wavefront of a workgroup
-constexpr int kTuneTimes = 6;       // entries of gpuqt_autotune's times_us: 4 load/order variants + 2 pencil
+constexpr int kTuneTimes = 7;       // entries of gpuqt_autotune's times_us: 4 load/order variants, 2 pencil, box
 constexpr int kNumB = 5;            // block widths 1, 2, 4, 8, 16
 constexpr int64_t kBandBudget = int64_t(5) << 19;   // 2.5 MiB: bytes one row window may stream per XCD
 
@@ -110,6 +110,8 @@ struct DevMat {
   const BlkPlan* plan;       // [G] row ranges of the logical workgroups
   const int32_t* units;      // banded or pencil unit order for this block width (first row of each unit), or NULL
   int32_t pencil;            // 1: units is a pencil order, visited as row_at_pencil says
+  int32_t box[3];            // (Lx, Ly, Lz) of a periodic box stencil the Hermitian step may use, else 0
+  int32_t use_box;           // 1: the Hermitian step runs the box stencil kernel
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   // the hoppings given at build time (before class scales), for class gradients
@@ -156,6 +158,10 @@ struct Handle {
   // 1: the series families (evolution terms, MSD term) use the other load variant
   // (non-temporal <-> plain) than nt
   int32_t series_nt_flip = 0;
+  // periodic box of the matrix (detect_box), and whether the Hermitian step of blocks of
+  // B >= 2 vectors uses the box stencil kernel for it
+  int32_t box[3] = {0, 0, 0};
+  int32_t use_box = 0;
   // at most this many resident workgroups per CU (0: as many as fit).  Fewer
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
@@ -226,9 +232,10 @@ struct Handle {
     return c;
   }
   // nt | banded << 1 | per_cu_cap << 2 | pencil << 6 | series_nt_flip << 7 | (fam_cap[f] + 1) << (8 + 3 f)
+  // | use_box << 26
   int32_t variant_code() const {
     return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (series_nt_flip << 7) |
-           (family_caps_code() << 8);
+           (family_caps_code() << 8) | ((box[0] > 0 ? use_box : 0) << 26);
   }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
@@ -246,6 +253,10 @@ struct Handle {
     const int lb = log2B(B);
     m.pencil = (banded && pencil && d_units_p[lb]) ? 1 : 0;
     m.units = m.pencil ? d_units_p[lb] : (banded ? d_units[lb] : nullptr);
+    m.box[0] = box[0];
+    m.box[1] = box[1];
+    m.box[2] = box[2];
+    m.use_box = (box[0] > 0 && use_box) ? 1 : 0;
     m.slice_ptr = d_slice_ptr;
     m.col = d_col;
     m.hop = d_hop;
@@ -341,6 +352,12 @@ void banded_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
 // D < 128 keep the plain order.
 void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t>& period,
                   const std::vector<int64_t>& width, std::vector<int32_t>* out);
+
+// A periodic simple cubic box in natural order: one segment, every row i = x + Lx (y + Ly z)
+// with exactly the six neighbours (x +- 1 mod Lx, y, z), (x, y +- 1 mod Ly, z),
+// (x, y, z +- 1 mod Lz) in any slot order, Lx, Ly, Lz >= 3.  box = (Lx, Ly, Lz) when it
+// is one (checked row by row), else (0, 0, 0).
+bool detect_box(const gpuqt_h_desc* d, int32_t box[3]);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
 // Transport quantities of Section 2.2 from reconstructed rows (see gpuqt_transport_lengths).

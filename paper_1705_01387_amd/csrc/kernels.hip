@@ -27,6 +27,8 @@
 // fixed-shape final reduction over workgroups.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "bessel.h"
@@ -125,6 +127,171 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
     }
     cdot_acc(cr, ci, y, y);
   });
+  block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
+  __syncthreads();
+  block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
+  if (first) {
+    __syncthreads();
+    block_reduce_store<B>(br, bi, part_b + (int64_t)lb * B);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The Hermitian moment step of k_moment_step_sym on a periodic box (every row
+// x + Lx (y + Ly z) with the six neighbours one step away in x, y and z, one
+// uniform hopping; detect_box), for blocks of B >= 2 vectors.  The gathers of
+// the general kernel fetch every element of x through the L1 five times per
+// step (as the row's own element and as the neighbour one line and one plane
+// away on either side).  Here a workgroup owns a TX x TY column of the box and
+// a run of zc planes and marches through them: each lane keeps its elements of
+// planes z - 1, z and z + 1 in registers (the z neighbours), plane z of the
+// tile and its one-row halo go to LDS (the x and y neighbours), so x is read
+// about (1 + halo) times instead of five, and the neighbour indices are not
+// read at all.  Planes z + 2 and the halo of z + 1 are loaded while plane z is
+// computed; one barrier per plane (double-buffered LDS).  Positions of a tile
+// past the box edge hold the wrapped rows (so the edge rows' periodic
+// neighbours are in place) and produce no output.  Work items (column, run of
+// planes) go round the G workgroups, each writing one partial like the
+// general kernel.
+// ---------------------------------------------------------------------------
+template <int B, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_moment_step_sym_box(DevMat A, StepIO io, int zc,
+                                                                double2* __restrict__ part_a,
+                                                                double2* __restrict__ part_b,
+                                                                double2* __restrict__ part_c) {
+  constexpr int PX = TX + 2, PY = TY + 2, PE = PX * PY * B;   // staged elements per plane
+  constexpr int OE = TX * TY * B;                              // own elements per plane
+  static_assert(OE % kBlock == 0, "a tile plane must give every thread the same count");
+  constexpr int OPT = OE / kBlock;
+  constexpr int HE = (2 * TX + 2 * TY) * B;                    // halo elements (no corners)
+  constexpr int HPT = (HE + kBlock - 1) / kBlock;
+  __shared__ double2 lds[2][PE];
+  const int lb = logical_block(A.G);
+  const int Lx = A.box[0], Ly = A.box[1], Lz = A.box[2];
+  const int txn = (Lx + TX - 1) / TX, tyn = (Ly + TY - 1) / TY, zn = (Lz + zc - 1) / zc;
+  const int64_t items = (int64_t)txn * tyn * zn;
+  const double hu = A.seg_hop[0];
+  const int b = threadIdx.x & (B - 1);
+  const double2* __restrict__ x = io.x;
+  double2* __restrict__ out = io.out;
+  const bool first = io.first;
+  const double2* __restrict__ wsrc = first ? x : io.w;
+  const int64_t plane = (int64_t)Lx * Ly;
+  auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
+  // tile-relative positions of this thread's own and halo elements (element b of each)
+  int oslot[OPT], olx[OPT], oly[OPT];
+#pragma unroll
+  for (int i = 0; i < OPT; ++i) {
+    const int p = (threadIdx.x + i * kBlock) / B;
+    olx[i] = p % TX;
+    oly[i] = p / TX;
+    oslot[i] = ((oly[i] + 1) * PX + olx[i] + 1) * B + b;
+  }
+  int hslot[HPT], hpx[HPT], hpy[HPT];
+  bool hval[HPT];
+#pragma unroll
+  for (int j = 0; j < HPT; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    const int q = e / B;
+    hval[j] = e < HE;
+    int px = 0, py = 0;
+    if (q < TX) {
+      px = q + 1;
+    } else if (q < 2 * TX) {
+      px = q - TX + 1;
+      py = PY - 1;
+    } else if (q < 2 * TX + TY) {
+      py = q - 2 * TX + 1;
+    } else {
+      px = PX - 1;
+      py = q - 2 * TX - TY + 1;
+    }
+    hpx[j] = px;
+    hpy[j] = py;
+    hslot[j] = hval[j] ? (py * PX + px) * B + b : 0;
+  }
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
+  int buf = 0;
+  for (int64_t it = lb; it < items; it += A.G) {
+    const int tz = (int)(it % zn);
+    const int64_t txy = it / zn;
+    const int x0 = (int)(txy % txn) * TX, y0 = (int)(txy / txn) * TY;
+    const int z0 = tz * zc, z1 = min(z0 + zc, Lz);
+    int64_t orow[OPT], hrow[HPT];
+    bool oval[OPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      const int X = x0 + olx[i], Y = y0 + oly[i];
+      oval[i] = X < Lx && Y < Ly;
+      orow[i] = (int64_t)wrap(Y, Ly) * Lx + wrap(X, Lx);
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j)
+      hrow[j] = (int64_t)wrap(y0 + hpy[j] - 1, Ly) * Lx + wrap(x0 + hpx[j] - 1, Lx);
+    auto ld = [&](int64_t row, int z) { return x[((int64_t)wrap(z, Lz) * plane + row) * B + b]; };
+    double2 xm[OPT], xc[OPT], xp[OPT], xq[OPT], hc[HPT], hn[HPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      xq[i] = make_double2(0.0, 0.0);
+      xm[i] = ld(orow[i], z0 - 1);
+      xc[i] = ld(orow[i], z0);
+      xp[i] = ld(orow[i], z0 + 1);
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+      hn[j] = make_double2(0.0, 0.0);
+      hc[j] = hval[j] ? ld(hrow[j], z0) : hn[j];
+    }
+    for (int z = z0; z < z1; ++z, buf ^= 1) {
+      const bool more = z + 1 < z1;
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) xq[i] = ld(orow[i], z + 2);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+          if (hval[j]) hn[j] = ld(hrow[j], z + 1);
+      }
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) lds[buf][oslot[i]] = xc[i];
+#pragma unroll
+      for (int j = 0; j < HPT; ++j)
+        if (hval[j]) lds[buf][hslot[j]] = hc[j];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        if (oval[i]) {
+          const int c = oslot[i];
+          double2 sn = cadd(lds[buf][c + B], lds[buf][c - B]);
+          sn = cadd(sn, lds[buf][c + PX * B]);
+          sn = cadd(sn, lds[buf][c - PX * B]);
+          sn = cadd(sn, xp[i]);
+          sn = cadd(sn, xm[i]);
+          const int64_t idx = ((int64_t)z * plane + orow[i]) * B + b;
+          const double dg = ldg<false>(A.diag + (int64_t)z * plane + orow[i]);
+          const double2 xr = xc[i];
+          const double2 h = make_double2(fma(dg, xr.x, hu * sn.x), fma(dg, xr.y, hu * sn.y));
+          const double2 wv = wsrc[idx];
+          const double2 y = first ? h : twice_minus(h, wv);
+          out[idx] = y;
+          if (first) {
+            cdot_acc(ar, ai, xr, xr);
+            cdot_acc(br, bi, xr, y);
+          } else {
+            cdot_acc(ar, ai, y, xr);
+          }
+          cdot_acc(cr, ci, y, y);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        xm[i] = xc[i];
+        xc[i] = xp[i];
+        xp[i] = xq[i];
+      }
+#pragma unroll
+      for (int j = 0; j < HPT; ++j) hc[j] = hn[j];
+    }
+  }
   block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
   __syncthreads();
   block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
@@ -670,6 +837,21 @@ hipError_t launch_moment_step_pair(const DevMat& A, int hop_mode, int B, const C
 
 hipError_t launch_moment_step_sym(const DevMat& A, int hop_mode, int B, const StepIO& io,
                                   double2* part_a, double2* part_b, double2* part_c, hipStream_t s) {
+  if (A.use_box && A.box[0] > 0 && hop_mode == HOP_UNIFORM && B >= 2) {
+    // runs of planes: about four work items per workgroup, at least 16 planes a run
+    const int tile_x = B == 2 ? 16 : 8, tile_y = 8;   // the tiles of the instances below
+    const int64_t cols = (int64_t)((A.box[0] + tile_x - 1) / tile_x) * ((A.box[1] + tile_y - 1) / tile_y);
+    int zc = (int)std::min<int64_t>(A.box[2], std::max<int64_t>(16, (A.box[2] * cols + 4 * A.G - 1) / (4 * (int64_t)A.G)));
+    zc = std::max(zc, 1);
+    const dim3 g(A.G);
+    switch (B) {
+      case 2: k_moment_step_sym_box<2, 16, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+      case 4: k_moment_step_sym_box<4, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+      case 8: k_moment_step_sym_box<8, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+      default: k_moment_step_sym_box<16, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+    }
+    return hipGetLastError();
+  }
   return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
     k_moment_step_sym<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value,
                       decltype(NTc)::value><<<dim3(A.G), kBlock, 0, s>>>(A, io, part_a, part_b, part_c);

@@ -551,4 +551,39 @@ void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
   }
 }
 
+bool detect_box(const gpuqt_h_desc* d, int32_t box[3]) {
+  box[0] = box[1] = box[2] = 0;
+  if (!d || d->n < 27 || d->max_nn < 6 || (d->n_segments > 1) || !d->nn || !d->nbr) return false;
+  const int64_t n = d->n;
+  const int64_t k = d->max_nn;
+  for (int64_t i = 0; i < n; ++i)
+    if (d->nn[i] != 6) return false;
+  // row 0 = (0, 0, 0): its neighbours sorted are 1, Lx - 1, Lx, (Ly - 1) Lx, Lx Ly, (Lz - 1) Lx Ly
+  int64_t c0[6];
+  for (int s = 0; s < 6; ++s) c0[s] = d->nbr[s];
+  std::sort(c0, c0 + 6);
+  const int64_t Lx = c0[2], LxLy = c0[4];
+  if (Lx < 3 || LxLy % Lx != 0) return false;
+  const int64_t Ly = LxLy / Lx;
+  if (Ly < 3 || n % LxLy != 0) return false;
+  const int64_t Lz = n / LxLy;
+  if (Lz < 3 || Lx > INT32_MAX || Ly > INT32_MAX || Lz > INT32_MAX) return false;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t x = i % Lx, y = (i / Lx) % Ly, z = i / LxLy;
+    int64_t e[6] = {(x + 1) % Lx + Lx * (y + Ly * z),      (x + Lx - 1) % Lx + Lx * (y + Ly * z),
+                    x + Lx * ((y + 1) % Ly + Ly * z),      x + Lx * ((y + Ly - 1) % Ly + Ly * z),
+                    x + Lx * (y + Ly * ((z + 1) % Lz)),    x + Lx * (y + Ly * ((z + Lz - 1) % Lz))};
+    int64_t c[6];
+    for (int s = 0; s < 6; ++s) c[s] = d->nbr[i * k + s];
+    std::sort(e, e + 6);
+    std::sort(c, c + 6);
+    for (int s = 0; s < 6; ++s)
+      if (c[s] != e[s]) return false;
+  }
+  box[0] = (int32_t)Lx;
+  box[1] = (int32_t)Ly;
+  box[2] = (int32_t)Lz;
+  return true;
+}
+
 }  // namespace gpuqt

@@ -158,23 +158,36 @@ def square(Lx: int, Ly: int, t1: float = -1.0, t2: Optional[float] = None,
 def cubic(L: int, t: float = -1.0, W: float = 0.0, seed: int = 0,
           onsite: Optional[np.ndarray] = None) -> Model:
     """Simple cubic L^3, periodic; index ix + L*(iy + L*iz); slots +-x, +-y, +-z."""
-    n = L ** 3
+    m = box(L, L, L, t=t, W=W, seed=seed, onsite=onsite)
+    m.name = f"cubic{L}"
+    return m
+
+
+def box(Lx: int, Ly: int, Lz: int, t: float = -1.0, W: float = 0.0, seed: int = 0,
+        onsite: Optional[np.ndarray] = None, slot_seed: Optional[int] = None) -> Model:
+    """Simple cubic Lx x Ly x Lz box, periodic in all three directions; index
+    ix + Lx*(iy + Ly*iz); slots +-x, +-y, +-z (each row's slots shuffled when slot_seed is
+    given)."""
+    n = Lx * Ly * Lz
     s = np.arange(n, dtype=np.int64)
-    ix = s % L
-    iy = (s // L) % L
-    iz = s // (L * L)
+    ix = s % Lx
+    iy = (s // Lx) % Ly
+    iz = s // (Lx * Ly)
 
     def idx(a, b, c):
-        return ((a % L) + L * ((b % L) + L * (c % L))).astype(np.int32)
+        return ((a % Lx) + Lx * ((b % Ly) + Ly * (c % Lz))).astype(np.int32)
 
     nbr = np.stack([idx(ix + 1, iy, iz), idx(ix - 1, iy, iz),
                     idx(ix, iy + 1, iz), idx(ix, iy - 1, iz),
                     idx(ix, iy, iz + 1), idx(ix, iy, iz - 1)], axis=1)
+    if slot_seed is not None:
+        order = np.argsort(np.random.default_rng(slot_seed).random((n, 6)), axis=1)
+        nbr = np.take_along_axis(nbr, order, axis=1).astype(np.int32)
     nn = np.full(n, 6, dtype=np.int32)
     hop = None if t == -1.0 else np.full((n, 6), t)
     U = onsite if onsite is not None else (anderson(n, W, seed) if W > 0 else None)
-    return Model(nn, nbr, hop, U, ix.astype(np.float64), float(L), float(n),
-                 name=f"cubic{L}")
+    return Model(nn, nbr, hop, U, ix.astype(np.float64), float(Lx), float(n),
+                 name=f"box{Lx}x{Ly}x{Lz}")
 
 
 def honeycomb(nx_cells: int, ny_cells: int, t: float = -2.7, a_cc: float = 0.142,

@@ -1,0 +1,101 @@
+"""The periodic-box Hermitian step (kernel variant bit 26): detection of periodic simple
+cubic boxes from the neighbour list, and moments through the box stencil kernel against the
+oracle for every block width it serves, box shapes that do and do not fill its 8 x 8 (16 x 8)
+tiles, shuffled neighbour slots and several workgroup counts.  Bar: normwise 1e-10."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1705_01387_amd as P
+from paper_1705_01387_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+BOX = 1 << 26
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def err(got, ref):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def oracle_dE(Hs):
+    return 1.01 * O.gershgorin_bound(Hs)
+
+
+def test_box_detection(gpu):
+    say("case: periodic box detection")
+    assert tuple(P.gpuqt_build_h_from_model(I.cubic(11, W=1.0, seed=1)).info.box) == (11, 11, 11)
+    assert tuple(P.gpuqt_build_h_from_model(I.box(13, 9, 7, W=1.0, seed=2)).info.box) == (13, 9, 7)
+    assert tuple(P.gpuqt_build_h_from_model(I.box(5, 4, 3, slot_seed=3)).info.box) == (5, 4, 3)
+    # not a box: bond disorder (not one hopping), a square lattice, a box of side 2, two segments
+    assert tuple(P.gpuqt_build_h_from_model(I.bond_disorder(I.cubic(5), 0.2, 4)).info.box) == (0, 0, 0)
+    assert tuple(P.gpuqt_build_h_from_model(I.square(12, 10)).info.box) == (0, 0, 0)
+    assert tuple(P.gpuqt_build_h_from_model(I.box(6, 5, 2)).info.box) == (0, 0, 0)
+    mods = [I.cubic(4), I.cubic(4)]
+    cat = I.concat_segments(mods)
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=[0, 64, 128], seg_length_x=[4.0, 4.0])
+    assert tuple(H.info.box) == (0, 0, 0)
+
+
+BOXES = {
+    "cubic11": lambda: I.cubic(11, W=4.0, seed=11),
+    "box19x13x10_shuffled": lambda: I.box(19, 13, 10, W=3.0, seed=12, slot_seed=13),
+    "box3x5x4": lambda: I.box(3, 5, 4, W=2.0, seed=14),
+    "box17x9x33": lambda: I.box(17, 9, 33, W=5.0, seed=15),
+}
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+@pytest.mark.parametrize("B", [2, 4, 8, 16])
+def test_box_moments_match_oracle(gpu, name, B):
+    """Hermitian moment sets (the step the box kernel runs) with the box bit on, at M = 2, 3
+    and 65, and at three per-CU caps (different workgroup counts, so different work item
+    rounds); the two-chain moments of phiL != phiR on the same handle stay right."""
+    say(f"case: box moments {name} B={B}")
+    m = BOXES[name]()
+    Hs, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    assert H.info.box[0] > 0
+    phi = I.random_phase(m.n, B, 16)
+    psi = I.random_phase(m.n, B, 17)
+    d = dev(phi)
+    for cap in (0, 2, 5):
+        P.gpuqt_set_variant(H, BOX | (cap << 2))
+        assert H.info.kernel_variant == BOX | (cap << 2)
+        for M in (2, 3, 65):
+            ref = O.chebyshev_moments(Hs / dE, phi, phi, M).T
+            assert err(host(P.gpuqt_moments(H, d, d, M))[0], ref) < TOL, (cap, M)
+    ref2 = O.chebyshev_moments(Hs / dE, phi, psi, 40).T
+    assert err(host(P.gpuqt_moments(H, d, dev(psi), 40))[0], ref2) < TOL
+
+
+def test_box_msd_rows(gpu):
+    """An MSD series on a box with the box bit: its rows' moment sets (Hermitian, chi) go
+    through the box kernel."""
+    say("case: box MSD rows B=4")
+    m = I.box(14, 11, 9, W=3.0, seed=18)
+    Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    P.gpuqt_set_variant(H, BOX)
+    phi = I.random_phase(m.n, 4, 19)
+    dts = [0.6, 1.1]
+    got = host(P.gpuqt_msd(H, dev(phi), dts, 48))[:, 0]
+    ref = O.msd_moments(Hs, XH, phi, dts, dE, 48)
+    for k in range(len(dts)):
+        assert err(got[k], ref[k].T) < TOL, k

@@ -116,12 +116,17 @@ def test_autotune_keeps_results(gpu):
     H = P.gpuqt_build_h_from_model(m)
     phi = dev(I.random_phase(m.n, 4, 66))
     t = P.gpuqt_autotune(H, 4)
-    assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:] == 0)   # no banded order
+    assert tuple(H.info.box) == (11, 11, 11)
+    # no banded or pencil order; the periodic-box stencil timed
+    assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:6] == 0) and t[6] > 0
     code = H.info.kernel_variant
     assert code & 3 in (0, 1) and (code >> 2) & 15 <= 8 and (code >> 6) & 1 == 0
+    code_box = (code >> 26) & 1
+    code = code & ~(1 << 26)                       # the family-cap checks below read bits 8-25
     fc = H.info.family_caps   # the pair (2), msd (4) and evolve pair (5) families got their own cap
     assert fc == code >> 8
-    assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 1, 3))
+    assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 3))
+    assert (fc >> 3) & 7 == 0 or code_box            # the Hermitian family: its own cap only with the box stencil
     a = host(P.gpuqt_moments(H, phi, phi, 200))
     Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     dE = oracle_dE(Ho)
@@ -131,17 +136,20 @@ def test_autotune_keeps_results(gpu):
     psi = dev(I.random_phase(m.n, 4, 67))
     ref2 = O.chebyshev_moments(Ho / dE, host(phi), host(psi), 200).T
     assert err(host(P.gpuqt_moments(H, phi, psi, 200))[0], ref2) < TOL
-    P.gpuqt_set_variant(H, code & 63)
-    assert H.info.family_caps == 0 and H.info.kernel_variant == code & 63
-    P.gpuqt_set_variant(H, code)                       # the tuned code round-trips
-    assert H.info.kernel_variant == code
-    for bad in (code | (1 << 6), 1 << 26, 9 << 2):
+    P.gpuqt_set_variant(H, code & 255)
+    assert H.info.family_caps == 0 and H.info.kernel_variant == code & 255
+    P.gpuqt_set_variant(H, code | (code_box << 26))    # the tuned code round-trips
+    assert H.info.kernel_variant == code | (code_box << 26)
+    for v in (code | (1 << 26), code):                 # box stencil on and off: same moments
+        P.gpuqt_set_variant(H, v)
+        assert err(host(P.gpuqt_moments(H, phi, phi, 200))[0], ref) < TOL, v
+    for bad in (code | (1 << 6), 1 << 27, 9 << 2):
         with pytest.raises(P.GpuqtError):
             P.gpuqt_set_variant(H, bad)
     Hb = P.gpuqt_build_h_from_model(m, band_rows=64)                      # period 121 > 64
     tb = P.gpuqt_autotune(Hb, 4)
     # banded variants timed; no pencil order below a period of 128 rows
-    assert np.all(np.isfinite(tb)) and np.all(tb[:4] > 0) and np.all(tb[4:] == 0)
+    assert np.all(np.isfinite(tb)) and np.all(tb[:4] > 0) and np.all(tb[4:6] == 0) and tb[6] > 0
     assert err(host(P.gpuqt_moments(Hb, phi, phi, 200))[0], ref) < TOL
     m12 = I.cubic(12, W=4.0, seed=68)                                      # period 144: pencils too
     Hp = P.gpuqt_build_h_from_model(m12, band_rows=64)
