@@ -98,10 +98,17 @@ def family_bytes(info, B, family="moment"):
 
 
 def box_used(info, B, family):
-    """Whether the Hermitian moment step runs the periodic-box stencil kernel (variant bit 26 on
-    a handle whose matrix is a periodic box, blocks of B >= 2)."""
-    return (family == "moment_sym" and B >= 2 and int(info.box[0]) > 0
-            and (int(info.kernel_variant) >> 26) & 1 == 1)
+    """Whether the family runs a periodic-box stencil kernel: the Hermitian moment step with
+    variant bit 26, the MSD term with bit 27 (a handle whose matrix is a periodic box, with
+    uniform x steps for the MSD term; blocks of B >= 2)."""
+    if B < 2 or int(info.box[0]) <= 0:
+        return False
+    v = int(info.kernel_variant)
+    if family == "moment_sym":
+        return (v >> 26) & 1 == 1
+    if family == "msd":
+        return (v >> 27) & 1 == 1 and int(info.box_msd) == 1
+    return False
 
 
 SERIES_FAMILIES = ("evolve", "msd", "evolve_pair")
@@ -122,7 +129,7 @@ def family_config(v, family):
     c = (v >> (8 + 3 * K_FAMILIES.index(family))) & 7
     if c:
         cap = c - 1
-    box = (v >> 26) & 1 if family == "moment_sym" else 0
+    box = (v >> 26) & 1 if family == "moment_sym" else ((v >> 27) & 1 if family == "msd" else 0)
     return nt, banded, banded & ((v >> 6) & 1), cap, box
 
 
@@ -145,7 +152,7 @@ def pick_variant(P, H, B, ws, args):
     Returns (autotune times per load variant or zeros, whether the choice came from the cache)."""
     if args.variant >= 0:
         P.gpuqt_set_variant(H, args.variant)
-        return [0.0] * 6, False
+        return [0.0] * 7, False
     t, cached = P.gpuqt_autotune_cached(H, B, ws=ws)
     return [float(x) for x in t], bool(cached)
 

@@ -151,6 +151,9 @@ typedef struct {
   int32_t box[3];            /* (Lx, Ly, Lz) when H is a periodic simple cubic box in natural
                                 order with one uniform hopping (see gpuqt_autotune, bit 26),
                                 else 0 */
+  int32_t box_msd;           /* 1: on that box the position differences are +-dx for the x
+                                neighbours and 0 for the others, so the MSD term can run as a
+                                box stencil too (bit 27) */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -407,7 +410,9 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * a column of the box, keeps each lane's elements of three consecutive planes in
  * registers and the current plane's tile in LDS, so x is read about once per step instead
  * of once per neighbour and no neighbour indices are read (timed against the best other
- * variant, kept when faster);
+ * variant, kept when faster); bit 27: the fused MSD term likewise (both chains staged,
+ * where the position differences are +-dx on the x neighbours and 0 on the others,
+ * gpuqt_h_info_t.box_msd), timed against the MSD family's best and kept when faster;
  * bit 6 (with bit 1): the pencil order instead (built for segments with a row
  * period of at least 128 rows: the four wavefronts of a workgroup take the
  * same rows of four consecutive periods at once, so a row's neighbours one
@@ -444,9 +449,10 @@ gpuqt_status gpuqt_autotune(gpuqt_h h, int32_t B, void *ws, size_t ws_bytes, voi
  * configuration.  The banded and pencil bits only take effect for block widths that have
  * such an order (gpuqt_h_info_t.banded_mask, pencil_mask); a pencil bit for a width without
  * a pencil order falls back to the banded order.  Bit 26 (the box stencil of the Hermitian
- * step) takes effect on a periodic box (gpuqt_h_info_t.box) for blocks of B >= 2.
+ * step) takes effect on a periodic box (gpuqt_h_info_t.box) for blocks of B >= 2, bit 27
+ * (that of the MSD term) where gpuqt_h_info_t.box_msd is also set.
  * GPUQT_ERR_ARG for a negative code, a per-CU cap above 8, bit 6 without bit 1 or bits set
- * above bit 26. */
+ * above bit 27. */
 gpuqt_status gpuqt_set_variant(gpuqt_h h, int32_t variant);
 
 /*

@@ -54,7 +54,7 @@ class HInfo(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
         ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32), ("max_nn", ctypes.c_int32),
-        ("pencil_mask", ctypes.c_int32), ("box", ctypes.c_int32 * 3),
+        ("pencil_mask", ctypes.c_int32), ("box", ctypes.c_int32 * 3), ("box_msd", ctypes.c_int32),
     ]
 
 
@@ -822,8 +822,8 @@ def gpuqt_set_variant(H: Hamiltonian, variant: int):
     """Pin the kernel variant code (bit 0: non-temporal streams, bit 1: banded row order,
     bits 2-5: resident workgroups per CU at most, 0 = no cap; bit 6 (with bit 1): the pencil
     order instead of the banded one; bit 7: the evolution and MSD terms on the other load
-    variant; bit 26: the periodic-box Hermitian step (blocks of B >= 2); from bit 8, 3 bits
-    per kernel
+    variant; bit 26: the periodic-box Hermitian step (blocks of B >= 2), bit 27: the
+    periodic-box MSD term; from bit 8, 3 bits per kernel
     family: 0 = that cap, 1 + c = the family's own cap c).  H.info.kernel_variant after
     gpuqt_autotune is such a code."""
     _check(lib().gpuqt_set_variant(H.handle, int(variant)), "gpuqt_set_variant")

@@ -683,7 +683,8 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   up((void**)&h->d_seg_hop, L.seg_hop.data(), L.seg_hop.size() * 8);
   up((void**)&h->d_seg_hop0, L.seg_hop.data(), L.seg_hop.size() * 8);
   h->max_nn_in = desc->max_nn;
-  if (L.hop_mode == HOP_UNIFORM && L.n_seg == 1 && L.uniform_width == 6) detect_box(desc, h->box);
+  if (L.hop_mode == HOP_UNIFORM && L.n_seg == 1 && L.uniform_width == 6 && detect_box(desc, h->box))
+    h->box_msd_ok = box_dx_uniform(L, h->box, &h->box_dx) ? 1 : 0;
   // plans for fewer resident workgroups per CU, and each hot family's occupancy
   h->d_plans[kPerCU - 1] = h->d_plan;
   h->d_blk0s[kPerCU - 1] = h->d_seg_blk0;
@@ -809,6 +810,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->family_caps = h->family_caps_code();
   info->max_nn = h->max_nn_in;
   for (int q = 0; q < 3; ++q) info->box[q] = h->box[q];
+  info->box_msd = h->box_msd_ok;
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -1594,6 +1596,7 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
   h->series_nt_flip = 0;
   h->use_box = 0;
+  h->use_box_msd = 0;
   float best = 0.0f;
   int best_v = (h->nt | (h->banded << 1) | ((h->banded & h->pencil) << 2)), best_cap = h->per_cu_cap;
   std::vector<int> vars = {0, 1};
@@ -1659,14 +1662,16 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
     double* J = reinterpret_cast<double*>(base + WF.off_J);
     HIP_TRY(launch_fill_phase(h->view(B), B, v[1], s));
     const double dt = 1.0;
+    // one timed run of family f's kernels
+    auto run_family = [&](int f) -> gpuqt_status {
+      if (f == FAM_PAIR) return run_moments(h, B, v[0], v[1], kSteps + 1, partF, v[2], v[3], s, false, v[4], v[5]);
+      if (f == FAM_EVOLVE_PAIR)
+        return run_evolve_pair(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], J, s);
+      return run_evolve(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], nullptr, J, s);
+    };
     // the best cap of family f at the current load variants (its time in *best_ms)
     auto tune_family = [&](int f, float* best_ms) -> gpuqt_status {
-      auto run = [&]() -> gpuqt_status {
-        if (f == FAM_PAIR) return run_moments(h, B, v[0], v[1], kSteps + 1, partF, v[2], v[3], s, false, v[4], v[5]);
-        if (f == FAM_EVOLVE_PAIR)
-          return run_evolve_pair(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], J, s);
-        return run_evolve(h, B, dt, kTuneNp, v[0], v[2], v[1], v[3], v[4], v[5], v[6], v[7], nullptr, J, s);
-      };
+      auto run = [&]() -> gpuqt_status { return run_family(f); };
       caps_of(f, &caps);
       float fbest = 0.0f;
       int fcap = -1;
@@ -1687,13 +1692,14 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
     st = tune_family(FAM_PAIR, &t_pair);
     // the series families (two-vector evolution and MSD terms) with the handle's
     // load variant and with the other one; the pair of caps of the faster total stays
-    float tot[2] = {0.0f, 0.0f};
+    float tot[2] = {0.0f, 0.0f}, tmsd[2] = {0.0f, 0.0f};
     int8_t cap_ev[2] = {-1, -1}, cap_msd[2] = {-1, -1};
     for (int flip = 0; flip < 2 && !st; ++flip) {
       h->series_nt_flip = flip;
       float te = 0.0f, tm = 0.0f;
       if ((st = tune_family(FAM_EVOLVE_PAIR, &te)) || (st = tune_family(FAM_MSD, &tm))) break;
       tot[flip] = te + tm;
+      tmsd[flip] = tm;
       cap_ev[flip] = h->fam_cap[FAM_EVOLVE_PAIR];
       cap_msd[flip] = h->fam_cap[FAM_MSD];
     }
@@ -1702,11 +1708,35 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
       h->series_nt_flip = fl;
       h->fam_cap[FAM_EVOLVE_PAIR] = cap_ev[fl];
       h->fam_cap[FAM_MSD] = cap_msd[fl];
+      // on a periodic box with uniform x steps, the MSD term's box stencil kernel,
+      // uncapped and at caps 2..6, kept (with its cap) when faster
+      if (h->box_msd_ok && B >= 2 && h->hop_mode == HOP_UNIFORM) {
+        h->use_box_msd = 1;
+        float bbest = 0.0f;
+        int bcap = 0;
+        for (int cap : {0, 2, 3, 4, 5, 6}) {
+          h->fam_cap[FAM_MSD] = (int8_t)cap;
+          float mb = 0.0f;
+          if ((st = time_run([&] { return run_family(FAM_MSD); }, &mb))) break;
+          if (bbest == 0.0f || mb < bbest) {
+            bbest = mb;
+            bcap = cap;
+          }
+        }
+        if (!st && bbest < tmsd[fl]) {
+          h->fam_cap[FAM_MSD] = (int8_t)bcap;
+        } else {
+          h->use_box_msd = 0;
+          h->fam_cap[FAM_MSD] = cap_msd[fl];
+        }
+      }
     }
   }
   if (st) {
     for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = -1;
     h->series_nt_flip = 0;
+    h->use_box = 0;
+    h->use_box_msd = 0;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1773,16 +1803,17 @@ gpuqt_status gpuqt_set_variant(gpuqt_h hh, int32_t variant) {
   Handle* h = reinterpret_cast<Handle*>(hh);
   if (!h) return fail(GPUQT_ERR_ARG, "NULL handle");
   if (variant < 0 || ((variant >> 2) & 15) > kPerCU || ((variant >> 6) & 1 && !((variant >> 1) & 1)) ||
-      (variant >> (8 + 3 * kFamilies + 1)))
+      (variant >> (8 + 3 * kFamilies + 2)))
     return fail(GPUQT_ERR_ARG,
                 "variant must be bits 0-1 load variant, bits 2-5 a per-CU cap of 0..8, bit 6 the pencil "
                 "order (with bit 1), bit 7 the series families' load flip, 3 bits per kernel family "
-                "from bit 8 and bit 26 the periodic-box Hermitian step");
+                "from bit 8, bit 26 the periodic-box Hermitian step and bit 27 the periodic-box MSD term");
   h->nt = variant & 1;
   h->banded = (variant >> 1) & 1;
   h->pencil = (variant >> 6) & 1;
   h->series_nt_flip = (variant >> 7) & 1;
   h->use_box = (variant >> (8 + 3 * kFamilies)) & 1;
+  h->use_box_msd = (variant >> (8 + 3 * kFamilies + 1)) & 1;
   h->per_cu_cap = (variant >> 2) & 15;
   for (int f = 0; f < kFamilies; ++f) h->fam_cap[f] = (int8_t)(((variant >> (8 + 3 * f)) & 7) - 1);
   return GPUQT_OK;

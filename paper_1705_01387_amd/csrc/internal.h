@@ -112,6 +112,8 @@ struct DevMat {
   int32_t pencil;            // 1: units is a pencil order, visited as row_at_pencil says
   int32_t box[3];            // (Lx, Ly, Lz) of a periodic box stencil the Hermitian step may use, else 0
   int32_t use_box;           // 1: the Hermitian step runs the box stencil kernel
+  int32_t use_box_msd;       // 1: the MSD term runs the box stencil kernel (box_dx valid)
+  double box_dx;             // x_{i+1} - x_i of the box's x neighbours (the only non-zero dx)
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   // the hoppings given at build time (before class scales), for class gradients
@@ -162,6 +164,11 @@ struct Handle {
   // B >= 2 vectors uses the box stencil kernel for it
   int32_t box[3] = {0, 0, 0};
   int32_t use_box = 0;
+  // the box's position differences: 0 for the y and z neighbours and +-box_dx for the x
+  // neighbours on every row (box_msd_ok), which the MSD term's box kernel needs
+  int32_t box_msd_ok = 0;
+  double box_dx = 0.0;
+  int32_t use_box_msd = 0;
   // at most this many resident workgroups per CU (0: as many as fit).  Fewer
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
@@ -232,10 +239,11 @@ struct Handle {
     return c;
   }
   // nt | banded << 1 | per_cu_cap << 2 | pencil << 6 | series_nt_flip << 7 | (fam_cap[f] + 1) << (8 + 3 f)
-  // | use_box << 26
+  // | use_box << 26 | use_box_msd << 27
   int32_t variant_code() const {
     return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (series_nt_flip << 7) |
-           (family_caps_code() << 8) | ((box[0] > 0 ? use_box : 0) << 26);
+           (family_caps_code() << 8) | ((box[0] > 0 ? use_box : 0) << 26) |
+           ((box_msd_ok ? use_box_msd : 0) << 27);
   }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
   const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
@@ -257,6 +265,8 @@ struct Handle {
     m.box[1] = box[1];
     m.box[2] = box[2];
     m.use_box = (box[0] > 0 && use_box) ? 1 : 0;
+    m.use_box_msd = (box[0] > 0 && box_msd_ok && use_box_msd) ? 1 : 0;
+    m.box_dx = box_dx;
     m.slice_ptr = d_slice_ptr;
     m.col = d_col;
     m.hop = d_hop;
@@ -358,6 +368,11 @@ void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
 // (x, y, z +- 1 mod Lz) in any slot order, Lx, Ly, Lz >= 3.  box = (Lx, Ly, Lz) when it
 // is one (checked row by row), else (0, 0, 0).
 bool detect_box(const gpuqt_h_desc* d, int32_t box[3]);
+
+// The position differences of a detected box in layout L (uniform width 6): true, with
+// *dx = x_{i+1} - x_i, when every row's x neighbours have dx = +dx and -dx and its y and z
+// neighbours dx = 0.
+bool box_dx_uniform(const HostLayout& L, const int32_t box[3], double* dx);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
 // Transport quantities of Section 2.2 from reconstructed rows (see gpuqt_transport_lengths).

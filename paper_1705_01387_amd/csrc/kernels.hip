@@ -773,9 +773,210 @@ hipError_t launch_evolve_term(const DevMat& A, int hop_mode, int B, const StepIO
   });
 }
 
+namespace {
+
+// The fused MSD term of k_msd_term on a periodic box whose position differences are
+// +-box_dx on the x neighbours and 0 on the others, as the box stencil of
+// k_moment_step_sym_box with both chains staged: [X,H~] a at a row is
+// -box_dx hu (a_{x+1} - a_{x-1}).  Work items and tiles as there; no partial sums.
+template <int B, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_msd_term_box(DevMat A, ChainIO io, double2* __restrict__ acc_a,
+                                                         double2* __restrict__ acc_b,
+                                                         const double* __restrict__ Jtab, int ldJ, int m,
+                                                         double2 ph_m, double2 ph_0, int zc) {
+  constexpr int PX = TX + 2, PY = TY + 2, PE = PX * PY * B;
+  constexpr int OE = TX * TY * B;
+  static_assert(OE % kBlock == 0, "a tile plane must give every thread the same count");
+  constexpr int OPT = OE / kBlock;
+  constexpr int HE = (2 * TX + 2 * TY) * B;
+  constexpr int HPT = (HE + kBlock - 1) / kBlock;
+  __shared__ double2 lda[2][PE], ldb[2][PE];
+  const int lb = logical_block(A.G);
+  const int Lx = A.box[0], Ly = A.box[1], Lz = A.box[2];
+  const int txn = (Lx + TX - 1) / TX, tyn = (Ly + TY - 1) / TY, zn = (Lz + zc - 1) / zc;
+  const int64_t items = (int64_t)txn * tyn * zn;
+  const double hu = A.seg_hop[0];
+  const double hdx = hu * A.box_dx;
+  const double2 cm = cscale(Jtab[m], ph_m);
+  const double2 c0 = cscale(Jtab[0], ph_0);
+  const int b = threadIdx.x & (B - 1);
+  const bool first = io.first;
+  const double2* __restrict__ xa = io.xa;
+  const double2* __restrict__ xb = io.xb;
+  const double2* __restrict__ wa = first ? io.xa : io.wa;   // unused on the first step
+  const double2* __restrict__ wb = first ? io.xb : io.wb;
+  const double2* __restrict__ sa = first ? io.xa : acc_a;
+  const double2* __restrict__ sb = first ? io.xb : acc_b;
+  const int64_t plane = (int64_t)Lx * Ly;
+  auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
+  int oslot[OPT], olx[OPT], oly[OPT];
+#pragma unroll
+  for (int i = 0; i < OPT; ++i) {
+    const int p = (threadIdx.x + i * kBlock) / B;
+    olx[i] = p % TX;
+    oly[i] = p / TX;
+    oslot[i] = ((oly[i] + 1) * PX + olx[i] + 1) * B + b;
+  }
+  int hslot[HPT], hpx[HPT], hpy[HPT];
+  bool hval[HPT];
+#pragma unroll
+  for (int j = 0; j < HPT; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    const int q = e / B;
+    hval[j] = e < HE;
+    int px = 0, py = 0;
+    if (q < TX) {
+      px = q + 1;
+    } else if (q < 2 * TX) {
+      px = q - TX + 1;
+      py = PY - 1;
+    } else if (q < 2 * TX + TY) {
+      py = q - 2 * TX + 1;
+    } else {
+      px = PX - 1;
+      py = q - 2 * TX - TY + 1;
+    }
+    hpx[j] = px;
+    hpy[j] = py;
+    hslot[j] = hval[j] ? (py * PX + px) * B + b : 0;
+  }
+  int buf = 0;
+  for (int64_t it = lb; it < items; it += A.G) {
+    const int tz = (int)(it % zn);
+    const int64_t txy = it / zn;
+    const int x0 = (int)(txy % txn) * TX, y0 = (int)(txy / txn) * TY;
+    const int z0 = tz * zc, z1 = min(z0 + zc, Lz);
+    int64_t orow[OPT], hrow[HPT];
+    bool oval[OPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      const int X = x0 + olx[i], Y = y0 + oly[i];
+      oval[i] = X < Lx && Y < Ly;
+      orow[i] = (int64_t)wrap(Y, Ly) * Lx + wrap(X, Lx);
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j)
+      hrow[j] = (int64_t)wrap(y0 + hpy[j] - 1, Ly) * Lx + wrap(x0 + hpx[j] - 1, Lx);
+    auto at = [&](int64_t row, int z) { return ((int64_t)wrap(z, Lz) * plane + row) * B + b; };
+    double2 am[OPT], ac[OPT], ap[OPT], aq[OPT], bm[OPT], bc[OPT], bp[OPT], bq[OPT];
+    double2 hac[HPT], han[HPT], hbc[HPT], hbn[HPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      aq[i] = bq[i] = make_double2(0.0, 0.0);
+      am[i] = xa[at(orow[i], z0 - 1)];
+      ac[i] = xa[at(orow[i], z0)];
+      ap[i] = xa[at(orow[i], z0 + 1)];
+      bm[i] = xb[at(orow[i], z0 - 1)];
+      bc[i] = xb[at(orow[i], z0)];
+      bp[i] = xb[at(orow[i], z0 + 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+      han[j] = hbn[j] = make_double2(0.0, 0.0);
+      hac[j] = hval[j] ? xa[at(hrow[j], z0)] : han[j];
+      hbc[j] = hval[j] ? xb[at(hrow[j], z0)] : hbn[j];
+    }
+    for (int z = z0; z < z1; ++z, buf ^= 1) {
+      if (z + 1 < z1) {
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) {
+          aq[i] = xa[at(orow[i], z + 2)];
+          bq[i] = xb[at(orow[i], z + 2)];
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+          if (hval[j]) {
+            han[j] = xa[at(hrow[j], z + 1)];
+            hbn[j] = xb[at(hrow[j], z + 1)];
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        lda[buf][oslot[i]] = ac[i];
+        ldb[buf][oslot[i]] = bc[i];
+      }
+#pragma unroll
+      for (int j = 0; j < HPT; ++j)
+        if (hval[j]) {
+          lda[buf][hslot[j]] = hac[j];
+          ldb[buf][hslot[j]] = hbc[j];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        if (oval[i]) {
+          const int c = oslot[i];
+          const double2 axp = lda[buf][c + B], axm = lda[buf][c - B];
+          double2 na = cadd(axp, axm);
+          na = cadd(na, lda[buf][c + PX * B]);
+          na = cadd(na, lda[buf][c - PX * B]);
+          na = cadd(na, ap[i]);
+          na = cadd(na, am[i]);
+          double2 nb = cadd(ldb[buf][c + B], ldb[buf][c - B]);
+          nb = cadd(nb, ldb[buf][c + PX * B]);
+          nb = cadd(nb, ldb[buf][c - PX * B]);
+          nb = cadd(nb, bp[i]);
+          nb = cadd(nb, bm[i]);
+          const int64_t r = (int64_t)z * plane + orow[i];
+          const int64_t idx = r * B + b;
+          const double dg = ldg<false>(A.diag + r);
+          const double2 ha = make_double2(fma(dg, ac[i].x, hu * na.x), fma(dg, ac[i].y, hu * na.y));
+          const double2 hb = make_double2(fma(dg, bc[i].x, hu * nb.x), fma(dg, bc[i].y, hu * nb.y));
+          // [X,H~] a + H~ b, [X,H~]_rj = -dx_rj H~_rj
+          const double2 g = make_double2(hb.x - hdx * (axp.x - axm.x), hb.y - hdx * (axp.y - axm.y));
+          if (first) {
+            io.oa[idx] = ha;
+            io.ob[idx] = g;
+            acc_a[idx] = cadd(cmul(c0, ac[i]), cmul(cm, ha));
+            acc_b[idx] = cadd(cmul(c0, bc[i]), cmul(cm, g));
+          } else {
+            const double2 ya = twice_minus(ha, wa[idx]);
+            const double2 yb = twice_minus(g, wb[idx]);
+            io.oa[idx] = ya;
+            io.ob[idx] = yb;
+            acc_a[idx] = cadd(sa[idx], cmul(cm, ya));
+            acc_b[idx] = cadd(sb[idx], cmul(cm, yb));
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        am[i] = ac[i];
+        ac[i] = ap[i];
+        ap[i] = aq[i];
+        bm[i] = bc[i];
+        bc[i] = bp[i];
+        bp[i] = bq[i];
+      }
+#pragma unroll
+      for (int j = 0; j < HPT; ++j) {
+        hac[j] = han[j];
+        hbc[j] = hbn[j];
+      }
+    }
+  }
+}
+
+}  // namespace
+
 hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
                            double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
                            double2 phase_0, hipStream_t s) {
+  if (A.use_box_msd && A.box[0] > 0 && hop_mode == HOP_UNIFORM && B >= 2) {
+    // tiles: 16 x 8 (B = 2), 8 x 8 (4), 8 x 4 (8), 4 x 4 (16): two staged chains fit the LDS
+    const int tile_x = B == 2 ? 16 : (B == 16 ? 4 : 8), tile_y = B >= 8 ? 4 : 8;
+    const int64_t cols = (int64_t)((A.box[0] + tile_x - 1) / tile_x) * ((A.box[1] + tile_y - 1) / tile_y);
+    int zc = (int)std::min<int64_t>(A.box[2], std::max<int64_t>(16, (A.box[2] * cols + 4 * A.G - 1) / (4 * (int64_t)A.G)));
+    zc = std::max(zc, 1);
+    const dim3 g(A.G);
+    switch (B) {
+      case 2: k_msd_term_box<2, 16, 8><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+      case 4: k_msd_term_box<4, 8, 8><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+      case 8: k_msd_term_box<8, 8, 4><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+      default: k_msd_term_box<16, 4, 4><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+    }
+    return hipGetLastError();
+  }
   return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
     k_msd_term<decltype(Bc)::value, decltype(Hc)::value, decltype(Kc)::value, decltype(NTc)::value>
         <<<dim3(A.G), kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0);

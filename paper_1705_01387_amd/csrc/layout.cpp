@@ -586,4 +586,42 @@ bool detect_box(const gpuqt_h_desc* d, int32_t box[3]) {
   return true;
 }
 
+bool box_dx_uniform(const HostLayout& L, const int32_t box[3], double* dx) {
+  const int64_t Lx = box[0], Ly = box[1], LxLy = (int64_t)box[0] * box[1];
+  if (Lx <= 0 || L.uniform_width != 6 || L.dx.empty() || L.col.empty()) return false;
+  const int S = L.S;
+  double delta = 0.0;
+  bool have = false;
+  for (int64_t r = 0; r < L.n; ++r) {
+    const int64_t x = r % Lx, yz = r / Lx;
+    const int64_t xp = (x + 1) % Lx + Lx * yz, xm = (x + Lx - 1) % Lx + Lx * yz;
+    const int64_t base = (r / S) * (int64_t)(6 * S) + (r % S);
+    for (int j = 0; j < 6; ++j) {
+      const int64_t e = base + (int64_t)j * S;
+      const int64_t c = L.col[e];
+      const double d = L.dx[e];
+      if (c == xp) {
+        if (!have) {
+          delta = d;
+          have = true;
+        }
+        if (d != delta) return false;
+      } else if (c == xm) {
+        if (!have) {
+          delta = -d;
+          have = true;
+        }
+        if (d != -delta) return false;
+      } else if (d != 0.0) {
+        return false;
+      }
+    }
+  }
+  (void)Ly;
+  (void)LxLy;
+  if (!have) return false;
+  *dx = delta;
+  return true;
+}
+
 }  // namespace gpuqt

@@ -170,5 +170,5 @@ def test_committed_tune_cache_is_well_formed():
         key, code = ln.split("\t")
         code = int(code)
         assert key.startswith("gfx950 ") and key.split()[-1].startswith("B")
-        assert ((code >> 2) & 15) <= 8 and code >> 27 == 0
+        assert ((code >> 2) & 15) <= 8 and code >> 28 == 0
         assert not (code >> 6) & 1 or (code >> 1) & 1          # the pencil bit only with the banded bit

@@ -204,7 +204,7 @@ def test_variant_codes(cubic26):
         P.gpuqt_set_variant(H, 1 | (cap << 2))
         assert H.info.kernel_variant == 1 | (cap << 2)
         assert err(host(P.gpuqt_moments(H, dev(phi), dev(phi), 64))[0], ref) < TOL, cap
-    for bad in (-1, 9 << 2, 1 << 6, 1 << 27):
+    for bad in (-1, 9 << 2, 1 << 6, 1 << 28):
         with pytest.raises(P.GpuqtError):
             P.gpuqt_set_variant(H, bad)
     P.gpuqt_set_variant(H, 0)

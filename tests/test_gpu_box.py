@@ -99,3 +99,36 @@ def test_box_msd_rows(gpu):
     ref = O.msd_moments(Hs, XH, phi, dts, dE, 48)
     for k in range(len(dts)):
         assert err(got[k], ref[k].T) < TOL, k
+
+
+def test_box_msd_detection(gpu):
+    """box_msd needs +-dx on the x neighbours and 0 on the others: lattice positions give it,
+    positions with a per-site jitter do not (the Hermitian box step still applies)."""
+    say("case: box MSD detection")
+    m = I.box(9, 7, 5)
+    assert P.gpuqt_build_h_from_model(m).info.box_msd == 1
+    m.x = m.x + 0.01 * np.random.default_rng(20).random(m.n)
+    H = P.gpuqt_build_h_from_model(m)
+    assert tuple(H.info.box) == (9, 7, 5) and H.info.box_msd == 0
+
+
+@pytest.mark.parametrize("name", ["cubic11", "box19x13x10_shuffled", "box3x5x4", "box17x9x33"])
+@pytest.mark.parametrize("B", [2, 4, 8, 16])
+def test_box_msd_term_matches_oracle(gpu, name, B):
+    """MSD rows with both box kernels (bits 26 and 27) at two caps: the fused evolution +
+    commutator series runs as the box stencil, the rows' moment sets as the Hermitian one."""
+    say(f"case: box MSD term {name} B={B}")
+    m = BOXES[name]()
+    Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
+    dE = oracle_dE(Hs)
+    H = P.gpuqt_build_h_from_model(m, energy_max=dE)
+    assert H.info.box_msd == 1
+    phi = I.random_phase(m.n, B, 21)
+    dts = [0.7, 1.3]
+    ref = O.msd_moments(Hs, XH, phi, dts, dE, 24)
+    for cap in (0, 3):
+        P.gpuqt_set_variant(H, BOX | (1 << 27) | (cap << 2))
+        assert H.info.kernel_variant == BOX | (1 << 27) | (cap << 2)
+        got = host(P.gpuqt_msd(H, dev(phi), dts, 24))[:, 0]
+        for k in range(len(dts)):
+            assert err(got[k], ref[k].T) < TOL, (cap, k)

@@ -121,12 +121,12 @@ def test_autotune_keeps_results(gpu):
     assert np.all(np.isfinite(t)) and np.all(t[:2] > 0) and np.all(t[2:6] == 0) and t[6] > 0
     code = H.info.kernel_variant
     assert code & 3 in (0, 1) and (code >> 2) & 15 <= 8 and (code >> 6) & 1 == 0
-    code_box = (code >> 26) & 1
-    code = code & ~(1 << 26)                       # the family-cap checks below read bits 8-25
+    code_box = (code >> 26) & 3                    # the box stencils of the Hermitian step and MSD term
+    code = code & ~(3 << 26)                       # the family-cap checks below read bits 8-25
     fc = H.info.family_caps   # the pair (2), msd (4) and evolve pair (5) families got their own cap
     assert fc == code >> 8
     assert all((fc >> (3 * f)) & 7 >= 1 for f in (2, 4, 5)) and all((fc >> (3 * f)) & 7 == 0 for f in (0, 3))
-    assert (fc >> 3) & 7 == 0 or code_box            # the Hermitian family: its own cap only with the box stencil
+    assert (fc >> 3) & 7 == 0 or code_box & 1        # the Hermitian family: its own cap only with the box stencil
     a = host(P.gpuqt_moments(H, phi, phi, 200))
     Ho, _, _ = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     dE = oracle_dE(Ho)
@@ -143,7 +143,7 @@ def test_autotune_keeps_results(gpu):
     for v in (code | (1 << 26), code):                 # box stencil on and off: same moments
         P.gpuqt_set_variant(H, v)
         assert err(host(P.gpuqt_moments(H, phi, phi, 200))[0], ref) < TOL, v
-    for bad in (code | (1 << 6), 1 << 27, 9 << 2):
+    for bad in (code | (1 << 6), 1 << 28, 9 << 2):
         with pytest.raises(P.GpuqtError):
             P.gpuqt_set_variant(H, bad)
     Hb = P.gpuqt_build_h_from_model(m, band_rows=64)                      # period 121 > 64
