@@ -413,6 +413,8 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * variant, kept when faster); bit 27: the fused MSD term likewise (both chains staged,
  * where the position differences are +-dx on the x neighbours and 0 on the others,
  * gpuqt_h_info_t.box_msd), timed against the MSD family's best and kept when faster;
+ * both box kernels are timed uncapped and at caps 1..6 and keep the fastest as their
+ * family's own cap;
  * bit 6 (with bit 1): the pencil order instead (built for segments with a row
  * period of at least 128 rows: the four wavefronts of a workgroup take the
  * same rows of four consecutive periods at once, so a row's neighbours one

@@ -1628,13 +1628,14 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   h->pencil = (best_v >> 2) & 1;
   h->per_cu_cap = best_cap;
   // on a periodic box, the box stencil kernel of the Hermitian step, uncapped and at
-  // caps 2..6; when it beats the best general variant it is kept, with its cap as the
-  // Hermitian family's own
+  // caps 1..6 (its loads run a plane ahead, so a few workgroups per CU fill HBM, and
+  // fewer concurrent streams use the DRAM pages and the L2 better); when it beats the
+  // best general variant it is kept, with its cap as the Hermitian family's own
   if (!st && h->box[0] > 0 && B >= 2 && h->hop_mode == HOP_UNIFORM) {
     h->use_box = 1;
     float bbest = 0.0f;
     int bcap = 0;
-    for (int cap : {0, 2, 3, 4, 5, 6}) {
+    for (int cap : {0, 1, 2, 3, 4, 5, 6}) {
       h->fam_cap[FAM_SYM] = (int8_t)cap;
       float mb = 0.0f;
       if ((st = time_run([&] { return run_moments(h, B, phi, phi, kSteps + 1, part, A, Bf, s, true); }, &mb)))
@@ -1709,12 +1710,12 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
       h->fam_cap[FAM_EVOLVE_PAIR] = cap_ev[fl];
       h->fam_cap[FAM_MSD] = cap_msd[fl];
       // on a periodic box with uniform x steps, the MSD term's box stencil kernel,
-      // uncapped and at caps 2..6, kept (with its cap) when faster
+      // uncapped and at caps 1..6, kept (with its cap) when faster
       if (h->box_msd_ok && B >= 2 && h->hop_mode == HOP_UNIFORM) {
         h->use_box_msd = 1;
         float bbest = 0.0f;
         int bcap = 0;
-        for (int cap : {0, 2, 3, 4, 5, 6}) {
+        for (int cap : {0, 1, 2, 3, 4, 5, 6}) {
           h->fam_cap[FAM_MSD] = (int8_t)cap;
           float mb = 0.0f;
           if ((st = time_run([&] { return run_family(FAM_MSD); }, &mb))) break;

@@ -365,7 +365,8 @@ void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
 
 // A periodic simple cubic box in natural order: one segment, every row i = x + Lx (y + Ly z)
 // with exactly the six neighbours (x +- 1 mod Lx, y, z), (x, y +- 1 mod Ly, z),
-// (x, y, z +- 1 mod Lz) in any slot order, Lx, Ly, Lz >= 3.  box = (Lx, Ly, Lz) when it
+// (x, y, z +- 1 mod Lz) in any slot order, Lx, Ly, Lz >= 3 and Lx Ly <= 2^24 (so that a
+// plane of a block of up to 16 vectors spans at most 4 GiB).  box = (Lx, Ly, Lz) when it
 // is one (checked row by row), else (0, 0, 0).
 bool detect_box(const gpuqt_h_desc* d, int32_t box[3]);
 

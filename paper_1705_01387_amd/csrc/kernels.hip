@@ -147,133 +147,203 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym(DevMat A, StepIO io,
 // planes z - 1, z and z + 1 in registers (the z neighbours), plane z of the
 // tile and its one-row halo go to LDS (the x and y neighbours), so x is read
 // about (1 + halo) times instead of five, and the neighbour indices are not
-// read at all.  Planes z + 2 and the halo of z + 1 are loaded while plane z is
-// computed; one barrier per plane (double-buffered LDS).  Positions of a tile
-// past the box edge hold the wrapped rows (so the edge rows' periodic
+// read at all.  Everything plane z + 1 needs (x of plane z + 2, the halo of
+// z + 1, w and the diagonal) is loaded while plane z is computed; one barrier
+// per plane (double-buffered LDS).  Addresses are a plane base, uniform over
+// the workgroup, plus a 32-bit byte offset per lane that is fixed for the run
+// (a plane of the block must span less than 4 GiB; box_fits).  Positions of a
+// tile past the box edge hold the wrapped rows (so the edge rows' periodic
 // neighbours are in place) and produce no output.  Work items (column, run of
 // planes) go round the G workgroups, each writing one partial like the
-// general kernel.
+// general kernel; the column index runs fastest, so the workgroups of one XCD
+// (consecutive logical blocks) hold a band of neighbouring columns at the same
+// run and march through z together, and the halo rows they read from each
+// other are hits in that XCD's L2.
 // ---------------------------------------------------------------------------
+
+// Which elements of a TX x TY box tile (plus its one-cell halo without the
+// corners) this thread handles, their LDS slots, and per work item their byte
+// offsets inside a plane of a block of B vectors and of the diagonal.
 template <int B, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_moment_step_sym_box(DevMat A, StepIO io, int zc,
-                                                                double2* __restrict__ part_a,
-                                                                double2* __restrict__ part_b,
-                                                                double2* __restrict__ part_c) {
-  constexpr int PX = TX + 2, PY = TY + 2, PE = PX * PY * B;   // staged elements per plane
-  constexpr int OE = TX * TY * B;                              // own elements per plane
+struct BoxTile {
+  static constexpr int PX = TX + 2, PY = TY + 2, PE = PX * PY * B;   // staged elements per plane
+  static constexpr int OE = TX * TY * B;                              // own elements per plane
   static_assert(OE % kBlock == 0, "a tile plane must give every thread the same count");
-  constexpr int OPT = OE / kBlock;
-  constexpr int HE = (2 * TX + 2 * TY) * B;                    // halo elements (no corners)
-  constexpr int HPT = (HE + kBlock - 1) / kBlock;
-  __shared__ double2 lds[2][PE];
-  const int lb = logical_block(A.G);
-  const int Lx = A.box[0], Ly = A.box[1], Lz = A.box[2];
-  const int txn = (Lx + TX - 1) / TX, tyn = (Ly + TY - 1) / TY, zn = (Lz + zc - 1) / zc;
-  const int64_t items = (int64_t)txn * tyn * zn;
-  const double hu = A.seg_hop[0];
-  const int b = threadIdx.x & (B - 1);
-  const double2* __restrict__ x = io.x;
-  double2* __restrict__ out = io.out;
-  const bool first = io.first;
-  const double2* __restrict__ wsrc = first ? x : io.w;
-  const int64_t plane = (int64_t)Lx * Ly;
-  auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
-  // tile-relative positions of this thread's own and halo elements (element b of each)
-  int oslot[OPT], olx[OPT], oly[OPT];
+  static constexpr int OPT = OE / kBlock;
+  static constexpr int HE = (2 * TX + 2 * TY) * B;                    // halo elements
+  static constexpr int HPT = (HE + kBlock - 1) / kBlock;
+  // hval: the lane's halo element exists (HE is not always a multiple of kBlock); the
+  // other lanes load the element of lane e mod HE instead and do not stage it, so that
+  // every lane issues the same loads (a load under a lane test would make the compiler
+  // wait for all loads in flight, prefetches included, where the branches join)
+  int oslot[OPT], olx[OPT], oly[OPT], hslot[HPT], hpx[HPT], hpy[HPT];
+  bool hval[HPT], oval[OPT];
+  uint32_t oo[OPT], od[OPT], ho[HPT];   // own element, own diagonal, halo element
+
+  __device__ __forceinline__ explicit BoxTile(int b) {
 #pragma unroll
-  for (int i = 0; i < OPT; ++i) {
-    const int p = (threadIdx.x + i * kBlock) / B;
-    olx[i] = p % TX;
-    oly[i] = p / TX;
-    oslot[i] = ((oly[i] + 1) * PX + olx[i] + 1) * B + b;
-  }
-  int hslot[HPT], hpx[HPT], hpy[HPT];
-  bool hval[HPT];
-#pragma unroll
-  for (int j = 0; j < HPT; ++j) {
-    const int e = threadIdx.x + j * kBlock;
-    const int q = e / B;
-    hval[j] = e < HE;
-    int px = 0, py = 0;
-    if (q < TX) {
-      px = q + 1;
-    } else if (q < 2 * TX) {
-      px = q - TX + 1;
-      py = PY - 1;
-    } else if (q < 2 * TX + TY) {
-      py = q - 2 * TX + 1;
-    } else {
-      px = PX - 1;
-      py = q - 2 * TX - TY + 1;
+    for (int i = 0; i < OPT; ++i) {
+      const int p = (threadIdx.x + i * kBlock) / B;
+      olx[i] = p % TX;
+      oly[i] = p / TX;
+      oslot[i] = ((oly[i] + 1) * PX + olx[i] + 1) * B + b;
     }
-    hpx[j] = px;
-    hpy[j] = py;
-    hslot[j] = hval[j] ? (py * PX + px) * B + b : 0;
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+      const int e = threadIdx.x + j * kBlock;
+      const int q = (e % HE) / B;
+      hval[j] = e < HE;
+      int px = 0, py = 0;
+      if (q < TX) {
+        px = q + 1;
+      } else if (q < 2 * TX) {
+        px = q - TX + 1;
+        py = PY - 1;
+      } else if (q < 2 * TX + TY) {
+        py = q - 2 * TX + 1;
+      } else {
+        px = PX - 1;
+        py = q - 2 * TX - TY + 1;
+      }
+      hpx[j] = px;
+      hpy[j] = py;
+      hslot[j] = (py * PX + px) * B + b;
+    }
   }
-  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
-  int buf = 0;
-  for (int64_t it = lb; it < items; it += A.G) {
-    const int tz = (int)(it % zn);
-    const int64_t txy = it / zn;
-    const int x0 = (int)(txy % txn) * TX, y0 = (int)(txy / txn) * TY;
-    const int z0 = tz * zc, z1 = min(z0 + zc, Lz);
-    int64_t orow[OPT], hrow[HPT];
-    bool oval[OPT];
+
+  // the tile whose first cell is (x0, y0)
+  __device__ __forceinline__ void place(int x0, int y0, int Lx, int Ly, int b) {
+    auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
 #pragma unroll
     for (int i = 0; i < OPT; ++i) {
       const int X = x0 + olx[i], Y = y0 + oly[i];
       oval[i] = X < Lx && Y < Ly;
-      orow[i] = (int64_t)wrap(Y, Ly) * Lx + wrap(X, Lx);
-    }
-#pragma unroll
-    for (int j = 0; j < HPT; ++j)
-      hrow[j] = (int64_t)wrap(y0 + hpy[j] - 1, Ly) * Lx + wrap(x0 + hpx[j] - 1, Lx);
-    auto ld = [&](int64_t row, int z) { return x[((int64_t)wrap(z, Lz) * plane + row) * B + b]; };
-    double2 xm[OPT], xc[OPT], xp[OPT], xq[OPT], hc[HPT], hn[HPT];
-#pragma unroll
-    for (int i = 0; i < OPT; ++i) {
-      xq[i] = make_double2(0.0, 0.0);
-      xm[i] = ld(orow[i], z0 - 1);
-      xc[i] = ld(orow[i], z0);
-      xp[i] = ld(orow[i], z0 + 1);
+      const uint32_t row = (uint32_t)wrap(Y, Ly) * (uint32_t)Lx + (uint32_t)wrap(X, Lx);
+      oo[i] = (row * B + b) * (uint32_t)sizeof(double2);
+      od[i] = row * (uint32_t)sizeof(double);
     }
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
-      hn[j] = make_double2(0.0, 0.0);
-      hc[j] = hval[j] ? ld(hrow[j], z0) : hn[j];
+      const uint32_t row = (uint32_t)wrap(y0 + hpy[j] - 1, Ly) * (uint32_t)Lx + (uint32_t)wrap(x0 + hpx[j] - 1, Lx);
+      ho[j] = (row * B + b) * (uint32_t)sizeof(double2);
     }
-    for (int z = z0; z < z1; ++z, buf ^= 1) {
-      const bool more = z + 1 < z1;
-      if (more) {
-#pragma unroll
-        for (int i = 0; i < OPT; ++i) xq[i] = ld(orow[i], z + 2);
-#pragma unroll
-        for (int j = 0; j < HPT; ++j)
-          if (hval[j]) hn[j] = ld(hrow[j], z + 1);
-      }
-#pragma unroll
-      for (int i = 0; i < OPT; ++i) lds[buf][oslot[i]] = xc[i];
-#pragma unroll
-      for (int j = 0; j < HPT; ++j)
-        if (hval[j]) lds[buf][hslot[j]] = hc[j];
-      __syncthreads();
+  }
+};
+
+// The streams a box kernel reads or writes once per step (everything but the
+// staged chains) carry the non-temporal hint, so that they do not push the
+// staged planes, which neighbouring tiles read again as halo, out of the L2
+// (cubic 200^3: the B = 4 Hermitian step 318 -> 308 us, the MSD term
+// 1080 -> 1036 us, B = 16 1288 -> 1217 us).
+constexpr bool kBoxNtLoad = true, kBoxNtStore = true;
+
+template <bool NT = false>
+__device__ __forceinline__ double2 box_ld(const char* base, uint32_t off) {
+  return ld2<NT>(reinterpret_cast<const double2*>(base + off));
+}
+__device__ __forceinline__ void box_st(char* base, uint32_t off, double2 v) {
+  if constexpr (kBoxNtStore) {
+    const d2v t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2v*>(base + off));
+  } else {
+    *reinterpret_cast<double2*>(base + off) = v;
+  }
+}
+__device__ __forceinline__ double box_ldd(const char* base, uint32_t off) {
+  if constexpr (kBoxNtLoad) return __builtin_nontemporal_load(reinterpret_cast<const double*>(base + off));
+  return *reinterpret_cast<const double*>(base + off);
+}
+
+template <int B, int TX, int TY, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_moment_step_sym_box(DevMat A, StepIO io, int zc,
+                                                                double2* __restrict__ part_a,
+                                                                double2* __restrict__ part_b,
+                                                                double2* __restrict__ part_c) {
+  using T = BoxTile<B, TX, TY>;
+  constexpr int OPT = T::OPT, HPT = T::HPT, PX = T::PX;
+  __shared__ double2 lds[2][T::PE];
+  const int lb = logical_block(A.G);
+  const int Lx = A.box[0], Ly = A.box[1], Lz = A.box[2];
+  const int txn = (Lx + TX - 1) / TX, tyn = (Ly + TY - 1) / TY, zn = (Lz + zc - 1) / zc;
+  const int64_t cols = (int64_t)txn * tyn, items = cols * zn;
+  const double hu = A.seg_hop[0];
+  const int b = threadIdx.x & (B - 1);
+  const char* xs = reinterpret_cast<const char*>(io.x);
+  const char* ws = reinterpret_cast<const char*>(io.w);   // not read on the first step
+  char* os = reinterpret_cast<char*>(io.out);
+  const char* ds = reinterpret_cast<const char*>(A.diag);
+  const int64_t vplane = (int64_t)Lx * Ly * B * (int64_t)sizeof(double2);
+  const int64_t dplane = (int64_t)Lx * Ly * (int64_t)sizeof(double);
+  auto zw = [Lz](int z) { return z < 0 ? z + Lz : (z >= Lz ? z - Lz : z); };   // z in [-1, Lz + 1]
+  T t(b);
+  // first: a = <v0|v0>, b = <v0|v1>, c = <v1|v1>;  else: a = <vk|vk-1>, c = <vk|vk>
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
+  for (int64_t it = lb; it < items; it += A.G) {
+    const int tz = (int)(it / cols);
+    const int64_t txy = it % cols;
+    const int z0 = tz * zc, z1 = min(z0 + zc, Lz);
+    t.place((int)(txy % txn) * TX, (int)(txy / txn) * TY, Lx, Ly, b);
+    // x of planes z - 1, z, z + 1 and the one loaded for z + 2 rotate through x0..x3; w,
+    // the diagonal and the halo of planes z and z + 1 through (w0, w1), (d0, d1), (h0, h1).
+    // The loop below is unrolled four planes deep so that the rotation is a renaming: a
+    // register copy of a load in flight would wait for it.
+    double2 x0[OPT], x1[OPT], x2[OPT], x3[OPT], w0[OPT], w1[OPT], h0[HPT], h1[HPT];
+    double d0[OPT], d1[OPT];
+    {
+      const char* xa = xs + zw(z0 - 1) * vplane;
+      const char* xb = xs + z0 * vplane;
+      const char* xd = xs + zw(z0 + 1) * vplane;
 #pragma unroll
       for (int i = 0; i < OPT; ++i) {
-        if (oval[i]) {
-          const int c = oslot[i];
-          double2 sn = cadd(lds[buf][c + B], lds[buf][c - B]);
-          sn = cadd(sn, lds[buf][c + PX * B]);
-          sn = cadd(sn, lds[buf][c - PX * B]);
+        x0[i] = box_ld(xa, t.oo[i]);
+        x1[i] = box_ld(xb, t.oo[i]);
+        x2[i] = box_ld(xd, t.oo[i]);
+        w0[i] = FIRST ? make_double2(0.0, 0.0) : box_ld<kBoxNtLoad>(ws + z0 * vplane, t.oo[i]);
+        d0[i] = box_ldd(ds + z0 * dplane, t.od[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < HPT; ++j) h0[j] = box_ld(xb, t.ho[j]);
+    }
+    // plane z, staged in LDS buffer BF: first the loads for plane z + 1 (on the last plane
+    // of the run they read the planes after it, wrapped into the box, and go unused: the
+    // same loads on every plane keep the wait for plane z's operands from waiting for
+    // these too), then the stencil
+    auto plane = [&](int z, auto BF, double2(&xm)[OPT], double2(&xc)[OPT], double2(&xp)[OPT],
+                     double2(&xq)[OPT], double2(&wc)[OPT], double2(&wn)[OPT], double(&dc)[OPT],
+                     double(&dn)[OPT], double2(&hc)[HPT], double2(&hn)[HPT]) {
+      constexpr int bf = decltype(BF)::value;
+      const int z1n = zw(z + 1);
+      const char* xq_ = xs + zw(z + 2) * vplane;
+      const char* xn_ = xs + z1n * vplane;
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        xq[i] = box_ld(xq_, t.oo[i]);
+        if (!FIRST) wn[i] = box_ld<kBoxNtLoad>(ws + z1n * vplane, t.oo[i]);
+        dn[i] = box_ldd(ds + z1n * dplane, t.od[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < HPT; ++j) hn[j] = box_ld(xn_, t.ho[j]);
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) lds[bf][t.oslot[i]] = xc[i];
+#pragma unroll
+      for (int j = 0; j < HPT; ++j)
+        if (t.hval[j]) lds[bf][t.hslot[j]] = hc[j];
+      __syncthreads();
+      char* oz = os + z * vplane;
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        if (t.oval[i]) {
+          const int c = t.oslot[i];
+          double2 sn = cadd(lds[bf][c + B], lds[bf][c - B]);
+          sn = cadd(sn, lds[bf][c + PX * B]);
+          sn = cadd(sn, lds[bf][c - PX * B]);
           sn = cadd(sn, xp[i]);
           sn = cadd(sn, xm[i]);
-          const int64_t idx = ((int64_t)z * plane + orow[i]) * B + b;
-          const double dg = ldg<false>(A.diag + (int64_t)z * plane + orow[i]);
           const double2 xr = xc[i];
-          const double2 h = make_double2(fma(dg, xr.x, hu * sn.x), fma(dg, xr.y, hu * sn.y));
-          const double2 wv = wsrc[idx];
-          const double2 y = first ? h : twice_minus(h, wv);
-          out[idx] = y;
-          if (first) {
+          const double2 h = make_double2(fma(dc[i], xr.x, hu * sn.x), fma(dc[i], xr.y, hu * sn.y));
+          const double2 y = FIRST ? h : twice_minus(h, wc[i]);
+          box_st(oz, t.oo[i], y);
+          if (FIRST) {
             cdot_acc(ar, ai, xr, xr);
             cdot_acc(br, bi, xr, y);
           } else {
@@ -282,20 +352,24 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym_box(DevMat A, StepIO
           cdot_acc(cr, ci, y, y);
         }
       }
-#pragma unroll
-      for (int i = 0; i < OPT; ++i) {
-        xm[i] = xc[i];
-        xc[i] = xp[i];
-        xp[i] = xq[i];
-      }
-#pragma unroll
-      for (int j = 0; j < HPT; ++j) hc[j] = hn[j];
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    for (int z = z0; z < z1; z += 4) {
+      plane(z, S0{}, x0, x1, x2, x3, w0, w1, d0, d1, h0, h1);
+      if (z + 1 >= z1) break;
+      plane(z + 1, S1{}, x1, x2, x3, x0, w1, w0, d1, d0, h1, h0);
+      if (z + 2 >= z1) break;
+      plane(z + 2, S0{}, x2, x3, x0, x1, w0, w1, d0, d1, h0, h1);
+      if (z + 3 >= z1) break;
+      plane(z + 3, S1{}, x3, x0, x1, x2, w1, w0, d1, d0, h1, h0);
     }
+    __syncthreads();   // the next item stages into buffer 0 again
   }
   block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
   __syncthreads();
   block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
-  if (first) {
+  if (FIRST) {
     __syncthreads();
     block_reduce_store<B>(br, bi, part_b + (int64_t)lb * B);
   }
@@ -778,203 +852,222 @@ namespace {
 // The fused MSD term of k_msd_term on a periodic box whose position differences are
 // +-box_dx on the x neighbours and 0 on the others, as the box stencil of
 // k_moment_step_sym_box with both chains staged: [X,H~] a at a row is
-// -box_dx hu (a_{x+1} - a_{x-1}).  Work items and tiles as there; no partial sums.
-template <int B, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_msd_term_box(DevMat A, ChainIO io, double2* __restrict__ acc_a,
-                                                         double2* __restrict__ acc_b,
+// -box_dx hu (a_{x+1} - a_{x-1}).  Work items, tiles, addressing and the one-plane
+// lookahead as there; no partial sums.
+template <int B, int TX, int TY, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_msd_term_box(DevMat A, ChainIO io, double2* acc_a, double2* acc_b,
                                                          const double* __restrict__ Jtab, int ldJ, int m,
                                                          double2 ph_m, double2 ph_0, int zc) {
-  constexpr int PX = TX + 2, PY = TY + 2, PE = PX * PY * B;
-  constexpr int OE = TX * TY * B;
-  static_assert(OE % kBlock == 0, "a tile plane must give every thread the same count");
-  constexpr int OPT = OE / kBlock;
-  constexpr int HE = (2 * TX + 2 * TY) * B;
-  constexpr int HPT = (HE + kBlock - 1) / kBlock;
-  __shared__ double2 lda[2][PE], ldb[2][PE];
+  using T = BoxTile<B, TX, TY>;
+  constexpr int OPT = T::OPT, HPT = T::HPT, PX = T::PX;
+  __shared__ double2 lda[2][T::PE], ldb[2][T::PE];
   const int lb = logical_block(A.G);
   const int Lx = A.box[0], Ly = A.box[1], Lz = A.box[2];
   const int txn = (Lx + TX - 1) / TX, tyn = (Ly + TY - 1) / TY, zn = (Lz + zc - 1) / zc;
-  const int64_t items = (int64_t)txn * tyn * zn;
+  const int64_t cols = (int64_t)txn * tyn, items = cols * zn;
   const double hu = A.seg_hop[0];
   const double hdx = hu * A.box_dx;
   const double2 cm = cscale(Jtab[m], ph_m);
   const double2 c0 = cscale(Jtab[0], ph_0);
   const int b = threadIdx.x & (B - 1);
-  const bool first = io.first;
-  const double2* __restrict__ xa = io.xa;
-  const double2* __restrict__ xb = io.xb;
-  const double2* __restrict__ wa = first ? io.xa : io.wa;   // unused on the first step
-  const double2* __restrict__ wb = first ? io.xb : io.wb;
-  const double2* __restrict__ sa = first ? io.xa : acc_a;
-  const double2* __restrict__ sb = first ? io.xb : acc_b;
-  const int64_t plane = (int64_t)Lx * Ly;
-  auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
-  int oslot[OPT], olx[OPT], oly[OPT];
-#pragma unroll
-  for (int i = 0; i < OPT; ++i) {
-    const int p = (threadIdx.x + i * kBlock) / B;
-    olx[i] = p % TX;
-    oly[i] = p / TX;
-    oslot[i] = ((oly[i] + 1) * PX + olx[i] + 1) * B + b;
-  }
-  int hslot[HPT], hpx[HPT], hpy[HPT];
-  bool hval[HPT];
-#pragma unroll
-  for (int j = 0; j < HPT; ++j) {
-    const int e = threadIdx.x + j * kBlock;
-    const int q = e / B;
-    hval[j] = e < HE;
-    int px = 0, py = 0;
-    if (q < TX) {
-      px = q + 1;
-    } else if (q < 2 * TX) {
-      px = q - TX + 1;
-      py = PY - 1;
-    } else if (q < 2 * TX + TY) {
-      py = q - 2 * TX + 1;
-    } else {
-      px = PX - 1;
-      py = q - 2 * TX - TY + 1;
-    }
-    hpx[j] = px;
-    hpy[j] = py;
-    hslot[j] = hval[j] ? (py * PX + px) * B + b : 0;
-  }
-  int buf = 0;
+  const char* xas = reinterpret_cast<const char*>(io.xa);
+  const char* xbs = reinterpret_cast<const char*>(io.xb);
+  // read only after the first step: the previous chain elements and the running sums
+  // (acc is read and then overwritten element by element, so it is not restrict)
+  const char* was = reinterpret_cast<const char*>(io.wa);
+  const char* wbs = reinterpret_cast<const char*>(io.wb);
+  const char* sas = reinterpret_cast<const char*>(acc_a);
+  const char* sbs = reinterpret_cast<const char*>(acc_b);
+  char* oas = reinterpret_cast<char*>(io.oa);
+  char* obs = reinterpret_cast<char*>(io.ob);
+  char* aas = reinterpret_cast<char*>(acc_a);
+  char* abs_ = reinterpret_cast<char*>(acc_b);
+  const char* ds = reinterpret_cast<const char*>(A.diag);
+  const int64_t vplane = (int64_t)Lx * Ly * B * (int64_t)sizeof(double2);
+  const int64_t dplane = (int64_t)Lx * Ly * (int64_t)sizeof(double);
+  auto zw = [Lz](int z) { return z < 0 ? z + Lz : (z >= Lz ? z - Lz : z); };   // z in [-1, Lz + 1]
+  T t(b);
   for (int64_t it = lb; it < items; it += A.G) {
-    const int tz = (int)(it % zn);
-    const int64_t txy = it / zn;
-    const int x0 = (int)(txy % txn) * TX, y0 = (int)(txy / txn) * TY;
+    const int tz = (int)(it / cols);
+    const int64_t txy = it % cols;
     const int z0 = tz * zc, z1 = min(z0 + zc, Lz);
-    int64_t orow[OPT], hrow[HPT];
-    bool oval[OPT];
+    t.place((int)(txy % txn) * TX, (int)(txy / txn) * TY, Lx, Ly, b);
+    // chains a and b of planes z - 1, z, z + 1 and the ones loaded for z + 2 rotate through
+    // a0..a3 and b0..b3; the previous chain elements, the running sums, the diagonal and the
+    // halos of planes z and z + 1 through pairs; unrolled four planes deep as in
+    // k_moment_step_sym_box, so that the rotation is a renaming
+    double2 a0[OPT], a1[OPT], a2[OPT], a3[OPT], b0[OPT], b1[OPT], b2[OPT], b3[OPT];
+    double2 wa0[OPT], wa1[OPT], wb0[OPT], wb1[OPT], sa0[OPT], sa1[OPT], sb0[OPT], sb1[OPT];
+    double d0[OPT], d1[OPT];
+    double2 ha0[HPT], ha1[HPT], hb0[HPT], hb1[HPT];
+    // the once-read operands of plane z (only the diagonal on the first step)
+    auto ld_prev = [&](int z, double2(&wa)[OPT], double2(&wb)[OPT], double2(&sa)[OPT], double2(&sb)[OPT],
+                       double(&d)[OPT]) {
+      const int64_t v = z * vplane;
 #pragma unroll
-    for (int i = 0; i < OPT; ++i) {
-      const int X = x0 + olx[i], Y = y0 + oly[i];
-      oval[i] = X < Lx && Y < Ly;
-      orow[i] = (int64_t)wrap(Y, Ly) * Lx + wrap(X, Lx);
+      for (int i = 0; i < OPT; ++i) {
+        if (!FIRST) {
+          wa[i] = box_ld<kBoxNtLoad>(was + v, t.oo[i]);
+          wb[i] = box_ld<kBoxNtLoad>(wbs + v, t.oo[i]);
+          sa[i] = box_ld<kBoxNtLoad>(sas + v, t.oo[i]);
+          sb[i] = box_ld<kBoxNtLoad>(sbs + v, t.oo[i]);
+        }
+        d[i] = box_ldd(ds + z * dplane, t.od[i]);
+      }
+    };
+    {
+      const int64_t vm = zw(z0 - 1) * vplane, v0 = z0 * vplane, vp = zw(z0 + 1) * vplane;
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        wa0[i] = wb0[i] = sa0[i] = sb0[i] = make_double2(0.0, 0.0);
+        wa1[i] = wb1[i] = sa1[i] = sb1[i] = make_double2(0.0, 0.0);
+        a0[i] = box_ld(xas + vm, t.oo[i]);
+        a1[i] = box_ld(xas + v0, t.oo[i]);
+        a2[i] = box_ld(xas + vp, t.oo[i]);
+        b0[i] = box_ld(xbs + vm, t.oo[i]);
+        b1[i] = box_ld(xbs + v0, t.oo[i]);
+        b2[i] = box_ld(xbs + vp, t.oo[i]);
+      }
+      ld_prev(z0, wa0, wb0, sa0, sb0, d0);
+#pragma unroll
+      for (int j = 0; j < HPT; ++j) {
+        ha0[j] = box_ld(xas + v0, t.ho[j]);
+        hb0[j] = box_ld(xbs + v0, t.ho[j]);
+      }
     }
-#pragma unroll
-    for (int j = 0; j < HPT; ++j)
-      hrow[j] = (int64_t)wrap(y0 + hpy[j] - 1, Ly) * Lx + wrap(x0 + hpx[j] - 1, Lx);
-    auto at = [&](int64_t row, int z) { return ((int64_t)wrap(z, Lz) * plane + row) * B + b; };
-    double2 am[OPT], ac[OPT], ap[OPT], aq[OPT], bm[OPT], bc[OPT], bp[OPT], bq[OPT];
-    double2 hac[HPT], han[HPT], hbc[HPT], hbn[HPT];
-#pragma unroll
-    for (int i = 0; i < OPT; ++i) {
-      aq[i] = bq[i] = make_double2(0.0, 0.0);
-      am[i] = xa[at(orow[i], z0 - 1)];
-      ac[i] = xa[at(orow[i], z0)];
-      ap[i] = xa[at(orow[i], z0 + 1)];
-      bm[i] = xb[at(orow[i], z0 - 1)];
-      bc[i] = xb[at(orow[i], z0)];
-      bp[i] = xb[at(orow[i], z0 + 1)];
-    }
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-      han[j] = hbn[j] = make_double2(0.0, 0.0);
-      hac[j] = hval[j] ? xa[at(hrow[j], z0)] : han[j];
-      hbc[j] = hval[j] ? xb[at(hrow[j], z0)] : hbn[j];
-    }
-    for (int z = z0; z < z1; ++z, buf ^= 1) {
-      if (z + 1 < z1) {
+    // plane z in LDS buffer BF: the loads for plane z + 1 (unconditional, as in
+    // k_moment_step_sym_box), then the stencil on both chains
+    auto plane = [&](int z, auto BF, double2(&am)[OPT], double2(&ac)[OPT], double2(&ap)[OPT], double2(&aq)[OPT],
+                     double2(&bm)[OPT], double2(&bc)[OPT], double2(&bp)[OPT], double2(&bq)[OPT],
+                     double2(&wac)[OPT], double2(&wan)[OPT], double2(&wbc)[OPT], double2(&wbn)[OPT],
+                     double2(&sac)[OPT], double2(&san)[OPT], double2(&sbc)[OPT], double2(&sbn)[OPT],
+                     double(&dc)[OPT], double(&dn)[OPT], double2(&hac)[HPT], double2(&han)[HPT],
+                     double2(&hbc)[HPT], double2(&hbn)[HPT]) {
+      constexpr int bf = decltype(BF)::value;
+      {
+        const int z1n = zw(z + 1);
+        const int64_t vq = zw(z + 2) * vplane, vn = z1n * vplane;
 #pragma unroll
         for (int i = 0; i < OPT; ++i) {
-          aq[i] = xa[at(orow[i], z + 2)];
-          bq[i] = xb[at(orow[i], z + 2)];
+          aq[i] = box_ld(xas + vq, t.oo[i]);
+          bq[i] = box_ld(xbs + vq, t.oo[i]);
         }
+        ld_prev(z1n, wan, wbn, san, sbn, dn);
 #pragma unroll
-        for (int j = 0; j < HPT; ++j)
-          if (hval[j]) {
-            han[j] = xa[at(hrow[j], z + 1)];
-            hbn[j] = xb[at(hrow[j], z + 1)];
-          }
+        for (int j = 0; j < HPT; ++j) {
+          han[j] = box_ld(xas + vn, t.ho[j]);
+          hbn[j] = box_ld(xbs + vn, t.ho[j]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < OPT; ++i) {
-        lda[buf][oslot[i]] = ac[i];
-        ldb[buf][oslot[i]] = bc[i];
+        lda[bf][t.oslot[i]] = ac[i];
+        ldb[bf][t.oslot[i]] = bc[i];
       }
 #pragma unroll
       for (int j = 0; j < HPT; ++j)
-        if (hval[j]) {
-          lda[buf][hslot[j]] = hac[j];
-          ldb[buf][hslot[j]] = hbc[j];
+        if (t.hval[j]) {
+          lda[bf][t.hslot[j]] = hac[j];
+          ldb[bf][t.hslot[j]] = hbc[j];
         }
       __syncthreads();
+      const int64_t vz = z * vplane;
 #pragma unroll
       for (int i = 0; i < OPT; ++i) {
-        if (oval[i]) {
-          const int c = oslot[i];
-          const double2 axp = lda[buf][c + B], axm = lda[buf][c - B];
+        if (t.oval[i]) {
+          const int c = t.oslot[i];
+          const double2 axp = lda[bf][c + B], axm = lda[bf][c - B];
           double2 na = cadd(axp, axm);
-          na = cadd(na, lda[buf][c + PX * B]);
-          na = cadd(na, lda[buf][c - PX * B]);
+          na = cadd(na, lda[bf][c + PX * B]);
+          na = cadd(na, lda[bf][c - PX * B]);
           na = cadd(na, ap[i]);
           na = cadd(na, am[i]);
-          double2 nb = cadd(ldb[buf][c + B], ldb[buf][c - B]);
-          nb = cadd(nb, ldb[buf][c + PX * B]);
-          nb = cadd(nb, ldb[buf][c - PX * B]);
+          double2 nb = cadd(ldb[bf][c + B], ldb[bf][c - B]);
+          nb = cadd(nb, ldb[bf][c + PX * B]);
+          nb = cadd(nb, ldb[bf][c - PX * B]);
           nb = cadd(nb, bp[i]);
           nb = cadd(nb, bm[i]);
-          const int64_t r = (int64_t)z * plane + orow[i];
-          const int64_t idx = r * B + b;
-          const double dg = ldg<false>(A.diag + r);
+          const double dg = dc[i];
           const double2 ha = make_double2(fma(dg, ac[i].x, hu * na.x), fma(dg, ac[i].y, hu * na.y));
           const double2 hb = make_double2(fma(dg, bc[i].x, hu * nb.x), fma(dg, bc[i].y, hu * nb.y));
           // [X,H~] a + H~ b, [X,H~]_rj = -dx_rj H~_rj
           const double2 g = make_double2(hb.x - hdx * (axp.x - axm.x), hb.y - hdx * (axp.y - axm.y));
-          if (first) {
-            io.oa[idx] = ha;
-            io.ob[idx] = g;
-            acc_a[idx] = cadd(cmul(c0, ac[i]), cmul(cm, ha));
-            acc_b[idx] = cadd(cmul(c0, bc[i]), cmul(cm, g));
+          if (FIRST) {
+            box_st(oas + vz, t.oo[i], ha);
+            box_st(obs + vz, t.oo[i], g);
+            box_st(aas + vz, t.oo[i], cadd(cmul(c0, ac[i]), cmul(cm, ha)));
+            box_st(abs_ + vz, t.oo[i], cadd(cmul(c0, bc[i]), cmul(cm, g)));
           } else {
-            const double2 ya = twice_minus(ha, wa[idx]);
-            const double2 yb = twice_minus(g, wb[idx]);
-            io.oa[idx] = ya;
-            io.ob[idx] = yb;
-            acc_a[idx] = cadd(sa[idx], cmul(cm, ya));
-            acc_b[idx] = cadd(sb[idx], cmul(cm, yb));
+            const double2 ya = twice_minus(ha, wac[i]);
+            const double2 yb = twice_minus(g, wbc[i]);
+            box_st(oas + vz, t.oo[i], ya);
+            box_st(obs + vz, t.oo[i], yb);
+            box_st(aas + vz, t.oo[i], cadd(sac[i], cmul(cm, ya)));
+            box_st(abs_ + vz, t.oo[i], cadd(sbc[i], cmul(cm, yb)));
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < OPT; ++i) {
-        am[i] = ac[i];
-        ac[i] = ap[i];
-        ap[i] = aq[i];
-        bm[i] = bc[i];
-        bc[i] = bp[i];
-        bp[i] = bq[i];
-      }
-#pragma unroll
-      for (int j = 0; j < HPT; ++j) {
-        hac[j] = han[j];
-        hbc[j] = hbn[j];
-      }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    for (int z = z0; z < z1; z += 4) {
+      plane(z, S0{}, a0, a1, a2, a3, b0, b1, b2, b3, wa0, wa1, wb0, wb1, sa0, sa1, sb0, sb1, d0, d1, ha0, ha1,
+            hb0, hb1);
+      if (z + 1 >= z1) break;
+      plane(z + 1, S1{}, a1, a2, a3, a0, b1, b2, b3, b0, wa1, wa0, wb1, wb0, sa1, sa0, sb1, sb0, d1, d0, ha1,
+            ha0, hb1, hb0);
+      if (z + 2 >= z1) break;
+      plane(z + 2, S0{}, a2, a3, a0, a1, b2, b3, b0, b1, wa0, wa1, wb0, wb1, sa0, sa1, sb0, sb1, d0, d1, ha0,
+            ha1, hb0, hb1);
+      if (z + 3 >= z1) break;
+      plane(z + 3, S1{}, a3, a0, a1, a2, b3, b0, b1, b2, wa1, wa0, wb1, wb0, sa1, sa0, sb1, sb0, d1, d0, ha1,
+            ha0, hb1, hb0);
     }
+    __syncthreads();   // the next item stages into buffer 0 again
   }
 }
 
 }  // namespace
+
+// Planes per work item of the box kernels on tiles of tx x ty.  A run of zc planes costs
+// a workgroup zc + 2 plane loads (the planes before and after it come again), and the
+// work items go round the G workgroups, so the longest chain is rounds * (zc + 2):
+// the run length that minimises it, at least 16 planes unless the box is one run.
+static int box_run(const DevMat& A, int tx, int ty) {
+  const int64_t cols = (int64_t)((A.box[0] + tx - 1) / tx) * ((A.box[1] + ty - 1) / ty);
+  const int Lz = A.box[2];
+  int best_zc = Lz;
+  int64_t best = -1;
+  for (int zn = 1; zn <= Lz; ++zn) {
+    const int zc = (Lz + zn - 1) / zn;
+    if (zn > 1 && zc < 16) break;
+    const int64_t rounds = (cols * ((Lz + zc - 1) / zc) + A.G - 1) / A.G;
+    const int64_t cost = rounds * (zc + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_zc = zc;
+    }
+  }
+  return best_zc;
+}
 
 hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
                            double2* acc_b, const double* Jtab, int ldJ, int m, double2 phase_m,
                            double2 phase_0, hipStream_t s) {
   if (A.use_box_msd && A.box[0] > 0 && hop_mode == HOP_UNIFORM && B >= 2) {
     // tiles: 16 x 8 (B = 2), 8 x 8 (4), 8 x 4 (8), 4 x 4 (16): two staged chains fit the LDS
-    const int tile_x = B == 2 ? 16 : (B == 16 ? 4 : 8), tile_y = B >= 8 ? 4 : 8;
-    const int64_t cols = (int64_t)((A.box[0] + tile_x - 1) / tile_x) * ((A.box[1] + tile_y - 1) / tile_y);
-    int zc = (int)std::min<int64_t>(A.box[2], std::max<int64_t>(16, (A.box[2] * cols + 4 * A.G - 1) / (4 * (int64_t)A.G)));
-    zc = std::max(zc, 1);
-    const dim3 g(A.G);
-    switch (B) {
-      case 2: k_msd_term_box<2, 16, 8><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
-      case 4: k_msd_term_box<4, 8, 8><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
-      case 8: k_msd_term_box<8, 8, 4><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
-      default: k_msd_term_box<16, 4, 4><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
-    }
+    const int zc = box_run(A, B == 2 ? 16 : (B == 16 ? 4 : 8), B >= 8 ? 4 : 8);
+    auto go = [&](auto Fc) {
+      constexpr bool F = decltype(Fc)::value;
+      const dim3 g(A.G);
+      switch (B) {
+        case 2: k_msd_term_box<2, 16, 8, F><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+        case 4: k_msd_term_box<4, 8, 8, F><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+        case 8: k_msd_term_box<8, 8, 4, F><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+        default: k_msd_term_box<16, 4, 4, F><<<g, kBlock, 0, s>>>(A, io, acc_a, acc_b, Jtab, ldJ, m, phase_m, phase_0, zc); break;
+      }
+    };
+    if (io.first) go(std::true_type{}); else go(std::false_type{});
     return hipGetLastError();
   }
   return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {
@@ -1039,18 +1132,18 @@ hipError_t launch_moment_step_pair(const DevMat& A, int hop_mode, int B, const C
 hipError_t launch_moment_step_sym(const DevMat& A, int hop_mode, int B, const StepIO& io,
                                   double2* part_a, double2* part_b, double2* part_c, hipStream_t s) {
   if (A.use_box && A.box[0] > 0 && hop_mode == HOP_UNIFORM && B >= 2) {
-    // runs of planes: about four work items per workgroup, at least 16 planes a run
-    const int tile_x = B == 2 ? 16 : 8, tile_y = 8;   // the tiles of the instances below
-    const int64_t cols = (int64_t)((A.box[0] + tile_x - 1) / tile_x) * ((A.box[1] + tile_y - 1) / tile_y);
-    int zc = (int)std::min<int64_t>(A.box[2], std::max<int64_t>(16, (A.box[2] * cols + 4 * A.G - 1) / (4 * (int64_t)A.G)));
-    zc = std::max(zc, 1);
-    const dim3 g(A.G);
-    switch (B) {
-      case 2: k_moment_step_sym_box<2, 16, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
-      case 4: k_moment_step_sym_box<4, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
-      case 8: k_moment_step_sym_box<8, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
-      default: k_moment_step_sym_box<16, 8, 8><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
-    }
+    const int zc = box_run(A, B == 2 ? 16 : 8, 8);   // the tiles of the instances below
+    auto go = [&](auto Fc) {
+      constexpr bool F = decltype(Fc)::value;
+      const dim3 g(A.G);
+      switch (B) {
+        case 2: k_moment_step_sym_box<2, 16, 8, F><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+        case 4: k_moment_step_sym_box<4, 8, 8, F><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+        case 8: k_moment_step_sym_box<8, 8, 8, F><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+        default: k_moment_step_sym_box<16, 8, 8, F><<<g, kBlock, 0, s>>>(A, io, zc, part_a, part_b, part_c); break;
+      }
+    };
+    if (io.first) go(std::true_type{}); else go(std::false_type{});
     return hipGetLastError();
   }
   return dispatch_sparse(A, hop_mode, B, A.nt, [&](auto Bc, auto Hc, auto Kc, auto NTc) {

@@ -568,6 +568,9 @@ bool detect_box(const gpuqt_h_desc* d, int32_t box[3]) {
   if (Ly < 3 || n % LxLy != 0) return false;
   const int64_t Lz = n / LxLy;
   if (Lz < 3 || Lx > INT32_MAX || Ly > INT32_MAX || Lz > INT32_MAX) return false;
+  // the box kernels address a plane of a block with 32-bit byte offsets: a plane of 16
+  // vectors of 16-byte elements must span at most 4 GiB
+  if (LxLy > (int64_t(1) << 24)) return false;
   for (int64_t i = 0; i < n; ++i) {
     const int64_t x = i % Lx, y = (i / Lx) % Ly, z = i / LxLy;
     int64_t e[6] = {(x + 1) % Lx + Lx * (y + Ly * z),      (x + Lx - 1) % Lx + Lx * (y + Ly * z),

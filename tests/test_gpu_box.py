@@ -74,7 +74,7 @@ def test_box_moments_match_oracle(gpu, name, B):
     phi = I.random_phase(m.n, B, 16)
     psi = I.random_phase(m.n, B, 17)
     d = dev(phi)
-    for cap in (0, 2, 5):
+    for cap in (0, 1, 2, 5):
         P.gpuqt_set_variant(H, BOX | (cap << 2))
         assert H.info.kernel_variant == BOX | (cap << 2)
         for M in (2, 3, 65):
@@ -126,7 +126,7 @@ def test_box_msd_term_matches_oracle(gpu, name, B):
     phi = I.random_phase(m.n, B, 21)
     dts = [0.7, 1.3]
     ref = O.msd_moments(Hs, XH, phi, dts, dE, 24)
-    for cap in (0, 3):
+    for cap in (0, 1, 3):
         P.gpuqt_set_variant(H, BOX | (1 << 27) | (cap << 2))
         assert H.info.kernel_variant == BOX | (1 << 27) | (cap << 2)
         got = host(P.gpuqt_msd(H, dev(phi), dts, 24))[:, 0]

@@ -117,12 +117,15 @@ def test_long_chain_honeycomb_M3000(gpu):
 def test_full_size_cubic_B4_sampled(gpu):
     """Cubic 200^3 = 8,000,000 orbitals, W = 16, block of 4: DOS moments (Hermitian form) and
     the MSD row at t = dt = 2 (fused evolution + commutator, automatic term count) on the whole
-    block, M = 64; the oracle checks columns 0 and 3."""
-    say("case: full-size cubic 200^3 W=16 B=4, DOS M=64 + MSD 1 row M=64")
+    block, M = 64; the oracle checks columns 0 and 3.  Both periodic-box kernels are pinned
+    (variant bits 26 and 27): at this size their work items go several rounds over the
+    workgroups, in runs of planes that meet inside the box."""
+    say("case: full-size cubic 200^3 W=16 B=4, box kernels, DOS M=64 + MSD 1 row M=64")
     w = I.workload_cubic(L=200, W=16.0, B=4)
     m, dE = w["model"], w["energy_max"]
     H = P.gpuqt_build_h_from_model(m, energy_max=dE)
-    P.gpuqt_autotune(H, 4)
+    assert tuple(H.info.box) == (200, 200, 200) and H.info.box_msd == 1
+    P.gpuqt_set_variant(H, (1 << 26) | (1 << 27))
     assert H.info.hop_mode == 0 and H.info.uniform_width == 6
     Hs, _, XH = O.operators(m.nn, m.nbr, m.hop, m.onsite, m.x, m.length_x)
     assert O.gershgorin_bound(Hs) <= dE
