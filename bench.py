@@ -99,16 +99,26 @@ def family_bytes(info, B, family="moment"):
 
 def box_used(info, B, family):
     """Whether the family runs a periodic-box stencil kernel: the Hermitian moment step with
-    variant bit 26, the MSD term with bit 27 (a handle whose matrix is a periodic box, with
-    uniform x steps for the MSD term; blocks of B >= 2)."""
-    if B < 2 or int(info.box[0]) <= 0:
+    variant bit 26 (a handle whose matrix is a periodic box, or whose segments are all
+    periodic squares: the sheet form), the MSD term with bit 27 (a periodic box with uniform
+    x steps); blocks of B >= 2."""
+    if B < 2 or (int(info.box[0]) <= 0 and int(info.sheets) == 0):
         return False
     v = int(info.kernel_variant)
     if family == "moment_sym":
         return (v >> 26) & 1 == 1
+    if int(info.box[0]) <= 0:
+        return False
     if family == "msd":
         return (v >> 27) & 1 == 1 and int(info.box_msd) == 1
     return False
+
+
+def kernel_name(info, B, family):
+    """The kernel the family runs on this handle: the general one, or its box or sheet form."""
+    if not box_used(info, B, family):
+        return FAMILY_KERNEL[family]
+    return FAMILY_KERNEL[family] + ("_box" if int(info.box[0]) > 0 else "_sheet")
 
 
 SERIES_FAMILIES = ("evolve", "msd", "evolve_pair")
@@ -140,7 +150,7 @@ def variant_text(v, family=None):
     else:
         nt, banded, pencil, cap, box = family_config(v, family)
         if box:
-            return "code %d: periodic-box stencil, %s" % (v, "%d workgroups/CU" % cap if cap else "full occupancy")
+            return "code %d: stencil form, %s" % (v, "%d workgroups/CU" % cap if cap else "full occupancy")
     order = "pencil" if pencil else ("banded" if banded else "plain")
     return "code %d: %s loads, %s row order, %s" % (v, "non-temporal" if nt else "plain", order,
                                                    "%d workgroups/CU" % cap if cap else "full occupancy")
@@ -167,7 +177,7 @@ def kernel_table(info, B, fam, elapsed_s):
             continue
         avg = ms / 1e3 / nl
         b = family_bytes(info, B, f)
-        table[f] = {"kernel": FAMILY_KERNEL[f] + ("_box" if box_used(info, B, f) else ""), "launches": nl, "total_ms": ms,
+        table[f] = {"kernel": kernel_name(info, B, f), "launches": nl, "total_ms": ms,
                     "share_of_elapsed": ms / 1e3 / elapsed_s, "avg_us": avg * 1e6,
                     "bytes_per_launch": b, "GBs": b / avg / 1e9}
     dominant = max(table, key=lambda f: table[f]["total_ms"])
@@ -205,7 +215,7 @@ def roofline_of(name, info, B, kernels, dominant, bound="hbm"):
     return {"bound": bound, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": None if tr is None else tr["bytes"] / 1e9,
             "traffic_detail": tr,
-            "kernel": "%s (B=%d, hop mode %d, K=%d, %s)" % (FAMILY_KERNEL[dominant] + ("_box" if box_used(info, B, dominant) else ""), B, info.hop_mode,
+            "kernel": "%s (B=%d, hop mode %d, K=%d, %s)" % (kernel_name(info, B, dominant), B, info.hop_mode,
                                                           info.uniform_width,
                                                           variant_text(info.kernel_variant, dominant)),
             "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_us"]}

@@ -154,6 +154,10 @@ typedef struct {
   int32_t box_msd;           /* 1: on that box the position differences are +-dx for the x
                                 neighbours and 0 for the others, so the MSD term can run as a
                                 box stencil too (bit 27) */
+  int32_t sheets;            /* 1: every segment is a periodic Lx x Ly square in natural order
+                                (rows off_s + x + Lx y, each with its four periodic neighbours,
+                                Lx, Ly >= 3, Lx Ly <= 2^24) with one uniform hopping, so the
+                                Hermitian step can run as a sheet stencil (bit 26) */
 } gpuqt_h_info_t;
 
 /* Describe the layout.  energy_max (may be NULL) receives [n_segments] DeltaE;
@@ -410,7 +414,10 @@ gpuqt_status gpuqt_vac_backward_tape_workspace_size(gpuqt_h h, int32_t B, int32_
  * a column of the box, keeps each lane's elements of three consecutive planes in
  * registers and the current plane's tile in LDS, so x is read about once per step instead
  * of once per neighbour and no neighbour indices are read (timed against the best other
- * variant, kept when faster); bit 27: the fused MSD term likewise (both chains staged,
+ * variant, kept when faster); on segments that are all periodic squares
+ * (gpuqt_h_info_t.sheets) bit 26 selects the two-dimensional form: a workgroup marches
+ * along y through a strip of 256 / B cells of one segment, rows y - 1, y, y + 1 in
+ * registers and row y in LDS; bit 27: the fused MSD term likewise (both chains staged,
  * where the position differences are +-dx on the x neighbours and 0 on the others,
  * gpuqt_h_info_t.box_msd), timed against the MSD family's best and kept when faster;
  * both box kernels are timed uncapped and at caps 1..6 and keep the fastest as their

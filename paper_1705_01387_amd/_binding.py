@@ -55,6 +55,7 @@ class HInfo(ctypes.Structure):
         ("device_bytes", ctypes.c_size_t), ("row_period", ctypes.c_int64),
         ("banded_mask", ctypes.c_int32), ("family_caps", ctypes.c_int32), ("max_nn", ctypes.c_int32),
         ("pencil_mask", ctypes.c_int32), ("box", ctypes.c_int32 * 3), ("box_msd", ctypes.c_int32),
+        ("sheets", ctypes.c_int32),
     ]
 
 

@@ -691,6 +691,8 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
   h->Gs[kPerCU - 1] = h->G;
   std::vector<std::vector<BlkPlan>> plans(kPerCU);   // alive until the stream is synchronised
   std::vector<std::vector<int32_t>> blk0s(kPerCU);
+  std::vector<int32_t> sheet_host, sheet_zc, sheet_blk0;   // alive until the stream is synchronised
+  std::vector<int64_t> sheet_off;
   for (int p = 1; p < kPerCU; ++p) {
     plan_blocks(L.seg_off, cus, p, &plans[p - 1], &blk0s[p - 1]);
     h->Gs[p - 1] = (int32_t)plans[p - 1].size();
@@ -703,6 +705,32 @@ gpuqt_status gpuqt_build_h(const gpuqt_h_desc* desc, void* stream, gpuqt_h* out)
       for (int lb = 0; lb < kNumB; ++lb)
         for (int v = 0; v < 2; ++v)
           h->occ[f][lb][v] = (int8_t)std::min(kPerCU, kernel_occupancy(f, D0, h->hop_mode, 1 << lb, v));
+  }
+  // segments that are all periodic squares with one uniform hopping: the sheet kernel's
+  // (Lx, Ly) and first row per segment, and per plan and block width its own split of the
+  // plan's workgroups over the segments (by work, not rows) and rows per work item
+  if (L.hop_mode == HOP_UNIFORM && h->box[0] == 0 && detect_sheets(desc, L.seg_off, &sheet_host)) {
+    const int ns = L.n_seg;
+    sheet_off.assign(L.seg_off.begin(), L.seg_off.end() - 1);
+    sheet_zc.assign((size_t)kPerCU * kNumB * ns, 1);
+    sheet_blk0.assign((size_t)kPerCU * kNumB * (ns + 1), 0);
+    std::vector<int32_t> len(ns), b0, zc;
+    std::vector<int64_t> cols(ns);
+    for (int sg = 0; sg < ns; ++sg) len[sg] = sheet_host[2 * sg + 1];
+    for (int p = 0; p < kPerCU; ++p) {
+      for (int lb = 1; lb < kNumB; ++lb) {   // blocks of B >= 2
+        const int tx = (kSheetCells * kBlock) >> lb;   // cells per strip (kSheetCells per lane)
+        for (int sg = 0; sg < ns; ++sg) cols[sg] = (sheet_host[2 * sg] + tx - 1) / tx;
+        sheet_split(cols, len, h->Gs[p], &b0, &zc);
+        std::copy(zc.begin(), zc.end(), sheet_zc.begin() + ((size_t)p * kNumB + lb) * ns);
+        std::copy(b0.begin(), b0.end(), sheet_blk0.begin() + ((size_t)p * kNumB + lb) * (ns + 1));
+      }
+    }
+    up((void**)&h->d_sheet, sheet_host.data(), sheet_host.size() * 4);
+    up((void**)&h->d_sheet_off, sheet_off.data(), sheet_off.size() * 8);
+    up((void**)&h->d_sheet_zc, sheet_zc.data(), sheet_zc.size() * 4);
+    up((void**)&h->d_sheet_blk0, sheet_blk0.data(), sheet_blk0.size() * 4);
+    h->sheet_ok = ok ? 1 : 0;
   }
   std::vector<double> zeros_g(h->G, 0.0);
   up((void**)&h->d_bound, zeros_g.data(), zeros_g.size() * 8);
@@ -772,7 +800,8 @@ void gpuqt_destroy_h(gpuqt_h hh) {
   if (!h) return;
   void* ptrs[] = {h->d_slice_ptr, h->d_col, h->d_hop, h->d_dx, h->d_diag, h->d_cls,
                   h->d_plan, h->d_seg_blk0, h->d_seg_dE, h->d_seg_hop, h->d_seg_hop0, h->d_hop0, h->d_bound,
-                  h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab, h->d_offtab};
+                  h->d_hidx, h->d_htab, h->d_htab0, h->d_dxtab, h->d_offtab, h->d_sheet, h->d_sheet_zc,
+                  h->d_sheet_off, h->d_sheet_blk0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int32_t* p : h->d_units)
@@ -811,6 +840,7 @@ gpuqt_status gpuqt_h_info(gpuqt_h hh, gpuqt_h_info_t* info, double* energy_max, 
   info->max_nn = h->max_nn_in;
   for (int q = 0; q < 3; ++q) info->box[q] = h->box[q];
   info->box_msd = h->box_msd_ok;
+  info->sheets = h->sheet_ok;
   info->row_period = 0;
   for (int64_t D : h->seg_period) info->row_period = std::max(info->row_period, D);
   info->banded_mask = 0;
@@ -1627,11 +1657,12 @@ gpuqt_status gpuqt_autotune(gpuqt_h hh, int32_t B, void* ws, size_t ws_bytes, vo
   h->banded = (best_v >> 1) & 1;
   h->pencil = (best_v >> 2) & 1;
   h->per_cu_cap = best_cap;
-  // on a periodic box, the box stencil kernel of the Hermitian step, uncapped and at
+  // on a periodic box (or segments that are all periodic squares: the sheet form), the
+  // stencil kernel of the Hermitian step, uncapped and at
   // caps 1..6 (its loads run a plane ahead, so a few workgroups per CU fill HBM, and
   // fewer concurrent streams use the DRAM pages and the L2 better); when it beats the
   // best general variant it is kept, with its cap as the Hermitian family's own
-  if (!st && h->box[0] > 0 && B >= 2 && h->hop_mode == HOP_UNIFORM) {
+  if (!st && (h->box[0] > 0 || h->sheet_ok) && B >= 2 && h->hop_mode == HOP_UNIFORM) {
     h->use_box = 1;
     float bbest = 0.0f;
     int bcap = 0;

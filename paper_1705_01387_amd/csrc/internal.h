@@ -45,6 +45,7 @@ struct BlkPlan {
 
 constexpr int kUnitLog2 = 6;        // rows per unit of a banded order: 64
 constexpr int kPencil = kBlock / 64;   // units per pencil: one per wavefront of a workgroup
+constexpr int kSheetCells = 1;      // cells per lane of a sheet kernel strip (kSheetCells * 256 / B cells)
 constexpr int kTuneTimes = 7;       // entries of gpuqt_autotune's times_us: 4 load/order variants, 2 pencil, box
 constexpr int kNumB = 5;            // block widths 1, 2, 4, 8, 16
 constexpr int64_t kBandBudget = int64_t(5) << 19;   // 2.5 MiB: bytes one row window may stream per XCD
@@ -114,6 +115,13 @@ struct DevMat {
   int32_t use_box;           // 1: the Hermitian step runs the box stencil kernel
   int32_t use_box_msd;       // 1: the MSD term runs the box stencil kernel (box_dx valid)
   double box_dx;             // x_{i+1} - x_i of the box's x neighbours (the only non-zero dx)
+  int32_t use_sheet;         // 1: the Hermitian step runs the sheet stencil kernel
+  int32_t sheet_nseg;        // segments of the sheet tables
+  const int32_t* sheet;      // [2 n_seg] (Lx, Ly) of each segment when all are periodic squares
+  const int64_t* sheet_off;  // [n_seg] first row of each segment
+  const int32_t* sheet_zc;   // [n_seg] rows per work item of the sheet kernel at this plan and B
+  const int32_t* sheet_blk0; // [n_seg + 1] first logical workgroup of each segment in the sheet
+                             // kernel's own split of this plan's workgroups at this B
   const double* seg_dE;      // [n_seg] DeltaE of each segment
   const double* seg_hop;     // [n_seg] uniform hopping / DeltaE (HOP_UNIFORM)
   // the hoppings given at build time (before class scales), for class gradients
@@ -169,6 +177,17 @@ struct Handle {
   int32_t box_msd_ok = 0;
   double box_dx = 0.0;
   int32_t use_box_msd = 0;
+  // every segment a periodic square (detect_sheets): d_sheet [2 n_seg] = (Lx, Ly),
+  // d_sheet_off [n_seg] their first rows, and per plan and block width the sheet kernel's
+  // split of the plan's workgroups over the segments (sheet_split),
+  // d_sheet_blk0[(plan * kNumB + log2 B) * (n_seg + 1) + s], and its rows per work item,
+  // d_sheet_zc[(plan * kNumB + log2 B) * n_seg + s]; use_box selects the sheet kernel too
+  int32_t sheet_ok = 0;
+  int32_t* d_sheet = nullptr;
+  int64_t* d_sheet_off = nullptr;
+  int32_t* d_sheet_zc = nullptr;
+  int32_t* d_sheet_blk0 = nullptr;
+  bool sheet_in_use(int B) const { return sheet_ok && use_box && B >= 2 && hop_mode == HOP_UNIFORM; }
   // at most this many resident workgroups per CU (0: as many as fit).  Fewer
   // waves in flight can beat full occupancy when the gathers reuse cached
   // lines: the window of rows in flight, and so the cache footprint, shrinks.
@@ -242,17 +261,25 @@ struct Handle {
   // | use_box << 26 | use_box_msd << 27
   int32_t variant_code() const {
     return nt | (banded << 1) | (per_cu_cap << 2) | ((banded & pencil) << 6) | (series_nt_flip << 7) |
-           (family_caps_code() << 8) | ((box[0] > 0 ? use_box : 0) << 26) |
+           (family_caps_code() << 8) | ((box[0] > 0 || sheet_ok ? use_box : 0) << 26) |
            ((box_msd_ok ? use_box_msd : 0) << 27);
   }
   int G_of(int B, int family) const { return Gs[plan_index(B, family)]; }
-  const int32_t* blk0_of(int B, int family) const { return d_blk0s[plan_index(B, family)]; }
+  // first logical workgroup of each segment for the reduction of a family's partials: the
+  // plan's, or for the Hermitian step on sheets the sheet kernel's own split
+  const int32_t* blk0_of(int B, int family) const {
+    const int i = plan_index(B, family);
+    if (family == FAM_SYM && sheet_in_use(B)) return d_sheet_blk0 + ((int64_t)i * kNumB + log2B(B)) * (n_seg + 1);
+    return d_blk0s[i];
+  }
   DevMat view(int B, int family) const {
     DevMat m = view(B);
     const int i = plan_index(B, family);
     m.plan = d_plans[i];
     m.G = Gs[i];
     m.nt = fam_nt(family);
+    m.sheet_zc = d_sheet_zc ? d_sheet_zc + ((int64_t)i * kNumB + log2B(B)) * n_seg : nullptr;
+    m.sheet_blk0 = d_sheet_blk0 ? d_sheet_blk0 + ((int64_t)i * kNumB + log2B(B)) * (n_seg + 1) : nullptr;
     return m;
   }
 
@@ -267,6 +294,12 @@ struct Handle {
     m.use_box = (box[0] > 0 && use_box) ? 1 : 0;
     m.use_box_msd = (box[0] > 0 && box_msd_ok && use_box_msd) ? 1 : 0;
     m.box_dx = box_dx;
+    m.use_sheet = (sheet_ok && use_box) ? 1 : 0;
+    m.sheet = d_sheet;
+    m.sheet_off = d_sheet_off;
+    m.sheet_nseg = n_seg;
+    m.sheet_zc = d_sheet_zc ? d_sheet_zc + ((int64_t)(kPerCU - 1) * kNumB + lb) * n_seg : nullptr;
+    m.sheet_blk0 = d_sheet_blk0 ? d_sheet_blk0 + ((int64_t)(kPerCU - 1) * kNumB + lb) * (n_seg + 1) : nullptr;
     m.slice_ptr = d_slice_ptr;
     m.col = d_col;
     m.hop = d_hop;
@@ -374,6 +407,28 @@ bool detect_box(const gpuqt_h_desc* d, int32_t box[3]);
 // *dx = x_{i+1} - x_i, when every row's x neighbours have dx = +dx and -dx and its y and z
 // neighbours dx = 0.
 bool box_dx_uniform(const HostLayout& L, const int32_t box[3], double* dx);
+
+// Every segment s of layout L (rows seg_off[s] ..) a periodic Lx x Ly square in natural
+// order: row seg_off[s] + x + Lx y with exactly the four neighbours (x +- 1 mod Lx, y) and
+// (x, y +- 1 mod Ly) in any slot order, Lx, Ly >= 3, Lx Ly <= 2^24 (a segment of a block
+// of 16 vectors spans at most 4 GiB: the sheet kernel addresses it with 32-bit offsets).
+// sheet = (Lx, Ly) per segment when all are, else false.
+bool detect_sheets(const gpuqt_h_desc* d, const std::vector<int64_t>& seg_off, std::vector<int32_t>* sheet);
+
+// Length of a run of a stencil kernel's march: cols columns (or strips) of work items
+// over len planes (or rows), shared by `workers` workgroups that take the items in turn.
+// A run of z steps costs a workgroup z + 2 loads of its column (the steps before and after
+// the run come again) and the items go round in ceil(cols * runs / workers) rounds: the
+// run length that minimises rounds * (z + 2), at least 16 unless one run covers len.
+int stencil_run(int64_t cols, int len, int64_t workers);
+
+// The sheet kernel's split of G workgroups over segments of cols[s] strips and len[s] rows:
+// the fewest workgroups per segment that keep every segment's longest chain (stencil_run's
+// rounds * (z + 2)) within a common bound, the least bound the G workgroups allow (found
+// by bisection); workgroups left over join the segment of most work.  blk0[s] = first
+// workgroup of segment s (blk0[n] = G), zc[s] = its rows per work item.  Needs G >= n.
+void sheet_split(const std::vector<int64_t>& cols, const std::vector<int32_t>& len, int64_t G,
+                 std::vector<int32_t>* blk0, std::vector<int32_t>* zc);
 
 // Running conductivity over time rows (mode 0: VAC integral, 1: MSD derivative).
 // Transport quantities of Section 2.2 from reconstructed rows (see gpuqt_transport_lengths).

@@ -376,6 +376,147 @@ __global__ __launch_bounds__(kBlock) void k_moment_step_sym_box(DevMat A, StepIO
 }
 
 // ---------------------------------------------------------------------------
+// The Hermitian step of k_moment_step_sym on segments that are each a periodic
+// Lx x Ly square (rows off_s + x + Lx y, four neighbours, one uniform hopping per
+// segment; detect_sheets), for blocks of B >= 2 vectors: the two-dimensional form
+// of k_moment_step_sym_box.  A workgroup holds a strip of TX = 256 / B cells of one
+// row (a lane per cell and vector) and marches along y: rows y - 1, y and y + 1 of
+// the strip stay in registers (the y neighbours), row y and its two halo cells go
+// to LDS (the x neighbours).  The workgroups of segment s (sheet_blk0: the plan's
+// workgroups split over the segments by their work, so that the segments finish
+// together) take its work items (strip, run of sheet_zc rows), strip index
+// fastest, so the workgroups of
+// one XCD hold neighbouring strips of the same rows.  Loads for row y + 1 are
+// issued unconditionally while row y is computed and the march is unrolled four
+// rows deep, as in the box kernel.
+// ---------------------------------------------------------------------------
+template <int B, int OPT, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_moment_step_sym_sheet(DevMat A, StepIO io,
+                                                                  double2* __restrict__ part_a,
+                                                                  double2* __restrict__ part_b,
+                                                                  double2* __restrict__ part_c) {
+  constexpr int TL = kBlock / B;               // cells per lane row of the strip
+  constexpr int TX = OPT * TL, PX = TX + 2;    // cells per strip: OPT per lane
+  __shared__ double2 lds[2][PX * B];
+  const int lb = logical_block(A.G);
+  // this workgroup's segment in the kernel's own split (sheet_blk0: by work, not rows)
+  int sg = 0;
+  for (int hi = A.sheet_nseg - 1; sg < hi;) {
+    const int mid = (sg + hi + 1) >> 1;
+    if (A.sheet_blk0[mid] <= lb) sg = mid;
+    else hi = mid - 1;
+  }
+  const int Lx = A.sheet[2 * sg], Ly = A.sheet[2 * sg + 1];
+  const int zc = A.sheet_zc[sg];
+  const int w0 = A.sheet_blk0[sg], nw = A.sheet_blk0[sg + 1] - w0;
+  const int64_t off = A.sheet_off[sg];
+  const int cols = (Lx + TX - 1) / TX, zn = (Ly + zc - 1) / zc;
+  const int64_t items = (int64_t)cols * zn;
+  const double hu = A.seg_hop[sg];
+  const int b = threadIdx.x & (B - 1);
+  const int cx = threadIdx.x / B;                       // first cell of this lane in the strip
+  const char* xs = reinterpret_cast<const char*>(io.x + off * B);
+  const char* ws = reinterpret_cast<const char*>((FIRST ? io.x : io.w) + off * B);   // not read when FIRST
+  char* os = reinterpret_cast<char*>(io.out + off * B);
+  const char* ds = reinterpret_cast<const char*>(A.diag + off);
+  const int64_t vrow = (int64_t)Lx * B * (int64_t)sizeof(double2), drow = (int64_t)Lx * (int64_t)sizeof(double);
+  auto zw = [Ly](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };   // y in [-1, Ly + 1]
+  auto wrap = [](int v, int L) { return ((v % L) + L) % L; };
+  // halo: lanes 0 .. B - 1 stage the cell left of the strip, B .. 2B - 1 the one right of
+  // it; the other lanes load lane (threadIdx.x mod 2B)'s element and do not stage it
+  const bool hval = threadIdx.x < 2 * B;
+  const bool hright = (threadIdx.x % (2 * B)) >= B;
+  const int hslot = (hright ? PX - 1 : 0) * B + b;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, cr = 0.0, ci = 0.0;
+  for (int64_t it = lb - w0; it < items; it += nw) {
+    const int tz = (int)(it / cols), strip = (int)(it % cols);
+    const int x0 = strip * TX;
+    const int y0 = tz * zc, y1 = min(y0 + zc, Ly);
+    bool oval[OPT];
+    uint32_t oo[OPT], od[OPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      const int X = x0 + cx + i * TL;
+      oval[i] = X < Lx;
+      const uint32_t xo = (uint32_t)wrap(X, Lx);
+      oo[i] = (xo * B + b) * (uint32_t)sizeof(double2);
+      od[i] = xo * (uint32_t)sizeof(double);
+    }
+    const uint32_t ho = ((uint32_t)wrap(hright ? x0 + TX : x0 - 1, Lx) * B + b) * (uint32_t)sizeof(double2);
+    // x of rows y - 1, y, y + 1 and the one loaded for y + 2 rotate through q0..q3; w, the
+    // diagonal and the halo of rows y and y + 1 through pairs (unrolled four rows deep)
+    double2 q0[OPT], q1[OPT], q2[OPT], q3[OPT], wa[OPT], wb[OPT], h0, h1;
+    double d0[OPT], d1[OPT];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      q0[i] = box_ld(xs + zw(y0 - 1) * vrow, oo[i]);
+      q1[i] = box_ld(xs + y0 * vrow, oo[i]);
+      q2[i] = box_ld(xs + zw(y0 + 1) * vrow, oo[i]);
+      wa[i] = FIRST ? make_double2(0.0, 0.0) : box_ld<kBoxNtLoad>(ws + y0 * vrow, oo[i]);
+      wb[i] = make_double2(0.0, 0.0);
+      d0[i] = box_ldd(ds + y0 * drow, od[i]);
+    }
+    h0 = box_ld(xs + y0 * vrow, ho);
+    auto row = [&](int y, auto BF, double2(&xm)[OPT], double2(&xc)[OPT], double2(&xp)[OPT], double2(&xq)[OPT],
+                   double2(&wc)[OPT], double2(&wn)[OPT], double(&dc)[OPT], double(&dn)[OPT], double2& hc,
+                   double2& hn) {
+      constexpr int bf = decltype(BF)::value;
+      const int y1n = zw(y + 1);
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        xq[i] = box_ld(xs + zw(y + 2) * vrow, oo[i]);
+        if (!FIRST) wn[i] = box_ld<kBoxNtLoad>(ws + y1n * vrow, oo[i]);
+        dn[i] = box_ldd(ds + y1n * drow, od[i]);
+      }
+      hn = box_ld(xs + y1n * vrow, ho);
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) lds[bf][(cx + i * TL + 1) * B + b] = xc[i];
+      if (hval) lds[bf][hslot] = hc;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < OPT; ++i) {
+        if (oval[i]) {
+          const int c = (cx + i * TL + 1) * B + b;
+          double2 sn = cadd(lds[bf][c + B], lds[bf][c - B]);
+          sn = cadd(sn, xp[i]);
+          sn = cadd(sn, xm[i]);
+          const double2 xr = xc[i];
+          const double2 h = make_double2(fma(dc[i], xr.x, hu * sn.x), fma(dc[i], xr.y, hu * sn.y));
+          const double2 yv = FIRST ? h : twice_minus(h, wc[i]);
+          box_st(os + y * vrow, oo[i], yv);
+          if (FIRST) {
+            cdot_acc(ar, ai, xr, xr);
+            cdot_acc(br, bi, xr, yv);
+          } else {
+            cdot_acc(ar, ai, yv, xr);
+          }
+          cdot_acc(cr, ci, yv, yv);
+        }
+      }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    for (int y = y0; y < y1; y += 4) {
+      row(y, S0{}, q0, q1, q2, q3, wa, wb, d0, d1, h0, h1);
+      if (y + 1 >= y1) break;
+      row(y + 1, S1{}, q1, q2, q3, q0, wb, wa, d1, d0, h1, h0);
+      if (y + 2 >= y1) break;
+      row(y + 2, S0{}, q2, q3, q0, q1, wa, wb, d0, d1, h0, h1);
+      if (y + 3 >= y1) break;
+      row(y + 3, S1{}, q3, q0, q1, q2, wb, wa, d1, d0, h1, h0);
+    }
+    __syncthreads();   // the next item stages into buffer 0 again
+  }
+  block_reduce_store<B>(ar, ai, part_a + (int64_t)lb * B);
+  __syncthreads();
+  block_reduce_store<B>(cr, ci, part_c + (int64_t)lb * B);
+  if (FIRST) {
+    __syncthreads();
+    block_reduce_store<B>(br, bi, part_b + (int64_t)lb * B);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Moment step for <a|T_n|b> with a != b: both chains a_k = T_k a, b_k = T_k b
 // advance in one launch (one matrix read, the two gathers share the indices)
 // and the identities give
@@ -1029,26 +1170,11 @@ __global__ __launch_bounds__(kBlock) void k_msd_term_box(DevMat A, ChainIO io, d
 
 }  // namespace
 
-// Planes per work item of the box kernels on tiles of tx x ty.  A run of zc planes costs
-// a workgroup zc + 2 plane loads (the planes before and after it come again), and the
-// work items go round the G workgroups, so the longest chain is rounds * (zc + 2):
-// the run length that minimises it, at least 16 planes unless the box is one run.
+// Planes per work item of the box kernels on tiles of tx x ty (stencil_run over the G
+// workgroups).
 static int box_run(const DevMat& A, int tx, int ty) {
   const int64_t cols = (int64_t)((A.box[0] + tx - 1) / tx) * ((A.box[1] + ty - 1) / ty);
-  const int Lz = A.box[2];
-  int best_zc = Lz;
-  int64_t best = -1;
-  for (int zn = 1; zn <= Lz; ++zn) {
-    const int zc = (Lz + zn - 1) / zn;
-    if (zn > 1 && zc < 16) break;
-    const int64_t rounds = (cols * ((Lz + zc - 1) / zc) + A.G - 1) / A.G;
-    const int64_t cost = rounds * (zc + 2);
-    if (best < 0 || cost < best) {
-      best = cost;
-      best_zc = zc;
-    }
-  }
-  return best_zc;
+  return stencil_run(cols, A.box[2], A.G);
 }
 
 hipError_t launch_msd_term(const DevMat& A, int hop_mode, int B, const ChainIO& io, double2* acc_a,
@@ -1131,6 +1257,20 @@ hipError_t launch_moment_step_pair(const DevMat& A, int hop_mode, int B, const C
 
 hipError_t launch_moment_step_sym(const DevMat& A, int hop_mode, int B, const StepIO& io,
                                   double2* part_a, double2* part_b, double2* part_c, hipStream_t s) {
+  if (A.use_sheet && A.sheet && A.sheet_zc && A.sheet_blk0 && hop_mode == HOP_UNIFORM && B >= 2) {
+    auto go = [&](auto Fc) {
+      constexpr bool F = decltype(Fc)::value;
+      const dim3 g(A.G);
+      switch (B) {
+        case 2: k_moment_step_sym_sheet<2, kSheetCells, F><<<g, kBlock, 0, s>>>(A, io, part_a, part_b, part_c); break;
+        case 4: k_moment_step_sym_sheet<4, kSheetCells, F><<<g, kBlock, 0, s>>>(A, io, part_a, part_b, part_c); break;
+        case 8: k_moment_step_sym_sheet<8, kSheetCells, F><<<g, kBlock, 0, s>>>(A, io, part_a, part_b, part_c); break;
+        default: k_moment_step_sym_sheet<16, kSheetCells, F><<<g, kBlock, 0, s>>>(A, io, part_a, part_b, part_c); break;
+      }
+    };
+    if (io.first) go(std::true_type{}); else go(std::false_type{});
+    return hipGetLastError();
+  }
   if (A.use_box && A.box[0] > 0 && hop_mode == HOP_UNIFORM && B >= 2) {
     const int zc = box_run(A, B == 2 ? 16 : 8, 8);   // the tiles of the instances below
     auto go = [&](auto Fc) {

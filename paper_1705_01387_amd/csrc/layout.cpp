@@ -551,6 +551,108 @@ void pencil_units(const std::vector<int64_t>& seg_off, const std::vector<int64_t
   }
 }
 
+bool detect_sheets(const gpuqt_h_desc* d, const std::vector<int64_t>& seg_off, std::vector<int32_t>* sheet) {
+  sheet->clear();
+  if (!d || d->max_nn < 4 || !d->nn || !d->nbr || seg_off.size() < 2) return false;
+  const int64_t k = d->max_nn;
+  const int n_seg = (int)seg_off.size() - 1;
+  std::vector<int32_t> out(2 * (size_t)n_seg);
+  for (int sg = 0; sg < n_seg; ++sg) {
+    const int64_t a = seg_off[sg], n = seg_off[sg + 1] - a;
+    if (n < 9) return false;
+    for (int64_t i = a; i < a + n; ++i)
+      if (d->nn[i] != 4) return false;
+    // the segment's first row (0, 0): its neighbours sorted are 1, Lx - 1, Lx, (Ly - 1) Lx
+    int64_t c0[4];
+    for (int q = 0; q < 4; ++q) c0[q] = (int64_t)d->nbr[a * k + q] - a;
+    std::sort(c0, c0 + 4);
+    const int64_t Lx = c0[2];
+    if (Lx < 3 || n % Lx != 0) return false;
+    const int64_t Ly = n / Lx;
+    if (Ly < 3 || n > (int64_t(1) << 24)) return false;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t x = i % Lx, y = i / Lx;
+      int64_t e[4] = {(x + 1) % Lx + Lx * y, (x + Lx - 1) % Lx + Lx * y, x + Lx * ((y + 1) % Ly),
+                      x + Lx * ((y + Ly - 1) % Ly)};
+      int64_t c[4];
+      for (int q = 0; q < 4; ++q) c[q] = (int64_t)d->nbr[(a + i) * k + q] - a;
+      std::sort(e, e + 4);
+      std::sort(c, c + 4);
+      for (int q = 0; q < 4; ++q)
+        if (c[q] != e[q]) return false;
+    }
+    out[2 * sg] = (int32_t)Lx;
+    out[2 * sg + 1] = (int32_t)Ly;
+  }
+  *sheet = out;
+  return true;
+}
+
+int stencil_run(int64_t cols, int len, int64_t workers) {
+  workers = std::max<int64_t>(workers, 1);
+  int best_z = len;
+  int64_t best = -1;
+  for (int runs = 1; runs <= len; ++runs) {
+    const int z = (len + runs - 1) / runs;
+    if (runs > 1 && z < 16) break;
+    const int64_t rounds = (cols * ((len + z - 1) / z) + workers - 1) / workers;
+    const int64_t cost = rounds * (z + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_z = z;
+    }
+  }
+  return std::max(best_z, 1);
+}
+
+void sheet_split(const std::vector<int64_t>& cols, const std::vector<int32_t>& len, int64_t G,
+                 std::vector<int32_t>* blk0, std::vector<int32_t>* zc) {
+  const int n = (int)cols.size();
+  auto cost = [&](int s, int64_t g) -> int64_t {
+    const int z = stencil_run(cols[s], len[s], g);
+    const int64_t rounds = (cols[s] * ((len[s] + z - 1) / z) + g - 1) / g;
+    return rounds * (z + 2);
+  };
+  // least workgroups that keep segment s within T (G + 1: none do); cost falls with g
+  auto need = [&](int s, int64_t T) -> int64_t {
+    if (cost(s, G) > T) return G + 1;
+    int64_t lo = 1, hi = G;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (cost(s, mid) <= T) hi = mid;
+      else lo = mid + 1;
+    }
+    return lo;
+  };
+  auto fits = [&](int64_t T) {
+    int64_t tot = 0;
+    for (int s = 0; s < n && tot <= G; ++s) tot += need(s, T);
+    return tot <= G;
+  };
+  int64_t lo = 1, hi = 1;
+  for (int s = 0; s < n; ++s) hi = std::max(hi, cost(s, 1));
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (fits(mid)) hi = mid;
+    else lo = mid + 1;
+  }
+  std::vector<int64_t> g(n);
+  int64_t used = 0;
+  int big = 0;
+  for (int s = 0; s < n; ++s) {
+    g[s] = std::max<int64_t>(1, need(s, lo));
+    used += g[s];
+    if (cols[s] * len[s] > cols[big] * len[big]) big = s;
+  }
+  g[big] += G - used;
+  blk0->assign(n + 1, 0);
+  zc->assign(n, 1);
+  for (int s = 0; s < n; ++s) {
+    (*blk0)[s + 1] = (*blk0)[s] + (int32_t)g[s];
+    (*zc)[s] = stencil_run(cols[s], len[s], g[s]);
+  }
+}
+
 bool detect_box(const gpuqt_h_desc* d, int32_t box[3]) {
   box[0] = box[1] = box[2] = 0;
   if (!d || d->n < 27 || d->max_nn < 6 || (d->n_segments > 1) || !d->nn || !d->nbr) return false;

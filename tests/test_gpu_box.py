@@ -1,7 +1,8 @@
-"""The periodic-box Hermitian step (kernel variant bit 26): detection of periodic simple
-cubic boxes from the neighbour list, and moments through the box stencil kernel against the
-oracle for every block width it serves, box shapes that do and do not fill its 8 x 8 (16 x 8)
-tiles, shuffled neighbour slots and several workgroup counts.  Bar: normwise 1e-10."""
+"""The periodic-box stencils (kernel variant bits 26 and 27): detection of periodic simple
+cubic boxes and of segments that are all periodic squares from the neighbour list, and
+moments (and MSD rows) through the box and sheet stencil kernels against the oracle for every
+block width they serve, shapes that do and do not fill their tiles, shuffled neighbour slots,
+uneven segments and several workgroup counts.  Bar: normwise 1e-10."""
 import numpy as np
 import pytest
 
@@ -132,3 +133,62 @@ def test_box_msd_term_matches_oracle(gpu, name, B):
         got = host(P.gpuqt_msd(H, dev(phi), dts, 24))[:, 0]
         for k in range(len(dts)):
             assert err(got[k], ref[k].T) < TOL, (cap, k)
+
+
+def _segments(mods, dEs):
+    cat = I.concat_segments(mods)
+    offs = np.cumsum([0] + [mm.n for mm in mods])
+    H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
+                        seg_offsets=offs, seg_energy_max=dEs, seg_length_x=[mm.length_x for mm in mods])
+    return H, offs
+
+
+def test_sheet_detection(gpu):
+    """Every segment a periodic square in natural order with four neighbours: sheets = 1; a
+    segment open in x, a cubic box, a square with next-nearest neighbours or a chain: 0."""
+    say("case: periodic square (sheet) detection")
+    sq = [I.square(13, 9, W=1.0, seed=40), I.square(5, 31, W=2.0, seed=41), I.square(3, 3, seed=42)]
+    assert P.gpuqt_build_h_from_model(sq[0]).info.sheets == 1
+    H, _ = _segments(sq, [6.0, 6.5, 4.5])
+    assert H.info.sheets == 1 and tuple(H.info.box) == (0, 0, 0)
+    H, _ = _segments([sq[0], I.square(13, 9, W=1.0, seed=43, periodic_x=False)], [6.0, 6.0])
+    assert H.info.sheets == 0
+    assert P.gpuqt_build_h_from_model(I.square(12, 10, t2=-0.3, seed=44)).info.sheets == 0
+    assert P.gpuqt_build_h_from_model(I.cubic(7, W=1.0, seed=45)).info.sheets == 0
+    assert P.gpuqt_build_h_from_model(I.chain(64, W=1.0, seed=46)).info.sheets == 0
+
+
+SHEETS = {
+    # strips narrower and wider than a tile (256 / B cells), ragged tails, a segment of
+    # many rows (runs of rows meet inside it), rectangles both ways, the smallest square
+    "uneven": lambda: [I.square(37, 5, W=2.0, seed=50), I.square(5, 41, W=3.0, seed=51),
+                       I.square(300, 33, W=1.0, seed=52), I.square(3, 3, W=0.5, seed=53),
+                       I.square(20, 200, W=2.5, seed=54)],
+    "one": lambda: [I.square(70, 70, W=4.0, seed=55)],
+}
+
+
+@pytest.mark.parametrize("name", list(SHEETS))
+@pytest.mark.parametrize("B", [2, 4, 8, 16])
+def test_sheet_moments_match_oracle(gpu, name, B):
+    """Hermitian moment sets through the sheet kernel (bit 26) on segments of periodic
+    squares with per-segment DeltaE, at M = 2, 3 and 65 and four per-CU caps (different
+    workgroups per segment, so different work item rounds and run lengths), each segment
+    against the oracle."""
+    say(f"case: sheet moments {name} B={B}")
+    mods = SHEETS[name]()
+    ops = [O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)[0] for mm in mods]
+    dEs = [oracle_dE(Hs) for Hs in ops]
+    H, offs = _segments(mods, dEs)
+    assert H.info.sheets == 1
+    phi = np.concatenate([I.random_phase(mm.n, B, 60 + s) for s, mm in enumerate(mods)], axis=0)
+    d = dev(phi)
+    for cap in (0, 1, 2, 5):
+        P.gpuqt_set_variant(H, BOX | (cap << 2))
+        assert H.info.kernel_variant == BOX | (cap << 2)
+        for M in (2, 3, 65):
+            mu = host(P.gpuqt_moments(H, d, d, M))                # [seg, B, M]
+            for s, Hs in enumerate(ops):
+                ph = phi[offs[s]:offs[s + 1]]
+                ref = O.chebyshev_moments(Hs / dEs[s], ph, ph, M).T
+                assert err(mu[s], ref) < TOL, (cap, M, s)

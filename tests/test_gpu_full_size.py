@@ -168,8 +168,9 @@ def test_full_size_cubic_other_disorder(gpu, W):
 def test_full_size_batched_B16_sampled(gpu):
     """Eight square realisations 200^2 .. 2000^2 (8,255,182 orbitals) with per-realisation
     DeltaE, block of 16, one launch per step: the first 64 moments of every realisation for
-    columns 0 and 15."""
-    say("case: full-size batched 8 segments B=16, DOS M=64")
+    columns 0 and 15, through the sheet stencil kernel (variant bit 26; every segment is a
+    periodic square)."""
+    say("case: full-size batched 8 segments B=16, sheet kernel, DOS M=64")
     w = I.workload_batched(B=16, M=64)
     mods = w["models"]
     cat = I.concat_segments(mods)
@@ -177,7 +178,9 @@ def test_full_size_batched_B16_sampled(gpu):
     H = P.gpuqt_build_h(cat.nn, cat.nbr, cat.hop, cat.onsite, cat.x, 0.0, cat.volume, 0.0,
                         seg_offsets=offs, seg_energy_max=w["seg_energy_max"],
                         seg_length_x=[mm.length_x for mm in mods])
-    P.gpuqt_autotune(H, 16)
+    assert H.info.sheets == 1
+    P.gpuqt_set_variant(H, 1 << 26)
+    assert H.info.kernel_variant == 1 << 26
     d = dev(w["phi"])
     mu = host(P.gpuqt_moments(H, d, d, 64))                    # [seg, B, M]
     del d
