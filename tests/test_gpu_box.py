@@ -192,3 +192,24 @@ def test_sheet_moments_match_oracle(gpu, name, B):
                 ph = phi[offs[s]:offs[s + 1]]
                 ref = O.chebyshev_moments(Hs / dEs[s], ph, ph, M).T
                 assert err(mu[s], ref) < TOL, (cap, M, s)
+
+
+def test_sheet_autotune(gpu):
+    """The autotuner on segments of periodic squares times the sheet kernel (times_us[6]) and
+    whatever it keeps gives the oracle's moments; with bit 26 in the kept code the sheet
+    kernel ran them."""
+    say("case: autotune on sheets B=4")
+    mods = SHEETS["uneven"]()
+    ops = [O.operators(mm.nn, mm.nbr, mm.hop, mm.onsite, mm.x, mm.length_x)[0] for mm in mods]
+    dEs = [oracle_dE(Hs) for Hs in ops]
+    H, offs = _segments(mods, dEs)
+    assert H.info.sheets == 1
+    t = P.gpuqt_autotune(H, 4)
+    assert t[6] > 0
+    code = H.info.kernel_variant
+    say(f"kept code {code}, sheet bit {(code >> 26) & 1}")
+    phi = np.concatenate([I.random_phase(mm.n, 4, 80 + s) for s, mm in enumerate(mods)], axis=0)
+    mu = host(P.gpuqt_moments(H, dev(phi), dev(phi), 40))
+    for s, Hs in enumerate(ops):
+        ph = phi[offs[s]:offs[s + 1]]
+        assert err(mu[s], O.chebyshev_moments(Hs / dEs[s], ph, ph, 40).T) < TOL, s
